@@ -1,0 +1,131 @@
+"""Serial CPU oracle for balanced butterfly counting.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product path never imports
+this package; it shares no code with the GPU library.
+
+``bbc_oracle.c`` holds the arithmetic (plain C, compiled with gcc):
+
+* :func:`count` - Algorithm 1 (BB2K) with k = 2, per-anchor symmetric /
+  asymmetric wedge buckets (Definitions 7-9, Lemma 1), plain id order;
+* :func:`brute` - Definitions 1 and 2 applied to every 2x2 vertex choice;
+* :func:`count_kinds` - balanced / unbalanced / all butterflies per pair;
+* :func:`per_vertex` and :func:`vertex` - balanced butterflies containing
+  each vertex (the paper reports totals only; see the C header).
+
+Graphs are passed as any object with ``n_u, n_v, offsets, adj, signs``
+(CSR over U, int32 / int32 / int8).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "bbc_oracle.c")
+
+SIDE_AUTO, SIDE_U, SIDE_V = 0, 1, 2
+
+
+def build() -> str:
+    subprocess.check_call(["gcc", "-O2", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", _SO, _SRC])
+    return _SO
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        P32 = ctypes.POINTER(ctypes.c_int32)
+        P8 = ctypes.POINTER(ctypes.c_int8)
+        PU = ctypes.POINTER(ctypes.c_uint64)
+        head = [i32, i32, i64, P32, P32, P8]
+        lib.oracle_count.argtypes = head + [ctypes.c_int, PU]
+        lib.oracle_count_kinds.argtypes = head + [ctypes.c_int, PU, PU, PU]
+        lib.oracle_per_vertex.argtypes = head + [ctypes.c_int, PU]
+        lib.oracle_vertex.argtypes = head + [i64, PU]
+        lib.oracle_brute.argtypes = head + [PU, PU, PU]
+        for f in (lib.oracle_count, lib.oracle_count_kinds, lib.oracle_per_vertex, lib.oracle_vertex,
+                  lib.oracle_brute):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _args(g):
+    off = np.ascontiguousarray(g.offsets, np.int32)
+    adj = np.ascontiguousarray(g.adj, np.int32)
+    sg = np.ascontiguousarray(g.signs, np.int8)
+    keep = (off, adj, sg)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    P8 = ctypes.POINTER(ctypes.c_int8)
+    return keep, [int(g.n_u), int(g.n_v), int(adj.shape[0]), off.ctypes.data_as(P32),
+                  adj.ctypes.data_as(P32), sg.ctypes.data_as(P8)]
+
+
+def _u64():
+    return ctypes.c_uint64(0)
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError("oracle: malformed graph (offsets, ids or signs)")
+
+
+def count(g, side: int = SIDE_AUTO) -> int:
+    """Number of balanced butterflies (Algorithm 1, k = 2)."""
+    keep, a = _args(g)
+    out = _u64()
+    _check(_load().oracle_count(*a, side, ctypes.byref(out)))
+    del keep
+    return int(out.value)
+
+
+def count_kinds(g, side: int = SIDE_AUTO):
+    """(balanced, unbalanced, all butterflies) from per-pair wedge counts."""
+    keep, a = _args(g)
+    b, u, t = _u64(), _u64(), _u64()
+    _check(_load().oracle_count_kinds(*a, side, ctypes.byref(b), ctypes.byref(u), ctypes.byref(t)))
+    del keep
+    return int(b.value), int(u.value), int(t.value)
+
+
+def per_vertex(g, side: int = SIDE_AUTO) -> np.ndarray:
+    """uint64 [n_u + n_v]: balanced butterflies containing each vertex (U first)."""
+    keep, a = _args(g)
+    out = np.zeros(int(g.n_u) + int(g.n_v), np.uint64)
+    _check(_load().oracle_per_vertex(*a, side, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    del keep
+    return out
+
+
+def vertex(g, x: int) -> int:
+    """Balanced butterflies containing vertex x (global index, U first)."""
+    keep, a = _args(g)
+    out = _u64()
+    _check(_load().oracle_vertex(*a, int(x), ctypes.byref(out)))
+    del keep
+    return int(out.value)
+
+
+def brute(g, per_vertex: bool = False):
+    """(balanced, unbalanced[, per-vertex]) by enumerating every 2x2 choice."""
+    keep, a = _args(g)
+    b, u = _u64(), _u64()
+    pv = np.zeros(int(g.n_u) + int(g.n_v), np.uint64) if per_vertex else None
+    ptr = pv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if per_vertex else None
+    _check(_load().oracle_brute(*a, ctypes.byref(b), ctypes.byref(u), ptr))
+    del keep
+    if per_vertex:
+        return int(b.value), int(u.value), pv
+    return int(b.value), int(u.value)

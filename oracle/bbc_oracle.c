@@ -1,0 +1,366 @@
+/* Balanced butterfly counting: serial CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it; the product path never
+ * does.  It shares no code, header or table with the GPU library.
+ *
+ * What is computed (paper, Sec. "Preliminaries and Problem Definition"):
+ *   - a butterfly is a 4-cycle u_i v_i u_j v_j with all four U x V edges
+ *     present (Definition 1);
+ *   - it is balanced when it holds an even number of negative edges
+ *     (Definition 2);
+ *   - the problem is the number of balanced butterflies (Problem Statement).
+ *
+ * Two independent computations of that number live here:
+ *   oracle_brute   - enumerates every pair {u1,u2} x {v1,v2} and tests the
+ *                    definition directly (tiny graphs only);
+ *   oracle_count   - the bucket method of Algorithm 1 (BB2K) with k = 2: for
+ *                    each anchor u, count symmetric wedges (both edges of one
+ *                    sign, Definition 8) and asymmetric wedges (Definition 9)
+ *                    per endpoint w, then add C(B1[w],2) + C(B2[w],2).  By
+ *                    Lemma 1 a balanced butterfly is two symmetric or two
+ *                    asymmetric wedges on the same endpoint pair, never a
+ *                    mix.  The pair filter uses plain vertex ids (w > u):
+ *                    any strict order counts each pair once, and the
+ *                    algorithms of the paper use several (priority in
+ *                    Algorithms 1 and 2, ids in Algorithms 3 and 4).
+ *
+ * Anchor side: the paper starts from the smaller side (Algorithm 2: S = V,
+ * replaced by U when |V| > |U|); the count does not depend on the side
+ * (Sec. "BB2K Algorithm", symmetry of the (2,2) case).  `side` selects
+ * 0 = that rule, 1 = U, 2 = V.
+ *
+ * Per-vertex counts (the paper counts totals only; this is the reading used
+ * for the optional per-vertex output): cnt[x] is the number of balanced
+ * butterflies that contain x, for x in U (indices 0..n_u-1) then V
+ * (n_u..n_u+n_v-1).
+ *
+ * Integer widths: a, b <= min(deg) < 2^31; every sum is uint64, which holds
+ * any count for n_edges < 2^31 (a graph has at most m^2/4 butterflies).
+ *
+ * Input: CSR over U - offsets[n_u+1], adj[m] (V ids), signs[m] (+1 / -1).
+ * The graph must be simple.  Functions return 0, or 1 for malformed input.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int check_csr(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                     const int8_t* sg) {
+    if (n_u < 0 || n_v < 0 || m < 0) return 1;
+    if (off[0] != 0 || off[n_u] != m) return 1;
+    for (int32_t u = 0; u < n_u; ++u)
+        if (off[u + 1] < off[u]) return 1;
+    for (int64_t e = 0; e < m; ++e) {
+        if (adj[e] < 0 || adj[e] >= n_v) return 1;
+        if (sg[e] != 1 && sg[e] != -1) return 1;
+    }
+    return 0;
+}
+
+/* Adjacency of the chosen anchor side S and of the centre side C, both as
+ * CSR with a sign per entry.  Built by a counting sort (the transpose). */
+typedef struct {
+    int32_t n_s, n_c;
+    int64_t* s_off; /* n_s + 1 */
+    int32_t* s_nbr; /* centres of each anchor */
+    int8_t* s_sgn;
+    int64_t* c_off; /* n_c + 1 */
+    int32_t* c_nbr; /* anchors of each centre */
+    int8_t* c_sgn;
+} sides_t;
+
+static void sides_free(sides_t* g) {
+    free(g->s_off);
+    free(g->s_nbr);
+    free(g->s_sgn);
+    free(g->c_off);
+    free(g->c_nbr);
+    free(g->c_sgn);
+}
+
+/* transpose of a CSR (rows n_r, columns n_col) by counting sort */
+static void transpose(int32_t n_r, int32_t n_col, int64_t m, const int64_t* off, const int32_t* nbr,
+                      const int8_t* sg, int64_t** t_off, int32_t** t_nbr, int8_t** t_sgn) {
+    int64_t* to = (int64_t*)calloc((size_t)n_col + 1, sizeof(int64_t));
+    int32_t* tn = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int8_t* ts = (int8_t*)malloc((size_t)(m > 0 ? m : 1));
+    for (int64_t e = 0; e < m; ++e) to[nbr[e] + 1]++;
+    for (int32_t c = 0; c < n_col; ++c) to[c + 1] += to[c];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_col > 0 ? n_col : 1));
+    for (int32_t c = 0; c < n_col; ++c) fill[c] = to[c];
+    for (int32_t r = 0; r < n_r; ++r)
+        for (int64_t e = off[r]; e < off[r + 1]; ++e) {
+            int64_t q = fill[nbr[e]]++;
+            tn[q] = r;
+            ts[q] = sg[e];
+        }
+    free(fill);
+    *t_off = to;
+    *t_nbr = tn;
+    *t_sgn = ts;
+}
+
+static int pick_side(int32_t n_u, int32_t n_v, int side) {
+    if (side == 1) return 1;
+    if (side == 2) return 2;
+    return n_u < n_v ? 1 : 2; /* the smaller side; a tie keeps V */
+}
+
+static void build_sides(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                        const int8_t* sg, int side, sides_t* g) {
+    int64_t* uoff = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_u + 1));
+    for (int32_t u = 0; u <= n_u; ++u) uoff[u] = off[u];
+    int32_t* unbr = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int8_t* usg = (int8_t*)malloc((size_t)(m > 0 ? m : 1));
+    memcpy(unbr, adj, sizeof(int32_t) * (size_t)m);
+    memcpy(usg, sg, (size_t)m);
+    int64_t* voff;
+    int32_t* vnbr;
+    int8_t* vsg;
+    transpose(n_u, n_v, m, uoff, unbr, usg, &voff, &vnbr, &vsg);
+    if (pick_side(n_u, n_v, side) == 1) {
+        g->n_s = n_u;
+        g->n_c = n_v;
+        g->s_off = uoff;
+        g->s_nbr = unbr;
+        g->s_sgn = usg;
+        g->c_off = voff;
+        g->c_nbr = vnbr;
+        g->c_sgn = vsg;
+    } else {
+        g->n_s = n_v;
+        g->n_c = n_u;
+        g->s_off = voff;
+        g->s_nbr = vnbr;
+        g->s_sgn = vsg;
+        g->c_off = uoff;
+        g->c_nbr = unbr;
+        g->c_sgn = usg;
+    }
+}
+
+/* C(x, 2); x < 2^32 so the product fits in 64 bits, and x = 0 gives 0 */
+static inline uint64_t choose2(uint64_t x) { return x * (x - 1) / 2; }
+
+/* Algorithm 1 (BB2K), k = 2.  B1 / B2 are dense arrays over the anchor side
+ * with a list of touched endpoints, cleared after each anchor. */
+int oracle_count(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                 const int8_t* sg, int side, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    uint32_t* B1 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B2 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    uint64_t total = 0;
+    for (int32_t u = 0; u < g.n_s; ++u) {
+        int32_t nt = 0;
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            int32_t c = g.s_nbr[i];
+            int8_t s1 = g.s_sgn[i];
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                int32_t w = g.c_nbr[j];
+                if (w <= u) continue; /* each endpoint pair once */
+                if (B1[w] == 0 && B2[w] == 0) touched[nt++] = w;
+                if (g.c_sgn[j] == s1) B1[w]++; /* symmetric wedge */
+                else B2[w]++;                  /* asymmetric wedge */
+            }
+        }
+        for (int32_t k = 0; k < nt; ++k) {
+            int32_t w = touched[k];
+            total += choose2(B1[w]) + choose2(B2[w]);
+            B1[w] = 0;
+            B2[w] = 0;
+        }
+    }
+    free(B1);
+    free(B2);
+    free(touched);
+    sides_free(&g);
+    *out = total;
+    return 0;
+}
+
+/* Pair-level split used by the invariant checks: over every anchor pair,
+ * balanced += C(a,2) + C(b,2), unbalanced += a*b (a mixed pair of wedges has
+ * an odd number of negative edges, Lemma 1 case 3), and every butterfly is
+ * counted once in butterflies += C(a+b,2). */
+int oracle_count_kinds(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                       const int8_t* sg, int side, uint64_t* balanced, uint64_t* unbalanced,
+                       uint64_t* butterflies) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    uint32_t* B1 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B2 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    uint64_t bal = 0, unb = 0, all = 0;
+    for (int32_t u = 0; u < g.n_s; ++u) {
+        int32_t nt = 0;
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            int32_t c = g.s_nbr[i];
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                if (B1[w] == 0 && B2[w] == 0) touched[nt++] = w;
+                if (g.c_sgn[j] == g.s_sgn[i]) B1[w]++;
+                else B2[w]++;
+            }
+        }
+        for (int32_t k = 0; k < nt; ++k) {
+            int32_t w = touched[k];
+            uint64_t a = B1[w], b = B2[w];
+            bal += choose2(a) + choose2(b);
+            unb += a * b;
+            all += choose2(a + b);
+            B1[w] = 0;
+            B2[w] = 0;
+        }
+    }
+    free(B1);
+    free(B2);
+    free(touched);
+    sides_free(&g);
+    *balanced = bal;
+    *unbalanced = unb;
+    *butterflies = all;
+    return 0;
+}
+
+/* Per-vertex counts.  For each anchor pair {u, w} with a symmetric and b
+ * asymmetric wedges, the pair closes C(a,2) + C(b,2) balanced butterflies,
+ * each containing u and w.  A centre c of a wedge u-c-w of one type lies in
+ * every balanced butterfly that pairs this wedge with another wedge of the
+ * same type on {u, w}: (a - 1) of them for a symmetric wedge, (b - 1) for an
+ * asymmetric one.  Anchors are indexed on their own side; the output puts U
+ * first, then V. */
+int oracle_per_vertex(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                      const int8_t* sg, int side, uint64_t* cnt) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    int s_is_u = pick_side(n_u, n_v, side) == 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    uint64_t* cs = cnt + (s_is_u ? 0 : n_u); /* anchor-side block */
+    uint64_t* cc = cnt + (s_is_u ? n_u : 0); /* centre-side block */
+    memset(cnt, 0, sizeof(uint64_t) * ((size_t)n_u + (size_t)n_v));
+    uint32_t* B1 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B2 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    for (int32_t u = 0; u < g.n_s; ++u) {
+        int32_t nt = 0;
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            int32_t c = g.s_nbr[i];
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                if (B1[w] == 0 && B2[w] == 0) touched[nt++] = w;
+                if (g.c_sgn[j] == g.s_sgn[i]) B1[w]++;
+                else B2[w]++;
+            }
+        }
+        /* second walk with the pair counts complete: the centres */
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            int32_t c = g.s_nbr[i];
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                uint32_t n_same = (g.c_sgn[j] == g.s_sgn[i]) ? B1[w] : B2[w];
+                cc[c] += n_same - 1;
+            }
+        }
+        for (int32_t k = 0; k < nt; ++k) {
+            int32_t w = touched[k];
+            uint64_t p = choose2(B1[w]) + choose2(B2[w]);
+            cs[u] += p;
+            cs[w] += p;
+            B1[w] = 0;
+            B2[w] = 0;
+        }
+    }
+    free(B1);
+    free(B2);
+    free(touched);
+    sides_free(&g);
+    return 0;
+}
+
+/* Count of one vertex x (global index: U first, then V), computed from x's
+ * own 2-hop neighbourhood, for spot checks on graphs too large for a full
+ * per-vertex pass.  For x on either side, its same-side 2-hop neighbours y
+ * give a_xy / b_xy over the common neighbours and x lies in
+ * sum_y C(a_xy,2) + C(b_xy,2) balanced butterflies. */
+int oracle_vertex(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                  const int8_t* sg, int64_t x, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    if (x < 0 || x >= (int64_t)n_u + n_v) return 1;
+    int on_u = x < n_u;
+    sides_t g; /* anchor side = x's side */
+    build_sides(n_u, n_v, m, off, adj, sg, on_u ? 1 : 2, &g);
+    int32_t u = (int32_t)(on_u ? x : x - n_u);
+    uint32_t* A = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    int32_t nt = 0;
+    for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+        int32_t c = g.s_nbr[i];
+        for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+            int32_t w = g.c_nbr[j];
+            if (w == u) continue;
+            if (A[w] == 0 && B[w] == 0) touched[nt++] = w;
+            if (g.c_sgn[j] == g.s_sgn[i]) A[w]++;
+            else B[w]++;
+        }
+    }
+    uint64_t t = 0;
+    for (int32_t k = 0; k < nt; ++k) t += choose2(A[touched[k]]) + choose2(B[touched[k]]);
+    free(A);
+    free(B);
+    free(touched);
+    sides_free(&g);
+    *out = t;
+    return 0;
+}
+
+/* Definitions 1 and 2 applied directly: every {u1,u2} x {v1,v2} with all
+ * four edges is a butterfly; it is balanced when the product of its four
+ * signs is +1 (an even number of negative edges).  O(n_u^2 n_v^2) with a
+ * dense sign matrix; for tiny graphs.  per_vertex (optional, n_u + n_v)
+ * receives the balanced count of every vertex. */
+int oracle_brute(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                 const int8_t* sg, uint64_t* balanced, uint64_t* unbalanced, uint64_t* per_vertex) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    if ((int64_t)n_u * n_v > (1LL << 28)) return 1;
+    int8_t* M = (int8_t*)calloc((size_t)n_u * (size_t)n_v + 1, 1);
+    for (int32_t u = 0; u < n_u; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) M[(size_t)u * n_v + adj[e]] = sg[e];
+    if (per_vertex) memset(per_vertex, 0, sizeof(uint64_t) * ((size_t)n_u + n_v));
+    uint64_t bal = 0, unb = 0;
+    for (int32_t u1 = 0; u1 < n_u; ++u1)
+        for (int32_t u2 = u1 + 1; u2 < n_u; ++u2)
+            for (int32_t v1 = 0; v1 < n_v; ++v1) {
+                int8_t a = M[(size_t)u1 * n_v + v1], b = M[(size_t)u2 * n_v + v1];
+                if (!a || !b) continue;
+                for (int32_t v2 = v1 + 1; v2 < n_v; ++v2) {
+                    int8_t c = M[(size_t)u1 * n_v + v2], d = M[(size_t)u2 * n_v + v2];
+                    if (!c || !d) continue;
+                    int negs = (a < 0) + (b < 0) + (c < 0) + (d < 0);
+                    if (negs % 2 == 0) {
+                        ++bal;
+                        if (per_vertex) {
+                            per_vertex[u1]++;
+                            per_vertex[u2]++;
+                            per_vertex[n_u + v1]++;
+                            per_vertex[n_u + v2]++;
+                        }
+                    } else {
+                        ++unb;
+                    }
+                }
+            }
+    free(M);
+    *balanced = bal;
+    *unbalanced = unb;
+    return 0;
+}

@@ -1,0 +1,339 @@
+"""Pins of the CPU oracle to facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every check is a value printed
+(or drawn) in the paper, a closed form, an invariant of the definition, or an
+exhaustive enumeration written independently below.
+"""
+import itertools
+import os
+import shutil
+import subprocess
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2601_17707_amd import synth
+from tests.fixtures import load_graphs, load_table8
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def py_brute(g):
+    """Definitions 1 and 2 in pure Python: (balanced, unbalanced, per-vertex)."""
+    sign = {}
+    for u in range(g.n_u):
+        for e in range(g.offsets[u], g.offsets[u + 1]):
+            sign[(u, int(g.adj[e]))] = int(g.signs[e])
+    bal = unb = 0
+    pv = [0] * (g.n_u + g.n_v)
+    for u1, u2 in itertools.combinations(range(g.n_u), 2):
+        for v1, v2 in itertools.combinations(range(g.n_v), 2):
+            quad = [(u1, v1), (u1, v2), (u2, v1), (u2, v2)]
+            if all(q in sign for q in quad):
+                negs = sum(sign[q] < 0 for q in quad)
+                if negs % 2 == 0:
+                    bal += 1
+                    for x in (u1, u2, g.n_u + v1, g.n_u + v2):
+                        pv[x] += 1
+                else:
+                    unb += 1
+    return bal, unb, pv
+
+
+FIXTURES = {}
+for fname in ("fig2_butterflies.txt", "fig1b_signed_k44.txt", "drug_target_sample.txt"):
+    FIXTURES.update(load_graphs(fname))
+
+
+# --------------------------------------------------------------- paper examples
+
+
+@pytest.mark.parametrize("name", sorted(FIXTURES))
+def test_paper_examples(name):
+    """Fig. 1(b), Fig. 2 panels and the case-study sample graph."""
+    g, exp = FIXTURES[name]
+    for side in (oracle.SIDE_AUTO, oracle.SIDE_U, oracle.SIDE_V):
+        assert oracle.count(g, side) == exp["balanced"]
+    b, u = oracle.brute(g)
+    assert b == exp["balanced"]
+    if "unbalanced" in exp:
+        assert u == exp["unbalanced"]
+        kb, ku, kt = oracle.count_kinds(g)
+        assert (kb, ku) == (exp["balanced"], exp["unbalanced"])
+        assert kt == exp["balanced"] + exp["unbalanced"]
+    if "butterflies" in exp:
+        assert b + u == exp["butterflies"]
+    pb, pu, _ = py_brute(g)
+    assert pb == exp["balanced"]
+
+
+def test_table8_identity():
+    """Table 8: the six classes sum to the stated 69,537 butterflies; balanced
+    (coherent + incoherent) and mixed split 65,741 / 3,796."""
+    total, classes = load_table8()
+    assert sum(c for _, c, _ in classes) == total == 69537
+    assert sum(c for _, c, k in classes if k == "balanced") == 65741
+    assert sum(c for _, c, k in classes if k == "unbalanced") == 3796
+    # the percentages quoted in the text: about 81 %, 13.5 % and 5.5 %
+    coh = sum(c for n, c, _ in classes if n.startswith("coherent"))
+    inc = sum(c for n, c, _ in classes if n.startswith("incoherent"))
+    assert round(100 * coh / total) == 81
+    assert round(100 * inc / total, 1) == 13.5
+    assert round(100 * 3796 / total, 1) == 5.5
+
+
+# ----------------------------------------------------------------- brute force
+
+
+def test_brute_matches_python_definition():
+    rng = np.random.default_rng(11)
+    for _ in range(150):
+        g = synth.small_random_graph(rng, max_n=7)
+        b, u, pv = oracle.brute(g, per_vertex=True)
+        pb, pu, ppv = py_brute(g)
+        assert (b, u) == (pb, pu)
+        assert list(pv) == ppv
+
+
+def test_bucket_method_equals_enumeration():
+    """Algorithm 1 (k = 2) on 1,500 random tiny graphs, every anchor side."""
+    rng = np.random.default_rng(12)
+    for i in range(1500):
+        g = synth.small_random_graph(rng, max_n=12)
+        b, u = oracle.brute(g)
+        for side in (oracle.SIDE_AUTO, oracle.SIDE_U, oracle.SIDE_V):
+            assert oracle.count(g, side) == b, (i, side)
+        kb, ku, kt = oracle.count_kinds(g)
+        assert (kb, ku, kt) == (b, u, b + u)
+
+
+def test_bucket_method_equals_enumeration_medium():
+    rng = np.random.default_rng(13)
+    for n_u, n_v, d in [(40, 25, 0.3), (25, 60, 0.5), (64, 64, 0.15), (30, 30, 0.9)]:
+        g = synth.random_graph(rng, n_u, n_v, d, 0.35)
+        b, u = oracle.brute(g)
+        assert oracle.count(g, oracle.SIDE_U) == b
+        assert oracle.count(g, oracle.SIDE_V) == b
+
+
+# ----------------------------------------------------------------- closed forms
+
+
+@pytest.mark.parametrize("m,n", [(2, 2), (2, 7), (5, 7), (6, 3), (9, 11)])
+def test_complete_bipartite_closed_forms(m, n):
+    base = comb(m, 2) * comb(n, 2)
+    g = synth.complete_graph(m, n)
+    assert oracle.count(g) == base
+    # signs s_uv = x_u y_v: every butterfly has an even number of negatives
+    rng = np.random.default_rng(m * 31 + n)
+    x = rng.choice([-1, 1], m)
+    y = rng.choice([-1, 1], n)
+    assert oracle.count(synth.complete_graph(m, n, np.outer(x, y))) == base
+    # one negative edge: it lies in (m-1)(n-1) butterflies, all unbalanced
+    s = np.ones((m, n), np.int8)
+    s[0, 0] = -1
+    assert oracle.count(synth.complete_graph(m, n, s)) == base - (m - 1) * (n - 1)
+    if n >= 2:  # two negatives sharing a U vertex: unbalanced 2(m-1)(n-1) - 2(m-1)
+        s = np.ones((m, n), np.int8)
+        s[0, 0] = s[0, 1] = -1
+        assert oracle.count(synth.complete_graph(m, n, s)) == base - (2 * (m - 1) * (n - 1) - 2 * (m - 1))
+    if m >= 2:  # sharing a V vertex
+        s = np.ones((m, n), np.int8)
+        s[0, 0] = s[1, 0] = -1
+        assert oracle.count(synth.complete_graph(m, n, s)) == base - (2 * (m - 1) * (n - 1) - 2 * (n - 1))
+    if m >= 2 and n >= 2:  # disjoint: only the butterfly holding both is balanced
+        s = np.ones((m, n), np.int8)
+        s[0, 0] = s[1, 1] = -1
+        assert oracle.count(synth.complete_graph(m, n, s)) == base - (2 * (m - 1) * (n - 1) - 2)
+
+
+def test_k57_values():
+    """K_{5,7} with one negative, two sharing u, two disjoint: 186 / 170 / 164."""
+    vals = []
+    for neg in ([(0, 0)], [(0, 0), (0, 1)], [(0, 0), (1, 1)]):
+        s = np.ones((5, 7), np.int8)
+        for a, b in neg:
+            s[a, b] = -1
+        vals.append(oracle.count(synth.complete_graph(5, 7, s)))
+    assert vals == [186, 170, 164]
+
+
+def test_k2n_closed_form():
+    """Two anchors: T = C(a,2) + C(b,2) over their agree / disagree columns."""
+    rng = np.random.default_rng(14)
+    for n in range(1, 30):
+        s = rng.choice([-1, 1], (2, n)).astype(np.int8)
+        a = int((s[0] == s[1]).sum())
+        assert oracle.count(synth.complete_graph(2, n, s)) == comb(a, 2) + comb(n - a, 2)
+
+
+def test_degenerate_graphs():
+    for n_u, n_v in [(0, 0), (0, 5), (5, 0), (1, 9), (9, 1)]:
+        g = synth.complete_graph(n_u, n_v)
+        assert oracle.count(g) == 0
+    g = synth.from_edges(10, 10, [], [], [])
+    assert oracle.count(g) == 0
+    assert oracle.per_vertex(g).sum() == 0
+
+
+# ------------------------------------------------------------------- invariants
+
+
+def _mid_graphs():
+    rng = np.random.default_rng(21)
+    out = [synth.random_graph(rng, 60, 40, 0.25, 0.3), synth.random_graph(rng, 35, 80, 0.2, 0.5)]
+    out.append(synth.chung_lu_graph(300, 200, 2500, 2.1, 2.1, 80, 80, seed=5, p_neg=0.25))
+    out.append(synth.chung_lu_graph(150, 400, 3000, 2.5, 1.8, 60, 200, seed=6, beta_bias=(2, 5, 0.7)))
+    return out
+
+
+def _with_signs(g, s):
+    return synth.Graph(g.n_u, g.n_v, g.offsets, g.adj, np.asarray(s, np.int8), {})
+
+
+def test_balanced_plus_unbalanced_is_unsigned_count():
+    for g in _mid_graphs():
+        t = oracle.count(g)
+        b, n, all_ = oracle.count_kinds(g)
+        assert b == t and b + n == all_
+        assert oracle.count(_with_signs(g, np.ones_like(g.signs))) == all_
+
+
+def test_switching_and_global_flip():
+    """Negating every edge at one vertex keeps each butterfly's parity (it has
+    0 or 2 edges at that vertex); a global flip negates all four edges."""
+    rng = np.random.default_rng(22)
+    for g in _mid_graphs():
+        t = oracle.count(g)
+        pv = oracle.per_vertex(g)
+        u, v, s = g.edges()
+        assert oracle.count(_with_signs(g, -s)) == t
+        for _ in range(5):
+            x = int(rng.integers(0, g.n_u + g.n_v))
+            s2 = s.copy()
+            if x < g.n_u:
+                s2[u == x] *= -1
+            else:
+                s2[v == x - g.n_u] *= -1
+            g2 = _with_signs(g, s2)
+            assert oracle.count(g2) == t
+            assert np.array_equal(oracle.per_vertex(g2), pv)
+        # switching a random vertex subset on both sides at once
+        fu = rng.choice([-1, 1], g.n_u)
+        fv = rng.choice([-1, 1], g.n_v)
+        assert oracle.count(_with_signs(g, s * fu[u] * fv[v])) == t
+
+
+def test_side_and_relabelling_invariance():
+    rng = np.random.default_rng(23)
+    for g in _mid_graphs():
+        t = oracle.count(g)
+        assert oracle.count(g, oracle.SIDE_U) == t == oracle.count(g, oracle.SIDE_V)
+        u, v, s = g.edges()
+        pu = rng.permutation(g.n_u)
+        pv = rng.permutation(g.n_v)
+        g2 = synth.from_edges(g.n_u, g.n_v, pu[u], pv[v], s)
+        assert oracle.count(g2) == t
+        assert oracle.count(synth.shuffle_rows(g, rng)) == t
+        # swapping the roles of U and V
+        assert oracle.count(synth.from_edges(g.n_v, g.n_u, v, u, s)) == t
+
+
+def test_disjoint_union_is_additive():
+    gs = _mid_graphs()
+    a, b = gs[0], gs[2]
+    ua, va, sa = a.edges()
+    ub, vb, sb = b.edges()
+    g = synth.from_edges(a.n_u + b.n_u, a.n_v + b.n_v, np.concatenate([ua, ub + a.n_u]),
+                         np.concatenate([va, vb + a.n_v]), np.concatenate([sa, sb]))
+    assert oracle.count(g) == oracle.count(a) + oracle.count(b)
+
+
+def test_pendant_and_isolated_vertices_add_nothing():
+    g = _mid_graphs()[1]
+    t = oracle.count(g)
+    u, v, s = g.edges()
+    # one isolated vertex per side, one degree-1 vertex per side
+    u2 = np.concatenate([u, [g.n_u + 1], [0]])
+    v2 = np.concatenate([v, [0], [g.n_v + 1]])
+    s2 = np.concatenate([s, [-1], [1]])
+    assert oracle.count(synth.from_edges(g.n_u + 2, g.n_v + 2, u2, v2, s2)) == t
+
+
+def test_per_vertex_definition_and_sums():
+    rng = np.random.default_rng(24)
+    for _ in range(300):
+        g = synth.small_random_graph(rng, max_n=9)
+        b, _, pv = oracle.brute(g, per_vertex=True)
+        for side in (oracle.SIDE_AUTO, oracle.SIDE_U, oracle.SIDE_V):
+            assert np.array_equal(oracle.per_vertex(g, side), pv)
+    for g in _mid_graphs():
+        t = oracle.count(g)
+        pv = oracle.per_vertex(g)
+        assert int(pv[: g.n_u].sum()) == 2 * t == int(pv[g.n_u:].sum())
+        for x in rng.choice(g.n_u + g.n_v, 12, replace=False):
+            assert oracle.vertex(g, int(x)) == int(pv[x])
+        assert np.array_equal(oracle.per_vertex(g, oracle.SIDE_U), oracle.per_vertex(g, oracle.SIDE_V))
+
+
+def test_malformed_input_rejected():
+    g = synth.complete_graph(3, 3)
+    bad = synth.Graph(3, 3, g.offsets, g.adj.copy(), g.signs, {})
+    bad.adj[0] = 7
+    with pytest.raises(ValueError):
+        oracle.count(bad)
+    bad = synth.Graph(3, 3, g.offsets, g.adj, g.signs.copy(), {})
+    bad.signs[0] = 0
+    with pytest.raises(ValueError):
+        oracle.count(bad)
+
+
+# ------------------------------------------------------- planted oracle mistakes
+
+MUTANTS = {
+    "pair filter admits w == u": ("if (w <= u) continue; /* each endpoint pair once */",
+                                  "if (w < u) continue; /* each endpoint pair once */"),
+    "no pair filter": ("if (w <= u) continue; /* each endpoint pair once */", ""),
+    "asymmetric term dropped": ("total += choose2(B1[w]) + choose2(B2[w]);", "total += choose2(B1[w]);"),
+    "C(x,2) off by one": ("return x * (x - 1) / 2;", "return x * (x + 1) / 2;"),
+    "sign of centre edge ignored": ("if (g.c_sgn[j] == s1) B1[w]++;", "if (s1 > 0) B1[w]++;"),
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_oracle_mistakes(name, tmp_path):
+    """Each plausible slip in the bucket method makes a pin fail."""
+    import ctypes
+
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "bbc_oracle.c")).read()
+    old, new = MUTANTS[name]
+    assert old in src
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), str(mut)])
+    lib = ctypes.CDLL(str(so))
+    P32, P8 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)
+    lib.oracle_count.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P32, P32, P8,
+                                 ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+
+    def mcount(g):
+        off = np.ascontiguousarray(g.offsets, np.int32)
+        adj = np.ascontiguousarray(g.adj, np.int32)
+        sg = np.ascontiguousarray(g.signs, np.int8)
+        out = ctypes.c_uint64()
+        lib.oracle_count(g.n_u, g.n_v, adj.size, off.ctypes.data_as(P32), adj.ctypes.data_as(P32),
+                         sg.ctypes.data_as(P8), 0, ctypes.byref(out))
+        return int(out.value)
+
+    failures = 0
+    for g, exp in FIXTURES.values():
+        failures += mcount(g) != exp["balanced"]
+    rng = np.random.default_rng(31)
+    for _ in range(50):
+        g = synth.small_random_graph(rng, max_n=8)
+        failures += mcount(g) != py_brute(g)[0]
+    assert failures > 0, f"mutant '{name}' passed every pin"
