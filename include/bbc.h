@@ -1,0 +1,134 @@
+/* bbc.h - C ABI of libbbc.so: balanced butterfly counting on one AMD MI355X
+ * (gfx950) GPU.
+ *
+ * Problem (paper, Sec. "Preliminaries and Problem Definition", Definitions 1
+ * and 2 and the Problem Statement): in a signed bipartite graph
+ * G = (U, V, E+ u E-), count the butterflies - 4-cycles u1 v1 u2 v2 with all
+ * four U x V edges present - that hold an even number of negative edges.
+ *
+ * Method (Sec. "proposed algorithms", Algorithms 1-4, Lemma 1): from each
+ * anchor u of one side S, walk the wedges u - c - w (c on the other side,
+ * w ranked above u), count per endpoint w the wedges whose two edges agree in
+ * sign (a) and disagree (b), and add C(a,2) + C(b,2).  Only pairs of agreeing
+ * or pairs of disagreeing wedges close a balanced butterfly (Lemma 1), so no
+ * unbalanced structure is ever formed.  Ranks follow the vertex priority of
+ * Definition 6 (degree, then id).  Every step runs in the library's own HIP
+ * kernels on the caller's stream; counts are exact integers.
+ *
+ * Conventions for every entry point
+ *   - Graphs are a CSR over U: offsets[n_u + 1] (int32, offsets[0] = 0,
+ *     non-decreasing, offsets[n_u] = n_edges), adj[n_edges] (int32 V ids in
+ *     [0, n_v)), signs[n_edges] (int8, +1 or -1).  Rows need not be sorted.
+ *     The graph must be simple: a repeated (u, v) pair is an error.
+ *   - Pointers marked "device" are HIP device pointers (for example a torch
+ *     tensor's data_ptr()); pointers marked "host" are ordinary host memory.
+ *   - The caller owns every input and output buffer; the library never frees
+ *     them.  The library owns its scratch memory, allocated inside the
+ *     context and grown on demand.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is ordered on it.
+ *   - On any error nothing is written to the outputs, and bbc_last_error()
+ *     describes the first offending input.
+ *   - A context is bound to one device and is not thread-safe: use one
+ *     context per host thread.
+ *   - Degenerate graphs (no edges, fewer than two vertices on a side) give 0.
+ *   - n_edges must be <= INT32_MAX and n_u + n_v <= INT32_MAX, otherwise
+ *     BBC_ETOOBIG.
+ */
+#ifndef BBC_H
+#define BBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BBC_OK = 0,
+    BBC_EINVAL = 1,   /* null pointer, negative size, bad option */
+    BBC_EOFFSETS = 2, /* offsets[0] != 0, decreasing offsets, or offsets[n_u] != n_edges */
+    BBC_ERANGE = 3,   /* an adjacency id outside [0, n_v) */
+    BBC_ESIGN = 4,    /* a sign other than +1 / -1 */
+    BBC_EDUP = 5,     /* a repeated (u, v) pair */
+    BBC_ENOMEM = 6,   /* device memory could not be allocated */
+    BBC_EDEVICE = 7,  /* HIP runtime error; bbc_last_error has the detail */
+    BBC_ETOOBIG = 8   /* sizes beyond the int32 CSR limits */
+} bbc_status;
+
+typedef struct bbc_ctx bbc_ctx;
+
+/* anchor side: the paper starts from the smaller side, a tie keeping V
+ * (Algorithm 2: S = V, replaced by U when |V| > |U|); the count is the same
+ * from either side (Sec. "BB2K Algorithm"). */
+enum { BBC_SIDE_AUTO = 0, BBC_SIDE_U = 1, BBC_SIDE_V = 2 };
+
+/* optional input checks (offsets and id ranges are always checked, since
+ * the kernels index with them) */
+enum { BBC_CHECK_SIGNS = 1, BBC_CHECK_DUPLICATES = 2, BBC_CHECK_ALL = 3 };
+
+typedef struct {
+    uint32_t struct_size; /* sizeof(bbc_options), set by bbc_options_init */
+    int32_t side;         /* BBC_SIDE_* */
+    uint32_t checks;      /* BBC_CHECK_* mask, default BBC_CHECK_ALL */
+    int32_t timing;       /* nonzero: record per-phase HIP event times (bbc_last_stats) */
+    int32_t band_words;   /* LDS counter band in 32-bit words per workgroup, 0 = default */
+    int32_t wg_per_cu;    /* persistent workgroups per compute unit, 0 = default */
+} bbc_options;
+
+/* Fills *opts with the defaults: auto side, all checks, no timing. */
+void bbc_options_init(bbc_options* opts);
+
+/* Creates a context on HIP device `device` (the current device if < 0).
+ * *out (host) receives the context.  BBC_EDEVICE if the device is missing or
+ * is not a gfx950 part. */
+bbc_status bbc_create(int device, bbc_ctx** out);
+
+/* Releases the context and its scratch memory.  NULL is accepted. */
+bbc_status bbc_destroy(bbc_ctx* ctx);
+
+/* Number of balanced butterflies of one graph (Problem Statement; computed
+ * by the wedge method of Algorithms 1-4, see above).
+ *   offsets, adj, signs  device, CSR over U as described above.
+ *   total                host, receives the count (written only on BBC_OK).
+ *   per_vertex           device or NULL; if given, n_u + n_v uint64 entries
+ *                        receive the number of balanced butterflies that
+ *                        contain each vertex, U ids first, then V ids (the
+ *                        paper counts totals only; this is the library's
+ *                        per-vertex reading).  Overwritten, not accumulated.
+ *   opts                 host or NULL (defaults).
+ * Synchronous with respect to *total: returns after the stream has
+ * produced it.  Errors: BBC_EINVAL, BBC_EOFFSETS, BBC_ERANGE, BBC_ESIGN,
+ * BBC_EDUP, BBC_ENOMEM, BBC_EDEVICE, BBC_ETOOBIG. */
+bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                     const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
+                     const bbc_options* opts, void* stream);
+
+/* Facts about the last successful bbc_count on this context. */
+typedef struct {
+    uint32_t struct_size; /* sizeof(bbc_stats) */
+    int32_t side;         /* BBC_SIDE_U or BBC_SIDE_V: the anchor side used */
+    int32_t n_anchor;     /* vertices on the anchor side */
+    int32_t n_centre;     /* vertices on the other side */
+    int64_t n_edges;
+    uint64_t wedges;      /* sum over centres c of C(deg c, 2): wedges walked once each */
+    uint64_t bands;       /* LDS counter bands processed by the wedge kernel */
+    int32_t grid;         /* persistent workgroups launched */
+    int32_t block;        /* threads per workgroup */
+    float ms_checks;      /* HIP event times on the caller's stream (timing option) */
+    float ms_build;       /* degrees, ranks, degree-ordered CSR, schedule */
+    float ms_count;       /* wedge aggregation kernel */
+    float ms_total;
+} bbc_stats;
+
+bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out);
+
+/* Static strings; never NULL. */
+const char* bbc_status_string(bbc_status s);
+const char* bbc_last_error(const bbc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBC_H */

@@ -1,0 +1,226 @@
+"""Python binding of libbbc.so (include/bbc.h): argument marshalling only.
+
+Device buffers are torch tensors; every step of the computation runs in the
+library's HIP kernels.  There is no fallback: if the library is missing or
+the device is not a gfx950 GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbbc.so")
+
+OK, EINVAL, EOFFSETS, ERANGE, ESIGN, EDUP, ENOMEM, EDEVICE, ETOOBIG = range(9)
+SIDE_AUTO, SIDE_U, SIDE_V = 0, 1, 2
+CHECK_SIGNS, CHECK_DUPLICATES, CHECK_ALL = 1, 2, 3
+_SIDES = {"auto": SIDE_AUTO, "u": SIDE_U, "v": SIDE_V, SIDE_AUTO: SIDE_AUTO, SIDE_U: SIDE_U, SIDE_V: SIDE_V}
+
+
+class BbcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"bbc status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("side", ctypes.c_int32),
+        ("checks", ctypes.c_uint32),
+        ("timing", ctypes.c_int32),
+        ("band_words", ctypes.c_int32),
+        ("wg_per_cu", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("side", ctypes.c_int32),
+        ("n_anchor", ctypes.c_int32),
+        ("n_centre", ctypes.c_int32),
+        ("n_edges", ctypes.c_int64),
+        ("wedges", ctypes.c_uint64),
+        ("bands", ctypes.c_uint64),
+        ("grid", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("ms_checks", ctypes.c_float),
+        ("ms_build", ctypes.c_float),
+        ("ms_count", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "struct_size"}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libbbc.so and declares its C signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() or "
+                          f"python -m paper_2601_17707_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.bbc_options_init.argtypes = [ctypes.POINTER(Options)]
+    lib.bbc_options_init.restype = None
+    lib.bbc_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.bbc_create.restype = ctypes.c_int
+    lib.bbc_destroy.argtypes = [vp]
+    lib.bbc_destroy.restype = ctypes.c_int
+    lib.bbc_count.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), vp,
+                              ctypes.POINTER(Options), vp]
+    lib.bbc_count.restype = ctypes.c_int
+    lib.bbc_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.bbc_last_stats.restype = ctypes.c_int
+    lib.bbc_status_string.argtypes = [ctypes.c_int]
+    lib.bbc_status_string.restype = ctypes.c_char_p
+    lib.bbc_last_error.argtypes = [vp]
+    lib.bbc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load_library().bbc_status_string(status).decode()
+
+
+def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_per_cu=0) -> Options:
+    o = Options()
+    load_library().bbc_options_init(ctypes.byref(o))
+    o.side = _SIDES[side]
+    o.checks = checks
+    o.timing = 1 if timing else 0
+    o.band_words = band_words
+    o.wg_per_cu = wg_per_cu
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def _check_tensor(name, t, dtype, torch):
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """One bbc_ctx (scratch arena, events) bound to a device."""
+
+    def __init__(self, device: int | None = None):
+        import torch
+
+        self._lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = self._lib.bbc_create(self.device, ctypes.byref(h))
+        if st != OK:
+            raise BbcError(st, f"bbc_create(device={self.device}) failed: {status_string(st)}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bbc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return self._lib.bbc_last_error(self._h).decode()
+
+    def count(self, offsets, adj, signs, n_v: int, per_vertex=None, opts: Options | None = None,
+              stream=None) -> int:
+        """Balanced butterfly count of the CSR (offsets, adj, signs) over U.
+
+        ``per_vertex``: optional uint64-compatible device tensor (torch.int64)
+        of n_u + n_v entries that receives per-vertex counts.
+        """
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        n_u = offsets.numel() - 1
+        if per_vertex is not None:
+            _check_tensor("per_vertex", per_vertex, torch.int64, torch)
+            if per_vertex.numel() != n_u + n_v:
+                raise ValueError("per_vertex must hold n_u + n_v entries")
+        if stream is None:
+            stream = torch.cuda.current_stream(offsets.device)
+        sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0))
+        out = ctypes.c_uint64(0)
+        o = opts if opts is not None else options()
+        st = self._lib.bbc_count(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj), _ptr(signs),
+                                 ctypes.byref(out), _ptr(per_vertex) if per_vertex is not None else None,
+                                 ctypes.byref(o), sp)
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return int(out.value)
+
+    def stats(self) -> dict:
+        s = Stats()
+        s.struct_size = ctypes.sizeof(Stats)
+        self._lib.bbc_last_stats(self._h, ctypes.byref(s))
+        return s.as_dict()
+
+
+_default = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    import torch
+
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default:
+        _default[dev] = Context(dev)
+    return _default[dev]
+
+
+def graph_tensors(g, device="cuda"):
+    """(offsets, adj, signs) device tensors of a CSR graph object."""
+    import numpy as np
+    import torch
+
+    off = torch.from_numpy(np.ascontiguousarray(g.offsets, np.int32)).to(device)
+    adj = torch.from_numpy(np.ascontiguousarray(g.adj, np.int32)).to(device)
+    sg = torch.from_numpy(np.ascontiguousarray(g.signs, np.int8)).to(device)
+    return off, adj, sg
+
+
+def count(g, per_vertex: bool = False, side="auto", checks=CHECK_ALL, ctx: Context | None = None):
+    """Counts a graph object (n_u, n_v, offsets, adj, signs) on the current GPU.
+
+    Returns the total, or (total, per-vertex int64 tensor) with per_vertex.
+    """
+    import torch
+
+    ctx = ctx or default_context()
+    off, adj, sg = graph_tensors(g, f"cuda:{ctx.device}")
+    pv = torch.empty(int(g.n_u) + int(g.n_v), dtype=torch.int64, device=off.device) if per_vertex else None
+    t = ctx.count(off, adj, sg, int(g.n_v), per_vertex=pv, opts=options(side=side, checks=checks))
+    return (t, pv) if per_vertex else t

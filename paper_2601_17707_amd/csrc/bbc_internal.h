@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP sources of libbbc.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbc {
+
+constexpr int kWave = 64;
+
+// Device-side status and accumulators of one bbc_count call.
+struct DevStatus {
+    int32_t flags;  // kBad* bits
+    int32_t pad0;
+    int64_t bad_offset;  // first offending index (atomicMin)
+    int64_t bad_range;
+    int64_t bad_sign;
+    int64_t bad_dup;
+    unsigned long long total;   // balanced butterflies
+    unsigned long long wedges;  // sum over centres of C(deg, 2)
+    unsigned long long bands;   // counter bands processed
+    unsigned int queue;         // persistent work queue head
+    unsigned int pad1;
+};
+
+enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8 };
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over a workgroup of NT threads; `tmp` holds NT/64 + 1
+// entries of LDS.  Returns this thread's exclusive prefix; *total receives
+// the sum.  Must be reached by every thread of the workgroup.
+template <int NT, class T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T* tmp, T* total) {
+    constexpr int NW = NT / kWave;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    T inc = wave_inclusive_scan(x);
+    if (lane == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < NW; ++i) {
+            T v = tmp[i];
+            tmp[i] = run;
+            run += v;
+        }
+        tmp[NW] = run;
+    }
+    __syncthreads();
+    T r = tmp[w] + inc - x;
+    *total = tmp[NW];
+    __syncthreads();  // tmp may be reused right after
+    return r;
+}
+
+template <int NT, class T>
+__device__ __forceinline__ T block_sum(T x, T* tmp) {
+    constexpr int NW = NT / kWave;
+    const int w = threadIdx.x / kWave;
+    x = wave_sum(x);
+    if (lane_id() == 0) tmp[w] = x;
+    __syncthreads();
+    T s = 0;
+    for (int i = 0; i < NW; ++i) s += tmp[i];
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------ host launchers
+
+// Exclusive scan: out[i] = sum(in[0..i)), out[n] = total.  `partials` needs
+// scan_partials_size(n) elements of Tacc.  in and out must not alias.
+size_t scan_partials_size(int64_t n);
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials, hipStream_t s);
+
+// Stable LSD radix sort of n uint32 keys on their low `bits` bits, carrying
+// up to two uint32 payloads.  The inputs are read only; the result lands in
+// one of the two ping-pong buffers, returned through *_out.  v0_in may be
+// NULL (no payload 0); v1_in == NULL with v1 buffers set means payload 1 is
+// the input index.  `hist` needs radix_hist_size(n) uint32 and `partials`
+// scan_partials_size(radix_hist_size(n)).
+size_t radix_hist_size(int64_t n);
+void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32_t* v0_in, uint32_t* v0_a,
+                uint32_t* v0_b, const uint32_t* v1_in, uint32_t* v1_a, uint32_t* v1_b, int64_t n, int bits,
+                uint32_t* hist, uint32_t* hist_scan, uint32_t* partials, hipStream_t s, const uint32_t** k_out,
+                const uint32_t** v0_out, const uint32_t** v1_out);
+
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void fill_bytes(void* p, int64_t bytes, hipStream_t s);  // zero fill
+
+}  // namespace bbc

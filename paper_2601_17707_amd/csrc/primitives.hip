@@ -1,0 +1,238 @@
+// Device-wide building blocks: fills, exclusive scan and a stable LSD radix
+// sort, used to build the degree-ordered CSR on the GPU.
+#include "bbc_internal.h"
+
+namespace bbc {
+
+// ------------------------------------------------------------------ fills
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_zero_bytes(uint8_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0;
+}
+
+static int grid_for(int64_t n, int threads, int cap = 8192) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+}
+
+void fill_bytes(void* p, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return;
+    if (bytes % 4 == 0 && ((uintptr_t)p % 4) == 0) {
+        fill_u32((uint32_t*)p, 0u, bytes / 4, s);
+        return;
+    }
+    hipLaunchKernelGGL(k_zero_bytes, dim3(grid_for(bytes, 256)), dim3(256), 0, s, (uint8_t*)p, bytes);
+}
+
+// ------------------------------------------------------------------- scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+size_t scan_partials_size(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 2; }
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* in, int64_t n, uint32_t* partial) {
+    __shared__ uint32_t tmp[kScanThreads / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    s = block_sum<kScanThreads>(s, tmp);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// exclusive scan of nb partials by one workgroup, in place
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, int64_t nb) {
+    __shared__ uint32_t tmp[1024 / kWave + 1];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+        int64_t i = b0 + threadIdx.x;
+        uint32_t v = i < nb ? partial[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan<1024>(v, tmp, &tot);
+        uint32_t c = carry;
+        if (i < nb) partial[i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+}
+
+// Each thread owns kScanItems consecutive inputs, staged through LDS so the
+// global reads and writes stay coalesced.
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
+                                                             const uint32_t* partial) {
+    __shared__ uint32_t stage[kScanTile];
+    __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        stage[k * kScanThreads + threadIdx.x] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = stage[threadIdx.x * kScanItems + k];
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan<kScanThreads>(s, tmp, &tot) + partial[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        stage[threadIdx.x * kScanItems + k] = ex;
+        ex += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) out[i] = stage[k * kScanThreads + threadIdx.x];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) out[n] = ex;
+}
+
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials, hipStream_t s) {
+    if (n <= 0) {
+        fill_u32(out, 0u, 1, s);
+        return;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
+                       (const uint32_t*)partials);
+}
+
+// ------------------------------------------------------------- radix sort
+
+constexpr int kRsThreads = 256;  // one thread per digit value
+constexpr int kRsRounds = 16;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+constexpr int kRsWaves = kRsThreads / kWave;
+
+size_t radix_hist_size(int64_t n) { return (size_t)256 * (size_t)((n + kRsTile - 1) / kRsTile) + 1; }
+
+// Digit counts of one tile; hist is digit-major: hist[d * nblk + block].
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* keys, int64_t n, int shift, uint32_t* hist,
+                                                        int64_t nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+    for (int r = 0; r < kRsRounds; ++r) {
+        int64_t i = base + (int64_t)r * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile.  Items are visited in rounds of 256 (round,
+// then wave, then lane is the input order).  Within a wave, the lanes that
+// share a digit are found with eight ballots; a lane's place among them is
+// the number of such lanes below it.  Wave counts are turned into offsets
+// per round by the thread that owns the digit.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys, uint32_t* keys_out,
+                                                           const uint32_t* v0, uint32_t* v0_out,
+                                                           const uint32_t* v1, uint32_t* v1_out, int v1_iota,
+                                                           int64_t n, int shift, const uint32_t* hist_scan,
+                                                           int64_t nblk) {
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[kRsWaves][256];
+    __shared__ uint32_t woff[kRsWaves][256];
+    const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+    running[t] = hist_scan[(int64_t)t * nblk + blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kRsWaves; ++k) wcnt[k][t] = 0;
+    __syncthreads();
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsRounds; ++r) {
+        int64_t i = base + (int64_t)r * kRsThreads + t;
+        bool valid = i < n;
+        uint32_t key = valid ? keys[i] : 0u;
+        uint32_t d = (key >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            int bit = (d >> b) & 1u;
+            unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t rk = (uint32_t)__popcll(peers & below);
+        if (valid && rk == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t run = running[t];
+#pragma unroll
+            for (int k = 0; k < kRsWaves; ++k) {
+                uint32_t c = wcnt[k][t];
+                woff[k][t] = run;
+                run += c;
+                wcnt[k][t] = 0;
+            }
+            running[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = woff[w][d] + rk;
+            keys_out[pos] = key;
+            if (v0) v0_out[pos] = v0[i];
+            if (v1_out) v1_out[pos] = v1_iota ? (uint32_t)i : v1[i];
+        }
+    }
+}
+
+void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32_t* v0_in, uint32_t* v0_a,
+                uint32_t* v0_b, const uint32_t* v1_in, uint32_t* v1_a, uint32_t* v1_b, int64_t n, int bits,
+                uint32_t* hist, uint32_t* hist_scan, uint32_t* partials, hipStream_t s, const uint32_t** k_out,
+                const uint32_t** v0_out, const uint32_t** v1_out) {
+    const uint32_t *ks = k_in, *v0s = v0_in, *v1s = v1_in;
+    int v1_iota = (v1_a != nullptr && v1_in == nullptr) ? 1 : 0;
+    int64_t nblk = (n + kRsTile - 1) / kRsTile;
+    if (bits < 1) bits = 1;
+    int pass = 0;
+    for (int shift = 0; shift < bits && n > 0; shift += 8, ++pass) {
+        uint32_t* kd = (pass & 1) ? k_b : k_a;
+        uint32_t* v0d = v0_in ? ((pass & 1) ? v0_b : v0_a) : nullptr;
+        uint32_t* v1d = v1_a ? ((pass & 1) ? v1_b : v1_a) : nullptr;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, n, shift, hist, nblk);
+        scan_exclusive_u32(hist, hist_scan, 256 * nblk, partials, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, kd, v0s, v0d, v1s, v1d,
+                           v1_iota, n, shift, (const uint32_t*)hist_scan, nblk);
+        ks = kd;
+        v0s = v0d;
+        v1s = v1d;
+        v1_iota = 0;
+    }
+    *k_out = ks;
+    if (v0_out) *v0_out = v0s;
+    if (v1_out) *v1_out = v1s;
+}
+
+}  // namespace bbc
