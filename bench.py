@@ -32,15 +32,31 @@ def algorithmic_bytes(stats: dict) -> int:
     return 4 * int(stats["wedges"]) + 13 * int(stats["n_edges"]) + 12 * int(stats["n_anchor"])
 
 
-def cpu_baseline(g, wedges: int, budget_s: float = 30.0) -> dict:
-    """The serial oracle timed on this host on the same graph (one core)."""
+def cpu_baseline(g, wedges: int, budget_s: float = 15.0) -> dict:
+    """The serial oracle (Algorithm 1) timed on this host on a bounded sample
+    of the same graph: the anchors with the lowest ids (ids are a random
+    permutation, so this is a random anchor sample).  The oracle's own
+    transpose is timed separately (an empty anchor range) and left out of the
+    rate, which is wedges bucketed per second of counting on one core."""
     import oracle
 
-    t0 = time.perf_counter()
-    total = oracle.count(g)
-    dt = time.perf_counter() - t0
-    return dict(value=wedges / dt / 1e9, unit="G/s", cores=1, kind="oracle",
-                sample=f"full {WORKLOAD} seed 1 graph, one serial pass ({dt:.1f} s)", seconds=dt, total=total)
+    def timed(lo, hi):
+        t0 = time.perf_counter()
+        part, w = oracle.count_anchors(g, lo, hi)
+        return time.perf_counter() - t0, w
+
+    n_s = g.n_u if g.n_u < g.n_v else g.n_v
+    t_setup, _ = timed(0, 0)
+    pilot = max(1, n_s // 500)
+    t1, w1 = timed(0, pilot)
+    rate = w1 / max(t1 - t_setup, 1e-6)
+    k = int(min(n_s, max(pilot, n_s * budget_s * rate / max(wedges, 1))))
+    t2, w2 = timed(0, k)
+    dt = max(t2 - t_setup, 1e-9)
+    return dict(value=w2 / dt / 1e9, unit="G/s", cores=1, kind="oracle",
+                sample=f"anchors 0..{k - 1} of {n_s} ({w2} wedges, {100.0 * w2 / max(wedges, 1):.2f}% of the "
+                       f"graph) counted in {dt:.1f} s; oracle transpose {t_setup:.1f} s excluded",
+                full_graph_estimate_s=wedges / (w2 / dt) + t_setup)
 
 
 def main():
@@ -124,10 +140,7 @@ def main():
                       traffic=None, kernel="k_wedge", algorithmic_bytes=nbytes),
     )
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(g, wedges)
-        if cb.pop("total") != total:
-            line["cpu_baseline_mismatch"] = True
-        line["cpu_baseline"] = cb
+        line["cpu_baseline"] = cpu_baseline(g, wedges)
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -8,6 +8,7 @@ this package; it shares no code with the GPU library.
 
 * :func:`count` - Algorithm 1 (BB2K) with k = 2, per-anchor symmetric /
   asymmetric wedge buckets (Definitions 7-9, Lemma 1), plain id order;
+* :func:`count_anchors` - the same over a range of anchors (timing samples);
 * :func:`brute` - Definitions 1 and 2 applied to every 2x2 vertex choice;
 * :func:`count_kinds` - balanced / unbalanced / all butterflies per pair;
 * :func:`per_vertex` and :func:`vertex` - balanced butterflies containing
@@ -55,7 +56,8 @@ def _load():
         lib.oracle_per_vertex.argtypes = head + [ctypes.c_int, PU]
         lib.oracle_vertex.argtypes = head + [i64, PU]
         lib.oracle_brute.argtypes = head + [PU, PU, PU]
-        for f in (lib.oracle_count, lib.oracle_count_kinds, lib.oracle_per_vertex, lib.oracle_vertex,
+        lib.oracle_count_anchors.argtypes = head + [ctypes.c_int, i32, i32, PU, PU]
+        for f in (lib.oracle_count_anchors, lib.oracle_count, lib.oracle_count_kinds, lib.oracle_per_vertex, lib.oracle_vertex,
                   lib.oracle_brute):
             f.restype = ctypes.c_int
         _lib = lib
@@ -89,6 +91,15 @@ def count(g, side: int = SIDE_AUTO) -> int:
     _check(_load().oracle_count(*a, side, ctypes.byref(out)))
     del keep
     return int(out.value)
+
+
+def count_anchors(g, a_lo: int, a_hi: int, side: int = SIDE_AUTO):
+    """(partial count, wedges bucketed) of Algorithm 1 over anchors a_lo <= u < a_hi."""
+    keep, a = _args(g)
+    p, w = _u64(), _u64()
+    _check(_load().oracle_count_anchors(*a, side, int(a_lo), int(a_hi), ctypes.byref(p), ctypes.byref(w)))
+    del keep
+    return int(p.value), int(w.value)
 
 
 def count_kinds(g, side: int = SIDE_AUTO):

@@ -144,28 +144,27 @@ static void build_sides(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off,
 /* C(x, 2); x < 2^32 so the product fits in 64 bits, and x = 0 gives 0 */
 static inline uint64_t choose2(uint64_t x) { return x * (x - 1) / 2; }
 
-/* Algorithm 1 (BB2K), k = 2.  B1 / B2 are dense arrays over the anchor side
- * with a list of touched endpoints, cleared after each anchor. */
-int oracle_count(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
-                 const int8_t* sg, int side, uint64_t* out) {
-    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
-    sides_t g;
-    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
-    uint32_t* B1 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
-    uint32_t* B2 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
-    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
-    uint64_t total = 0;
-    for (int32_t u = 0; u < g.n_s; ++u) {
+/* Algorithm 1 (BB2K), k = 2, over the anchors a_lo <= u < a_hi.  B1 / B2 are
+ * dense arrays over the anchor side with a list of touched endpoints,
+ * cleared after each anchor.  *wedges receives the number of wedges u - c - w
+ * with w > u that were bucketed. */
+static uint64_t bb2k_range(const sides_t* g, int32_t a_lo, int32_t a_hi, uint64_t* wedges) {
+    uint32_t* B1 = (uint32_t*)calloc((size_t)g->n_s + 1, sizeof(uint32_t));
+    uint32_t* B2 = (uint32_t*)calloc((size_t)g->n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g->n_s + 1));
+    uint64_t total = 0, nw = 0;
+    for (int32_t u = a_lo; u < a_hi; ++u) {
         int32_t nt = 0;
-        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
-            int32_t c = g.s_nbr[i];
-            int8_t s1 = g.s_sgn[i];
-            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
-                int32_t w = g.c_nbr[j];
+        for (int64_t i = g->s_off[u]; i < g->s_off[u + 1]; ++i) {
+            int32_t c = g->s_nbr[i];
+            int8_t s1 = g->s_sgn[i];
+            for (int64_t j = g->c_off[c]; j < g->c_off[c + 1]; ++j) {
+                int32_t w = g->c_nbr[j];
                 if (w <= u) continue; /* each endpoint pair once */
+                ++nw;
                 if (B1[w] == 0 && B2[w] == 0) touched[nt++] = w;
-                if (g.c_sgn[j] == s1) B1[w]++; /* symmetric wedge */
-                else B2[w]++;                  /* asymmetric wedge */
+                if (g->c_sgn[j] == s1) B1[w]++; /* symmetric wedge */
+                else B2[w]++;                   /* asymmetric wedge */
             }
         }
         for (int32_t k = 0; k < nt; ++k) {
@@ -178,8 +177,35 @@ int oracle_count(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const 
     free(B1);
     free(B2);
     free(touched);
+    *wedges = nw;
+    return total;
+}
+
+int oracle_count(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                 const int8_t* sg, int side, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    uint64_t nw;
+    *out = bb2k_range(&g, 0, g.n_s, &nw);
     sides_free(&g);
-    *out = total;
+    return 0;
+}
+
+/* The same count restricted to anchors with id in [a_lo, a_hi) (a partial
+ * sum; the ranges of a partition of the anchor side add up to the total).
+ * Used to time the oracle on a bounded sample of a large graph. */
+int oracle_count_anchors(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                         const int8_t* sg, int side, int32_t a_lo, int32_t a_hi, uint64_t* partial,
+                         uint64_t* wedges) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    if (a_lo < 0) a_lo = 0;
+    if (a_hi > g.n_s) a_hi = g.n_s;
+    if (a_hi < a_lo) a_hi = a_lo;
+    *partial = bb2k_range(&g, a_lo, a_hi, wedges);
+    sides_free(&g);
     return 0;
 }
 

@@ -18,9 +18,12 @@
 //   - counter width follows the anchor degree d (a, b <= d): 4-bit pairs for
 //     d <= 15, 8-bit for d <= 255, 16-bit for d <= 65535, else 32-bit, so a
 //     64 KiB band spans 64K, 32K, 16K or 8K endpoint ranks;
-//   - the slices of a band are flattened across all lanes (prefix sum over
-//     slice lengths), so a wave reads consecutive entries of one list
-//     (coalesced 4-byte reads) regardless of how uneven the lists are;
+//   - the non-empty slices of a band are flattened into rows of 64 wedges
+//     (prefix sum over slice lengths); waves own contiguous runs of rows and
+//     lanes keep a cursor on their slice, so a wave reads consecutive entries
+//     of one list (coalesced 4-byte reads) however uneven the lists are;
+//   - endpoint slots are scattered over the band by an odd multiplier so
+//     that rank-sorted lists do not pile onto a few LDS banks;
 //   - the first increment of a counter word sets a bit in an LDS bitmap, so
 //     the reduction only visits touched words;
 //   - sums stay in registers across tasks and are reduced once per wave at
@@ -29,15 +32,43 @@
 
 namespace bbc {
 
-// first position q in [lo, hi) of a rank-sorted list with rank(q) >= target
-__device__ __forceinline__ int32_t lower_bound_rank(const uint32_t* __restrict__ packed, int32_t lo, int32_t hi,
+// First position q in [lo, hi) of a rank-sorted list with rank(q) >= target
+// (hi if none), found by one wave: each round probes 64 evenly spaced
+// positions and keeps the gap where the ranks cross the target, so a list of
+// length L takes ceil(log64 L) dependent loads.  Every lane of the wave must
+// call it with the same arguments; every lane returns the answer.
+__device__ __forceinline__ int32_t wave_lower_bound(const uint32_t* __restrict__ packed, int32_t lo, int32_t hi,
                                                     uint32_t target) {
-    while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
-        if ((packed[mid] >> 1) < target) lo = mid + 1;
-        else hi = mid;
+    const int lane = lane_id();
+    while (lo < hi) {  // the answer lies in [lo, hi]
+        const int32_t len = hi - lo;
+        const int32_t step = (len + kWave - 1) / kWave;
+        const int32_t off = lane * step;
+        const bool probe = off < len;
+        const bool ge = probe && (packed[lo + off] >> 1) >= target;
+        const unsigned long long b = __ballot(ge);
+        if (b == 0) {
+            const unsigned long long pm = __ballot(probe);
+            const int last = 63 - __clzll(pm);
+            lo += last * step + 1;
+        } else {
+            const int f = __ffsll(b) - 1;
+            if (f == 0) return lo;
+            hi = lo + f * step;
+            lo += (f - 1) * step + 1;
+        }
     }
     return lo;
+}
+
+// Whether any counter field of a word is >= 2 (only those close butterflies;
+// most endpoint pairs share a single wedge).
+template <int MODE>
+__device__ __forceinline__ bool has_pairs(uint32_t v) {
+    if constexpr (MODE == 0) return (v & 0xEEEEEEEEu) != 0;
+    else if constexpr (MODE == 1) return (v & 0xFEFEFEFEu) != 0;
+    else if constexpr (MODE == 2) return (v & 0xFFFEFFFEu) != 0;
+    else return v > 1u;
 }
 
 // Sum of C(x,2) over the counter fields of one LDS word.
@@ -68,10 +99,25 @@ __device__ __forceinline__ unsigned long long word_pairs(uint32_t v) {
     }
 }
 
+// Band capacity in endpoint slots for a counter mode (a power of two).
+template <int MODE, int BAND_WORDS>
+__host__ __device__ constexpr uint32_t band_capacity() {
+    return MODE == 0 ? BAND_WORDS * 4u : MODE == 1 ? BAND_WORDS * 2u : MODE == 2 ? BAND_WORDS * 1u : BAND_WORDS / 2u;
+}
+
+// Multiplier of the slot scatter.  Centre lists are sorted by rank, so the
+// lanes of a wave read endpoints at a near-regular stride; mapped straight
+// onto LDS words that stride lands on a few banks.  Any bijection between
+// endpoint slots and counter fields is valid (the reduction sums every
+// touched field), so slots are scattered by an odd multiplier modulo the
+// power-of-two capacity.
+constexpr uint32_t kSlotMul = 0x9E3779B1u;
+
 // LDS word and increment for endpoint slot `slot` (rank - band start) and
 // wedge type t (0 = signs agree, 1 = disagree).
-template <int MODE>
+template <int MODE, int BAND_WORDS>
 __device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& word, uint32_t& inc) {
+    slot = (slot * kSlotMul) & (band_capacity<MODE, BAND_WORDS>() - 1u);
     if constexpr (MODE == 0) {
         word = slot >> 2;
         inc = 1u << (((slot & 3u) << 3) + (t << 2));
@@ -87,92 +133,142 @@ __device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& w
     }
 }
 
-template <int MODE>
-__host__ __device__ constexpr int slots_per_word_x2() {
-    return MODE == 0 ? 8 : MODE == 1 ? 4 : MODE == 2 ? 2 : 1;  // twice the slots per word
-}
-
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 
 template <int WG, int BAND_WORDS>
 struct WedgeShared {
     uint32_t cnt[BAND_WORDS];
     uint32_t bmp[BAND_WORDS / 32];
-    uint32_t c_start[WG];  // slice start | negative-edge bit << 31
-    int32_t c_pre[WG + 1];
-    int32_t scan_tmp[WG / kWave + 1];
+    uint32_t c_cur[WG];    // slice start of each centre | negative-edge bit << 31
+    int32_t c_end[WG];     // slice end (exclusive) in the current band
+    int32_t c_ce[WG];      // end of the centre's whole list
+    uint32_t w_start[WG];  // non-empty slices only: start | negative-edge bit << 31
+    int32_t w_pre[WG + 1]; // their exclusive prefix of lengths
+    long long scan_tmp[WG / kWave + 1];
     int32_t task;
 };
 
-// Count one band [lo, hi) of anchor r.  Returns the sum of pair terms seen
-// by this thread.
-template <int MODE, int WG, int BAND_WORDS>
-__device__ unsigned long long count_band(WedgeShared<WG, BAND_WORDS>& sh, const int32_t* __restrict__ acent,
-                                         const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
-                                         const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
-                                         int32_t a0, int32_t deg, int32_t r, int64_t lo, int64_t hi, int64_t n_s) {
+// Loads the centres k0 .. k0+nk-1 of anchor list entry a0: slice start just
+// past the anchor's own position in the centre list (the ranked-above
+// suffix), the list end, and the sign of the anchor edge.
+template <int WG, int BAND_WORDS>
+__device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS>& sh, const int32_t* __restrict__ acent,
+                                             const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
+                                             const uint32_t* __restrict__ coff, int32_t a0, int32_t k0,
+                                             int32_t nk) {
     const int tid = threadIdx.x;
-    const bool first = lo == (int64_t)r + 1, last = hi == n_s;
-    const uint32_t band = (uint32_t)(hi - lo);
-    for (int32_t k0 = 0; k0 < deg; k0 += WG) {
-        const int32_t nk = min(WG, deg - k0);
-        int32_t len = 0;
-        if (tid < nk) {
-            const int32_t p = a0 + k0 + tid;
-            const int32_t c = acent[p];
-            const int32_t ce = (int32_t)coff[c + 1];
-            const int32_t sfx = back[p] + 1;
-            const int32_t s = first ? sfx : lower_bound_rank(packed, sfx, ce, (uint32_t)lo);
-            const int32_t e = last ? ce : lower_bound_rank(packed, s, ce, (uint32_t)hi);
-            sh.c_start[tid] = (uint32_t)s | ((uint32_t)aneg[p] << 31);
-            len = e - s;
-        }
-        int32_t total;
-        int32_t ex = block_exclusive_scan<WG>(len, sh.scan_tmp, &total);
-        if (tid < nk) sh.c_pre[tid] = ex;
-        if (tid == 0) sh.c_pre[nk] = total;
-        __syncthreads();
+    if (tid < nk) {
+        const int32_t p = a0 + k0 + tid;
+        sh.c_cur[tid] = (uint32_t)(back[p] + 1) | ((uint32_t)aneg[p] << 31);
+        sh.c_ce[tid] = (int32_t)coff[acent[p] + 1];
+    }
+}
 
-        for (int32_t j0 = 0; j0 < total; j0 += WG * kUnroll) {
+// Counts the wedges of the centres currently in the slice tables whose
+// endpoint rank lies in [lo, hi).  Slice starts are in c_cur; when
+// `seek_start` they are first advanced to the first rank >= lo.
+//
+// The non-empty slices are compacted and flattened into rows of 64 wedges;
+// each wave owns a contiguous run of rows and each lane keeps a cursor on
+// the slice holding its wedge, so moving to the next row costs a compare
+// (and a short advance when the lane crosses into the next slice).  Lanes
+// of a wave read consecutive entries of a list: coalesced 4-byte loads.
+template <int MODE, int WG, int BAND_WORDS>
+__device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS>& sh, const uint32_t* __restrict__ packed,
+                                          int32_t nk, int64_t lo, int64_t hi, bool seek_start, bool last) {
+    constexpr int NW = WG / kWave;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const uint32_t band = (uint32_t)(hi - lo);
+    if (seek_start || !last) {
+        for (int32_t k = wave; k < nk; k += NW) {
+            const uint32_t cur = sh.c_cur[k];
+            int32_t st = (int32_t)(cur & 0x7fffffffu);
+            const int32_t ce = sh.c_ce[k];
+            if (seek_start) st = wave_lower_bound(packed, st, ce, (uint32_t)lo);
+            const int32_t en = last ? ce : wave_lower_bound(packed, st, ce, (uint32_t)hi);
+            if (lane == 0) {
+                sh.c_cur[k] = (uint32_t)st | (cur & 0x80000000u);
+                sh.c_end[k] = en;
+            }
+        }
+    } else if (tid < nk) {
+        sh.c_end[tid] = sh.c_ce[tid];
+    }
+    __syncthreads();
+
+    // compact the non-empty slices: one scan carries (length, count << 40)
+    const uint32_t cur = tid < nk ? sh.c_cur[tid] : 0u;
+    const int32_t len = tid < nk ? sh.c_end[tid] - (int32_t)(cur & 0x7fffffffu) : 0;
+    long long tot;
+    const long long ex =
+        block_exclusive_scan<WG>((long long)len + ((long long)(len > 0) << 40), sh.scan_tmp, &tot);
+    const int32_t total = (int32_t)(tot & ((1ll << 40) - 1));
+    const int32_t nkc = (int32_t)(tot >> 40);
+    if (len > 0) {
+        const int32_t idx = (int32_t)(ex >> 40);
+        sh.w_start[idx] = cur;
+        sh.w_pre[idx] = (int32_t)(ex & ((1ll << 40) - 1));
+    }
+    if (tid == 0) sh.w_pre[nkc] = total;
+    __syncthreads();
+
+    const int32_t rows = (total + kWave - 1) / kWave;
+    const int32_t rpw = (rows + NW - 1) / NW;
+    const int32_t r0 = wave * rpw, r1 = min(rows, r0 + rpw);
+    if (r0 < r1) {
+        int32_t j = r0 * kWave + lane;
+        // slice of wedge min(j, total-1): largest k with w_pre[k] <= it
+        const int32_t jq = min(j, total - 1);
+        int32_t k = 0, b = nkc - 1;
+        while (k < b) {
+            const int32_t mid = (k + b + 1) >> 1;
+            if (sh.w_pre[mid] <= jq) k = mid;
+            else b = mid - 1;
+        }
+        int32_t nb = sh.w_pre[k + 1];
+        uint32_t st = sh.w_start[k];
+        int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+        for (int32_t r = r0; r < r1; r += kUnroll) {
             uint32_t x[kUnroll], ng[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int32_t j = j0 + u * WG + tid;
+                const int32_t jj = j + u * kWave;
                 x[u] = 0xffffffffu;
                 ng[u] = 0;
-                if (j < total) {
-                    // slice holding flattened wedge j: largest k with c_pre[k] <= j
-                    int32_t a = 0, b = nk - 1;
-                    while (a < b) {
-                        int32_t mid = (a + b + 1) >> 1;
-                        if (sh.c_pre[mid] <= j) a = mid;
-                        else b = mid - 1;
+                if (r + u < r1 && jj < total) {
+                    while (jj >= nb) {  // stays below nkc: w_pre[nkc] = total > jj
+                        ++k;
+                        nb = sh.w_pre[k + 1];
+                        st = sh.w_start[k];
+                        base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
                     }
-                    const uint32_t st = sh.c_start[a];
-                    x[u] = packed[(st & 0x7fffffffu) + (uint32_t)(j - sh.c_pre[a])];
+                    x[u] = packed[base + jj];
                     ng[u] = st >> 31;
                 }
             }
+            j += kUnroll * kWave;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t slot = (x[u] >> 1) - (uint32_t)lo;
                 if (slot < band) {  // also rejects the padding lanes
                     uint32_t word, inc;
-                    slot_word<MODE>(slot, (x[u] ^ ng[u]) & 1u, word, inc);
+                    slot_word<MODE, BAND_WORDS>(slot, (x[u] ^ ng[u]) & 1u, word, inc);
                     const uint32_t old = atomicAdd(&sh.cnt[word], inc);
                     if (old == 0) atomicOr(&sh.bmp[word >> 5], 1u << (word & 31u));
                 }
             }
         }
-        __syncthreads();  // slice tables are rewritten by the next chunk
     }
+    __syncthreads();
+}
 
-    // reduce and clear the touched words of this band
+// Sum of the pair terms of every touched counter word, and clears them.
+// Slots are scattered over the whole band capacity, so the bitmap is
+// scanned in full (BAND_WORDS / 32 words).  Ends with a barrier.
+template <int MODE, int WG, int BAND_WORDS>
+__device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_WORDS>& sh) {
     unsigned long long acc = 0;
-    const uint32_t nwords = MODE == 3 ? 2u * band : (band * 2u + slots_per_word_x2<MODE>() - 1u) /
-                                                        (uint32_t)slots_per_word_x2<MODE>();
-    const uint32_t nbm = (nwords + 31u) >> 5;
-    for (uint32_t b = tid; b < nbm; b += WG) {
+    for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
         uint32_t bits = sh.bmp[b];
         if (bits) {
             sh.bmp[b] = 0;
@@ -180,12 +276,53 @@ __device__ unsigned long long count_band(WedgeShared<WG, BAND_WORDS>& sh, const 
                 const uint32_t i = __ffs(bits) - 1;
                 bits &= bits - 1u;
                 const uint32_t wd = (b << 5) + i;
-                acc += word_pairs<MODE>(sh.cnt[wd]);
+                const uint32_t v = sh.cnt[wd];
                 sh.cnt[wd] = 0;
+                if (has_pairs<MODE>(v)) acc += word_pairs<MODE>(v);
             }
         }
     }
     __syncthreads();
+    return acc;
+}
+
+// All bands of anchor r (rank), a0 = first entry of its list, deg entries.
+// Anchors with at most WG centres keep one slice cursor per centre across
+// bands (each band starts where the previous one ended); wider anchors
+// re-load their centres per chunk and seek the band start.
+template <int MODE, int WG, int BAND_WORDS>
+__device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS>& sh, const int32_t* __restrict__ acent,
+                                           const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
+                                           const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
+                                           int32_t a0, int32_t deg, int32_t r, int64_t n_s,
+                                           unsigned long long& bands) {
+    constexpr int64_t band_slots = band_capacity<MODE, BAND_WORDS>();
+    unsigned long long acc = 0;
+    if (deg <= WG) {
+        load_centres(sh, acent, aneg, back, coff, a0, 0, deg);
+        __syncthreads();
+        for (int64_t lo = (int64_t)r + 1; lo < n_s; lo += band_slots) {
+            const int64_t hi = min(n_s, lo + band_slots);
+            walk_band<MODE>(sh, packed, deg, lo, hi, false, hi == n_s);
+            if (threadIdx.x < deg)
+                sh.c_cur[threadIdx.x] = (uint32_t)sh.c_end[threadIdx.x] | (sh.c_cur[threadIdx.x] & 0x80000000u);
+            acc += reduce_band<MODE>(sh);
+            ++bands;
+        }
+    } else {
+        for (int64_t lo = (int64_t)r + 1; lo < n_s; lo += band_slots) {
+            const int64_t hi = min(n_s, lo + band_slots);
+            const bool first = lo == (int64_t)r + 1;
+            for (int32_t k0 = 0; k0 < deg; k0 += WG) {
+                const int32_t nk = min(WG, deg - k0);
+                load_centres(sh, acent, aneg, back, coff, a0, k0, nk);
+                __syncthreads();
+                walk_band<MODE>(sh, packed, nk, lo, hi, !first, hi == n_s);
+            }
+            acc += reduce_band<MODE>(sh);
+            ++bands;
+        }
+    }
     return acc;
 }
 
@@ -208,33 +345,14 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
         const int32_t r = (int32_t)order[task];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
         if (deg < 2 || r >= n_s - 1) continue;  // no endpoint pair can close a butterfly
-        int64_t band_slots;
-        int mode;
-        if (deg <= 15) {
-            mode = 0;
-            band_slots = (int64_t)BAND_WORDS * 4;
-        } else if (deg <= 255) {
-            mode = 1;
-            band_slots = (int64_t)BAND_WORDS * 2;
-        } else if (deg <= 65535) {
-            mode = 2;
-            band_slots = BAND_WORDS;
-        } else {
-            mode = 3;
-            band_slots = BAND_WORDS / 2;
-        }
-        for (int64_t lo = (int64_t)r + 1; lo < n_s; lo += band_slots) {
-            const int64_t hi = min((int64_t)n_s, lo + band_slots);
-            if (mode == 0)
-                acc += count_band<0, WG, BAND_WORDS>(sh, acent, aneg, back, coff, packed, a0, deg, r, lo, hi, n_s);
-            else if (mode == 1)
-                acc += count_band<1, WG, BAND_WORDS>(sh, acent, aneg, back, coff, packed, a0, deg, r, lo, hi, n_s);
-            else if (mode == 2)
-                acc += count_band<2, WG, BAND_WORDS>(sh, acent, aneg, back, coff, packed, a0, deg, r, lo, hi, n_s);
-            else
-                acc += count_band<3, WG, BAND_WORDS>(sh, acent, aneg, back, coff, packed, a0, deg, r, lo, hi, n_s);
-            ++bands;
-        }
+        if (deg <= 15)
+            acc += count_anchor<0>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+        else if (deg <= 255)
+            acc += count_anchor<1>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+        else if (deg <= 65535)
+            acc += count_anchor<2>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+        else
+            acc += count_anchor<3>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
     }
     acc = wave_sum(acc);
     if (lane_id() == 0 && acc) atomicAdd(&st->total, acc);

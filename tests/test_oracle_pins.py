@@ -278,6 +278,18 @@ def test_per_vertex_definition_and_sums():
         assert np.array_equal(oracle.per_vertex(g, oracle.SIDE_U), oracle.per_vertex(g, oracle.SIDE_V))
 
 
+def test_anchor_ranges_partition_the_count():
+    for g in _mid_graphs():
+        t = oracle.count(g)
+        n_s = g.n_u if g.n_u < g.n_v else g.n_v
+        cuts = [0, n_s // 3, n_s // 2, n_s]
+        parts = [oracle.count_anchors(g, a, b) for a, b in zip(cuts, cuts[1:])]
+        assert sum(p for p, _ in parts) == t
+        # wedges bucketed over all anchors = sum over centres of C(d, 2)
+        deg_c = np.diff(g.offsets) if n_s == g.n_v else np.bincount(g.adj, minlength=g.n_v)
+        assert sum(w for _, w in parts) == int((deg_c.astype(np.int64) * (deg_c - 1) // 2).sum())
+
+
 def test_malformed_input_rejected():
     g = synth.complete_graph(3, 3)
     bad = synth.Graph(3, 3, g.offsets, g.adj.copy(), g.signs, {})
@@ -298,7 +310,7 @@ MUTANTS = {
     "no pair filter": ("if (w <= u) continue; /* each endpoint pair once */", ""),
     "asymmetric term dropped": ("total += choose2(B1[w]) + choose2(B2[w]);", "total += choose2(B1[w]);"),
     "C(x,2) off by one": ("return x * (x - 1) / 2;", "return x * (x + 1) / 2;"),
-    "sign of centre edge ignored": ("if (g.c_sgn[j] == s1) B1[w]++;", "if (s1 > 0) B1[w]++;"),
+    "sign of centre edge ignored": ("if (g->c_sgn[j] == s1) B1[w]++;", "if (s1 > 0) B1[w]++;"),
 }
 
 
