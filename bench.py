@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps(dict(error="this benchmark runs on one GPU only; multi-GPU sharding is not built",
@@ -89,6 +92,14 @@ def main():
           f"(generated in {gen_s:.1f} s)", file=sys.stderr, flush=True)
     ctx = bbc.Context(0)
     off, adj, sg = bbc.graph_tensors(g, dev)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     opts_t = bbc.options(timing=True)
     opts = bbc.options()
 

@@ -73,7 +73,8 @@ typedef struct {
     uint32_t checks;      /* BBC_CHECK_* mask, default BBC_CHECK_ALL */
     int32_t timing;       /* nonzero: record per-phase HIP event times (bbc_last_stats) */
     int32_t band_words;   /* LDS counter band in 32-bit words per workgroup, 0 = default */
-    int32_t wg_per_cu;    /* persistent workgroups per compute unit, 0 = default */
+    int32_t wg_size;      /* threads per wedge-kernel workgroup, 0 = default */
+    int32_t wg_per_cu;    /* persistent workgroups per compute unit, 0 = as many as fit */
 } bbc_options;
 
 /* Fills *opts with the defaults: auto side, all checks, no timing. */
@@ -96,7 +97,10 @@ bbc_status bbc_destroy(bbc_ctx* ctx);
  *                        contain each vertex, U ids first, then V ids (the
  *                        paper counts totals only; this is the library's
  *                        per-vertex reading).  Overwritten, not accumulated.
- *   opts                 host or NULL (defaults).
+ *   opts                 host or NULL (defaults).  band_words / wg_size must
+ *                        name an instantiated kernel shape (BBC_EINVAL
+ *                        otherwise): 16384/512 (default), 16384/256,
+ *                        8192/256, 8192/512, 32768/1024, 16384/1024.
  * Synchronous with respect to *total: returns after the stream has
  * produced it.  Errors: BBC_EINVAL, BBC_EOFFSETS, BBC_ERANGE, BBC_ESIGN,
  * BBC_EDUP, BBC_ENOMEM, BBC_EDEVICE, BBC_ETOOBIG. */

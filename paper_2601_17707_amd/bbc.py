@@ -32,6 +32,7 @@ class Options(ctypes.Structure):
         ("checks", ctypes.c_uint32),
         ("timing", ctypes.c_int32),
         ("band_words", ctypes.c_int32),
+        ("wg_size", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
     ]
 
@@ -93,13 +94,14 @@ def status_string(status: int) -> str:
     return load_library().bbc_status_string(status).decode()
 
 
-def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_per_cu=0) -> Options:
+def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0) -> Options:
     o = Options()
     load_library().bbc_options_init(ctypes.byref(o))
     o.side = _SIDES[side]
     o.checks = checks
     o.timing = 1 if timing else 0
     o.band_words = band_words
+    o.wg_size = wg_size
     o.wg_per_cu = wg_per_cu
     return o
 

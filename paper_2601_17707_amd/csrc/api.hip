@@ -23,9 +23,10 @@ void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
                  uint32_t* key, DevStatus* st, hipStream_t s);
-int wedge_block();
-int wedge_blocks_per_cu();
-void launch_wedge(int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* back,
+bool wedge_shape_ok(int band_words, int wg);
+int wedge_block(int band_words, int wg);
+int wedge_blocks_per_cu(int band_words, int wg);
+void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* back,
                   const uint32_t* coff, const uint32_t* packed, const uint32_t* order, int32_t n_s, DevStatus* st,
                   hipStream_t s);
 
@@ -123,6 +124,7 @@ struct Plan {
         Carve c(base);
         int64_t ns1 = (int64_t)n_s + 1, nc1 = (int64_t)n_c + 1;
         int64_t nmax = m > ns1 ? m : ns1;
+        if (nc1 > nmax) nmax = nc1;
         deg_u = c.take<uint32_t>(n_u);
         deg_v = c.take<uint32_t>(n_v);
         rk_key = c.take<uint32_t>(n_s);
@@ -279,6 +281,9 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
         return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
     if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
     if (opts.side < BBC_SIDE_AUTO || opts.side > BBC_SIDE_V) return fail(ctx, BBC_EINVAL, "bad side option");
+    if (!wedge_shape_ok(opts.band_words, opts.wg_size))
+        return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
+    if (opts.wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
     if (per_vertex) return fail(ctx, BBC_EINVAL, "per-vertex output is not available in this build");
 
     hipStream_t s = (hipStream_t)stream;
@@ -351,10 +356,11 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     HIP_OR_FAIL(hipGetLastError());
     if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[2], s));
 
-    const int block = wedge_block();
-    const int grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu());
+    const int block = wedge_block(opts.band_words, opts.wg_size);
+    const int grid =
+        ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size));
     if (P.n_s >= 2 && m > 0)
-        launch_wedge(grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order, P.n_s, ctx->st_dev, s);
+        launch_wedge(opts.band_words, opts.wg_size, grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order, P.n_s, ctx->st_dev, s);
     HIP_OR_FAIL(hipGetLastError());
     if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[3], s));
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));

@@ -111,13 +111,14 @@ __host__ __device__ constexpr uint32_t band_capacity() {
 // endpoint slots and counter fields is valid (the reduction sums every
 // touched field), so slots are scattered by an odd multiplier modulo the
 // power-of-two capacity.
-constexpr uint32_t kSlotMul = 0x9E3779B1u;
+constexpr uint32_t kSlotMul = 0x9E3779u;  // < 2^24: a full-rate 24-bit multiply
 
 // LDS word and increment for endpoint slot `slot` (rank - band start) and
 // wedge type t (0 = signs agree, 1 = disagree).
 template <int MODE, int BAND_WORDS>
 __device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& word, uint32_t& inc) {
-    slot = (slot * kSlotMul) & (band_capacity<MODE, BAND_WORDS>() - 1u);
+    constexpr uint32_t mask = band_capacity<MODE, BAND_WORDS>() - 1u;  // slot <= mask already
+    slot = ((slot & mask) * kSlotMul) & mask;
     if constexpr (MODE == 0) {
         word = slot >> 2;
         inc = 1u << (((slot & 3u) << 3) + (t << 2));
@@ -137,7 +138,7 @@ constexpr int kUnroll = 8;
 
 template <int WG, int BAND_WORDS>
 struct WedgeShared {
-    uint32_t cnt[BAND_WORDS];
+    uint32_t cnt[BAND_WORDS + kWave];  // counters, then one spare word per lane for padding
     uint32_t bmp[BAND_WORDS / 32];
     uint32_t c_cur[WG];    // slice start of each centre | negative-edge bit << 31
     int32_t c_end[WG];     // slice end (exclusive) in the current band
@@ -229,34 +230,51 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS>& sh, const
         uint32_t st = sh.w_start[k];
         int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
         for (int32_t r = r0; r < r1; r += kUnroll) {
-            uint32_t x[kUnroll], ng[kUnroll];
+            uint32_t x[kUnroll];
+            uint32_t ngmask;  // bit u: the anchor edge of wedge u is negative
+            if (r + kUnroll <= r1 && __all(j + (kUnroll - 1) * kWave < nb)) {
+                // whole block inside each lane's current slice: one address,
+                // immediate offsets
+                const uint32_t* row = packed + (uint32_t)(base + j);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const int32_t jj = j + u * kWave;
-                x[u] = 0xffffffffu;
-                ng[u] = 0;
-                if (r + u < r1 && jj < total) {
-                    while (jj >= nb) {  // stays below nkc: w_pre[nkc] = total > jj
-                        ++k;
-                        nb = sh.w_pre[k + 1];
-                        st = sh.w_start[k];
-                        base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+                for (int u = 0; u < kUnroll; ++u) x[u] = row[u * kWave];
+                ngmask = (st >> 31) ? 0xffffffffu : 0u;
+            } else {
+                uint32_t ngm = 0;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int32_t jj = j + u * kWave;
+                    x[u] = 0xffffffffu;
+                    if (r + u < r1 && jj < total) {
+                        while (jj >= nb) {  // stays below nkc: w_pre[nkc] = total > jj
+                            ++k;
+                            nb = sh.w_pre[k + 1];
+                            st = sh.w_start[k];
+                            base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+                        }
+                        x[u] = packed[(uint32_t)(base + jj)];
+                        ngm |= (st >> 31) << u;
                     }
-                    x[u] = packed[base + jj];
-                    ng[u] = st >> 31;
                 }
+                ngmask = ngm;
             }
             j += kUnroll * kWave;
+            uint32_t word[kUnroll], inc[kUnroll], old[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t slot = (x[u] >> 1) - (uint32_t)lo;
-                if (slot < band) {  // also rejects the padding lanes
-                    uint32_t word, inc;
-                    slot_word<MODE, BAND_WORDS>(slot, (x[u] ^ ng[u]) & 1u, word, inc);
-                    const uint32_t old = atomicAdd(&sh.cnt[word], inc);
-                    if (old == 0) atomicOr(&sh.bmp[word >> 5], 1u << (word & 31u));
+                if (slot < band) {  // padding lanes fall through to a spare word
+                    slot_word<MODE, BAND_WORDS>(slot, (x[u] ^ (ngmask >> u)) & 1u, word[u], inc[u]);
+                } else {
+                    word[u] = BAND_WORDS + lane;
+                    inc[u] = 0;
                 }
             }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) old[u] = atomicAdd(&sh.cnt[word[u]], inc[u]);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[word[u] >> 5], 1u << (word[u] & 31u));
         }
     }
     __syncthreads();
@@ -361,23 +379,59 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
 
 // ------------------------------------------------------------------ launch
 
-constexpr int kWedgeWG = 512;
-constexpr int kBandWords = 16384;  // 64 KiB of counters per workgroup
+// Instantiated shapes: (threads per workgroup, counter words per band).
+// The first is the default.
+struct WedgeShape {
+    int wg, band_words;
+};
+static const WedgeShape kShapes[] = {{512, 16384}, {256, 16384}, {256, 8192}, {512, 8192}, {1024, 32768},
+                                     {1024, 16384}};
 
-int wedge_block() { return kWedgeWG; }
+static int shape_index(int band_words, int wg) {
+    int n = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
+    for (int i = 0; i < n; ++i)
+        if ((band_words == 0 || kShapes[i].band_words == band_words) && (wg == 0 || kShapes[i].wg == wg)) return i;
+    return -1;
+}
 
-int wedge_blocks_per_cu() {
+bool wedge_shape_ok(int band_words, int wg) { return shape_index(band_words, wg) >= 0; }
+
+int wedge_block(int band_words, int wg) { return kShapes[shape_index(band_words, wg)].wg; }
+
+template <int WG, int BW>
+static int occupancy() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<kWedgeWG, kBandWords>, kWedgeWG, 0) != hipSuccess)
-        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW>, WG, 0) != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 
-void launch_wedge(int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* back,
-                  const uint32_t* coff, const uint32_t* packed, const uint32_t* order, int32_t n_s, DevStatus* st,
-                  hipStream_t s) {
-    hipLaunchKernelGGL((k_wedge<kWedgeWG, kBandWords>), dim3(grid), dim3(kWedgeWG), 0, s, aoff, acent, aneg, back,
-                       coff, packed, order, n_s, st);
+int wedge_blocks_per_cu(int band_words, int wg) {
+    switch (shape_index(band_words, wg)) {
+        case 0: return occupancy<512, 16384>();
+        case 1: return occupancy<256, 16384>();
+        case 2: return occupancy<256, 8192>();
+        case 3: return occupancy<512, 8192>();
+        case 4: return occupancy<1024, 32768>();
+        case 5: return occupancy<1024, 16384>();
+    }
+    return 1;
+}
+
+void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
+                  const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
+                  int32_t n_s, DevStatus* st, hipStream_t s) {
+#define BBC_LAUNCH(W, B)                                                                                       \
+    hipLaunchKernelGGL((k_wedge<W, B>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, order, \
+                       n_s, st)
+    switch (shape_index(band_words, wg)) {
+        case 0: BBC_LAUNCH(512, 16384); break;
+        case 1: BBC_LAUNCH(256, 16384); break;
+        case 2: BBC_LAUNCH(256, 8192); break;
+        case 3: BBC_LAUNCH(512, 8192); break;
+        case 4: BBC_LAUNCH(1024, 32768); break;
+        case 5: BBC_LAUNCH(1024, 16384); break;
+    }
+#undef BBC_LAUNCH
 }
 
 }  // namespace bbc

@@ -128,6 +128,32 @@ def test_band_boundaries(ctx, n_s):
     assert gpu_count(ctx, g, "v") == want
 
 
+SHAPES = [(16384, 512), (16384, 256), (8192, 256), (8192, 512), (32768, 1024), (16384, 1024)]
+
+
+@pytest.mark.parametrize("bw,wg", SHAPES)
+def test_kernel_shapes(ctx, bw, wg):
+    """Every instantiated (band words, workgroup) shape on graphs that cross
+    band edges in all four counter widths."""
+    say("shape", bw, wg)
+    cases = [synth.chung_lu_graph(140_000, 70_000, 700_000, 2.1, 2.0, 3000, 600, seed=21),
+             _degree_graph([3, 15, 16, 200, 255, 256, 900], 40_000, seed=22)]
+    for g in cases:
+        want = oracle.count(g)
+        for side in ("auto", "u", "v"):
+            assert gpu_count(ctx, g, side, band_words=bw, wg_size=wg) == want, (bw, wg, side)
+    g = cases[0]
+    assert gpu_count(ctx, g, band_words=bw, wg_size=wg, wg_per_cu=1) == oracle.count(g)
+
+
+def test_unknown_shape_rejected(ctx):
+    g = synth.complete_graph(3, 3)
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    with pytest.raises(bbc.BbcError) as e:
+        ctx.count(off, adj, sg, g.n_v, opts=bbc.options(band_words=1000))
+    assert e.value.status == bbc.EINVAL
+
+
 def test_mid_degree_band_split(ctx):
     """Anchors of degree 16..300 over an anchor side wider than a band."""
     g = synth.chung_lu_graph(60000, 50000, 1_500_000, 2.3, 2.3, 2000, 2000, seed=9, p_neg=0.35)
