@@ -11,7 +11,7 @@ this package; it shares no code with the GPU library.
 * :func:`count_anchors` - the same over a range of anchors (timing samples);
 * :func:`brute` - Definitions 1 and 2 applied to every 2x2 vertex choice;
 * :func:`count_kinds` - balanced / unbalanced / all butterflies per pair;
-* :func:`per_vertex` and :func:`vertex` - balanced butterflies containing
+* :func:`per_vertex`, :func:`vertex` and :func:`vertices` - balanced butterflies containing
   each vertex (the paper reports totals only; see the C header).
 
 Graphs are passed as any object with ``n_u, n_v, offsets, adj, signs``
@@ -57,6 +57,8 @@ def _load():
         lib.oracle_vertex.argtypes = head + [i64, PU]
         lib.oracle_brute.argtypes = head + [PU, PU, PU]
         lib.oracle_count_anchors.argtypes = head + [ctypes.c_int, i32, i32, PU, PU]
+        lib.oracle_vertices.argtypes = head + [ctypes.POINTER(ctypes.c_int64), i64, PU]
+        lib.oracle_vertices.restype = ctypes.c_int
         for f in (lib.oracle_count_anchors, lib.oracle_count, lib.oracle_count_kinds, lib.oracle_per_vertex, lib.oracle_vertex,
                   lib.oracle_brute):
             f.restype = ctypes.c_int
@@ -127,6 +129,17 @@ def vertex(g, x: int) -> int:
     _check(_load().oracle_vertex(*a, int(x), ctypes.byref(out)))
     del keep
     return int(out.value)
+
+
+def vertices(g, xs) -> np.ndarray:
+    """uint64 counts of the vertices xs (global indices, U first)."""
+    keep, a = _args(g)
+    xs = np.ascontiguousarray(xs, np.int64)
+    out = np.zeros(xs.size, np.uint64)
+    _check(_load().oracle_vertices(*a, xs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), xs.size,
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    del keep
+    return out
 
 
 def brute(g, per_vertex: bool = False):

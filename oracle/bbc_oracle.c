@@ -312,41 +312,60 @@ int oracle_per_vertex(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, c
     return 0;
 }
 
-/* Count of one vertex x (global index: U first, then V), computed from x's
- * own 2-hop neighbourhood, for spot checks on graphs too large for a full
- * per-vertex pass.  For x on either side, its same-side 2-hop neighbours y
- * give a_xy / b_xy over the common neighbours and x lies in
- * sum_y C(a_xy,2) + C(b_xy,2) balanced butterflies. */
-int oracle_vertex(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
-                  const int8_t* sg, int64_t x, uint64_t* out) {
-    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
-    if (x < 0 || x >= (int64_t)n_u + n_v) return 1;
-    int on_u = x < n_u;
-    sides_t g; /* anchor side = x's side */
-    build_sides(n_u, n_v, m, off, adj, sg, on_u ? 1 : 2, &g);
-    int32_t u = (int32_t)(on_u ? x : x - n_u);
-    uint32_t* A = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
-    uint32_t* B = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
-    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+/* Balanced butterflies containing x, for x on the anchor side of g, from
+ * x's own 2-hop neighbourhood: every same-side vertex y sharing neighbours
+ * with x gives a_xy agreeing and b_xy disagreeing common neighbours, and x
+ * lies in sum_y C(a_xy,2) + C(b_xy,2) balanced butterflies. */
+static uint64_t vertex_count(const sides_t* g, int32_t u, uint32_t* A, uint32_t* B, int32_t* touched) {
     int32_t nt = 0;
-    for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
-        int32_t c = g.s_nbr[i];
-        for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
-            int32_t w = g.c_nbr[j];
+    for (int64_t i = g->s_off[u]; i < g->s_off[u + 1]; ++i) {
+        int32_t c = g->s_nbr[i];
+        for (int64_t j = g->c_off[c]; j < g->c_off[c + 1]; ++j) {
+            int32_t w = g->c_nbr[j];
             if (w == u) continue;
             if (A[w] == 0 && B[w] == 0) touched[nt++] = w;
-            if (g.c_sgn[j] == g.s_sgn[i]) A[w]++;
+            if (g->c_sgn[j] == g->s_sgn[i]) A[w]++;
             else B[w]++;
         }
     }
     uint64_t t = 0;
-    for (int32_t k = 0; k < nt; ++k) t += choose2(A[touched[k]]) + choose2(B[touched[k]]);
-    free(A);
-    free(B);
-    free(touched);
-    sides_free(&g);
-    *out = t;
+    for (int32_t k = 0; k < nt; ++k) {
+        t += choose2(A[touched[k]]) + choose2(B[touched[k]]);
+        A[touched[k]] = 0;
+        B[touched[k]] = 0;
+    }
+    return t;
+}
+
+/* Counts of the vertices xs[0..n) (global indices: U first, then V), for
+ * spot checks on graphs too large for a full per-vertex pass. */
+int oracle_vertices(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                    const int8_t* sg, const int64_t* xs, int64_t n, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    for (int64_t i = 0; i < n; ++i)
+        if (xs[i] < 0 || xs[i] >= (int64_t)n_u + n_v) return 1;
+    for (int side = 1; side <= 2; ++side) {
+        sides_t g;
+        build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+        uint32_t* A = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+        uint32_t* B = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+        int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+        for (int64_t i = 0; i < n; ++i) {
+            int on_u = xs[i] < n_u;
+            if (on_u != (side == 1)) continue;
+            out[i] = vertex_count(&g, (int32_t)(on_u ? xs[i] : xs[i] - n_u), A, B, touched);
+        }
+        free(A);
+        free(B);
+        free(touched);
+        sides_free(&g);
+    }
     return 0;
+}
+
+int oracle_vertex(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                  const int8_t* sg, int64_t x, uint64_t* out) {
+    return oracle_vertices(n_u, n_v, m, off, adj, sg, &x, 1, out);
 }
 
 /* Definitions 1 and 2 applied directly: every {u1,u2} x {v1,v2} with all

@@ -24,11 +24,12 @@ void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, D
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
                  uint32_t* key, DevStatus* st, hipStream_t s);
 bool wedge_shape_ok(int band_words, int wg);
-int wedge_block(int band_words, int wg);
-int wedge_blocks_per_cu(int band_words, int wg);
-void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* back,
-                  const uint32_t* coff, const uint32_t* packed, const uint32_t* order, int32_t n_s, DevStatus* st,
-                  hipStream_t s);
+int wedge_block(int band_words, int wg, bool full);
+int wedge_blocks_per_cu(int band_words, int wg, bool full);
+void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
+                  const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
+                  int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
+                  int64_t centre_base, int64_t n_centre, hipStream_t s);
 
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -284,7 +285,6 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     if (!wedge_shape_ok(opts.band_words, opts.wg_size))
         return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
     if (opts.wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
-    if (per_vertex) return fail(ctx, BBC_EINVAL, "per-vertex output is not available in this build");
 
     hipStream_t s = (hipStream_t)stream;
     DeviceGuard guard(ctx->device);
@@ -356,11 +356,15 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     HIP_OR_FAIL(hipGetLastError());
     if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[2], s));
 
-    const int block = wedge_block(opts.band_words, opts.wg_size);
+    const bool full = per_vertex != nullptr;
+    unsigned long long* pv = (unsigned long long*)per_vertex;
+    if (full) fill_bytes(pv, ((int64_t)n_u + n_v) * 8, s);
+    const int block = wedge_block(opts.band_words, opts.wg_size, full);
     const int grid =
-        ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size));
+        ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
     if (P.n_s >= 2 && m > 0)
-        launch_wedge(opts.band_words, opts.wg_size, grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order, P.n_s, ctx->st_dev, s);
+        launch_wedge(opts.band_words, opts.wg_size, grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order,
+                     P.n_s, ctx->st_dev, pv, inv, s_is_u ? 0 : n_u, s_is_u ? n_u : 0, P.n_c, s);
     HIP_OR_FAIL(hipGetLastError());
     if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[3], s));
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
@@ -371,7 +375,8 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
         snprintf(buf, sizeof buf, "repeated (u, v) pair at centre-list position %lld", (long long)h.bad_dup);
         return fail(ctx, BBC_EDUP, buf);
     }
-    *total = (uint64_t)h.total;
+    // per-vertex mode sums every anchor's pairs from both ends
+    *total = full ? (uint64_t)h.total / 2 : (uint64_t)h.total;
 
     bbc_stats& S = ctx->stats;
     memset(&S, 0, sizeof S);

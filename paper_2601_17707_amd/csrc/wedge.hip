@@ -28,6 +28,15 @@
 //     the reduction only visits touched words;
 //   - sums stay in registers across tasks and are reduced once per wave at
 //     exit (one 64-bit atomic per wave).
+//
+// Per-vertex mode (FULL): every anchor walks its whole 2-hop range (endpoints
+// ranked above and below it), so cnt[u] = sum over w != u of
+// C(a_uw,2) + C(b_uw,2) is summed locally and stored once, and the total is
+// half the sum over anchors.  A second walk of each band, with the counters
+// complete, adds n_t(u,w) - 1 for every wedge u - c - w of type t to the
+// centre c (the balanced butterflies pairing that wedge with another of its
+// type); every unordered pair is seen from both ends, so centre sums are
+// halved at the end.  No endpoint count is ever scattered.
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -136,47 +145,74 @@ __device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& w
 
 constexpr int kUnroll = 8;
 
-template <int WG, int BAND_WORDS>
+template <int WG, int BAND_WORDS, bool FULL>
 struct WedgeShared {
     uint32_t cnt[BAND_WORDS + kWave];  // counters, then one spare word per lane for padding
     uint32_t bmp[BAND_WORDS / 32];
-    uint32_t c_cur[WG];    // slice start of each centre | negative-edge bit << 31
-    int32_t c_end[WG];     // slice end (exclusive) in the current band
-    int32_t c_ce[WG];      // end of the centre's whole list
-    uint32_t w_start[WG];  // non-empty slices only: start | negative-edge bit << 31
-    int32_t w_pre[WG + 1]; // their exclusive prefix of lengths
+    uint32_t c_cur[WG];     // slice start of each centre | negative-edge bit << 31
+    int32_t c_end[WG];      // slice end (exclusive) in the current band
+    int32_t c_ce[WG];       // end of the centre's whole list
+    uint32_t w_start[WG];   // non-empty slices only: start | negative-edge bit << 31
+    int32_t w_pre[WG + 1];  // their exclusive prefix of lengths
     long long scan_tmp[WG / kWave + 1];
+    // per-vertex mode only
+    int32_t c_id[FULL ? WG : 1];                // centre id of each chunk entry
+    int32_t w_k[FULL ? WG : 1];                 // chunk entry of each compacted slice
+    unsigned long long c_sum[FULL ? WG : 1];    // centre contributions of this anchor
     int32_t task;
 };
 
-// Loads the centres k0 .. k0+nk-1 of anchor list entry a0: slice start just
-// past the anchor's own position in the centre list (the ranked-above
-// suffix), the list end, and the sign of the anchor edge.
-template <int WG, int BAND_WORDS>
-__device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS>& sh, const int32_t* __restrict__ acent,
-                                             const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
-                                             const uint32_t* __restrict__ coff, int32_t a0, int32_t k0,
-                                             int32_t nk) {
+// Loads the centres k0 .. k0+nk-1 of the anchor list starting at a0: the
+// slice start (just past the anchor's own entry in the centre list, the
+// ranked-above suffix; or the list start in per-vertex mode), the list end,
+// and the sign of the anchor edge.
+template <bool FULL, int WG, int BAND_WORDS>
+__device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS, FULL>& sh,
+                                             const int32_t* __restrict__ acent, const uint8_t* __restrict__ aneg,
+                                             const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
+                                             int32_t a0, int32_t k0, int32_t nk) {
     const int tid = threadIdx.x;
     if (tid < nk) {
         const int32_t p = a0 + k0 + tid;
-        sh.c_cur[tid] = (uint32_t)(back[p] + 1) | ((uint32_t)aneg[p] << 31);
-        sh.c_ce[tid] = (int32_t)coff[acent[p] + 1];
+        const int32_t c = acent[p];
+        const uint32_t start = FULL ? coff[c] : (uint32_t)(back[p] + 1);
+        sh.c_cur[tid] = start | ((uint32_t)aneg[p] << 31);
+        sh.c_ce[tid] = (int32_t)coff[c + 1];
+        if constexpr (FULL) {
+            sh.c_id[tid] = c;
+            sh.c_sum[tid] = 0;
+        }
     }
 }
 
-// Counts the wedges of the centres currently in the slice tables whose
-// endpoint rank lies in [lo, hi).  Slice starts are in c_cur; when
-// `seek_start` they are first advanced to the first rank >= lo.
+// Position of the first compacted slice holding flattened wedge jq.
+template <int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FULL>& sh, int32_t nkc, int32_t jq) {
+    int32_t k = 0, b = nkc - 1;
+    while (k < b) {
+        const int32_t mid = (k + b + 1) >> 1;
+        if (sh.w_pre[mid] <= jq) k = mid;
+        else b = mid - 1;
+    }
+    return k;
+}
+
+// Counts the wedges of the centres in the slice tables whose endpoint rank
+// lies in [lo, hi).  Slice starts are in c_cur; when `seek_start` they are
+// first advanced to the first rank >= lo.  `self` is the anchor's own rank
+// (its entries are skipped in the per-vertex centre walk).  `phases`: bit 0
+// counts the wedges, bit 1 runs the per-vertex centre walk, which needs the
+// band's counters complete over every centre of the anchor.
 //
 // The non-empty slices are compacted and flattened into rows of 64 wedges;
 // each wave owns a contiguous run of rows and each lane keeps a cursor on
 // the slice holding its wedge, so moving to the next row costs a compare
 // (and a short advance when the lane crosses into the next slice).  Lanes
 // of a wave read consecutive entries of a list: coalesced 4-byte loads.
-template <int MODE, int WG, int BAND_WORDS>
-__device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS>& sh, const uint32_t* __restrict__ packed,
-                                          int32_t nk, int64_t lo, int64_t hi, bool seek_start, bool last) {
+template <int MODE, bool FULL, int WG, int BAND_WORDS>
+__device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
+                                          int32_t nk, int64_t lo, int64_t hi, bool seek_start, bool last,
+                                          int32_t self, int phases) {
     constexpr int NW = WG / kWave;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const uint32_t band = (uint32_t)(hi - lo);
@@ -209,6 +245,7 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS>& sh, const
         const int32_t idx = (int32_t)(ex >> 40);
         sh.w_start[idx] = cur;
         sh.w_pre[idx] = (int32_t)(ex & ((1ll << 40) - 1));
+        if constexpr (FULL) sh.w_k[idx] = tid;
     }
     if (tid == 0) sh.w_pre[nkc] = total;
     __syncthreads();
@@ -216,16 +253,9 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS>& sh, const
     const int32_t rows = (total + kWave - 1) / kWave;
     const int32_t rpw = (rows + NW - 1) / NW;
     const int32_t r0 = wave * rpw, r1 = min(rows, r0 + rpw);
-    if (r0 < r1) {
+    if ((phases & 1) && r0 < r1) {
         int32_t j = r0 * kWave + lane;
-        // slice of wedge min(j, total-1): largest k with w_pre[k] <= it
-        const int32_t jq = min(j, total - 1);
-        int32_t k = 0, b = nkc - 1;
-        while (k < b) {
-            const int32_t mid = (k + b + 1) >> 1;
-            if (sh.w_pre[mid] <= jq) k = mid;
-            else b = mid - 1;
-        }
+        int32_t k = slice_of(sh, nkc, min(j, total - 1));
         int32_t nb = sh.w_pre[k + 1];
         uint32_t st = sh.w_start[k];
         int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
@@ -278,13 +308,58 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS>& sh, const
         }
     }
     __syncthreads();
+
+    if constexpr (FULL) {
+        // centre walk over the same rows with the band's counters complete
+        if ((phases & 2) && r0 < r1) {
+            constexpr uint32_t fmask = MODE == 0 ? 15u : MODE == 1 ? 255u : MODE == 2 ? 0xffffu : 0xffffffffu;
+            int32_t j = r0 * kWave + lane;
+            int32_t k = slice_of(sh, nkc, min(j, total - 1));
+            int32_t nb = sh.w_pre[k + 1];
+            uint32_t st = sh.w_start[k];
+            int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+            unsigned long long run = 0;
+            for (int32_t r = r0; r < r1; ++r, j += kWave) {
+                if (j >= total) continue;
+                while (j >= nb) {
+                    if (run) atomicAdd(&sh.c_sum[sh.w_k[k]], run);
+                    run = 0;
+                    ++k;
+                    nb = sh.w_pre[k + 1];
+                    st = sh.w_start[k];
+                    base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+                }
+                const uint32_t x = packed[(uint32_t)(base + j)];
+                if ((int32_t)(x >> 1) != self) {
+                    uint32_t word, inc;
+                    slot_word<MODE, BAND_WORDS>((x >> 1) - (uint32_t)lo, (x ^ (st >> 31)) & 1u, word, inc);
+                    run += ((sh.cnt[word] >> (31 - __clz(inc))) & fmask) - 1u;
+                }
+            }
+            if (run) atomicAdd(&sh.c_sum[sh.w_k[k]], run);
+        }
+        __syncthreads();
+    }
 }
 
 // Sum of the pair terms of every touched counter word, and clears them.
 // Slots are scattered over the whole band capacity, so the bitmap is
-// scanned in full (BAND_WORDS / 32 words).  Ends with a barrier.
-template <int MODE, int WG, int BAND_WORDS>
-__device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_WORDS>& sh) {
+// scanned in full (BAND_WORDS / 32 words).  In per-vertex mode the anchor's
+// own slot (w = u), if in [lo, hi), is left out.  Ends with a barrier.
+template <int MODE, bool FULL, int WG, int BAND_WORDS>
+__device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, int64_t lo,
+                                                          int64_t hi, int32_t self) {
+    uint32_t sw0 = 0xffffffffu, sm0 = 0, sw1 = 0xffffffffu, sm1 = 0;
+    if constexpr (FULL) {
+        if ((int64_t)self >= lo && (int64_t)self < hi) {
+            constexpr uint32_t fmask = MODE == 0 ? 15u : MODE == 1 ? 255u : MODE == 2 ? 0xffffu : 0xffffffffu;
+            uint32_t inc0, inc1;
+            slot_word<MODE, BAND_WORDS>((uint32_t)(self - lo), 0u, sw0, inc0);
+            slot_word<MODE, BAND_WORDS>((uint32_t)(self - lo), 1u, sw1, inc1);
+            sm0 = fmask << (31 - __clz(inc0));
+            sm1 = fmask << (31 - __clz(inc1));
+        }
+    }
     unsigned long long acc = 0;
     for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
         uint32_t bits = sh.bmp[b];
@@ -294,8 +369,12 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
                 const uint32_t i = __ffs(bits) - 1;
                 bits &= bits - 1u;
                 const uint32_t wd = (b << 5) + i;
-                const uint32_t v = sh.cnt[wd];
+                uint32_t v = sh.cnt[wd];
                 sh.cnt[wd] = 0;
+                if constexpr (FULL) {
+                    if (wd == sw0) v &= ~sm0;
+                    if (wd == sw1) v &= ~sm1;
+                }
                 if (has_pairs<MODE>(v)) acc += word_pairs<MODE>(v);
             }
         }
@@ -304,54 +383,74 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
     return acc;
 }
 
-// All bands of anchor r (rank), a0 = first entry of its list, deg entries.
-// Anchors with at most WG centres keep one slice cursor per centre across
-// bands (each band starts where the previous one ended); wider anchors
-// re-load their centres per chunk and seek the band start.
-template <int MODE, int WG, int BAND_WORDS>
-__device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS>& sh, const int32_t* __restrict__ acent,
+// All bands of anchor r (rank), list start a0, deg entries.  Anchors with
+// at most WG centres keep one slice cursor per centre across bands (each
+// band starts where the previous one ended); wider anchors re-load their
+// centres per chunk and seek the band start.  Returns this thread's share
+// of the anchor's pair terms.
+template <int MODE, bool FULL, int WG, int BAND_WORDS>
+__device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh, const int32_t* __restrict__ acent,
                                            const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
                                            int32_t a0, int32_t deg, int32_t r, int64_t n_s,
+                                           unsigned long long* __restrict__ pv, int64_t centre_base,
                                            unsigned long long& bands) {
     constexpr int64_t band_slots = band_capacity<MODE, BAND_WORDS>();
+    const int64_t lo0 = FULL ? 0 : (int64_t)r + 1;
     unsigned long long acc = 0;
     if (deg <= WG) {
-        load_centres(sh, acent, aneg, back, coff, a0, 0, deg);
+        load_centres<FULL>(sh, acent, aneg, back, coff, a0, 0, deg);
         __syncthreads();
-        for (int64_t lo = (int64_t)r + 1; lo < n_s; lo += band_slots) {
+        for (int64_t lo = lo0; lo < n_s; lo += band_slots) {
             const int64_t hi = min(n_s, lo + band_slots);
-            walk_band<MODE>(sh, packed, deg, lo, hi, false, hi == n_s);
+            walk_band<MODE, FULL>(sh, packed, deg, lo, hi, false, hi == n_s, r, FULL ? 3 : 1);
             if (threadIdx.x < deg)
                 sh.c_cur[threadIdx.x] = (uint32_t)sh.c_end[threadIdx.x] | (sh.c_cur[threadIdx.x] & 0x80000000u);
-            acc += reduce_band<MODE>(sh);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r);
             ++bands;
         }
+        if constexpr (FULL) {
+            if (threadIdx.x < deg && sh.c_sum[threadIdx.x])
+                atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
+        }
     } else {
-        for (int64_t lo = (int64_t)r + 1; lo < n_s; lo += band_slots) {
+        for (int64_t lo = lo0; lo < n_s; lo += band_slots) {
             const int64_t hi = min(n_s, lo + band_slots);
-            const bool first = lo == (int64_t)r + 1;
+            const bool first = lo == lo0;
             for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                 const int32_t nk = min(WG, deg - k0);
-                load_centres(sh, acent, aneg, back, coff, a0, k0, nk);
+                load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk);
                 __syncthreads();
-                walk_band<MODE>(sh, packed, nk, lo, hi, !first, hi == n_s);
+                walk_band<MODE, FULL>(sh, packed, nk, lo, hi, !first, hi == n_s, r, 1);
             }
-            acc += reduce_band<MODE>(sh);
+            if constexpr (FULL) {
+                // second pass over the chunks once every wedge of the band is counted
+                for (int32_t k0 = 0; k0 < deg; k0 += WG) {
+                    const int32_t nk = min(WG, deg - k0);
+                    load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk);
+                    __syncthreads();
+                    walk_band<MODE, FULL>(sh, packed, nk, lo, hi, !first, hi == n_s, r, 2);
+                    if (threadIdx.x < nk && sh.c_sum[threadIdx.x])
+                        atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
+                }
+            }
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r);
             ++bands;
         }
     }
     return acc;
 }
 
-template <int WG, int BAND_WORDS>
+template <int WG, int BAND_WORDS, bool FULL>
 __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
-                                              const uint32_t* __restrict__ order, int32_t n_s, DevStatus* st) {
-    __shared__ WedgeShared<WG, BAND_WORDS> sh;
+                                              const uint32_t* __restrict__ order, int32_t n_s, DevStatus* st,
+                                              unsigned long long* __restrict__ pv, const uint32_t* __restrict__ inv,
+                                              int64_t anchor_base, int64_t centre_base) {
+    __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
-    for (int i = tid; i < BAND_WORDS; i += WG) sh.cnt[i] = 0;
+    for (int i = tid; i < BAND_WORDS + kWave; i += WG) sh.cnt[i] = 0;
     for (int i = tid; i < BAND_WORDS / 32; i += WG) sh.bmp[i] = 0;
     unsigned long long acc = 0, bands = 0;
     for (;;) {
@@ -362,30 +461,46 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
         if (task >= n_s) break;
         const int32_t r = (int32_t)order[task];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
-        if (deg < 2 || r >= n_s - 1) continue;  // no endpoint pair can close a butterfly
+        // fewer than two centres: no endpoint pair shares two wedges
+        if (deg < 2 || (!FULL && r >= n_s - 1)) continue;
+        unsigned long long a;
         if (deg <= 15)
-            acc += count_anchor<0>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
         else if (deg <= 255)
-            acc += count_anchor<1>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
         else if (deg <= 65535)
-            acc += count_anchor<2>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
         else
-            acc += count_anchor<3>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, bands);
+            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
+        if constexpr (FULL) {
+            const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
+            if (tid == 0) pv[anchor_base + inv[r]] = s;
+        }
+        acc += a;
     }
     acc = wave_sum(acc);
     if (lane_id() == 0 && acc) atomicAdd(&st->total, acc);
     if (tid == 0 && bands) atomicAdd(&st->bands, bands);
 }
 
+// In per-vertex mode every unordered endpoint pair is seen from both ends:
+// halve the centre sums.
+__global__ void k_halve(unsigned long long* pv, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) pv[i] >>= 1;
+}
+
 // ------------------------------------------------------------------ launch
 
 // Instantiated shapes: (threads per workgroup, counter words per band).
-// The first is the default.
+// The first is the default.  Per-vertex mode uses one shape of its own.
 struct WedgeShape {
     int wg, band_words;
 };
 static const WedgeShape kShapes[] = {{512, 16384}, {256, 16384}, {256, 8192}, {512, 8192}, {1024, 32768},
                                      {1024, 16384}};
+constexpr int kFullWG = 256, kFullBW = 16384;
 
 static int shape_index(int band_words, int wg) {
     int n = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
@@ -396,40 +511,51 @@ static int shape_index(int band_words, int wg) {
 
 bool wedge_shape_ok(int band_words, int wg) { return shape_index(band_words, wg) >= 0; }
 
-int wedge_block(int band_words, int wg) { return kShapes[shape_index(band_words, wg)].wg; }
+int wedge_block(int band_words, int wg, bool full) { return full ? kFullWG : kShapes[shape_index(band_words, wg)].wg; }
 
-template <int WG, int BW>
+template <int WG, int BW, bool FULL>
 static int occupancy() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW>, WG, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL>, WG, 0) != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 
-int wedge_blocks_per_cu(int band_words, int wg) {
+int wedge_blocks_per_cu(int band_words, int wg, bool full) {
+    if (full) return occupancy<kFullWG, kFullBW, true>();
     switch (shape_index(band_words, wg)) {
-        case 0: return occupancy<512, 16384>();
-        case 1: return occupancy<256, 16384>();
-        case 2: return occupancy<256, 8192>();
-        case 3: return occupancy<512, 8192>();
-        case 4: return occupancy<1024, 32768>();
-        case 5: return occupancy<1024, 16384>();
+        case 0: return occupancy<512, 16384, false>();
+        case 1: return occupancy<256, 16384, false>();
+        case 2: return occupancy<256, 8192, false>();
+        case 3: return occupancy<512, 8192, false>();
+        case 4: return occupancy<1024, 32768, false>();
+        case 5: return occupancy<1024, 16384, false>();
     }
     return 1;
 }
 
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
-                  int32_t n_s, DevStatus* st, hipStream_t s) {
-#define BBC_LAUNCH(W, B)                                                                                       \
-    hipLaunchKernelGGL((k_wedge<W, B>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, order, \
-                       n_s, st)
+                  int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
+                  int64_t centre_base, int64_t n_centre, hipStream_t s) {
+#define BBC_LAUNCH(W, B, F)                                                                                      \
+    hipLaunchKernelGGL((k_wedge<W, B, F>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, order, \
+                       n_s, st, pv, inv, anchor_base, centre_base)
+    if (pv) {
+        BBC_LAUNCH(kFullWG, kFullBW, true);
+        if (n_centre > 0) {
+            int64_t g = (n_centre + 255) / 256;
+            hipLaunchKernelGGL(k_halve, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, s, pv + centre_base,
+                               n_centre);
+        }
+        return;
+    }
     switch (shape_index(band_words, wg)) {
-        case 0: BBC_LAUNCH(512, 16384); break;
-        case 1: BBC_LAUNCH(256, 16384); break;
-        case 2: BBC_LAUNCH(256, 8192); break;
-        case 3: BBC_LAUNCH(512, 8192); break;
-        case 4: BBC_LAUNCH(1024, 32768); break;
-        case 5: BBC_LAUNCH(1024, 16384); break;
+        case 0: BBC_LAUNCH(512, 16384, false); break;
+        case 1: BBC_LAUNCH(256, 16384, false); break;
+        case 2: BBC_LAUNCH(256, 8192, false); break;
+        case 3: BBC_LAUNCH(512, 8192, false); break;
+        case 4: BBC_LAUNCH(1024, 32768, false); break;
+        case 5: BBC_LAUNCH(1024, 16384, false); break;
     }
 #undef BBC_LAUNCH
 }

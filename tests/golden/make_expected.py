@@ -1,0 +1,68 @@
+"""Writes tests/golden/expected_counts.json: oracle results on the full-size
+synthetic workloads, for the GPU parity tests at those sizes.
+
+Calls only the CPU oracle (oracle/) and the seeded generator; no value here
+comes from the GPU library.  Each entry records the generator's SHA-256 of
+the graph so a test can tell that it regenerated the same input.
+
+    python tests/golden/make_expected.py [workload:seed ...]
+
+The full-size oracle runs take minutes (the 20M-edge graph) to tens of
+minutes (the 200M-edge graph) on one core.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2601_17707_amd import synth  # noqa: E402
+
+OUT = os.path.join(HERE, "expected_counts.json")
+DEFAULT = ["uniform-2k-1k-20k:1", "uniform-2k-1k-20k:2", "uniform-2k-1k-20k:3", "powerlaw-1m-500k-20m:1",
+           "skewed-5m-200k-200m:1"]
+N_VERTEX_SAMPLES = 48
+
+
+def vertex_sample(g, seed):
+    """Seeded vertex ids: the largest-degree vertex of each side plus uniform picks."""
+    rng = np.random.default_rng(seed + 7919)
+    deg_u = np.diff(g.offsets.astype(np.int64))
+    deg_v = np.bincount(g.adj, minlength=g.n_v)
+    picks = {int(np.argmax(deg_u)), g.n_u + int(np.argmax(deg_v))}
+    picks.update(int(x) for x in rng.choice(g.n_u + g.n_v, N_VERTEX_SAMPLES, replace=False))
+    return sorted(picks)
+
+
+def main(keys):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for key in keys:
+        name, seed = key.split(":")
+        seed = int(seed)
+        t0 = time.time()
+        g = synth.workload(name, seed)
+        sha = g.sha256()
+        t1 = time.time()
+        total = oracle.count(g)
+        t2 = time.time()
+        xs = vertex_sample(g, seed)
+        vc = oracle.vertices(g, xs)
+        t3 = time.time()
+        data[key] = dict(workload=name, seed=seed, sha256=sha, n_u=g.n_u, n_v=g.n_v, m=g.m, total=str(total),
+                         vertex_ids=xs, vertex_counts=[str(int(v)) for v in vc],
+                         oracle_seconds=round(t2 - t1, 1))
+        print(f"{key}: total {total} (gen {t1 - t0:.1f}s, count {t2 - t1:.1f}s, vertices {t3 - t2:.1f}s)",
+              flush=True)
+        with open(OUT + ".tmp", "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(OUT + ".tmp", OUT)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or DEFAULT)

@@ -282,3 +282,62 @@ def test_stream_ordering(ctx):
         off, adj, sg = bbc.graph_tensors(g, "cuda:0")
         got = ctx.count(off, adj, sg, g.n_v, stream=s)
     assert got == want
+
+
+# --------------------------------------------------------------- per vertex
+
+
+def gpu_per_vertex(ctx, g, side="auto"):
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    pv = torch.full((g.n_u + g.n_v,), 7, dtype=torch.int64, device="cuda:0")  # overwritten, not accumulated
+    t = ctx.count(off, adj, sg, g.n_v, per_vertex=pv, opts=bbc.options(side=side))
+    return t, pv.cpu().numpy().astype(np.uint64)
+
+
+@pytest.mark.parametrize("name", sorted(FIXTURES))
+def test_per_vertex_paper_examples(ctx, name):
+    g, exp = FIXTURES[name]
+    _, _, want = oracle.brute(g, per_vertex=True)
+    for side in ("auto", "u", "v"):
+        t, pv = gpu_per_vertex(ctx, g, side)
+        assert t == exp["balanced"]
+        assert np.array_equal(pv, want)
+
+
+def test_per_vertex_tiny_random(ctx):
+    rng = np.random.default_rng(202)
+    for i in range(150):
+        g = synth.small_random_graph(rng, max_n=10)
+        want = oracle.per_vertex(g)
+        side = ("auto", "u", "v")[i % 3]
+        t, pv = gpu_per_vertex(ctx, g, side)
+        assert t == oracle.count(g), i
+        assert np.array_equal(pv, want), i
+
+
+@pytest.mark.parametrize("case", ["bands", "widths", "wide", "skewed"])
+def test_per_vertex_structured(ctx, case):
+    """Band crossings (above and below the anchor), every counter width, and
+    anchors wider than one workgroup (chunked centre lists)."""
+    if case == "bands":
+        g = synth.chung_lu_graph(200_000, 70_000, 600_000, 2.1, 2.0, 3000, 600, seed=31)
+    elif case == "widths":
+        g = _degree_graph([2, 3, 15, 16, 200, 255, 256, 257, 900, 2000], 30_000, seed=32)
+    elif case == "wide":
+        rng = np.random.default_rng(33)
+        us, vs = [], []
+        for a, d in enumerate([65535, 65536, 66000]):
+            us.append(np.full(d, a))
+            vs.append(rng.choice(70_000, size=d, replace=False))
+        u, v = np.concatenate(us), np.concatenate(vs)
+        g = synth.from_edges(3, 70_000, u, v, np.where(rng.random(u.size) < 0.4, -1, 1))
+    else:
+        g = synth.chung_lu_graph(120_000, 6_000, 800_000, 2.5, 1.8, 900, 12_000, seed=34, beta_bias=(2, 5, 0.7))
+    want = oracle.per_vertex(g)
+    t_want = oracle.count(g)
+    say("per-vertex", case, "m", g.m, "total", t_want)
+    for side in ("auto", "u", "v"):
+        t, pv = gpu_per_vertex(ctx, g, side)
+        assert t == t_want, side
+        assert np.array_equal(pv, want), side
+        assert int(pv[: g.n_u].sum()) == 2 * t == int(pv[g.n_u:].sum())

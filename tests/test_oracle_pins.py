@@ -273,8 +273,10 @@ def test_per_vertex_definition_and_sums():
         t = oracle.count(g)
         pv = oracle.per_vertex(g)
         assert int(pv[: g.n_u].sum()) == 2 * t == int(pv[g.n_u:].sum())
-        for x in rng.choice(g.n_u + g.n_v, 12, replace=False):
+        xs = rng.choice(g.n_u + g.n_v, 12, replace=False)
+        for x in xs:
             assert oracle.vertex(g, int(x)) == int(pv[x])
+        assert np.array_equal(oracle.vertices(g, xs), pv[xs])
         assert np.array_equal(oracle.per_vertex(g, oracle.SIDE_U), oracle.per_vertex(g, oracle.SIDE_V))
 
 
