@@ -108,6 +108,53 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
                      const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
                      const bbc_options* opts, void* stream);
 
+/* One graph of a batch.  Its offsets are local (offsets[0] = 0, n_u + 1
+ * entries starting at offsets_cat[off_base]); its edges are adj_cat /
+ * signs_cat[edge_base .. edge_base + n_edges).  Graphs may sit anywhere in
+ * the concatenated arrays. */
+typedef struct {
+    int32_t n_u, n_v;
+    int64_t n_edges;
+    int64_t off_base;
+    int64_t edge_base;
+} bbc_graph_desc;
+
+/* Balanced butterfly counts of n_graphs independent graphs in one pass of
+ * the pipeline (the batch is counted as one disjoint union in which every
+ * graph keeps its own anchor side and a contiguous range of ranks, so the
+ * heavy anchors of every graph share one persistent launch).
+ *   descs                host, n_graphs entries.
+ *   offsets_cat, adj_cat, signs_cat  device, as described by descs.
+ *   totals               device, n_graphs uint64, overwritten on BBC_OK (on
+ *                        error their content is unspecified).
+ * Sums over all graphs must satisfy the bbc_count size limits.  Returns
+ * after the stream has produced the totals (input errors are reported). */
+bbc_status bbc_count_batched(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* descs,
+                             const int32_t* offsets_cat, const int32_t* adj_cat, const int8_t* signs_cat,
+                             uint64_t* totals, const bbc_options* opts, void* stream);
+
+/* A batch plan: the whole batched pipeline for a fixed batch layout,
+ * captured once into a HIP graph with its own scratch memory, then replayed.
+ * The buffers named at creation must stay allocated while the plan lives;
+ * their contents may change between launches (same sizes). */
+typedef struct bbc_batch_plan bbc_batch_plan;
+
+/* Arguments as bbc_count_batched; *out (host) receives the plan.  Allocates
+ * all scratch and captures the graph; nothing is computed yet. */
+bbc_status bbc_batch_plan_create(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* descs,
+                                 const int32_t* offsets_cat, const int32_t* adj_cat, const int8_t* signs_cat,
+                                 uint64_t* totals, const bbc_options* opts, bbc_batch_plan** out);
+
+/* Replays the captured graph on `stream` (asynchronous). */
+bbc_status bbc_batch_launch(bbc_batch_plan* plan, void* stream);
+
+/* Waits for `stream` and reports the input checks of the last launch
+ * (BBC_OK, or the error bbc_count_batched would have returned). */
+bbc_status bbc_batch_wait(bbc_batch_plan* plan, void* stream);
+
+/* Releases the plan (NULL is accepted). */
+bbc_status bbc_batch_plan_destroy(bbc_batch_plan* plan);
+
 /* Facts about the last successful bbc_count on this context. */
 typedef struct {
     uint32_t struct_size; /* sizeof(bbc_stats) */

@@ -37,6 +37,16 @@ class Options(ctypes.Structure):
     ]
 
 
+class GraphDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_u", ctypes.c_int32),
+        ("n_v", ctypes.c_int32),
+        ("n_edges", ctypes.c_int64),
+        ("off_base", ctypes.c_int64),
+        ("edge_base", ctypes.c_int64),
+    ]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32),
@@ -80,6 +90,17 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_count.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), vp,
                               ctypes.POINTER(Options), vp]
     lib.bbc_count.restype = ctypes.c_int
+    PD = ctypes.POINTER(GraphDesc)
+    lib.bbc_count_batched.argtypes = [vp, i32, PD, vp, vp, vp, vp, ctypes.POINTER(Options), vp]
+    lib.bbc_count_batched.restype = ctypes.c_int
+    lib.bbc_batch_plan_create.argtypes = [vp, i32, PD, vp, vp, vp, vp, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.bbc_batch_plan_create.restype = ctypes.c_int
+    lib.bbc_batch_launch.argtypes = [vp, vp]
+    lib.bbc_batch_launch.restype = ctypes.c_int
+    lib.bbc_batch_wait.argtypes = [vp, vp]
+    lib.bbc_batch_wait.restype = ctypes.c_int
+    lib.bbc_batch_plan_destroy.argtypes = [vp]
+    lib.bbc_batch_plan_destroy.restype = ctypes.c_int
     lib.bbc_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.bbc_last_stats.restype = ctypes.c_int
     lib.bbc_status_string.argtypes = [ctypes.c_int]
@@ -108,6 +129,14 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def _stream_ptr(stream, like):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(like.device)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0))
 
 
 def _check_tensor(name, t, dtype, torch):
@@ -172,9 +201,7 @@ class Context:
             _check_tensor("per_vertex", per_vertex, torch.int64, torch)
             if per_vertex.numel() != n_u + n_v:
                 raise ValueError("per_vertex must hold n_u + n_v entries")
-        if stream is None:
-            stream = torch.cuda.current_stream(offsets.device)
-        sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0))
+        sp = _stream_ptr(stream, offsets)
         out = ctypes.c_uint64(0)
         o = opts if opts is not None else options()
         st = self._lib.bbc_count(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj), _ptr(signs),
@@ -183,6 +210,19 @@ class Context:
         if st != OK:
             raise BbcError(st, self.last_error())
         return int(out.value)
+
+    def count_batched(self, batch: "Batch", opts: Options | None = None, stream=None):
+        """Per-graph counts of a Batch; returns its totals tensor (int64, on device)."""
+        o = opts if opts is not None else options()
+        st = self._lib.bbc_count_batched(self._h, batch.n_graphs, batch.descs, _ptr(batch.offsets),
+                                         _ptr(batch.adj), _ptr(batch.signs), _ptr(batch.totals),
+                                         ctypes.byref(o), _stream_ptr(stream, batch.offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return batch.totals
+
+    def plan(self, batch: "Batch", opts: Options | None = None) -> "BatchPlan":
+        return BatchPlan(self, batch, opts)
 
     def stats(self) -> dict:
         s = Stats()
@@ -226,3 +266,81 @@ def count(g, per_vertex: bool = False, side="auto", checks=CHECK_ALL, ctx: Conte
     pv = torch.empty(int(g.n_u) + int(g.n_v), dtype=torch.int64, device=off.device) if per_vertex else None
     t = ctx.count(off, adj, sg, int(g.n_v), per_vertex=pv, opts=options(side=side, checks=checks))
     return (t, pv) if per_vertex else t
+
+
+class Batch:
+    """Device-resident batch of graphs: concatenated CSR arrays, descriptors
+    and a totals tensor (int64, one per graph)."""
+
+    def __init__(self, graphs, device="cuda", layout=None):
+        """``layout`` (optional) lists, per graph, (off_base, edge_base) to
+        place graphs anywhere in larger arrays; by default graphs are packed
+        end to end."""
+        import numpy as np
+        import torch
+
+        n = len(graphs)
+        self.n_graphs = n
+        descs = (GraphDesc * max(n, 1))()
+        if layout is None:
+            ob, eb = 0, 0
+            layout = []
+            for g in graphs:
+                layout.append((ob, eb))
+                ob += int(g.n_u) + 1
+                eb += int(g.m)
+        n_off = max([ob + int(g.n_u) + 1 for (ob, _), g in zip(layout, graphs)] + [1])
+        n_edge = max([eb + int(g.m) for (_, eb), g in zip(layout, graphs)] + [1])
+        off = np.zeros(n_off, np.int32)
+        adj = np.zeros(n_edge, np.int32)
+        sg = np.ones(n_edge, np.int8)
+        for i, (g, (ob, eb)) in enumerate(zip(graphs, layout)):
+            off[ob: ob + g.n_u + 1] = g.offsets
+            adj[eb: eb + g.m] = g.adj
+            sg[eb: eb + g.m] = g.signs
+            descs[i].n_u, descs[i].n_v, descs[i].n_edges = int(g.n_u), int(g.n_v), int(g.m)
+            descs[i].off_base, descs[i].edge_base = int(ob), int(eb)
+        self.descs = descs
+        self.offsets = torch.from_numpy(off).to(device)
+        self.adj = torch.from_numpy(adj).to(device)
+        self.signs = torch.from_numpy(sg).to(device)
+        self.totals = torch.zeros(max(n, 1), dtype=torch.int64, device=device)
+
+
+class BatchPlan:
+    """A captured batch pipeline (bbc_batch_plan): launch() replays it."""
+
+    def __init__(self, ctx: Context, batch: Batch, opts: Options | None = None):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.batch = batch  # keeps the captured buffers alive
+        o = opts if opts is not None else options()
+        h = ctypes.c_void_p()
+        st = self._lib.bbc_batch_plan_create(ctx._h, batch.n_graphs, batch.descs, _ptr(batch.offsets),
+                                             _ptr(batch.adj), _ptr(batch.signs), _ptr(batch.totals),
+                                             ctypes.byref(o), ctypes.byref(h))
+        if st != OK:
+            raise BbcError(st, ctx.last_error())
+        self._h = h
+
+    def launch(self, stream=None):
+        st = self._lib.bbc_batch_launch(self._h, _stream_ptr(stream, self.batch.offsets))
+        if st != OK:
+            raise BbcError(st, self.ctx.last_error())
+
+    def wait(self, stream=None):
+        st = self._lib.bbc_batch_wait(self._h, _stream_ptr(stream, self.batch.offsets))
+        if st != OK:
+            raise BbcError(st, self.ctx.last_error())
+        return self.batch.totals
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.bbc_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

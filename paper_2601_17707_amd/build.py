@@ -21,6 +21,7 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
+    "-Wl,-z,defs",  # no undefined symbols in the shared library
     # no packed fp32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -1,24 +1,30 @@
-// C ABI of libbbc.so (declared in include/bbc.h): context, scratch arena,
-// launch sequence and error mapping.
+// C ABI of libbbc.so (declared in include/bbc.h): contexts, batch plans,
+// scratch arenas, the launch sequence and error mapping.
 #include <stdio.h>
 #include <string.h>
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/bbc.h"
 #include "bbc_internal.h"
 
 namespace bbc {
-void launch_checks(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v, int64_t m,
-                   int check_sign, DevStatus* st, hipStream_t s);
-void launch_degrees(const int32_t* off, const int32_t* adj, int32_t n_u, int64_t m, uint32_t* deg_u,
-                    uint32_t* deg_v, int32_t n_v, hipStream_t s);
-void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int32_t n_s, int32_t* rank, uint32_t* adeg,
-                  hipStream_t s);
-void launch_fill_anchor(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int64_t m,
-                        int s_is_u, const int32_t* rank, const uint32_t* aoff, uint32_t* fill, int32_t n_s,
-                        int32_t* acent, uint8_t* aneg, uint32_t* apack, hipStream_t s);
+void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v,
+                          int64_t m, int s_is_u, int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec,
+                          uint8_t* en, hipStream_t s);
+void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
+                           const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
+                           uint32_t* ea, uint32_t* ec, uint8_t* en, hipStream_t s);
+void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st, hipStream_t s);
+void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
+void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
+void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
+                  const uint32_t* agid, int32_t* agraph, hipStream_t s);
+void launch_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
+                       const uint32_t* aoff, uint32_t* fill, int64_t n_s, int32_t* acent, uint8_t* aneg,
+                       uint32_t* apack, const DevStatus* st, hipStream_t s);
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
@@ -29,7 +35,8 @@ int wedge_blocks_per_cu(int band_words, int wg, bool full);
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
-                  int64_t centre_base, int64_t n_centre, hipStream_t s);
+                  int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
+                  unsigned long long* gtotals, hipStream_t s);
 
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -52,9 +59,18 @@ struct bbc_ctx {
     size_t arena_bytes = 0;
     DevStatus* st_dev = nullptr;
     DevStatus* st_host = nullptr;  // pinned
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[4] = {};
     bbc_stats stats = {};
     std::string err;
+};
+
+struct bbc_batch_plan {
+    bbc_ctx* ctx = nullptr;
+    char* arena = nullptr;
+    DevStatus* st_dev = nullptr;
+    DevStatus* st_host = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -71,7 +87,8 @@ struct DeviceGuard {
     }
 };
 
-// Bump allocator over the context arena (256-byte aligned pieces).
+// Bump allocator over an arena (256-byte aligned pieces); with a null base
+// it only measures.
 struct Carve {
     char* base;
     size_t used = 0;
@@ -79,7 +96,7 @@ struct Carve {
     template <class T>
     T* take(int64_t n) {
         size_t bytes = ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) & ~(size_t)255;
-        T* p = (T*)(base + used);
+        T* p = base ? (T*)(base + used) : nullptr;
         used += bytes;
         return p;
     }
@@ -100,18 +117,32 @@ bbc_status hip_fail(bbc_ctx* ctx, hipError_t e, const char* where) {
     return fail(ctx, BBC_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_OR_FAIL(call)                                \
-    do {                                                 \
-        hipError_t _e = (call);                          \
+#define HIP_OR_FAIL(call)                                      \
+    do {                                                       \
+        hipError_t _e = (call);                                \
         if (_e != hipSuccess) return hip_fail(ctx, _e, #call); \
     } while (0)
 
-// All buffers of one call, carved from the arena in a fixed order.
+// Everything one pass of the pipeline needs (a single graph or a batch).
+struct Job {
+    bool batched = false;
+    // single graph (CSR over U) or concatenated batch arrays
+    const int32_t *off = nullptr, *adj = nullptr;
+    const int8_t* sg = nullptr;
+    int32_t n_u = 0, n_v = 0;
+    bool s_is_u = false;
+    unsigned long long* pv = nullptr;  // single graph: per-vertex output or null
+    int32_t n_graphs = 0;              // batch
+    unsigned long long* totals = nullptr;
+    int64_t m = 0, n_s = 0, n_c = 0;
+    uint32_t checks = BBC_CHECK_ALL;
+    int band_words = 0, wg_size = 0, grid = 0;
+};
+
+// All device buffers of one pass, carved from an arena in a fixed order.
 struct Plan {
-    int64_t m;
-    int32_t n_u, n_v, n_s, n_c;
-    uint32_t *deg_u, *deg_v;
-    uint32_t *rk_key, *rk_ka, *rk_kb, *rk_va, *rk_vb;  // rank sort
+    uint32_t *deg_s, *deg_c;
+    uint32_t *rk_ka, *rk_kb, *rk_va, *rk_vb;  // rank sort
     int32_t* rank;
     uint32_t *adeg, *aoff, *fill, *coff;
     int32_t* acent;
@@ -120,24 +151,28 @@ struct Plan {
     int32_t* back;
     uint32_t *wkey, *ord_a, *ord_b, *ord_va, *ord_vb;
     uint32_t *hist, *hist_scan, *partials;
+    uint32_t* agid;    // batch: graph of each anchor id
+    int32_t* agraph;   // batch: graph of each rank
+    DevGraph* graphs;  // batch descriptors
+    int64_t *vstart, *rank_end;
 
-    size_t carve(char* base) {
+    size_t carve(char* base, const Job& J) {
         Carve c(base);
-        int64_t ns1 = (int64_t)n_s + 1, nc1 = (int64_t)n_c + 1;
-        int64_t nmax = m > ns1 ? m : ns1;
-        if (nc1 > nmax) nmax = nc1;
-        deg_u = c.take<uint32_t>(n_u);
-        deg_v = c.take<uint32_t>(n_v);
-        rk_key = c.take<uint32_t>(n_s);
+        const int64_t m = J.m, n_s = J.n_s, n_c = J.n_c;
+        int64_t nmax = m;
+        if (n_s + 1 > nmax) nmax = n_s + 1;
+        if (n_c + 1 > nmax) nmax = n_c + 1;
+        deg_s = c.take<uint32_t>(n_s);
+        deg_c = c.take<uint32_t>(n_c);
         rk_ka = c.take<uint32_t>(n_s);
         rk_kb = c.take<uint32_t>(n_s);
         rk_va = c.take<uint32_t>(n_s);
         rk_vb = c.take<uint32_t>(n_s);
         rank = c.take<int32_t>(n_s);
-        adeg = c.take<uint32_t>(ns1);
-        aoff = c.take<uint32_t>(ns1);
+        adeg = c.take<uint32_t>(n_s + 1);
+        aoff = c.take<uint32_t>(n_s + 1);
         fill = c.take<uint32_t>(n_s);
-        coff = c.take<uint32_t>(nc1);
+        coff = c.take<uint32_t>(n_c + 1);
         acent = c.take<int32_t>(m);
         aneg = c.take<uint8_t>(m);
         apack = c.take<uint32_t>(m);
@@ -156,28 +191,233 @@ struct Plan {
         int64_t hs = (int64_t)radix_hist_size(nmax);
         hist = c.take<uint32_t>(hs);
         hist_scan = c.take<uint32_t>(hs + 1);
-        int64_t ps = (int64_t)scan_partials_size(hs + nmax + 8);
-        partials = c.take<uint32_t>(ps);
+        partials = c.take<uint32_t>((int64_t)scan_partials_size(hs + nmax + 8));
+        agid = c.take<uint32_t>(J.batched ? n_s : 0);
+        agraph = c.take<int32_t>(J.batched ? n_s : 0);
+        graphs = c.take<DevGraph>(J.n_graphs);
+        vstart = c.take<int64_t>(J.n_graphs + 1);
+        rank_end = c.take<int64_t>(J.n_graphs + 1);
         return c.used;
     }
 };
 
-bbc_status ensure_arena(bbc_ctx* ctx, size_t bytes) {
-    if (bytes <= ctx->arena_bytes) return BBC_OK;
-    if (ctx->arena) {
-        (void)hipFree(ctx->arena);
-        ctx->arena = nullptr;
-        ctx->arena_bytes = 0;
+// Queues the whole pipeline on stream s: kernel launches only (no host
+// waits, copies or allocations), so it can be captured in a graph.
+// ev (optional) receives [after checks, after build, after count].
+void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev) {
+    const int64_t m = J.m, n_s = J.n_s, n_c = J.n_c;
+    const int check_sign = (J.checks & BBC_CHECK_SIGNS) ? 1 : 0;
+    // edge decode buffers alias space that is free until the centre sort
+    uint32_t* ea = P.v1_a;
+    uint32_t* ec = P.v1_b;
+    uint8_t* en = (uint8_t*)P.back;
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, st);
+    if (J.batched)
+        launch_decode_batched(J.off, J.adj, J.sg, P.graphs, P.vstart, J.n_graphs, m, check_sign, st, ea, ec, en, s);
+    else
+        launch_decode_single(J.off, J.adj, J.sg, J.n_u, J.n_v, m, J.s_is_u ? 1 : 0, check_sign, st, ea, ec, en, s);
+    if (ev) (void)hipEventRecord(ev[0], s);
+
+    // degrees and ranks (Definition 6: degree, then id; ascending; a batch
+    // orders by graph first)
+    fill_u32(P.deg_s, 0u, n_s, s);
+    fill_u32(P.deg_c, 0u, n_c, s);
+    launch_hist(ea, m, P.deg_s, st, s);
+    launch_hist(ec, m, P.deg_c, st, s);
+    const uint32_t *rk_k = nullptr, *inv = nullptr;
+    radix_sort(P.deg_s, P.rk_ka, P.rk_kb, nullptr, nullptr, nullptr, nullptr, P.rk_va, P.rk_vb, n_s,
+               bits_for((uint64_t)(m > 0 ? m : 1)), P.hist, P.hist_scan, P.partials, s, &rk_k, nullptr, &inv);
+    if (J.batched && n_s > 0) {
+        launch_anchor_graph(P.graphs, J.n_graphs, P.agid, s);
+        launch_gather(inv, P.agid, n_s, P.wkey, s);
+        const uint32_t* gk = nullptr;
+        radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, inv, P.ord_va, P.ord_vb, n_s,
+                   bits_for((uint64_t)(J.n_graphs > 1 ? J.n_graphs - 1 : 1)), P.hist, P.hist_scan, P.partials, s,
+                   &gk, nullptr, &inv);
+    }
+    launch_ranks(inv, P.deg_s, n_s, P.rank, P.adeg, J.batched ? P.agid : nullptr, J.batched ? P.agraph : nullptr, s);
+    scan_exclusive_u32(P.adeg, P.aoff, n_s, P.partials, s);
+
+    // anchor lists, then centre lists by a stable sort on the centre id of
+    // the rank-ordered anchor entries (each centre list comes out rank-sorted)
+    launch_fill_edges(ea, ec, en, m, P.rank, P.aoff, P.fill, n_s, P.acent, P.aneg, P.apack, st, s);
+    const uint32_t *ckey = nullptr, *packed = nullptr, *perm = nullptr;
+    radix_sort((const uint32_t*)P.acent, P.k_a, P.k_b, P.apack, P.v0_a, P.v0_b, nullptr, P.v1_a, P.v1_b, m,
+               bits_for(n_c > 0 ? (uint64_t)(n_c - 1) : 0), P.hist, P.hist_scan, P.partials, s, &ckey, &packed,
+               &perm);
+    scan_exclusive_u32(P.deg_c, P.coff, n_c, P.partials, s);
+    launch_back(perm, m, P.back, s);
+    if (J.checks & BBC_CHECK_DUPLICATES) launch_check_dup(ckey, packed, m, st, s);
+
+    // schedule: anchors by descending work
+    launch_work(P.aoff, P.acent, P.back, P.coff, (int32_t)n_s, P.wkey, st, s);
+    const uint32_t *ok = nullptr, *order = nullptr;
+    radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, nullptr, P.ord_va, P.ord_vb, n_s, 32, P.hist,
+               P.hist_scan, P.partials, s, &ok, nullptr, &order);
+    if (ev) (void)hipEventRecord(ev[1], s);
+
+    if (J.pv) fill_bytes(J.pv, ((int64_t)J.n_u + J.n_v) * 8, s);
+    if (J.batched) fill_bytes(J.totals, (int64_t)J.n_graphs * 8, s);
+    if (n_s >= 2 && m > 0)
+        launch_wedge(J.band_words, J.wg_size, J.grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order,
+                     (int32_t)n_s, st, J.pv, inv, J.s_is_u ? 0 : J.n_u, J.s_is_u ? J.n_u : 0, n_c,
+                     J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
+                     J.batched ? J.totals : nullptr, s);
+    if (ev) (void)hipEventRecord(ev[2], s);
+}
+
+bbc_status grow(bbc_ctx* ctx, char** arena, size_t* have, size_t bytes) {
+    if (bytes <= *have) return BBC_OK;
+    if (*arena) {
+        (void)hipFree(*arena);
+        *arena = nullptr;
+        *have = 0;
     }
     size_t want = bytes + bytes / 8 + (1u << 20);
-    hipError_t e = hipMalloc((void**)&ctx->arena, want);
-    if (e != hipSuccess) {
-        ctx->arena = nullptr;
+    if (hipMalloc((void**)arena, want) != hipSuccess) {
+        *arena = nullptr;
         (void)hipGetLastError();
         return fail(ctx, BBC_ENOMEM, "scratch allocation of " + std::to_string(want) + " bytes failed");
     }
-    ctx->arena_bytes = want;
+    *have = want;
     return BBC_OK;
+}
+
+bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
+    bbc_options_init(o);
+    if (in) {
+        if (in->struct_size != sizeof(bbc_options)) return fail(ctx, BBC_EINVAL, "bbc_options.struct_size");
+        *o = *in;
+    }
+    if (o->side < BBC_SIDE_AUTO || o->side > BBC_SIDE_V) return fail(ctx, BBC_EINVAL, "bad side option");
+    if (!wedge_shape_ok(o->band_words, o->wg_size))
+        return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
+    if (o->wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
+    return BBC_OK;
+}
+
+bool side_is_u(int side, int32_t n_u, int32_t n_v) { return side == BBC_SIDE_U || (side == BBC_SIDE_AUTO && n_u < n_v); }
+
+// Validates a batch on the host and fills the job and device descriptors.
+bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, const int32_t* off_cat,
+                     const int32_t* adj_cat, const int8_t* sg_cat, uint64_t* totals, const bbc_options& o, Job& J,
+                     std::vector<DevGraph>& dg, std::vector<int64_t>& vstart, std::vector<int64_t>& rend) {
+    if (n_graphs < 0) return fail(ctx, BBC_EINVAL, "negative n_graphs");
+    if (n_graphs > 0 && (!d || !off_cat || !totals)) return fail(ctx, BBC_EINVAL, "batch pointer is NULL");
+    dg.resize((size_t)n_graphs);
+    vstart.assign((size_t)n_graphs + 1, 0);
+    rend.assign((size_t)n_graphs + 1, 0);
+    int64_t m = 0, ns = 0, nc = 0;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        const bbc_graph_desc& x = d[g];
+        if (x.n_u < 0 || x.n_v < 0 || x.n_edges < 0 || x.off_base < 0 || x.edge_base < 0)
+            return fail(ctx, BBC_EINVAL, "graph " + std::to_string(g) + ": negative size or base");
+        if (x.n_edges > 0 && (!adj_cat || !sg_cat)) return fail(ctx, BBC_EINVAL, "batch edge pointer is NULL");
+        const bool su = side_is_u(o.side, x.n_u, x.n_v);
+        DevGraph& y = dg[g];
+        y.off_base = x.off_base;
+        y.edge_base = x.edge_base;
+        y.n_edges = x.n_edges;
+        y.anchor_base = ns;
+        y.centre_base = nc;
+        y.n_u = x.n_u;
+        y.n_v = x.n_v;
+        y.s_is_u = su ? 1 : 0;
+        y.pad = 0;
+        vstart[g] = m;
+        rend[g] = ns;
+        m += x.n_edges;
+        ns += su ? x.n_u : x.n_v;
+        nc += su ? x.n_v : x.n_u;
+        if (m > INT32_MAX || ns + nc > INT32_MAX)
+            return fail(ctx, BBC_ETOOBIG, "batch exceeds INT32_MAX edges or vertices");
+    }
+    vstart[(size_t)n_graphs] = m;
+    rend[(size_t)n_graphs] = ns;
+    J.batched = true;
+    J.off = off_cat;
+    J.adj = adj_cat;
+    J.sg = sg_cat;
+    J.n_graphs = n_graphs;
+    J.totals = (unsigned long long*)totals;
+    J.m = m;
+    J.n_s = ns;
+    J.n_c = nc;
+    J.checks = o.checks;
+    J.band_words = o.band_words;
+    J.wg_size = o.wg_size;
+    J.grid = ctx->n_cu * (o.wg_per_cu > 0 ? o.wg_per_cu : wedge_blocks_per_cu(o.band_words, o.wg_size, false));
+    return BBC_OK;
+}
+
+// Maps the device status of a finished pass to a return code.
+bbc_status status_result(bbc_ctx* ctx, const DevStatus& h) {
+    char buf[160];
+    if (h.flags & kBadOffsets) {
+        snprintf(buf, sizeof buf, "offsets invalid at index %lld", (long long)h.bad_offset);
+        return fail(ctx, BBC_EOFFSETS, buf);
+    }
+    if (h.flags & kBadRange) {
+        snprintf(buf, sizeof buf, "adjacency id out of [0, n_v) at edge %lld", (long long)h.bad_range);
+        return fail(ctx, BBC_ERANGE, buf);
+    }
+    if (h.flags & kBadSign) {
+        snprintf(buf, sizeof buf, "sign not +1/-1 at edge %lld", (long long)h.bad_sign);
+        return fail(ctx, BBC_ESIGN, buf);
+    }
+    if (h.flags & kBadDup) {
+        snprintf(buf, sizeof buf, "repeated (u, v) pair at centre-list position %lld", (long long)h.bad_dup);
+        return fail(ctx, BBC_EDUP, buf);
+    }
+    return BBC_OK;
+}
+
+void fill_stats(bbc_ctx* ctx, const Job& J, const DevStatus& h, int block) {
+    bbc_stats& S = ctx->stats;
+    memset(&S, 0, sizeof S);
+    S.struct_size = sizeof(bbc_stats);
+    S.side = J.batched ? BBC_SIDE_AUTO : (J.s_is_u ? BBC_SIDE_U : BBC_SIDE_V);
+    S.n_anchor = (int32_t)J.n_s;
+    S.n_centre = (int32_t)J.n_c;
+    S.n_edges = J.m;
+    S.wedges = h.wedges;
+    S.bands = h.bands;
+    S.grid = J.grid;
+    S.block = block;
+}
+
+bbc_status timed_stats(bbc_ctx* ctx) {
+    bbc_stats& S = ctx->stats;
+    HIP_OR_FAIL(hipEventElapsedTime(&S.ms_checks, ctx->ev[3], ctx->ev[0]));
+    HIP_OR_FAIL(hipEventElapsedTime(&S.ms_build, ctx->ev[0], ctx->ev[1]));
+    HIP_OR_FAIL(hipEventElapsedTime(&S.ms_count, ctx->ev[1], ctx->ev[2]));
+    HIP_OR_FAIL(hipEventElapsedTime(&S.ms_total, ctx->ev[3], ctx->ev[2]));
+    return BBC_OK;
+}
+
+// Runs a job on the context's arena and stream and waits for its status.
+bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStream_t s,
+                   const std::vector<DevGraph>* dg, const std::vector<int64_t>* vstart,
+                   const std::vector<int64_t>* rend) {
+    Plan P;
+    bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, P.carve(nullptr, J));
+    if (rc != BBC_OK) return rc;
+    P.carve(ctx->arena, J);
+    if (dg && !dg->empty()) {
+        HIP_OR_FAIL(hipMemcpyAsync(P.graphs, dg->data(), dg->size() * sizeof(DevGraph), hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(P.vstart, vstart->data(), vstart->size() * 8, hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(P.rank_end, rend->data(), rend->size() * 8, hipMemcpyHostToDevice, s));
+    }
+    const bool timing = opts.timing != 0;
+    if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[3], s));
+    enqueue(J, P, ctx->st_dev, s, timing ? ctx->ev : nullptr);
+    HIP_OR_FAIL(hipGetLastError());
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rc = status_result(ctx, *ctx->st_host);
+    if (rc != BBC_OK) return rc;
+    fill_stats(ctx, J, *ctx->st_host, wedge_block(opts.band_words, opts.wg_size, J.pv != nullptr));
+    return timing ? timed_stats(ctx) : BBC_OK;
 }
 
 }  // namespace
@@ -271,131 +511,140 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     if (!ctx) return BBC_EINVAL;
     ctx->err.clear();
     bbc_options opts;
-    bbc_options_init(&opts);
-    if (opts_in) {
-        if (opts_in->struct_size != sizeof(bbc_options)) return fail(ctx, BBC_EINVAL, "bbc_options.struct_size");
-        opts = *opts_in;
-    }
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
     if (!total) return fail(ctx, BBC_EINVAL, "total is NULL");
     if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
     if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
         return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
     if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
-    if (opts.side < BBC_SIDE_AUTO || opts.side > BBC_SIDE_V) return fail(ctx, BBC_EINVAL, "bad side option");
-    if (!wedge_shape_ok(opts.band_words, opts.wg_size))
-        return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
-    if (opts.wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
 
-    hipStream_t s = (hipStream_t)stream;
     DeviceGuard guard(ctx->device);
-    const int64_t m = n_edges;
-    const bool s_is_u = opts.side == BBC_SIDE_U || (opts.side == BBC_SIDE_AUTO && n_u < n_v);
-    Plan P;
-    P.m = m;
-    P.n_u = n_u;
-    P.n_v = n_v;
-    P.n_s = s_is_u ? n_u : n_v;
-    P.n_c = s_is_u ? n_v : n_u;
-    size_t need = P.carve(nullptr);
-    bbc_status rc = ensure_arena(ctx, need);
-    if (rc != BBC_OK) return rc;
-    P.carve(ctx->arena);
-    const bool timing = opts.timing != 0;
-
-    if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[0], s));
-    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, ctx->st_dev);
-    launch_checks(offsets, adj, signs, n_u, n_v, m, (opts.checks & BBC_CHECK_SIGNS) ? 1 : 0, ctx->st_dev, s);
-    HIP_OR_FAIL(hipGetLastError());
-    HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(hipStreamSynchronize(s));
-    {
-        const DevStatus& h = *ctx->st_host;
-        char buf[160];
-        if (h.flags & kBadOffsets) {
-            snprintf(buf, sizeof buf, "offsets invalid at index %lld", (long long)h.bad_offset);
-            return fail(ctx, BBC_EOFFSETS, buf);
-        }
-        if (h.flags & kBadRange) {
-            snprintf(buf, sizeof buf, "adjacency id out of [0, n_v) at edge %lld", (long long)h.bad_range);
-            return fail(ctx, BBC_ERANGE, buf);
-        }
-        if (h.flags & kBadSign) {
-            snprintf(buf, sizeof buf, "sign not +1/-1 at edge %lld", (long long)h.bad_sign);
-            return fail(ctx, BBC_ESIGN, buf);
-        }
-    }
-    if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[1], s));
-
-    // degrees and ranks (Definition 6: degree, then id; ascending)
-    launch_degrees(offsets, adj, n_u, m, P.deg_u, P.deg_v, n_v, s);
-    const uint32_t* deg_s = s_is_u ? P.deg_u : P.deg_v;
-    const uint32_t* deg_c = s_is_u ? P.deg_v : P.deg_u;
-    const uint32_t *rk_k = nullptr, *inv = nullptr;
-    radix_sort(deg_s, P.rk_ka, P.rk_kb, nullptr, nullptr, nullptr, nullptr, P.rk_va, P.rk_vb, P.n_s,
-               bits_for((uint64_t)P.n_c), P.hist, P.hist_scan, P.partials, s, &rk_k, nullptr, &inv);
-    launch_ranks(inv, deg_s, P.n_s, P.rank, P.adeg, s);
-    scan_exclusive_u32(P.adeg, P.aoff, P.n_s, P.partials, s);
-
-    // anchor lists, then centre lists by a stable sort on the centre id of
-    // the rank-ordered anchor entries (each centre list comes out rank-sorted)
-    launch_fill_anchor(offsets, adj, signs, n_u, m, s_is_u ? 1 : 0, P.rank, P.aoff, P.fill, P.n_s, P.acent, P.aneg,
-                       P.apack, s);
-    const uint32_t *ckey = nullptr, *packed = nullptr, *perm = nullptr;
-    radix_sort((const uint32_t*)P.acent, P.k_a, P.k_b, P.apack, P.v0_a, P.v0_b, nullptr, P.v1_a, P.v1_b, m,
-               bits_for(P.n_c > 0 ? (uint64_t)(P.n_c - 1) : 0), P.hist, P.hist_scan, P.partials, s, &ckey, &packed,
-               &perm);
-    scan_exclusive_u32(deg_c, P.coff, P.n_c, P.partials, s);
-    launch_back(perm, m, P.back, s);
-    if (opts.checks & BBC_CHECK_DUPLICATES) launch_check_dup(ckey, packed, m, ctx->st_dev, s);
-
-    // schedule: anchors by descending work
-    launch_work(P.aoff, P.acent, P.back, P.coff, P.n_s, P.wkey, ctx->st_dev, s);
-    const uint32_t *ok = nullptr, *order = nullptr;
-    radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, nullptr, P.ord_va, P.ord_vb, P.n_s, 32, P.hist,
-               P.hist_scan, P.partials, s, &ok, nullptr, &order);
-    HIP_OR_FAIL(hipGetLastError());
-    if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[2], s));
-
+    Job J;
+    J.off = offsets;
+    J.adj = adj;
+    J.sg = signs;
+    J.n_u = n_u;
+    J.n_v = n_v;
+    J.s_is_u = side_is_u(opts.side, n_u, n_v);
+    J.pv = (unsigned long long*)per_vertex;
+    J.m = n_edges;
+    J.n_s = J.s_is_u ? n_u : n_v;
+    J.n_c = J.s_is_u ? n_v : n_u;
+    J.checks = opts.checks;
+    J.band_words = opts.band_words;
+    J.wg_size = opts.wg_size;
     const bool full = per_vertex != nullptr;
-    unsigned long long* pv = (unsigned long long*)per_vertex;
-    if (full) fill_bytes(pv, ((int64_t)n_u + n_v) * 8, s);
-    const int block = wedge_block(opts.band_words, opts.wg_size, full);
-    const int grid =
-        ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
-    if (P.n_s >= 2 && m > 0)
-        launch_wedge(opts.band_words, opts.wg_size, grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order,
-                     P.n_s, ctx->st_dev, pv, inv, s_is_u ? 0 : n_u, s_is_u ? n_u : 0, P.n_c, s);
-    HIP_OR_FAIL(hipGetLastError());
-    if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[3], s));
-    HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(hipStreamSynchronize(s));
-    const DevStatus& h = *ctx->st_host;
-    if (h.flags & kBadDup) {
-        char buf[160];
-        snprintf(buf, sizeof buf, "repeated (u, v) pair at centre-list position %lld", (long long)h.bad_dup);
-        return fail(ctx, BBC_EDUP, buf);
-    }
+    J.grid = ctx->n_cu *
+             (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
+    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
+    if (rc != BBC_OK) return rc;
     // per-vertex mode sums every anchor's pairs from both ends
-    *total = full ? (uint64_t)h.total / 2 : (uint64_t)h.total;
-
-    bbc_stats& S = ctx->stats;
-    memset(&S, 0, sizeof S);
-    S.struct_size = sizeof(bbc_stats);
-    S.side = s_is_u ? BBC_SIDE_U : BBC_SIDE_V;
-    S.n_anchor = P.n_s;
-    S.n_centre = P.n_c;
-    S.n_edges = m;
-    S.wedges = h.wedges;
-    S.bands = h.bands;
-    S.grid = grid;
-    S.block = block;
-    if (timing) {
-        HIP_OR_FAIL(hipEventElapsedTime(&S.ms_checks, ctx->ev[0], ctx->ev[1]));
-        HIP_OR_FAIL(hipEventElapsedTime(&S.ms_build, ctx->ev[1], ctx->ev[2]));
-        HIP_OR_FAIL(hipEventElapsedTime(&S.ms_count, ctx->ev[2], ctx->ev[3]));
-        HIP_OR_FAIL(hipEventElapsedTime(&S.ms_total, ctx->ev[0], ctx->ev[3]));
-    }
+    *total = full ? (uint64_t)ctx->st_host->total / 2 : (uint64_t)ctx->st_host->total;
     return BBC_OK;
+}
+
+bbc_status bbc_count_batched(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* descs,
+                             const int32_t* offsets_cat, const int32_t* adj_cat, const int8_t* signs_cat,
+                             uint64_t* totals, const bbc_options* opts_in, void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    bbc_options opts;
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    Job J;
+    std::vector<DevGraph> dg;
+    std::vector<int64_t> vstart, rend;
+    rc = batch_job(ctx, n_graphs, descs, offsets_cat, adj_cat, signs_cat, totals, opts, J, dg, vstart, rend);
+    if (rc != BBC_OK || n_graphs == 0) return rc;
+    return run_job(ctx, J, opts, (hipStream_t)stream, &dg, &vstart, &rend);
+}
+
+bbc_status bbc_batch_plan_destroy(bbc_batch_plan* p) {
+    if (!p) return BBC_OK;
+    {
+        DeviceGuard g(p->ctx ? p->ctx->device : 0);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->arena) (void)hipFree(p->arena);
+        if (p->st_dev) (void)hipFree(p->st_dev);
+        if (p->st_host) (void)hipHostFree(p->st_host);
+    }
+    delete p;
+    return BBC_OK;
+}
+
+bbc_status bbc_batch_plan_create(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* descs,
+                                 const int32_t* offsets_cat, const int32_t* adj_cat, const int8_t* signs_cat,
+                                 uint64_t* totals, const bbc_options* opts_in, bbc_batch_plan** out) {
+    if (!ctx || !out) return BBC_EINVAL;
+    *out = nullptr;
+    ctx->err.clear();
+    bbc_options opts;
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    Job J;
+    std::vector<DevGraph> dg;
+    std::vector<int64_t> vstart, rend;
+    rc = batch_job(ctx, n_graphs, descs, offsets_cat, adj_cat, signs_cat, totals, opts, J, dg, vstart, rend);
+    if (rc != BBC_OK) return rc;
+    bbc_batch_plan* p = new (std::nothrow) bbc_batch_plan();
+    if (!p) return BBC_ENOMEM;
+    p->ctx = ctx;
+    Plan P;
+    const size_t bytes = P.carve(nullptr, J);
+    if (hipMalloc((void**)&p->arena, bytes) != hipSuccess ||
+        hipMalloc((void**)&p->st_dev, sizeof(DevStatus)) != hipSuccess ||
+        hipHostMalloc((void**)&p->st_host, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        bbc_batch_plan_destroy(p);
+        return fail(ctx, BBC_ENOMEM, "batch plan allocation failed");
+    }
+    P.carve(p->arena, J);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess && n_graphs > 0) {
+        e = hipMemcpyAsync(P.graphs, dg.data(), dg.size() * sizeof(DevGraph), hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess) e = hipMemcpyAsync(P.vstart, vstart.data(), vstart.size() * 8, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess) e = hipMemcpyAsync(P.rank_end, rend.data(), rend.size() * 8, hipMemcpyHostToDevice, cs);
+        if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    }
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        if (n_graphs > 0) enqueue(J, P, p->st_dev, cs, nullptr);
+        else hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, cs, p->st_dev);
+        hipError_t le = hipGetLastError();
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        bbc_batch_plan_destroy(p);
+        return hip_fail(ctx, e, "batch plan capture");
+    }
+    *out = p;
+    return BBC_OK;
+}
+
+bbc_status bbc_batch_launch(bbc_batch_plan* p, void* stream) {
+    if (!p) return BBC_EINVAL;
+    bbc_ctx* ctx = p->ctx;
+    DeviceGuard guard(ctx->device);
+    HIP_OR_FAIL(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return BBC_OK;
+}
+
+bbc_status bbc_batch_wait(bbc_batch_plan* p, void* stream) {
+    if (!p) return BBC_EINVAL;
+    bbc_ctx* ctx = p->ctx;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OR_FAIL(hipMemcpyAsync(p->st_host, p->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    return status_result(ctx, *p->st_host);
 }
 
 }  // extern "C"

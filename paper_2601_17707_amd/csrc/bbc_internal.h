@@ -25,6 +25,18 @@ struct DevStatus {
 
 enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8 };
 
+// One graph of a batch, as the device sees it.
+struct DevGraph {
+    int64_t off_base;     // first offset in the concatenated offsets array
+    int64_t edge_base;    // first edge in the concatenated adjacency / sign arrays
+    int64_t n_edges;
+    int64_t anchor_base;  // first global anchor id (and first rank) of this graph
+    int64_t centre_base;  // first global centre id
+    int32_t n_u, n_v;
+    int32_t s_is_u;       // anchor side of this graph
+    int32_t pad;
+};
+
 // ------------------------------------------------------------ wave helpers
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }

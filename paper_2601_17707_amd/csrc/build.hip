@@ -3,6 +3,8 @@
 // Anchor side S and centre side C: every wedge is u - c - w with u, w in S
 // and c in C.  Anchors are ranked by the vertex priority of Definition 6
 // (degree, then id), ascending, so "w ranked above u" is rank(w) > rank(u).
+// In a batch every graph keeps its own anchor side and the ranks are
+// ordered by (graph, degree, id), so each graph owns a contiguous rank range.
 // Two views are built:
 //   anchor lists (rank order): aoff[n_S + 1], acent[m] (centre id),
 //     aneg[m] (1 = negative edge), back[m] = position of the anchor inside
@@ -13,6 +15,10 @@
 // The paper sorts each neighbour list by priority (Algorithm 1) and, for
 // G-BBC++, sorts anchors by a fanout work estimate on the host
 // (Algorithm 4); here both are device radix sorts.
+//
+// Every kernel after the input checks first reads the status flags and does
+// nothing once an input error is flagged, so the whole sequence can be
+// queued (or captured in a graph) without waiting for the checks.
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -22,56 +28,37 @@ __device__ __forceinline__ void flag_bad(DevStatus* st, int32_t bit, int64_t* sl
     atomicMin((unsigned long long*)slot, (unsigned long long)idx);
 }
 
+__device__ __forceinline__ bool input_bad(const DevStatus* st) { return *(volatile const int32_t*)&st->flags != 0; }
+
+#define GRID_STRIDE(i, n)                                                       \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------------ checks
+
 // offsets[0] == 0, offsets[n_u] == m, non-decreasing
 __global__ void k_check_offsets(const int32_t* off, int32_t n_u, int64_t m, DevStatus* st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i <= n_u; i += stride) {
+    GRID_STRIDE(i, (int64_t)n_u + 1) {
         int32_t o = off[i];
         bool bad = (i == 0 && o != 0) || (i == n_u && (int64_t)o != m) || (i < n_u && off[i + 1] < o);
         if (bad) flag_bad(st, kBadOffsets, &st->bad_offset, i);
     }
 }
 
-__global__ void k_check_edges(const int32_t* adj, const int8_t* sg, int64_t m, int32_t n_v, int check_sign,
-                              DevStatus* st) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < m; i += stride) {
-        int32_t v = adj[i];
-        if (v < 0 || v >= n_v) flag_bad(st, kBadRange, &st->bad_range, i);
-        if (check_sign) {
-            int8_t s = sg[i];
-            if (s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, i);
-        }
+// The same per graph of a batch, one workgroup per graph; the reported
+// index is the position in the concatenated offsets array.
+__global__ void k_check_offsets_batched(const int32_t* off_cat, const DevGraph* gr, DevStatus* st) {
+    const DevGraph g = gr[blockIdx.x];
+    const int32_t* off = off_cat + g.off_base;
+    for (int64_t i = threadIdx.x; i <= g.n_u; i += blockDim.x) {
+        int32_t o = off[i];
+        bool bad = (i == 0 && o != 0) || (i == g.n_u && (int64_t)o != g.n_edges) || (i < g.n_u && off[i + 1] < o);
+        if (bad) flag_bad(st, kBadOffsets, &st->bad_offset, g.off_base + i);
     }
 }
 
-__global__ void k_degrees_u(const int32_t* off, int32_t n_u, uint32_t* deg_u) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n_u; i += stride) deg_u[i] = (uint32_t)(off[i + 1] - off[i]);
-}
-
-__global__ void k_degrees_v(const int32_t* adj, int64_t m, uint32_t* deg_v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < m; i += stride) atomicAdd(&deg_v[adj[i]], 1u);
-}
-
-// inv[r] = anchor id of rank r (the sorted payload); rank[id] = r;
-// adeg[r] = degree of that anchor
-__global__ void k_ranks(const uint32_t* inv, const uint32_t* deg_s, int32_t n_s, int32_t* rank, uint32_t* adeg) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; r < n_s; r += stride) {
-        uint32_t id = inv[r];
-        rank[id] = (int32_t)r;
-        adeg[r] = deg_s[id];
-    }
-}
-
-// Row of CSR entry e: the u with off[u] <= e < off[u + 1].
+// Row of CSR entry e: the u with off[u] <= e < off[u + 1] (in range even
+// for malformed offsets; those are flagged separately).
 __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n_u, int64_t e) {
     int32_t lo = 0, hi = n_u - 1;
     while (lo < hi) {
@@ -82,42 +69,110 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n_u, int64
     return lo;
 }
 
-// Scatter every input edge into its anchor's list (rank order).  With
-// S = U an anchor's entries keep their row order; with S = V they are placed
-// by an atomic fill counter (their order inside an anchor list is free).
-__global__ void k_fill_anchor(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int64_t m,
-                              int s_is_u, const int32_t* rank, const uint32_t* aoff, uint32_t* fill,
-                              int32_t* acent, uint8_t* aneg, uint32_t* apack) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; e < m; e += stride) {
-        int32_t u = row_of(off, n_u, e);
-        int32_t v = adj[e];
-        uint32_t neg = sg[e] < 0 ? 1u : 0u;
-        int32_t anchor = s_is_u ? u : v, centre = s_is_u ? v : u;
-        int32_t r = rank[anchor];
-        uint32_t slot = s_is_u ? aoff[r] + (uint32_t)(e - off[u]) : aoff[r] + atomicAdd(&fill[r], 1u);
-        acent[slot] = centre;
-        aneg[slot] = (uint8_t)neg;
-        apack[slot] = ((uint32_t)r << 1) | neg;
+// Edge e of a single graph -> (anchor id, centre id, negative), with the
+// id-range and sign checks.
+__global__ void k_decode_single(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v,
+                                int64_t m, int s_is_u, int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec,
+                                uint8_t* en) {
+    GRID_STRIDE(e, m) {
+        const int32_t u = row_of(off, n_u, e);
+        const int32_t v = adj[e];
+        const int8_t s = sg[e];
+        if (v < 0 || v >= n_v) flag_bad(st, kBadRange, &st->bad_range, e);
+        if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, e);
+        ea[e] = (uint32_t)(s_is_u ? u : v);
+        ec[e] = (uint32_t)(s_is_u ? v : u);
+        en[e] = s < 0 ? 1 : 0;
+    }
+}
+
+// Edge j of a batch (graphs laid end to end by vstart, a prefix of the edge
+// counts) -> global (anchor id, centre id, negative).  Each graph's anchors
+// and centres are numbered from its anchor_base / centre_base.
+__global__ void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat,
+                                 const DevGraph* gr, const int64_t* vstart, int32_t n_graphs, int64_t m,
+                                 int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec, uint8_t* en) {
+    GRID_STRIDE(j, m) {
+        int32_t lo = 0, hi = n_graphs - 1;  // graph holding j: last g with vstart[g] <= j
+        while (lo < hi) {
+            int32_t mid = lo + (hi - lo + 1) / 2;
+            if (vstart[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const DevGraph g = gr[lo];
+        const int64_t e = j - vstart[lo];  // edge index inside the graph
+        const int64_t pe = g.edge_base + e;  // position in the concatenated arrays
+        const int32_t u = row_of(off_cat + g.off_base, g.n_u, e);
+        const int32_t v = adj_cat[pe];
+        const int8_t s = sg_cat[pe];
+        if (v < 0 || v >= g.n_v) flag_bad(st, kBadRange, &st->bad_range, pe);
+        if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, pe);
+        ea[j] = (uint32_t)(g.anchor_base + (g.s_is_u ? u : v));
+        ec[j] = (uint32_t)(g.centre_base + (g.s_is_u ? v : u));
+        en[j] = s < 0 ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------------ degrees
+
+__global__ void k_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(i, n) atomicAdd(&deg[ids[i]], 1u);
+}
+
+// graph id of every anchor of a batch (one workgroup per graph)
+__global__ void k_anchor_graph(const DevGraph* gr, uint32_t* agid) {
+    const DevGraph g = gr[blockIdx.x];
+    const int64_t n_s = g.s_is_u ? g.n_u : g.n_v;
+    for (int64_t i = threadIdx.x; i < n_s; i += blockDim.x) agid[g.anchor_base + i] = blockIdx.x;
+}
+
+__global__ void k_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out) {
+    GRID_STRIDE(i, n) out[i] = src[idx[i]];
+}
+
+// inv[r] = anchor id of rank r (the sorted payload); rank[id] = r;
+// adeg[r] = degree of that anchor; agraph[r] = its graph (batches)
+__global__ void k_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
+                        const uint32_t* agid, int32_t* agraph) {
+    GRID_STRIDE(r, n_s) {
+        uint32_t id = inv[r];
+        rank[id] = (int32_t)r;
+        adeg[r] = deg_s[id];
+        if (agraph) agraph[r] = (int32_t)agid[id];
+    }
+}
+
+// ------------------------------------------------------------- anchor lists
+
+// Every edge into its anchor's list (rank order), placed by an atomic fill
+// counter (the order inside an anchor list is free).
+__global__ void k_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m,
+                             const int32_t* rank, const uint32_t* aoff, uint32_t* fill, int32_t* acent,
+                             uint8_t* aneg, uint32_t* apack, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(e, m) {
+        const int32_t r = rank[ea[e]];
+        const uint32_t slot = aoff[r] + atomicAdd(&fill[r], 1u);
+        acent[slot] = (int32_t)ec[e];
+        aneg[slot] = en[e];
+        apack[slot] = ((uint32_t)r << 1) | en[e];
     }
 }
 
 // back[perm[q]] = q: where each anchor entry sits in its centre's list
 __global__ void k_back(const uint32_t* perm, int64_t m, int32_t* back) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; q < m; q += stride) back[perm[q]] = (int32_t)q;
+    GRID_STRIDE(q, m) back[perm[q]] = (int32_t)q;
 }
 
 // A repeated (u, v) pair shows up as the same anchor rank twice in a row of
 // one centre's sorted list.
 __global__ void k_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; q + 1 < m; q += stride)
+    if (input_bad(st)) return;
+    GRID_STRIDE(q, m - 1) {
         if (ckey[q] == ckey[q + 1] && (packed[q] >> 1) == (packed[q + 1] >> 1))
             flag_bad(st, kBadDup, &st->bad_dup, q);
+    }
 }
 
 // Per-anchor work: the number of wedges the anchor walks, i.e. the suffix
@@ -127,6 +182,7 @@ __global__ void k_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_
 // the fanout ordering of Algorithm 4).
 __global__ __launch_bounds__(256) void k_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back,
                                               const uint32_t* coff, int32_t n_s, uint32_t* key, DevStatus* st) {
+    if (input_bad(st)) return;
     const int lane = lane_id();
     int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     int64_t nwv = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -157,33 +213,51 @@ static int grid_for(int64_t n, int threads, int cap = 16384) {
     return (int)g;
 }
 
-void launch_checks(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v, int64_t m,
-                   int check_sign, DevStatus* st, hipStream_t s) {
+void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v,
+                          int64_t m, int s_is_u, int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec,
+                          uint8_t* en, hipStream_t s) {
     hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n_u + 1, 256)), dim3(256), 0, s, off, n_u, m, st);
     if (m > 0)
-        hipLaunchKernelGGL(k_check_edges, dim3(grid_for(m, 256)), dim3(256), 0, s, adj, sg, m, n_v, check_sign,
-                           st);
+        hipLaunchKernelGGL(k_decode_single, dim3(grid_for(m, 256)), dim3(256), 0, s, off, adj, sg, n_u, n_v, m,
+                           s_is_u, check_sign, st, ea, ec, en);
 }
 
-void launch_degrees(const int32_t* off, const int32_t* adj, int32_t n_u, int64_t m, uint32_t* deg_u,
-                    uint32_t* deg_v, int32_t n_v, hipStream_t s) {
-    fill_u32(deg_v, 0u, n_v, s);
-    if (n_u > 0) hipLaunchKernelGGL(k_degrees_u, dim3(grid_for(n_u, 256)), dim3(256), 0, s, off, n_u, deg_u);
-    if (m > 0) hipLaunchKernelGGL(k_degrees_v, dim3(grid_for(m, 256)), dim3(256), 0, s, adj, m, deg_v);
-}
-
-void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int32_t n_s, int32_t* rank, uint32_t* adeg,
-                  hipStream_t s) {
-    if (n_s > 0) hipLaunchKernelGGL(k_ranks, dim3(grid_for(n_s, 256)), dim3(256), 0, s, inv, deg_s, n_s, rank, adeg);
-}
-
-void launch_fill_anchor(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int64_t m,
-                        int s_is_u, const int32_t* rank, const uint32_t* aoff, uint32_t* fill, int32_t n_s,
-                        int32_t* acent, uint8_t* aneg, uint32_t* apack, hipStream_t s) {
-    if (!s_is_u) fill_u32(fill, 0u, n_s, s);
+void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
+                           const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
+                           uint32_t* ea, uint32_t* ec, uint8_t* en, hipStream_t s) {
+    if (n_graphs <= 0) return;
+    hipLaunchKernelGGL(k_check_offsets_batched, dim3(n_graphs), dim3(256), 0, s, off_cat, gr, st);
     if (m > 0)
-        hipLaunchKernelGGL(k_fill_anchor, dim3(grid_for(m, 256)), dim3(256), 0, s, off, adj, sg, n_u, m, s_is_u,
-                           rank, aoff, fill, acent, aneg, apack);
+        hipLaunchKernelGGL(k_decode_batched, dim3(grid_for(m, 256)), dim3(256), 0, s, off_cat, adj_cat, sg_cat, gr,
+                           vstart, n_graphs, m, check_sign, st, ea, ec, en);
+}
+
+void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256)), dim3(256), 0, s, ids, n, deg, st);
+}
+
+void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s) {
+    if (n_graphs > 0) hipLaunchKernelGGL(k_anchor_graph, dim3(n_graphs), dim3(256), 0, s, gr, agid);
+}
+
+void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256)), dim3(256), 0, s, idx, src, n, out);
+}
+
+void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
+                  const uint32_t* agid, int32_t* agraph, hipStream_t s) {
+    if (n_s > 0)
+        hipLaunchKernelGGL(k_ranks, dim3(grid_for(n_s, 256)), dim3(256), 0, s, inv, deg_s, n_s, rank, adeg, agid,
+                           agraph);
+}
+
+void launch_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
+                       const uint32_t* aoff, uint32_t* fill, int64_t n_s, int32_t* acent, uint8_t* aneg,
+                       uint32_t* apack, const DevStatus* st, hipStream_t s) {
+    fill_u32(fill, 0u, n_s, s);
+    if (m > 0)
+        hipLaunchKernelGGL(k_fill_edges, dim3(grid_for(m, 256)), dim3(256), 0, s, ea, ec, en, m, rank, aoff, fill,
+                           acent, aneg, apack, st);
 }
 
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s) {

@@ -441,13 +441,20 @@ __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh
     return acc;
 }
 
+// Batched launches pass agraph (graph of each rank), rank_end (first rank of
+// each graph, n_graphs + 1 entries) and per-graph totals; an anchor's
+// endpoints then stop at the end of its graph's rank range.
 template <int WG, int BAND_WORDS, bool FULL>
 __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
                                               const uint32_t* __restrict__ order, int32_t n_s, DevStatus* st,
                                               unsigned long long* __restrict__ pv, const uint32_t* __restrict__ inv,
-                                              int64_t anchor_base, int64_t centre_base) {
+                                              int64_t anchor_base, int64_t centre_base,
+                                              const int32_t* __restrict__ agraph,
+                                              const int64_t* __restrict__ rank_end,
+                                              unsigned long long* __restrict__ gtotals) {
+    if (*(volatile const int32_t*)&st->flags) return;  // input error: nothing to count
     __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
     for (int i = tid; i < BAND_WORDS + kWave; i += WG) sh.cnt[i] = 0;
@@ -461,20 +468,24 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
         if (task >= n_s) break;
         const int32_t r = (int32_t)order[task];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
+        const int64_t n_end = agraph ? rank_end[agraph[r] + 1] : (int64_t)n_s;
         // fewer than two centres: no endpoint pair shares two wedges
-        if (deg < 2 || (!FULL && r >= n_s - 1)) continue;
+        if (deg < 2 || (!FULL && r >= n_end - 1)) continue;
         unsigned long long a;
         if (deg <= 15)
-            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
+            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
         else if (deg <= 255)
-            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
+            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
         else if (deg <= 65535)
-            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
+            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
         else
-            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_s, pv, centre_base, bands);
+            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
         if constexpr (FULL) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
             if (tid == 0) pv[anchor_base + inv[r]] = s;
+        } else if (gtotals) {
+            const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
+            if (tid == 0 && s) atomicAdd(&gtotals[agraph[r]], s);
         }
         acc += a;
     }
@@ -536,10 +547,11 @@ int wedge_blocks_per_cu(int band_words, int wg, bool full) {
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
-                  int64_t centre_base, int64_t n_centre, hipStream_t s) {
+                  int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
+                  unsigned long long* gtotals, hipStream_t s) {
 #define BBC_LAUNCH(W, B, F)                                                                                      \
     hipLaunchKernelGGL((k_wedge<W, B, F>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, order, \
-                       n_s, st, pv, inv, anchor_base, centre_base)
+                       n_s, st, pv, inv, anchor_base, centre_base, agraph, rank_end, gtotals)
     if (pv) {
         BBC_LAUNCH(kFullWG, kFullBW, true);
         if (n_centre > 0) {

@@ -1,0 +1,199 @@
+"""GPU parity of the batched path (bbc_count_batched) and of captured batch
+plans (bbc_batch_plan_*): per-graph totals against the oracle, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2601_17707_amd import bbc, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import __graft_entry__
+
+    __graft_entry__._ensure_built()
+    c = bbc.Context(0)
+    yield c
+    c.close()
+
+
+def mixed_graphs(seed, n=120):
+    """Tiny, empty, degenerate, complete and power-law graphs of uneven size."""
+    rng = np.random.default_rng(seed)
+    out = [synth.from_edges(0, 0, [], [], []), synth.from_edges(3, 5, [], [], []), synth.complete_graph(1, 9),
+           synth.complete_graph(6, 4, rng.choice([-1, 1], (6, 4)))]
+    for i in range(n):
+        k = i % 4
+        if k == 0:
+            out.append(synth.small_random_graph(rng, max_n=12))
+        elif k == 1:
+            nu, nv = int(rng.integers(20, 400)), int(rng.integers(20, 400))
+            m = min(int(rng.integers(50, 3000)), nu * nv // 3)
+            out.append(synth.chung_lu_graph(nu, nv, m, 2.2, 2.2, 60, 60, seed=int(rng.integers(1 << 30)), p_neg=0.3))
+        elif k == 2:
+            q = synth.batch_member_params(seed, i, 100, 20_000)
+            out.append(synth.chung_lu_graph(q["n_u"], q["n_v"], q["m"], q["gamma"], q["gamma"],
+                                            min(np.sqrt(q["m"]), q["n_v"]), min(np.sqrt(q["m"]), q["n_u"]),
+                                            q["seed"], p_neg=q["p_neg"]))
+        else:
+            out.append(synth.random_graph(rng, int(rng.integers(2, 40)), int(rng.integers(2, 40)), 0.4, 0.4))
+    return out
+
+
+def test_batch_matches_oracle(ctx):
+    graphs = mixed_graphs(1)
+    want = np.array([oracle.count(g) for g in graphs], np.int64)
+    b = bbc.Batch(graphs, "cuda:0")
+    got = ctx.count_batched(b).cpu().numpy()[: len(graphs)]
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("side", ["u", "v"])
+def test_batch_sides(ctx, side):
+    graphs = mixed_graphs(2, 40)
+    want = np.array([oracle.count(g) for g in graphs], np.int64)
+    b = bbc.Batch(graphs, "cuda:0")
+    got = ctx.count_batched(b, opts=bbc.options(side=side)).cpu().numpy()[: len(graphs)]
+    assert np.array_equal(got, want)
+
+
+def test_batch_arbitrary_layout(ctx):
+    """Graphs placed in reverse order with gaps in the concatenated arrays."""
+    graphs = mixed_graphs(3, 30)
+    layout = []
+    ob, eb = 7, 11
+    for g in reversed(graphs):
+        layout.append((ob, eb))
+        ob += g.n_u + 1 + 3
+        eb += g.m + 5
+    layout.reverse()
+    b = bbc.Batch(graphs, "cuda:0", layout=layout)
+    got = ctx.count_batched(b).cpu().numpy()[: len(graphs)]
+    assert np.array_equal(got, [oracle.count(g) for g in graphs])
+
+
+def test_batch_band_crossing_members(ctx):
+    """Members whose anchor side is wider than an LDS band, among small ones:
+    each anchor's endpoints stop at its own graph's rank range."""
+    graphs = [synth.chung_lu_graph(200_000, 70_000, 500_000, 2.1, 2.0, 3000, 600, seed=41),
+              synth.small_random_graph(np.random.default_rng(4)),
+              synth.chung_lu_graph(150_000, 90_000, 400_000, 2.3, 2.1, 2000, 800, seed=42),
+              synth.complete_graph(40, 30, np.random.default_rng(5).choice([-1, 1], (40, 30)))]
+    b = bbc.Batch(graphs, "cuda:0")
+    got = ctx.count_batched(b).cpu().numpy()[: len(graphs)]
+    assert np.array_equal(got, [oracle.count(g) for g in graphs])
+
+
+def test_batch_equals_single_calls_and_union(ctx):
+    graphs = mixed_graphs(6, 40)
+    b = bbc.Batch(graphs, "cuda:0")
+    got = ctx.count_batched(b).cpu().numpy()[: len(graphs)]
+    singles = []
+    for g in graphs:
+        off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+        singles.append(ctx.count(off, adj, sg, g.n_v))
+    assert list(got) == singles
+    # disjoint union is additive
+    us, vs, ss = [], [], []
+    bu = bv = 0
+    for g in graphs:
+        u, v, s = g.edges()
+        us.append(u + bu)
+        vs.append(v + bv)
+        ss.append(s)
+        bu += g.n_u
+        bv += g.n_v
+    union = synth.from_edges(bu, bv, np.concatenate(us), np.concatenate(vs), np.concatenate(ss))
+    off, adj, sg = bbc.graph_tensors(union, "cuda:0")
+    assert ctx.count(off, adj, sg, union.n_v) == int(got.sum())
+
+
+def test_batch_errors(ctx):
+    graphs = mixed_graphs(7, 12)
+    # an id out of range in the sixth graph
+    bad = [synth.Graph(g.n_u, g.n_v, g.offsets, g.adj.copy(), g.signs, {}) for g in graphs]
+    j = next(i for i in range(5, len(bad)) if bad[i].m > 0)
+    bad[j].adj[0] = bad[j].n_v
+    with pytest.raises(bbc.BbcError) as e:
+        ctx.count_batched(bbc.Batch(bad, "cuda:0"))
+    assert e.value.status == bbc.ERANGE
+    # a repeated edge
+    dup = [synth.Graph(g.n_u, g.n_v, g.offsets, g.adj.copy(), g.signs, {}) for g in graphs]
+    k = next(i for i, g in enumerate(dup) if np.any(np.diff(g.offsets) >= 2))
+    r = int(np.argmax(np.diff(dup[k].offsets) >= 2))
+    dup[k].adj[dup[k].offsets[r] + 1] = dup[k].adj[dup[k].offsets[r]]
+    with pytest.raises(bbc.BbcError) as e:
+        ctx.count_batched(bbc.Batch(dup, "cuda:0"))
+    assert e.value.status == bbc.EDUP
+    # bad offsets
+    offg = [synth.Graph(g.n_u, g.n_v, g.offsets.copy(), g.adj, g.signs, {}) for g in graphs]
+    offg[4].offsets[-1] += 1
+    with pytest.raises(bbc.BbcError) as e:
+        ctx.count_batched(bbc.Batch(offg, "cuda:0"))
+    assert e.value.status == bbc.EOFFSETS
+    # the context still works
+    b = bbc.Batch(graphs, "cuda:0")
+    assert list(ctx.count_batched(b).cpu().numpy()[: len(graphs)]) == [oracle.count(g) for g in graphs]
+
+
+def test_plan_replays(ctx):
+    """A captured plan replayed several times with eager work and
+    synchronisations in between; every replay matches the eager result, also
+    after the input contents change."""
+    graphs = mixed_graphs(8, 60)
+    want = np.array([oracle.count(g) for g in graphs], np.int64)
+    b = bbc.Batch(graphs, "cuda:0")
+    eager = ctx.count_batched(b).clone()
+    assert np.array_equal(eager.cpu().numpy()[: len(graphs)], want)
+    plan = ctx.plan(b)
+    other = synth.chung_lu_graph(3000, 2000, 40_000, 2.1, 2.1, 400, 400, seed=8)
+    off, adj, sg = bbc.graph_tensors(other, "cuda:0")
+    t_other = oracle.count(other)
+    for rep in range(4):
+        b.totals.fill_(-1)
+        plan.launch()
+        got = plan.wait()
+        assert torch.equal(got, eager), rep
+        assert ctx.count(off, adj, sg, other.n_v) == t_other  # eager work between replays
+        x = torch.randn(1000, device="cuda:0").sum()
+        torch.cuda.synchronize()
+    # new signs in place: replays see the new contents
+    rng = np.random.default_rng(9)
+    new_graphs = [synth.Graph(g.n_u, g.n_v, g.offsets, g.adj, rng.choice([-1, 1], g.m).astype(np.int8), {})
+                  for g in graphs]
+    nb = bbc.Batch(new_graphs, "cuda:0")
+    b.signs.copy_(nb.signs)
+    plan.launch()
+    got = plan.wait().cpu().numpy()[: len(graphs)]
+    assert np.array_equal(got, [oracle.count(g) for g in new_graphs])
+    del x
+    plan.close()
+
+
+def test_plan_reports_input_errors(ctx):
+    graphs = mixed_graphs(10, 20)
+    b = bbc.Batch(graphs, "cuda:0")
+    plan = ctx.plan(b)
+    plan.launch()
+    ok = plan.wait().clone()
+    saved = b.adj.clone()
+    b.adj[3] = 1 << 30
+    plan.launch()
+    with pytest.raises(bbc.BbcError) as e:
+        plan.wait()
+    assert e.value.status == bbc.ERANGE
+    b.adj.copy_(saved)
+    plan.launch()
+    assert torch.equal(plan.wait(), ok)
+    plan.close()
+
+
+def test_workload_batch_sample(ctx):
+    """The first 200 members of the 10,000-graph batch workload."""
+    graphs = synth.batch_graphs(200, seed=1)
+    b = bbc.Batch(graphs, "cuda:0")
+    got = ctx.count_batched(b).cpu().numpy()[: len(graphs)]
+    assert np.array_equal(got, [oracle.count(g) for g in graphs])
