@@ -67,6 +67,15 @@ enum { BBC_SIDE_AUTO = 0, BBC_SIDE_U = 1, BBC_SIDE_V = 2 };
  * the kernels index with them) */
 enum { BBC_CHECK_SIGNS = 1, BBC_CHECK_DUPLICATES = 2, BBC_CHECK_ALL = 3 };
 
+/* A dense block: a set of U vertices and a set of V vertices whose edges
+ * are counted on int8 matrix cores (see bbc_options.blocks).  Blocks must be
+ * pairwise disjoint on both sides. */
+typedef struct {
+    int32_t n_u_ids, n_v_ids;
+    const int32_t* u_ids; /* device, n_u_ids distinct U ids */
+    const int32_t* v_ids; /* device, n_v_ids distinct V ids */
+} bbc_dense_block;
+
 typedef struct {
     uint32_t struct_size; /* sizeof(bbc_options), set by bbc_options_init */
     int32_t side;         /* BBC_SIDE_* */
@@ -75,6 +84,17 @@ typedef struct {
     int32_t band_words;   /* LDS counter band in 32-bit words per workgroup, 0 = default */
     int32_t wg_size;      /* threads per wedge-kernel workgroup, 0 = default */
     int32_t wg_per_cu;    /* persistent workgroups per compute unit, 0 = as many as fit */
+    /* Dense-block hybrid (bbc_count only, no per-vertex output).  For the
+     * vertices of each block, with S the block's signed adjacency (entries
+     * +1 / -1 / 0), S S^T = a - b and |S| |S|^T = a + b count the agreeing
+     * and disagreeing wedges through the block's centres exactly (int8
+     * operands, int32 accumulation).  Every other wedge - including those
+     * with one block edge and one other edge - stays in the sparse walk, and
+     * pairs inside a block add the cross term a_dense a_sparse +
+     * b_dense b_sparse, so the count is exact for any choice of blocks.
+     * Per block: at most 16384 anchor-side and 65535 centre-side ids. */
+    int32_t n_blocks;
+    const bbc_dense_block* blocks; /* host array of n_blocks, or NULL */
 } bbc_options;
 
 /* Fills *opts with the defaults: auto side, all checks, no timing. */
@@ -168,8 +188,12 @@ typedef struct {
     int32_t block;        /* threads per workgroup */
     float ms_checks;      /* HIP event times on the caller's stream (timing option) */
     float ms_build;       /* degrees, ranks, degree-ordered CSR, schedule */
-    float ms_count;       /* wedge aggregation kernel */
+    float ms_count;       /* wedge aggregation kernel (and the dense blocks, if any) */
     float ms_total;
+    float ms_dense;       /* int8 matrix-core kernel of the dense blocks */
+    int32_t n_blocks;
+    uint64_t dense_ops;   /* int8 multiply-adds x 2 of the upper-triangle block tiles */
+    uint64_t wedges_all;  /* sum over centres of C(deg c, 2), dense blocks included */
 } bbc_stats;
 
 bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out);

@@ -25,6 +25,15 @@ class BbcError(RuntimeError):
         self.message = message
 
 
+class DenseBlock(ctypes.Structure):
+    _fields_ = [
+        ("n_u_ids", ctypes.c_int32),
+        ("n_v_ids", ctypes.c_int32),
+        ("u_ids", ctypes.c_void_p),
+        ("v_ids", ctypes.c_void_p),
+    ]
+
+
 class Options(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32),
@@ -34,6 +43,8 @@ class Options(ctypes.Structure):
         ("band_words", ctypes.c_int32),
         ("wg_size", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int32),
+        ("blocks", ctypes.POINTER(DenseBlock)),
     ]
 
 
@@ -62,6 +73,10 @@ class Stats(ctypes.Structure):
         ("ms_build", ctypes.c_float),
         ("ms_count", ctypes.c_float),
         ("ms_total", ctypes.c_float),
+        ("ms_dense", ctypes.c_float),
+        ("n_blocks", ctypes.c_int32),
+        ("dense_ops", ctypes.c_uint64),
+        ("wedges_all", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -115,7 +130,10 @@ def status_string(status: int) -> str:
     return load_library().bbc_status_string(status).decode()
 
 
-def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0) -> Options:
+def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0,
+            blocks=None) -> Options:
+    """Options struct.  ``blocks``: list of (u_ids, v_ids) int32 device
+    tensors naming dense blocks (kept alive by the returned object)."""
     o = Options()
     load_library().bbc_options_init(ctypes.byref(o))
     o.side = _SIDES[side]
@@ -124,6 +142,14 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
     o.band_words = band_words
     o.wg_size = wg_size
     o.wg_per_cu = wg_per_cu
+    if blocks:
+        arr = (DenseBlock * len(blocks))()
+        for i, (uids, vids) in enumerate(blocks):
+            arr[i].n_u_ids, arr[i].n_v_ids = int(uids.numel()), int(vids.numel())
+            arr[i].u_ids, arr[i].v_ids = uids.data_ptr(), vids.data_ptr()
+        o.n_blocks = len(blocks)
+        o.blocks = ctypes.cast(arr, ctypes.POINTER(DenseBlock))
+        o._keep = (arr, blocks)
     return o
 
 

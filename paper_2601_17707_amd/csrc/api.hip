@@ -41,7 +41,7 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->flags = 0;
-        st->bad_offset = st->bad_range = st->bad_sign = st->bad_dup = INT64_MAX;
+        st->bad_offset = st->bad_range = st->bad_sign = st->bad_dup = st->bad_block = INT64_MAX;
         st->total = 0;
         st->wedges = 0;
         st->bands = 0;
@@ -293,6 +293,8 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
     if (!wedge_shape_ok(o->band_words, o->wg_size))
         return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
     if (o->wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
+    if (o->n_blocks < 0 || (o->n_blocks > 0 && !o->blocks)) return fail(ctx, BBC_EINVAL, "bad dense block list");
+    if (o->n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks are not supported by this build");
     return BBC_OK;
 }
 

@@ -16,6 +16,7 @@ struct DevStatus {
     int64_t bad_range;
     int64_t bad_sign;
     int64_t bad_dup;
+    int64_t bad_block;          // first offending dense-block vertex (block * 2^32 + position)
     unsigned long long total;   // balanced butterflies
     unsigned long long wedges;  // sum over centres of C(deg, 2)
     unsigned long long bands;   // counter bands processed
@@ -23,7 +24,34 @@ struct DevStatus {
     unsigned int pad1;
 };
 
-enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8 };
+enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8, kBadBlocks = 16 };
+
+// One dense block as the device sees it.
+struct DevBlock {
+    int64_t mat_off;  // int8 matrix [rpad][kpad] (anchor rows x centre columns)
+    int64_t tab_off;  // uint32 table [rpad][rpad]: a_dense | b_dense << 16 per anchor pair
+    int64_t rank0;    // first rank of the block's anchors (they are contiguous)
+    int32_t n_r, n_k; // anchors, centres
+    int32_t rpad, kpad;
+    int32_t n_aid, n_cid;  // caller's id counts on the anchor and centre side
+    const int32_t* aid;    // anchor-side ids (device)
+    const int32_t* cid;    // centre-side ids (device)
+};
+
+// One 128 x 128 upper-triangle output tile of a block product.
+struct DevTile {
+    int32_t blk, ti, tj, pad;
+};
+
+// Dense-block data the wedge kernel reads (all null without blocks).
+struct HybridView {
+    const int32_t* ablk;   // per rank: block of the anchor, or -1
+    const int32_t* abidx;  // per rank: index inside its block
+    const int32_t* cblk;   // per centre id: block, or -1
+    const int32_t* cpos;   // per centre id in a block: list position past the block's anchors
+    const DevBlock* blocks;
+    const uint32_t* tabs;
+};
 
 // One graph of a batch, as the device sees it.
 struct DevGraph {
