@@ -9,6 +9,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbbc.so")
 
@@ -280,17 +282,26 @@ def graph_tensors(g, device="cuda"):
     return off, adj, sg
 
 
-def count(g, per_vertex: bool = False, side="auto", checks=CHECK_ALL, ctx: Context | None = None):
+def count(g, per_vertex: bool = False, side="auto", checks=CHECK_ALL, blocks=None, ctx: Context | None = None,
+          **kw):
     """Counts a graph object (n_u, n_v, offsets, adj, signs) on the current GPU.
 
-    Returns the total, or (total, per-vertex int64 tensor) with per_vertex.
+    ``blocks``: optional list of (u_ids, v_ids) integer arrays naming dense
+    blocks.  Returns the total, or (total, per-vertex int64 tensor) with
+    per_vertex.
     """
     import torch
 
     ctx = ctx or default_context()
-    off, adj, sg = graph_tensors(g, f"cuda:{ctx.device}")
+    dev = f"cuda:{ctx.device}"
+    off, adj, sg = graph_tensors(g, dev)
     pv = torch.empty(int(g.n_u) + int(g.n_v), dtype=torch.int64, device=off.device) if per_vertex else None
-    t = ctx.count(off, adj, sg, int(g.n_v), per_vertex=pv, opts=options(side=side, checks=checks))
+    dblocks = None
+    if blocks is not None:
+        dblocks = [(torch.as_tensor(np.asarray(u, np.int32)).to(dev), torch.as_tensor(np.asarray(v, np.int32)).to(dev))
+                   for u, v in blocks]
+    t = ctx.count(off, adj, sg, int(g.n_v), per_vertex=pv,
+                  opts=options(side=side, checks=checks, blocks=dblocks, **kw))
     return (t, pv) if per_vertex else t
 
 

@@ -28,7 +28,16 @@ void launch_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
-                 uint32_t* key, DevStatus* st, hipStream_t s);
+                 uint32_t* key, DevStatus* st, const HybridView& hv, hipStream_t s);
+void launch_block_mark(const DevBlock* blocks, int32_t n_blocks, int64_t max_ids, int32_t n_s, int32_t n_c,
+                       uint32_t* agrp, int32_t* cblk, int32_t* cidx, DevStatus* st, hipStream_t s);
+void launch_block_cpos(const int32_t* cblk, int32_t n_c, const DevBlock* blocks, const uint32_t* coff,
+                       const uint32_t* packed, int32_t* cpos, const DevStatus* st, hipStream_t s);
+void launch_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s, const DevBlock* blocks,
+                       const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* cblk,
+                       const int32_t* cidx, int8_t* mats, const DevStatus* st, hipStream_t s);
+void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles, const int8_t* mats, uint32_t* tabs,
+                  DevStatus* st, hipStream_t s);
 bool wedge_shape_ok(int band_words, int wg);
 int wedge_block(int band_words, int wg, bool full);
 int wedge_blocks_per_cu(int band_words, int wg, bool full);
@@ -36,7 +45,7 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
-                  unsigned long long* gtotals, hipStream_t s);
+                  unsigned long long* gtotals, const HybridView& hv, hipStream_t s);
 
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -44,6 +53,7 @@ __global__ void k_status_init(DevStatus* st) {
         st->bad_offset = st->bad_range = st->bad_sign = st->bad_dup = st->bad_block = INT64_MAX;
         st->total = 0;
         st->wedges = 0;
+        st->walked = 0;
         st->bands = 0;
         st->queue = 0;
     }
@@ -59,7 +69,7 @@ struct bbc_ctx {
     size_t arena_bytes = 0;
     DevStatus* st_dev = nullptr;
     DevStatus* st_host = nullptr;  // pinned
-    hipEvent_t ev[4] = {};
+    hipEvent_t ev[6] = {};  // [checks, build, count, start, dense start, dense end]
     bbc_stats stats = {};
     std::string err;
 };
@@ -137,6 +147,11 @@ struct Job {
     int64_t m = 0, n_s = 0, n_c = 0;
     uint32_t checks = BBC_CHECK_ALL;
     int band_words = 0, wg_size = 0, grid = 0;
+    // dense blocks (single graph only)
+    int32_t n_blocks = 0, n_tiles = 0;
+    int64_t r_first = 0;  // first rank of the block anchors (they sit at the top)
+    int64_t max_ids = 0, mat_bytes = 0, tab_words = 0;
+    uint64_t dense_ops = 0;
 };
 
 // All device buffers of one pass, carved from an arena in a fixed order.
@@ -155,6 +170,12 @@ struct Plan {
     int32_t* agraph;   // batch: graph of each rank
     DevGraph* graphs;  // batch descriptors
     int64_t *vstart, *rank_end;
+    uint32_t *agrp, *ablk1;  // dense blocks: block + 1 per anchor id / per rank
+    int32_t *cblk, *cidx, *cpos;
+    DevBlock* dblocks;
+    DevTile* dtiles;
+    int8_t* mats;
+    uint32_t* tabs;
 
     size_t carve(char* base, const Job& J) {
         Carve c(base);
@@ -197,6 +218,16 @@ struct Plan {
         graphs = c.take<DevGraph>(J.n_graphs);
         vstart = c.take<int64_t>(J.n_graphs + 1);
         rank_end = c.take<int64_t>(J.n_graphs + 1);
+        const bool hy = J.n_blocks > 0;
+        agrp = c.take<uint32_t>(hy ? n_s : 0);
+        ablk1 = c.take<uint32_t>(hy ? n_s : 0);
+        cblk = c.take<int32_t>(hy ? n_c : 0);
+        cidx = c.take<int32_t>(hy ? n_c : 0);
+        cpos = c.take<int32_t>(hy ? n_c : 0);
+        dblocks = c.take<DevBlock>(J.n_blocks);
+        dtiles = c.take<DevTile>(J.n_tiles);
+        mats = c.take<int8_t>(J.mat_bytes);
+        tabs = c.take<uint32_t>(J.tab_words);
         return c.used;
     }
 };
@@ -206,6 +237,7 @@ struct Plan {
 // ev (optional) receives [after checks, after build, after count].
 void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev) {
     const int64_t m = J.m, n_s = J.n_s, n_c = J.n_c;
+    const bool hybrid = J.n_blocks > 0;
     const int check_sign = (J.checks & BBC_CHECK_SIGNS) ? 1 : 0;
     // edge decode buffers alias space that is free until the centre sort
     uint32_t* ea = P.v1_a;
@@ -216,6 +248,12 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
         launch_decode_batched(J.off, J.adj, J.sg, P.graphs, P.vstart, J.n_graphs, m, check_sign, st, ea, ec, en, s);
     else
         launch_decode_single(J.off, J.adj, J.sg, J.n_u, J.n_v, m, J.s_is_u ? 1 : 0, check_sign, st, ea, ec, en, s);
+    if (hybrid) {  // block of every block vertex; ids checked in range, distinct and disjoint
+        fill_u32(P.agrp, 0u, n_s, s);
+        fill_u32((uint32_t*)P.cblk, 0xffffffffu, n_c, s);
+        launch_block_mark(P.dblocks, J.n_blocks, J.max_ids, (int32_t)n_s, (int32_t)n_c, P.agrp, P.cblk, P.cidx, st,
+                          s);
+    }
     if (ev) (void)hipEventRecord(ev[0], s);
 
     // degrees and ranks (Definition 6: degree, then id; ascending; a batch
@@ -235,6 +273,13 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
                    bits_for((uint64_t)(J.n_graphs > 1 ? J.n_graphs - 1 : 1)), P.hist, P.hist_scan, P.partials, s,
                    &gk, nullptr, &inv);
     }
+    if (hybrid && n_s > 0) {  // block anchors last, block by block: ranks (block, degree, id)
+        launch_gather(inv, P.agrp, n_s, P.wkey, s);
+        const uint32_t* gk = nullptr;
+        radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, inv, P.ord_va, P.ord_vb, n_s,
+                   bits_for((uint64_t)J.n_blocks), P.hist, P.hist_scan, P.partials, s, &gk, nullptr, &inv);
+        launch_gather(inv, P.agrp, n_s, P.ablk1, s);
+    }
     launch_ranks(inv, P.deg_s, n_s, P.rank, P.adeg, J.batched ? P.agid : nullptr, J.batched ? P.agraph : nullptr, s);
     scan_exclusive_u32(P.adeg, P.aoff, n_s, P.partials, s);
 
@@ -248,9 +293,19 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     scan_exclusive_u32(P.deg_c, P.coff, n_c, P.partials, s);
     launch_back(perm, m, P.back, s);
     if (J.checks & BBC_CHECK_DUPLICATES) launch_check_dup(ckey, packed, m, st, s);
+    HybridView hv{nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (hybrid) {
+        hv = HybridView{P.ablk1, P.cblk, P.cpos, P.dblocks, P.tabs};
+        launch_block_cpos(P.cblk, (int32_t)n_c, P.dblocks, P.coff, packed, P.cpos, st, s);
+        if (J.n_tiles > 0) {
+            fill_bytes(P.mats, J.mat_bytes, s);
+            launch_block_pack(P.ablk1, (int32_t)J.r_first, (int32_t)n_s, P.dblocks, P.aoff, P.acent, P.aneg, P.cblk,
+                              P.cidx, P.mats, st, s);
+        }
+    }
 
     // schedule: anchors by descending work
-    launch_work(P.aoff, P.acent, P.back, P.coff, (int32_t)n_s, P.wkey, st, s);
+    launch_work(P.aoff, P.acent, P.back, P.coff, (int32_t)n_s, P.wkey, st, hv, s);
     const uint32_t *ok = nullptr, *order = nullptr;
     radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, nullptr, P.ord_va, P.ord_vb, n_s, 32, P.hist,
                P.hist_scan, P.partials, s, &ok, nullptr, &order);
@@ -258,11 +313,16 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
 
     if (J.pv) fill_bytes(J.pv, ((int64_t)J.n_u + J.n_v) * 8, s);
     if (J.batched) fill_bytes(J.totals, (int64_t)J.n_graphs * 8, s);
+    if (hybrid) {  // dense block products (int8 matrix cores), then the sparse walk reads their tables
+        if (ev) (void)hipEventRecord(ev[4], s);
+        launch_dense(P.dblocks, P.dtiles, J.n_tiles, P.mats, P.tabs, st, s);
+        if (ev) (void)hipEventRecord(ev[5], s);
+    }
     if (n_s >= 2 && m > 0)
         launch_wedge(J.band_words, J.wg_size, J.grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order,
                      (int32_t)n_s, st, J.pv, inv, J.s_is_u ? 0 : J.n_u, J.s_is_u ? J.n_u : 0, n_c,
                      J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
-                     J.batched ? J.totals : nullptr, s);
+                     J.batched ? J.totals : nullptr, hv, s);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
@@ -294,7 +354,6 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
         return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
     if (o->wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
     if (o->n_blocks < 0 || (o->n_blocks > 0 && !o->blocks)) return fail(ctx, BBC_EINVAL, "bad dense block list");
-    if (o->n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks are not supported by this build");
     return BBC_OK;
 }
 
@@ -305,6 +364,7 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
                      const int32_t* adj_cat, const int8_t* sg_cat, uint64_t* totals, const bbc_options& o, Job& J,
                      std::vector<DevGraph>& dg, std::vector<int64_t>& vstart, std::vector<int64_t>& rend) {
     if (n_graphs < 0) return fail(ctx, BBC_EINVAL, "negative n_graphs");
+    if (o.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks apply to bbc_count only");
     if (n_graphs > 0 && (!d || !off_cat || !totals)) return fail(ctx, BBC_EINVAL, "batch pointer is NULL");
     dg.resize((size_t)n_graphs);
     vstart.assign((size_t)n_graphs + 1, 0);
@@ -352,6 +412,55 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
     return BBC_OK;
 }
 
+// Validates the dense blocks on the host (sizes, pointers) and lays out their
+// device data; ids are checked on the device.  Block anchors take the top
+// ranks, block by block.
+bbc_status block_job(bbc_ctx* ctx, const bbc_options& o, Job& J, std::vector<DevBlock>& db,
+                     std::vector<DevTile>& dt) {
+    constexpr int32_t kMaxAnchors = 16384, kMaxCentres = 65535, kTile = 128, kK = 64;
+    J.n_blocks = o.n_blocks;
+    db.resize((size_t)o.n_blocks);
+    int64_t n_anchors = 0;
+    for (int32_t i = 0; i < o.n_blocks; ++i) {
+        const bbc_dense_block& b = o.blocks[i];
+        const std::string tag = "dense block " + std::to_string(i) + ": ";
+        if (b.n_u_ids < 0 || b.n_v_ids < 0) return fail(ctx, BBC_EINVAL, tag + "negative id count");
+        if ((b.n_u_ids > 0 && !b.u_ids) || (b.n_v_ids > 0 && !b.v_ids)) return fail(ctx, BBC_EINVAL, tag + "NULL ids");
+        const int32_t na = J.s_is_u ? b.n_u_ids : b.n_v_ids, nk = J.s_is_u ? b.n_v_ids : b.n_u_ids;
+        if (na > kMaxAnchors || nk > kMaxCentres)
+            return fail(ctx, BBC_EINVAL, tag + "more than 16384 anchor-side or 65535 centre-side ids");
+        DevBlock& d = db[(size_t)i];
+        d.n_r = d.n_aid = na;
+        d.n_k = d.n_cid = nk;
+        d.aid = J.s_is_u ? b.u_ids : b.v_ids;
+        d.cid = J.s_is_u ? b.v_ids : b.u_ids;
+        d.rpad = (na + kTile - 1) / kTile * kTile;
+        d.kpad = (nk + kK - 1) / kK * kK;
+        n_anchors += na;
+        if (na + nk > J.max_ids) J.max_ids = na + nk;
+    }
+    if (n_anchors > J.n_s) return fail(ctx, BBC_EINVAL, "dense blocks list more anchor-side ids than there are vertices");
+    J.r_first = J.n_s - n_anchors;
+    int64_t rank0 = J.r_first;
+    for (int32_t i = 0; i < o.n_blocks; ++i) {
+        DevBlock& d = db[(size_t)i];
+        d.rank0 = rank0;
+        rank0 += d.n_r;
+        d.mat_off = d.tab_off = 0;
+        if (d.n_r < 2 || d.n_k < 1) continue;  // no anchor pair: no dense wedge
+        d.mat_off = J.mat_bytes;
+        d.tab_off = J.tab_words;
+        J.mat_bytes += (int64_t)d.rpad * d.kpad;
+        J.tab_words += (int64_t)d.rpad * d.rpad;
+        J.dense_ops += 2ull * (uint64_t)d.n_r * (uint64_t)(d.n_r - 1) * (uint64_t)d.n_k;
+        const int32_t t = d.rpad / kTile;
+        for (int32_t ti = 0; ti < t; ++ti)
+            for (int32_t tj = ti; tj < t; ++tj) dt.push_back(DevTile{i, ti, tj, 0});
+    }
+    J.n_tiles = (int32_t)dt.size();
+    return BBC_OK;
+}
+
 // Maps the device status of a finished pass to a return code.
 bbc_status status_result(bbc_ctx* ctx, const DevStatus& h) {
     char buf[160];
@@ -371,6 +480,13 @@ bbc_status status_result(bbc_ctx* ctx, const DevStatus& h) {
         snprintf(buf, sizeof buf, "repeated (u, v) pair at centre-list position %lld", (long long)h.bad_dup);
         return fail(ctx, BBC_EDUP, buf);
     }
+    if (h.flags & kBadBlocks) {
+        snprintf(buf, sizeof buf,
+                 "dense block %lld: id at position %lld (anchor-side ids first) is out of range, repeated or in "
+                 "another block",
+                 (long long)(h.bad_block >> 32), (long long)(h.bad_block & 0xffffffffll));
+        return fail(ctx, BBC_EINVAL, buf);
+    }
     return BBC_OK;
 }
 
@@ -382,8 +498,11 @@ void fill_stats(bbc_ctx* ctx, const Job& J, const DevStatus& h, int block) {
     S.n_anchor = (int32_t)J.n_s;
     S.n_centre = (int32_t)J.n_c;
     S.n_edges = J.m;
-    S.wedges = h.wedges;
+    S.wedges = h.walked;
+    S.wedges_all = h.wedges;
     S.bands = h.bands;
+    S.n_blocks = J.n_blocks;
+    S.dense_ops = J.dense_ops;
     S.grid = J.grid;
     S.block = block;
 }
@@ -394,13 +513,15 @@ bbc_status timed_stats(bbc_ctx* ctx) {
     HIP_OR_FAIL(hipEventElapsedTime(&S.ms_build, ctx->ev[0], ctx->ev[1]));
     HIP_OR_FAIL(hipEventElapsedTime(&S.ms_count, ctx->ev[1], ctx->ev[2]));
     HIP_OR_FAIL(hipEventElapsedTime(&S.ms_total, ctx->ev[3], ctx->ev[2]));
+    if (S.n_blocks > 0) HIP_OR_FAIL(hipEventElapsedTime(&S.ms_dense, ctx->ev[4], ctx->ev[5]));
     return BBC_OK;
 }
 
 // Runs a job on the context's arena and stream and waits for its status.
 bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStream_t s,
                    const std::vector<DevGraph>* dg, const std::vector<int64_t>* vstart,
-                   const std::vector<int64_t>* rend) {
+                   const std::vector<int64_t>* rend, const std::vector<DevBlock>* db = nullptr,
+                   const std::vector<DevTile>* dt = nullptr) {
     Plan P;
     bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, P.carve(nullptr, J));
     if (rc != BBC_OK) return rc;
@@ -410,6 +531,10 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
         HIP_OR_FAIL(hipMemcpyAsync(P.vstart, vstart->data(), vstart->size() * 8, hipMemcpyHostToDevice, s));
         HIP_OR_FAIL(hipMemcpyAsync(P.rank_end, rend->data(), rend->size() * 8, hipMemcpyHostToDevice, s));
     }
+    if (db && !db->empty())
+        HIP_OR_FAIL(hipMemcpyAsync(P.dblocks, db->data(), db->size() * sizeof(DevBlock), hipMemcpyHostToDevice, s));
+    if (dt && !dt->empty())
+        HIP_OR_FAIL(hipMemcpyAsync(P.dtiles, dt->data(), dt->size() * sizeof(DevTile), hipMemcpyHostToDevice, s));
     const bool timing = opts.timing != 0;
     if (timing) HIP_OR_FAIL(hipEventRecord(ctx->ev[3], s));
     enqueue(J, P, ctx->st_dev, s, timing ? ctx->ev : nullptr);
@@ -539,7 +664,14 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     const bool full = per_vertex != nullptr;
     J.grid = ctx->n_cu *
              (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
-    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
+    std::vector<DevBlock> db;
+    std::vector<DevTile> dt;
+    if (opts.n_blocks > 0) {
+        if (full) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with per-vertex counts");
+        rc = block_job(ctx, opts, J, db, dt);
+        if (rc != BBC_OK) return rc;
+    }
+    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr, &db, &dt);
     if (rc != BBC_OK) return rc;
     // per-vertex mode sums every anchor's pairs from both ends
     *total = full ? (uint64_t)ctx->st_host->total / 2 : (uint64_t)ctx->st_host->total;

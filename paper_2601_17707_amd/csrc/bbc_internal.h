@@ -19,6 +19,7 @@ struct DevStatus {
     int64_t bad_block;          // first offending dense-block vertex (block * 2^32 + position)
     unsigned long long total;   // balanced butterflies
     unsigned long long wedges;  // sum over centres of C(deg, 2)
+    unsigned long long walked;  // wedges the sparse walk visits (dense-block wedges excluded)
     unsigned long long bands;   // counter bands processed
     unsigned int queue;         // persistent work queue head
     unsigned int pad1;
@@ -28,11 +29,12 @@ enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8, kBad
 
 // One dense block as the device sees it.
 struct DevBlock {
+    // matrix and table exist only for blocks with n_r >= 2 and n_k >= 1
     int64_t mat_off;  // int8 matrix [rpad][kpad] (anchor rows x centre columns)
-    int64_t tab_off;  // uint32 table [rpad][rpad]: a_dense | b_dense << 16 per anchor pair
+    int64_t tab_off;  // uint32 table [rpad][rpad]: a_dense | b_dense << 16 per anchor pair (u < w)
     int64_t rank0;    // first rank of the block's anchors (they are contiguous)
     int32_t n_r, n_k; // anchors, centres
-    int32_t rpad, kpad;
+    int32_t rpad, kpad;    // padded rows (multiple of 128) and columns (multiple of 64)
     int32_t n_aid, n_cid;  // caller's id counts on the anchor and centre side
     const int32_t* aid;    // anchor-side ids (device)
     const int32_t* cid;    // centre-side ids (device)
@@ -43,14 +45,13 @@ struct DevTile {
     int32_t blk, ti, tj, pad;
 };
 
-// Dense-block data the wedge kernel reads (all null without blocks).
+// Dense-block data the wedge kernel reads (ablk1 is null without blocks).
 struct HybridView {
-    const int32_t* ablk;   // per rank: block of the anchor, or -1
-    const int32_t* abidx;  // per rank: index inside its block
-    const int32_t* cblk;   // per centre id: block, or -1
-    const int32_t* cpos;   // per centre id in a block: list position past the block's anchors
+    const uint32_t* ablk1;  // per rank: block + 1 of the anchor, 0 for none
+    const int32_t* cblk;    // per centre id: block, or -1
+    const int32_t* cpos;    // per centre id of a block: list position past the block's anchors
     const DevBlock* blocks;
-    const uint32_t* tabs;
+    const uint32_t* tabs;   // per block: a_dense | b_dense << 16 for anchor pairs (upper triangle)
 };
 
 // One graph of a batch, as the device sees it.

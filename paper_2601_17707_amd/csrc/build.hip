@@ -176,32 +176,41 @@ __global__ void k_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_
 }
 
 // Per-anchor work: the number of wedges the anchor walks, i.e. the suffix
-// lengths of its centres' lists (ranked-above endpoints).  One wave per
-// anchor.  key = bitwise complement of the clamped work, so an ascending
-// sort orders anchors by descending work (heavy anchors start first, as in
-// the fanout ordering of Algorithm 4).
+// lengths of its centres' lists (ranked-above endpoints; an anchor of a
+// dense block starts past the block's anchors in the block's centres).  One
+// wave per anchor.  key = bitwise complement of the clamped work, so an
+// ascending sort orders anchors by descending work (heavy anchors start
+// first, as in the fanout ordering of Algorithm 4).  st->wedges receives the
+// sum over centres of C(deg, 2), st->walked the wedges the walk visits.
 __global__ __launch_bounds__(256) void k_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back,
-                                              const uint32_t* coff, int32_t n_s, uint32_t* key, DevStatus* st) {
+                                              const uint32_t* coff, int32_t n_s, uint32_t* key, DevStatus* st,
+                                              HybridView hv) {
     if (input_bad(st)) return;
     const int lane = lane_id();
     int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     int64_t nwv = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    unsigned long long all = 0;
+    unsigned long long all = 0, walked = 0;
     for (int64_t r = wv; r < n_s; r += nwv) {
         uint32_t a0 = aoff[r], a1 = aoff[r + 1];
-        unsigned long long w = 0;
+        const int32_t blk = hv.ablk1 ? (int32_t)hv.ablk1[r] - 1 : -1;
+        unsigned long long w = 0, wk = 0;
         for (uint32_t p = a0 + lane; p < a1; p += kWave) {
             int32_t c = acent[p];
-            w += (unsigned long long)(coff[c + 1] - (uint32_t)back[p] - 1u);
+            const uint32_t suffix = coff[c + 1] - (uint32_t)back[p] - 1u;
+            w += suffix;
+            wk += (blk >= 0 && hv.cblk[c] == blk) ? coff[c + 1] - (uint32_t)hv.cpos[c] : suffix;
         }
         w = wave_sum(w);
+        wk = wave_sum(wk);
         if (lane == 0) {
-            uint32_t cl = w > 0xffffffffull ? 0xffffffffu : (uint32_t)w;
+            uint32_t cl = wk > 0xffffffffull ? 0xffffffffu : (uint32_t)wk;
             key[r] = ~cl;
         }
         all += w;
+        walked += wk;
     }
     if (lane == 0 && all) atomicAdd(&st->wedges, all);
+    if (lane == 0 && walked) atomicAdd(&st->walked, walked);
 }
 
 // ------------------------------------------------------------ host launchers
@@ -269,10 +278,10 @@ void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, D
 }
 
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
-                 uint32_t* key, DevStatus* st, hipStream_t s) {
+                 uint32_t* key, DevStatus* st, const HybridView& hv, hipStream_t s) {
     if (n_s > 0)
         hipLaunchKernelGGL(k_work, dim3(grid_for((int64_t)n_s * kWave, 256)), dim3(256), 0, s, aoff, acent, back,
-                           coff, n_s, key, st);
+                           coff, n_s, key, st, hv);
 }
 
 }  // namespace bbc

@@ -1,0 +1,224 @@
+// Dense-block hybrid: the wedges of dense anchor x centre blocks counted on
+// int8 matrix cores.
+//
+// A block is a set R of anchors and a set C of centres; its dense edges are
+// the graph's edges between R and C.  With S the |R| x |C| signed adjacency
+// of those edges (+1, -1, 0 when absent), the wedges u - c - w with both
+// edges dense give, for every anchor pair,
+//     (S S^T)[u][w]     = a - b   (agreeing minus disagreeing wedges)
+//     (|S| |S|^T)[u][w] = a + b
+// so a and b come out of two int8 products with exact int32 accumulation.
+// By Lemma 1 the pair contributes C(a,2) + C(b,2).  The paper counts every
+// wedge through hash maps or shared-memory tiles (Algorithms 2-4); this
+// split is the library's own.  It is exact for any choice of blocks: per
+// pair, with a = a_dense + a_sparse (likewise b),
+//     C(a,2) = C(a_dense,2) + C(a_sparse,2) + a_dense * a_sparse,
+// so the sparse walk skips exactly the dense wedges (an anchor of R walking
+// a centre of C jumps past R's run of that centre's rank-sorted list) and,
+// for endpoint pairs inside R, adds the cross term from a table of
+// (a_dense, b_dense) written here.
+//
+// Layout: each block's anchors take a contiguous rank range at the top of
+// the rank order (ranks by (block, degree, id)); the block matrix is int8,
+// row-major, rows in rank order (padded to 128), columns in the caller's
+// centre order (padded to 64).  |S| is S & 1 per byte, formed in registers.
+// Each workgroup computes one 128 x 128 tile of the upper triangle with
+// v_mfma_i32_32x32x32_i8: four waves, each 64 x 64 (2 x 2 MFMA tiles, two
+// products), operands staged through LDS 64 bytes of K at a time.
+#include "bbc_internal.h"
+
+namespace bbc {
+
+__device__ __forceinline__ void flag_block(DevStatus* st, int64_t idx) {
+    atomicOr(&st->flags, kBadBlocks);
+    atomicMin((unsigned long long*)&st->bad_block, (unsigned long long)idx);
+}
+
+__device__ __forceinline__ bool status_bad(const DevStatus* st) { return *(volatile const int32_t*)&st->flags != 0; }
+
+// Marks the block of every listed anchor (agrp[id] = block + 1) and centre
+// (cblk[id] = block, cidx[id] = position in the block's centre list).  An id
+// out of range, repeated, or listed by two blocks flags kBadBlocks with
+// bad_block = block * 2^32 + position (anchor list first, then centre list
+// positions offset by the anchor count).  agrp starts at 0, cblk at -1.
+__global__ void k_block_mark(const DevBlock* blocks, int32_t n_s, int32_t n_c, uint32_t* agrp, int32_t* cblk,
+                             int32_t* cidx, DevStatus* st) {
+    const int32_t b = blockIdx.y;
+    const DevBlock B = blocks[b];
+    const int64_t tot = (int64_t)B.n_aid + B.n_cid;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < tot; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tag = ((int64_t)b << 32) + p;
+        if (p < B.n_aid) {
+            const int32_t x = B.aid[p];
+            if (x < 0 || x >= n_s || atomicCAS(&agrp[x], 0u, (uint32_t)b + 1u) != 0u) flag_block(st, tag);
+        } else {
+            const int32_t q = (int32_t)(p - B.n_aid);
+            const int32_t c = B.cid[q];
+            if (c < 0 || c >= n_c || atomicCAS(&cblk[c], -1, b) != -1) flag_block(st, tag);
+            else cidx[c] = q;
+        }
+    }
+}
+
+// For each centre of a block: the first position of its list past the
+// block's anchors (their ranks form [rank0, rank0 + n_r)).
+__global__ void k_block_cpos(const int32_t* cblk, int32_t n_c, const DevBlock* blocks, const uint32_t* coff,
+                             const uint32_t* packed, int32_t* cpos, const DevStatus* st) {
+    if (status_bad(st)) return;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_c; c += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = cblk[c];
+        if (b < 0) continue;
+        const uint32_t end_rank = (uint32_t)(blocks[b].rank0 + blocks[b].n_r);
+        uint32_t lo = coff[c], hi = coff[c + 1];
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((packed[mid] >> 1) < end_rank) lo = mid + 1;
+            else hi = mid;
+        }
+        cpos[c] = (int32_t)lo;
+    }
+}
+
+// One wave per block anchor: writes its dense edges into the block matrix
+// (already zeroed): +1 or -1 at (rank - rank0, position of the centre).
+__global__ void k_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s, const DevBlock* blocks,
+                             const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* cblk,
+                             const int32_t* cidx, int8_t* mats, const DevStatus* st) {
+    if (status_bad(st)) return;
+    const int lane = lane_id();
+    const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = r_first + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < n_s; r += nwv) {
+        const int32_t b = (int32_t)ablk1[r] - 1;
+        if (b < 0) continue;
+        const DevBlock B = blocks[b];
+        if (B.n_r < 2 || B.n_k < 1) continue;  // no anchor pair: the block has no matrix
+        int8_t* row = mats + B.mat_off + (r - B.rank0) * (int64_t)B.kpad;
+        for (uint32_t p = aoff[r] + lane; p < aoff[r + 1]; p += kWave) {
+            const int32_t c = acent[p];
+            if (cblk[c] == b) row[cidx[c]] = aneg[p] ? (int8_t)-1 : (int8_t)1;
+        }
+    }
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kDTile = 128;  // output tile edge
+constexpr int kDK = 64;      // K bytes per LDS stage
+constexpr int kDRow = kDK + 16;  // LDS row pitch in bytes (padding spreads banks)
+
+// Output element of accumulator i in lane l of a 32 x 32 MFMA tile: column
+// l % 32, row 8 * (i / 4) + 4 * (l / 32) + i % 4.
+__device__ __forceinline__ int mfma_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
+
+__global__ __launch_bounds__(256) void k_dense(const DevBlock* __restrict__ blocks, const DevTile* __restrict__ tiles,
+                                               const int8_t* __restrict__ mats, uint32_t* __restrict__ tabs,
+                                               DevStatus* st) {
+    if (status_bad(st)) return;
+    __shared__ __align__(16) int8_t As[kDTile * kDRow];
+    __shared__ __align__(16) int8_t Bs[kDTile * kDRow];
+    const DevTile T = tiles[blockIdx.x];
+    const DevBlock B = blocks[T.blk];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int8_t* arow = mats + B.mat_off + (int64_t)T.ti * kDTile * B.kpad;
+    const int8_t* brow = mats + B.mat_off + (int64_t)T.tj * kDTile * B.kpad;
+
+    v16i accD[2][2], accP[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            accD[i][j] = v16i{};
+            accP[i][j] = v16i{};
+        }
+
+    // staging: 128 rows x 64 bytes per matrix = 512 16-byte pieces, two per thread
+    const int lr = tid >> 2, lc = (tid & 3) * 16;
+    for (int k0 = 0; k0 < B.kpad; k0 += kDK) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = lr + 64 * h;
+            *(int4*)&As[r * kDRow + lc] = *(const int4*)&arow[(int64_t)r * B.kpad + k0 + lc];
+            *(int4*)&Bs[r * kDRow + lc] = *(const int4*)&brow[(int64_t)r * B.kpad + k0 + lc];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kDK; ks += 32) {
+            v4i a[2], b[2], aa[2], ba[2];
+            const int kk = ks + 16 * (lane >> 5);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *(const v4i*)&As[(wr * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                b[i] = *(const v4i*)&Bs[(wc * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                aa[i] = a[i] & 0x01010101;
+                ba[i] = b[i] & 0x01010101;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    accD[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], accD[i][j], 0, 0, 0);
+                    accP[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[i], ba[j], accP[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: pair terms of the upper triangle and the (a, b) table
+    unsigned long long acc = 0;
+    uint32_t* tab = tabs + B.tab_off;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int gu = T.ti * kDTile + wr * 64 + i * 32 + mfma_row(e, lane);
+                const int gw = T.tj * kDTile + wc * 64 + j * 32 + (lane & 31);
+                if (gu < gw && gw < B.n_r) {
+                    const int32_t P = accP[i][j][e], D = accD[i][j][e];
+                    const unsigned long long a = (uint32_t)(P + D) >> 1, b = (uint32_t)(P - D) >> 1;
+                    acc += a * (a - (a > 0)) / 2 + b * (b - (b > 0)) / 2;
+                    tab[(int64_t)gu * B.rpad + gw] = (uint32_t)a | ((uint32_t)b << 16);
+                }
+            }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(&st->total, acc);
+}
+
+// ------------------------------------------------------------ host launchers
+
+void launch_block_mark(const DevBlock* blocks, int32_t n_blocks, int64_t max_ids, int32_t n_s, int32_t n_c,
+                       uint32_t* agrp, int32_t* cblk, int32_t* cidx, DevStatus* st, hipStream_t s) {
+    if (n_blocks <= 0 || max_ids <= 0) return;
+    int64_t g = (max_ids + 255) / 256;
+    hipLaunchKernelGGL(k_block_mark, dim3((unsigned)(g > 1024 ? 1024 : g), (unsigned)n_blocks), dim3(256), 0, s,
+                       blocks, n_s, n_c, agrp, cblk, cidx, st);
+}
+
+void launch_block_cpos(const int32_t* cblk, int32_t n_c, const DevBlock* blocks, const uint32_t* coff,
+                       const uint32_t* packed, int32_t* cpos, const DevStatus* st, hipStream_t s) {
+    if (n_c <= 0) return;
+    int64_t g = ((int64_t)n_c + 255) / 256;
+    hipLaunchKernelGGL(k_block_cpos, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, s, cblk, n_c, blocks, coff,
+                       packed, cpos, st);
+}
+
+void launch_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s, const DevBlock* blocks,
+                       const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* cblk,
+                       const int32_t* cidx, int8_t* mats, const DevStatus* st, hipStream_t s) {
+    const int64_t rows = (int64_t)n_s - r_first;
+    if (rows <= 0) return;
+    int64_t g = (rows * kWave + 255) / 256;
+    hipLaunchKernelGGL(k_block_pack, dim3((unsigned)(g > 8192 ? 8192 : g)), dim3(256), 0, s, ablk1, r_first, n_s,
+                       blocks, aoff, acent, aneg, cblk, cidx, mats, st);
+}
+
+void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles, const int8_t* mats, uint32_t* tabs,
+                  DevStatus* st, hipStream_t s) {
+    if (n_tiles > 0)
+        hipLaunchKernelGGL(k_dense, dim3((unsigned)n_tiles), dim3(256), 0, s, blocks, tiles, mats, tabs, st);
+}
+
+}  // namespace bbc

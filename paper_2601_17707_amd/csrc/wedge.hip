@@ -122,6 +122,16 @@ __host__ __device__ constexpr uint32_t band_capacity() {
 // power-of-two capacity.
 constexpr uint32_t kSlotMul = 0x9E3779u;  // < 2^24: a full-rate 24-bit multiply
 
+// Inverse of an odd number modulo 2^32 (Newton iteration; each step doubles
+// the number of correct low bits).
+constexpr uint32_t inverse_odd(uint32_t m) {
+    uint32_t x = m;  // correct to 3 bits
+    for (int i = 0; i < 5; ++i) x *= 2u - m * x;
+    return x;
+}
+constexpr uint32_t kSlotInv = inverse_odd(kSlotMul);
+static_assert(kSlotMul * kSlotInv == 1u, "slot scatter must be invertible");
+
 // LDS word and increment for endpoint slot `slot` (rank - band start) and
 // wedge type t (0 = signs agree, 1 = disagree).
 template <int MODE, int BAND_WORDS>
@@ -141,6 +151,49 @@ __device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& w
         word = (slot << 1) + t;
         inc = 1u;
     }
+}
+
+// The dense-block table row of an anchor inside a block (row == null
+// otherwise): entries for endpoint ranks rank0 .. rank0 + n_r - 1.
+struct CrossRow {
+    const uint32_t* row;
+    int64_t rank0;
+    int64_t n_r;
+};
+
+// Cross term a_dense * a_sparse + b_dense * b_sparse of every counter field
+// of word wd (value v) whose endpoint lies in the anchor's block: the slot
+// of a field is recovered by inverting the scatter.
+template <int MODE, int BAND_WORDS>
+__device__ __forceinline__ unsigned long long cross_term(uint32_t wd, uint32_t v, int64_t lo, const CrossRow& cr) {
+    constexpr uint32_t mask = band_capacity<MODE, BAND_WORDS>() - 1u;
+    unsigned long long acc = 0;
+    if constexpr (MODE == 3) {  // word = slot * 2 + type
+        const uint32_t slot = ((wd >> 1) * kSlotInv) & mask;
+        const int64_t i = lo + slot - cr.rank0;
+        if ((uint64_t)i < (uint64_t)cr.n_r) {
+            const uint32_t t = cr.row[i];
+            acc = (unsigned long long)v * ((wd & 1u) ? (t >> 16) : (t & 0xffffu));
+        }
+    } else {
+        constexpr int F = MODE == 0 ? 4 : MODE == 1 ? 2 : 1;     // slots per word
+        constexpr int FB = MODE == 0 ? 8 : MODE == 1 ? 16 : 32;  // bits per slot: a, then b
+        constexpr uint32_t fm = (1u << (FB / 2)) - 1u;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const uint32_t x = v >> (f * FB);
+            const uint32_t a = x & fm, b = (x >> (FB / 2)) & fm;
+            if (a | b) {
+                const uint32_t slot = ((wd * (uint32_t)F + (uint32_t)f) * kSlotInv) & mask;
+                const int64_t i = lo + slot - cr.rank0;
+                if ((uint64_t)i < (uint64_t)cr.n_r) {
+                    const uint32_t t = cr.row[i];
+                    acc += (unsigned long long)a * (t & 0xffffu) + (unsigned long long)b * (t >> 16);
+                }
+            }
+        }
+    }
+    return acc;
 }
 
 constexpr int kUnroll = 8;
@@ -170,12 +223,15 @@ template <bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                                              const int32_t* __restrict__ acent, const uint8_t* __restrict__ aneg,
                                              const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
-                                             int32_t a0, int32_t k0, int32_t nk) {
+                                             int32_t a0, int32_t k0, int32_t nk, int32_t blk, const HybridView& hv) {
     const int tid = threadIdx.x;
     if (tid < nk) {
         const int32_t p = a0 + k0 + tid;
         const int32_t c = acent[p];
-        const uint32_t start = FULL ? coff[c] : (uint32_t)(back[p] + 1);
+        uint32_t start = FULL ? coff[c] : (uint32_t)(back[p] + 1);
+        // an anchor of a dense block skips the block's anchors in the lists
+        // of the block's centres (those wedges are counted on matrix cores)
+        if (!FULL && blk >= 0 && hv.cblk[c] == blk) start = (uint32_t)hv.cpos[c];
         sh.c_cur[tid] = start | ((uint32_t)aneg[p] << 31);
         sh.c_ce[tid] = (int32_t)coff[c + 1];
         if constexpr (FULL) {
@@ -345,10 +401,13 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
 // Sum of the pair terms of every touched counter word, and clears them.
 // Slots are scattered over the whole band capacity, so the bitmap is
 // scanned in full (BAND_WORDS / 32 words).  In per-vertex mode the anchor's
-// own slot (w = u), if in [lo, hi), is left out.  Ends with a barrier.
+// own slot (w = u), if in [lo, hi), is left out.  For an anchor of a dense
+// block the cross term of endpoints in the same block is added.  Ends with
+// a barrier.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, int64_t lo,
-                                                          int64_t hi, int32_t self) {
+                                                          int64_t hi, int32_t self, const CrossRow& cr) {
+    const bool cross = cr.row && lo < cr.rank0 + cr.n_r && hi > cr.rank0;
     uint32_t sw0 = 0xffffffffu, sm0 = 0, sw1 = 0xffffffffu, sm1 = 0;
     if constexpr (FULL) {
         if ((int64_t)self >= lo && (int64_t)self < hi) {
@@ -376,6 +435,7 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
                     if (wd == sw1) v &= ~sm1;
                 }
                 if (has_pairs<MODE>(v)) acc += word_pairs<MODE>(v);
+                if (cross) acc += cross_term<MODE, BAND_WORDS>(wd, v, lo, cr);
             }
         }
     }
@@ -394,19 +454,30 @@ __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh
                                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
                                            int32_t a0, int32_t deg, int32_t r, int64_t n_s,
                                            unsigned long long* __restrict__ pv, int64_t centre_base,
-                                           unsigned long long& bands) {
+                                           unsigned long long& bands, const HybridView& hv) {
     constexpr int64_t band_slots = band_capacity<MODE, BAND_WORDS>();
     const int64_t lo0 = FULL ? 0 : (int64_t)r + 1;
     unsigned long long acc = 0;
+    int32_t blk = -1;
+    CrossRow cr{nullptr, 0, 0};
+    if (!FULL && hv.ablk1) {
+        blk = (int32_t)hv.ablk1[r] - 1;
+        const DevBlock& B = hv.blocks[blk < 0 ? 0 : blk];
+        if (blk >= 0 && B.n_r >= 2 && B.n_k >= 1) {  // blocks without an anchor pair have no table
+            cr.rank0 = B.rank0;
+            cr.n_r = B.n_r;
+            cr.row = hv.tabs + B.tab_off + (int64_t)(r - B.rank0) * B.rpad;
+        }
+    }
     if (deg <= WG) {
-        load_centres<FULL>(sh, acent, aneg, back, coff, a0, 0, deg);
+        load_centres<FULL>(sh, acent, aneg, back, coff, a0, 0, deg, blk, hv);
         __syncthreads();
         for (int64_t lo = lo0; lo < n_s; lo += band_slots) {
             const int64_t hi = min(n_s, lo + band_slots);
             walk_band<MODE, FULL>(sh, packed, deg, lo, hi, false, hi == n_s, r, FULL ? 3 : 1);
             if (threadIdx.x < deg)
                 sh.c_cur[threadIdx.x] = (uint32_t)sh.c_end[threadIdx.x] | (sh.c_cur[threadIdx.x] & 0x80000000u);
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr);
             ++bands;
         }
         if constexpr (FULL) {
@@ -419,7 +490,7 @@ __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh
             const bool first = lo == lo0;
             for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                 const int32_t nk = min(WG, deg - k0);
-                load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk);
+                load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk, blk, hv);
                 __syncthreads();
                 walk_band<MODE, FULL>(sh, packed, nk, lo, hi, !first, hi == n_s, r, 1);
             }
@@ -427,14 +498,14 @@ __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh
                 // second pass over the chunks once every wedge of the band is counted
                 for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                     const int32_t nk = min(WG, deg - k0);
-                    load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk);
+                    load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk, blk, hv);
                     __syncthreads();
                     walk_band<MODE, FULL>(sh, packed, nk, lo, hi, !first, hi == n_s, r, 2);
                     if (threadIdx.x < nk && sh.c_sum[threadIdx.x])
                         atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
                 }
             }
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr);
             ++bands;
         }
     }
@@ -453,7 +524,7 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
                                               int64_t anchor_base, int64_t centre_base,
                                               const int32_t* __restrict__ agraph,
                                               const int64_t* __restrict__ rank_end,
-                                              unsigned long long* __restrict__ gtotals) {
+                                              unsigned long long* __restrict__ gtotals, HybridView hv) {
     if (*(volatile const int32_t*)&st->flags) return;  // input error: nothing to count
     __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
@@ -473,13 +544,17 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
         if (deg < 2 || (!FULL && r >= n_end - 1)) continue;
         unsigned long long a;
         if (deg <= 15)
-            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
+            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
+                                        hv);
         else if (deg <= 255)
-            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
+            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
+                                        hv);
         else if (deg <= 65535)
-            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
+            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
+                                        hv);
         else
-            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands);
+            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
+                                        hv);
         if constexpr (FULL) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
             if (tid == 0) pv[anchor_base + inv[r]] = s;
@@ -548,10 +623,10 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
-                  unsigned long long* gtotals, hipStream_t s) {
+                  unsigned long long* gtotals, const HybridView& hv, hipStream_t s) {
 #define BBC_LAUNCH(W, B, F)                                                                                      \
     hipLaunchKernelGGL((k_wedge<W, B, F>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, order, \
-                       n_s, st, pv, inv, anchor_base, centre_base, agraph, rank_end, gtotals)
+                       n_s, st, pv, inv, anchor_base, centre_base, agraph, rank_end, gtotals, hv)
     if (pv) {
         BBC_LAUNCH(kFullWG, kFullBW, true);
         if (n_centre > 0) {
