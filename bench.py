@@ -10,8 +10,9 @@ Prints one JSON line.  value = wedges/s, where the wedges are
 sum over centres c of C(deg c, 2): every wedge u - c - w with w ranked above
 u, walked exactly once.  The line also carries the batched measurement
 (graphs/s of 10,000 graphs of uneven size, one captured batch plan, against
-a loop of plain per-graph calls), the roofline of the wedge kernel and the
-CPU oracle's rate.
+a loop of plain per-graph calls), the dense-block workload (hybrid int8
+matrix-core path against the sparse-only path), the roofline of the wedge
+kernel and the CPU oracle's rate.
 """
 from __future__ import annotations
 
@@ -25,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "powerlaw-1m-500k-20m"
+HYBRID_WORKLOAD = "hybrid-2m-1m-50m-16x4096"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix throughput, 5.0 POPS
 
 
 def algorithmic_bytes(stats: dict) -> int:
@@ -112,6 +115,61 @@ def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
                 totals_match_loop=bool(list(totals) == loop), balanced_butterflies=int(totals.sum()))
 
 
+def bench_hybrid(ctx, steps: int, warmup: int, seed: int) -> dict:
+    """The planted-block workload (power-law background, |U| = 2e6, |V| = 1e6,
+    5e7 background edges, 16 blocks of 4096 x 4096 at density 0.5) counted
+    with its blocks on int8 matrix cores, against the sparse-only path on the
+    same resident graph.  Both totals must agree.  Effective wedges/s counts
+    every wedge (dense ones included); the dense kernel's rate is int8
+    operations (2 products x 2 ops per multiply-add, upper triangle) per
+    second of its HIP-event duration."""
+    import torch
+
+    from paper_2601_17707_amd import bbc, synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    g = synth.workload(HYBRID_WORKLOAD, seed)
+    gen_s = time.perf_counter() - t0
+    print(f"# {HYBRID_WORKLOAD}: n_u={g.n_u} n_v={g.n_v} m={g.m} (generated in {gen_s:.1f} s)", file=sys.stderr,
+          flush=True)
+    off, adj, sg = bbc.graph_tensors(g, dev)
+    blocks = [(torch.from_numpy(c).to(dev), torch.from_numpy(r).to(dev)) for r, c in g.meta["blocks"]]
+    opts_h, opts_ht = bbc.options(blocks=blocks), bbc.options(blocks=blocks, timing=True)
+    opts_s = bbc.options()
+
+    def timed_calls(opts, n):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            tot = ctx.count(off, adj, sg, g.n_v, opts=opts)
+        torch.cuda.synchronize()
+        return tot, 1000.0 * (time.perf_counter() - t) / n
+
+    for _ in range(max(1, warmup)):
+        ctx.count(off, adj, sg, g.n_v, opts=opts_h)
+    total_h, ms_h = timed_calls(opts_h, steps)
+    dense_ms, count_ms = [], []
+    for _ in range(3):
+        ctx.count(off, adj, sg, g.n_v, opts=opts_ht)
+        st = ctx.stats()
+        dense_ms.append(st["ms_dense"])
+        count_ms.append(st["ms_count"])
+    ops = int(st["dense_ops"])
+    dms = sum(dense_ms) / len(dense_ms)
+    ctx.count(off, adj, sg, g.n_v, opts=opts_s)
+    total_s, ms_s = timed_calls(opts_s, max(1, min(steps, 3)))
+    tops = ops / (dms / 1e3) / 1e12
+    return dict(workload=HYBRID_WORKLOAD, seed=seed, n_u=g.n_u, n_v=g.n_v, n_edges=g.m, blocks="16 x (4096 x 4096)",
+                wedges=int(st["wedges_all"]), wedges_sparse_walk=int(st["wedges"]),
+                ms_per_call=ms_h, ms_per_call_sparse_only=ms_s, speedup_vs_sparse_only=ms_s / ms_h,
+                effective_wedges_per_s=int(st["wedges_all"]) / (ms_h / 1e3) / 1e9, unit="G/s",
+                count_ms=sum(count_ms) / len(count_ms),
+                dense=dict(kernel="k_dense", ms=dms, int8_ops=ops, achieved=tops, peak=INT8_PEAK_TOPS, unit="TOP/s",
+                           frac=tops / INT8_PEAK_TOPS, bound="mfma"),
+                balanced_butterflies=total_h, totals_match_sparse_only=bool(total_h == total_s))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +179,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-graph batch measurement")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the dense-block workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -206,6 +265,9 @@ def main():
     )
     if not args.no_batch and args.workload == WORKLOAD:
         line["batched"] = bench_batched(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
+    if not args.no_hybrid and args.workload == WORKLOAD:
+        del off, adj, sg
+        line["hybrid"] = bench_hybrid(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wedges)
     ctx.close()

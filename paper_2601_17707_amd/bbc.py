@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libbbc.so")
 OK, EINVAL, EOFFSETS, ERANGE, ESIGN, EDUP, ENOMEM, EDEVICE, ETOOBIG = range(9)
 SIDE_AUTO, SIDE_U, SIDE_V = 0, 1, 2
 CHECK_SIGNS, CHECK_DUPLICATES, CHECK_ALL = 1, 2, 3
+# instantiated wedge-kernel shapes (band_words, wg_size); the first is the default
+WEDGE_SHAPES = [(16384, 512), (16384, 256), (8192, 256), (8192, 512), (32768, 1024), (16384, 1024)]
 _SIDES = {"auto": SIDE_AUTO, "u": SIDE_U, "v": SIDE_V, SIDE_AUTO: SIDE_AUTO, SIDE_U: SIDE_U, SIDE_V: SIDE_V}
 
 
@@ -47,6 +49,7 @@ class Options(ctypes.Structure):
         ("wg_per_cu", ctypes.c_int32),
         ("n_blocks", ctypes.c_int32),
         ("blocks", ctypes.POINTER(DenseBlock)),
+        ("no_tuning", ctypes.c_int32),
     ]
 
 
@@ -79,6 +82,8 @@ class Stats(ctypes.Structure):
         ("n_blocks", ctypes.c_int32),
         ("dense_ops", ctypes.c_uint64),
         ("wedges_all", ctypes.c_uint64),
+        ("band_words", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -124,6 +129,12 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_status_string.restype = ctypes.c_char_p
     lib.bbc_last_error.argtypes = [vp]
     lib.bbc_last_error.restype = ctypes.c_char_p
+    lib.bbc_autotune.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, ctypes.POINTER(Options), vp]
+    lib.bbc_autotune.restype = ctypes.c_int
+    lib.bbc_tune_save.argtypes = [vp, ctypes.c_char_p]
+    lib.bbc_tune_save.restype = ctypes.c_int
+    lib.bbc_tune_load.argtypes = [vp, ctypes.c_char_p]
+    lib.bbc_tune_load.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -133,7 +144,7 @@ def status_string(status: int) -> str:
 
 
 def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0,
-            blocks=None) -> Options:
+            blocks=None, no_tuning=False) -> Options:
     """Options struct.  ``blocks``: list of (u_ids, v_ids) int32 device
     tensors naming dense blocks (kept alive by the returned object)."""
     o = Options()
@@ -144,6 +155,7 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
     o.band_words = band_words
     o.wg_size = wg_size
     o.wg_per_cu = wg_per_cu
+    o.no_tuning = 1 if no_tuning else 0
     if blocks:
         arr = (DenseBlock * len(blocks))()
         for i, (uids, vids) in enumerate(blocks):
@@ -248,6 +260,31 @@ class Context:
         if st != OK:
             raise BbcError(st, self.last_error())
         return batch.totals
+
+    def autotune(self, offsets, adj, signs, n_v: int, reps: int = 2, stream=None) -> dict:
+        """Times every wedge-kernel shape on this calibration graph and
+        records the fastest for its size class; returns the chosen shape."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        chosen = Options()
+        st = self._lib.bbc_autotune(self._h, offsets.numel() - 1, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj),
+                                    _ptr(signs), int(reps), ctypes.byref(chosen), _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return dict(band_words=chosen.band_words, wg_size=chosen.wg_size, wg_per_cu=chosen.wg_per_cu)
+
+    def tune_save(self, path: str):
+        st = self._lib.bbc_tune_save(self._h, os.fsencode(path))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+
+    def tune_load(self, path: str):
+        st = self._lib.bbc_tune_load(self._h, os.fsencode(path))
+        if st != OK:
+            raise BbcError(st, self.last_error())
 
     def plan(self, batch: "Batch", opts: Options | None = None) -> "BatchPlan":
         return BatchPlan(self, batch, opts)

@@ -41,6 +41,9 @@ void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles,
 bool wedge_shape_ok(int band_words, int wg);
 int wedge_block(int band_words, int wg, bool full);
 int wedge_blocks_per_cu(int band_words, int wg, bool full);
+int wedge_band(int band_words, int wg, bool full);
+int wedge_shape_count();
+void wedge_shape(int i, int* wg, int* band_words);
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
@@ -58,6 +61,13 @@ __global__ void k_status_init(DevStatus* st) {
         st->queue = 0;
     }
 }
+// One entry of the tuning table: the fastest wedge-kernel shape measured
+// for a size class (bit lengths of n_S and of m / n_S).
+struct TuneEntry {
+    int32_t ns_bits, deg_bits;
+    int32_t band_words, wg_size, wg_per_cu;
+    float ms;
+};
 }  // namespace bbc
 
 using namespace bbc;
@@ -72,6 +82,7 @@ struct bbc_ctx {
     hipEvent_t ev[6] = {};  // [checks, build, count, start, dense start, dense end]
     bbc_stats stats = {};
     std::string err;
+    std::vector<TuneEntry> tune;
 };
 
 struct bbc_batch_plan {
@@ -147,6 +158,7 @@ struct Job {
     int64_t m = 0, n_s = 0, n_c = 0;
     uint32_t checks = BBC_CHECK_ALL;
     int band_words = 0, wg_size = 0, grid = 0;
+    bool tuned = false;  // shape taken from the tuning table
     // dense blocks (single graph only)
     int32_t n_blocks = 0, n_tiles = 0;
     int64_t r_first = 0;  // first rank of the block anchors (they sit at the top)
@@ -359,11 +371,42 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
 
 bool side_is_u(int side, int32_t n_u, int32_t n_v) { return side == BBC_SIDE_U || (side == BBC_SIDE_AUTO && n_u < n_v); }
 
+void tune_class(int64_t n_s, int64_t m, int32_t* ns_bits, int32_t* deg_bits) {
+    *ns_bits = bits_for((uint64_t)(n_s > 0 ? n_s : 0));
+    *deg_bits = bits_for((uint64_t)(m / (n_s > 0 ? n_s : 1)));
+}
+
+// Fills the kernel shape from the tuning table when the options leave it
+// open.  Returns whether an entry was used.
+bool apply_tuning(const bbc_ctx* ctx, bbc_options& o, int64_t n_s, int64_t m, bool full) {
+    if (o.no_tuning || full || o.band_words || o.wg_size || o.wg_per_cu) return false;
+    int32_t a, b;
+    tune_class(n_s, m, &a, &b);
+    for (const TuneEntry& e : ctx->tune)
+        if (e.ns_bits == a && e.deg_bits == b) {
+            o.band_words = e.band_words;
+            o.wg_size = e.wg_size;
+            o.wg_per_cu = e.wg_per_cu;
+            return true;
+        }
+    return false;
+}
+
+void tune_store(bbc_ctx* ctx, const TuneEntry& e) {
+    for (TuneEntry& x : ctx->tune)
+        if (x.ns_bits == e.ns_bits && x.deg_bits == e.deg_bits) {
+            x = e;
+            return;
+        }
+    ctx->tune.push_back(e);
+}
+
 // Validates a batch on the host and fills the job and device descriptors.
 bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, const int32_t* off_cat,
-                     const int32_t* adj_cat, const int8_t* sg_cat, uint64_t* totals, const bbc_options& o, Job& J,
+                     const int32_t* adj_cat, const int8_t* sg_cat, uint64_t* totals, const bbc_options& o_in, Job& J,
                      std::vector<DevGraph>& dg, std::vector<int64_t>& vstart, std::vector<int64_t>& rend) {
     if (n_graphs < 0) return fail(ctx, BBC_EINVAL, "negative n_graphs");
+    bbc_options o = o_in;
     if (o.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks apply to bbc_count only");
     if (n_graphs > 0 && (!d || !off_cat || !totals)) return fail(ctx, BBC_EINVAL, "batch pointer is NULL");
     dg.resize((size_t)n_graphs);
@@ -406,6 +449,7 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
     J.n_s = ns;
     J.n_c = nc;
     J.checks = o.checks;
+    J.tuned = apply_tuning(ctx, o, ns, m, false);
     J.band_words = o.band_words;
     J.wg_size = o.wg_size;
     J.grid = ctx->n_cu * (o.wg_per_cu > 0 ? o.wg_per_cu : wedge_blocks_per_cu(o.band_words, o.wg_size, false));
@@ -505,6 +549,8 @@ void fill_stats(bbc_ctx* ctx, const Job& J, const DevStatus& h, int block) {
     S.dense_ops = J.dense_ops;
     S.grid = J.grid;
     S.block = block;
+    S.band_words = wedge_band(J.band_words, J.wg_size, J.pv != nullptr);
+    S.tuned = J.tuned ? 1 : 0;
 }
 
 bbc_status timed_stats(bbc_ctx* ctx) {
@@ -543,7 +589,7 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rc = status_result(ctx, *ctx->st_host);
     if (rc != BBC_OK) return rc;
-    fill_stats(ctx, J, *ctx->st_host, wedge_block(opts.band_words, opts.wg_size, J.pv != nullptr));
+    fill_stats(ctx, J, *ctx->st_host, wedge_block(J.band_words, J.wg_size, J.pv != nullptr));
     return timing ? timed_stats(ctx) : BBC_OK;
 }
 
@@ -659,9 +705,10 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     J.n_s = J.s_is_u ? n_u : n_v;
     J.n_c = J.s_is_u ? n_v : n_u;
     J.checks = opts.checks;
+    const bool full = per_vertex != nullptr;
+    J.tuned = apply_tuning(ctx, opts, J.n_s, n_edges, full);
     J.band_words = opts.band_words;
     J.wg_size = opts.wg_size;
-    const bool full = per_vertex != nullptr;
     J.grid = ctx->n_cu *
              (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
     std::vector<DevBlock> db;
@@ -779,6 +826,106 @@ bbc_status bbc_batch_wait(bbc_batch_plan* p, void* stream) {
     HIP_OR_FAIL(hipMemcpyAsync(p->st_host, p->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     return status_result(ctx, *p->st_host);
+}
+
+bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                        const int32_t* adj, const int8_t* signs, int32_t reps, bbc_options* chosen, void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    if (reps <= 0) reps = 2;
+    uint64_t total = 0, first = 0;
+    TuneEntry best{0, 0, 0, 0, 0, 0.f};
+    bool have = false, counted = false;
+    const int n_shapes = wedge_shape_count();
+    for (int i = 0; i < n_shapes; ++i) {
+        int wg, bw;
+        wedge_shape(i, &wg, &bw);
+        const int occ = wedge_blocks_per_cu(bw, wg, false);
+        for (int wpc = 1; wpc <= occ; ++wpc) {
+            if (wpc > 2 && wpc < occ) continue;  // 1, 2 and as many as fit
+            bbc_options o;
+            bbc_options_init(&o);
+            o.band_words = bw;
+            o.wg_size = wg;
+            o.wg_per_cu = wpc;
+            o.timing = 1;
+            o.no_tuning = 1;
+            float ms = 0.f;
+            for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
+                bbc_status rc = bbc_count(ctx, n_u, n_v, n_edges, offsets, adj, signs, &total, nullptr, &o, stream);
+                if (rc != BBC_OK) return rc;
+                if (!counted) {
+                    first = total;
+                    counted = true;
+                } else if (total != first) {
+                    return fail(ctx, BBC_EDEVICE, "autotune: kernel shapes disagree on the count");
+                }
+                if (r > 0 && (r == 1 || ctx->stats.ms_count < ms)) ms = ctx->stats.ms_count;
+            }
+            if (!have || ms < best.ms) {
+                best = TuneEntry{0, 0, bw, wg, wpc, ms};
+                have = true;
+            }
+        }
+    }
+    const bool su = side_is_u(BBC_SIDE_AUTO, n_u, n_v);
+    tune_class(su ? n_u : n_v, n_edges, &best.ns_bits, &best.deg_bits);
+    tune_store(ctx, best);
+    if (chosen) {
+        bbc_options_init(chosen);
+        chosen->band_words = best.band_words;
+        chosen->wg_size = best.wg_size;
+        chosen->wg_per_cu = best.wg_per_cu;
+    }
+    return BBC_OK;
+}
+
+bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path) {
+    if (!ctx || !path) return BBC_EINVAL;
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(const_cast<bbc_ctx*>(ctx), BBC_EINVAL, std::string("cannot write ") + path);
+    bool ok = fprintf(f, "bbc-tune 1 gfx950\n") > 0;
+    for (const TuneEntry& e : ctx->tune)
+        ok = ok && fprintf(f, "%d %d %d %d %d %.4f\n", e.ns_bits, e.deg_bits, e.band_words, e.wg_size, e.wg_per_cu,
+                           (double)e.ms) > 0;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? BBC_OK : fail(const_cast<bbc_ctx*>(ctx), BBC_EINVAL, std::string("write failed: ") + path);
+}
+
+bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path) {
+    if (!ctx || !path) return BBC_EINVAL;
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(ctx, BBC_EINVAL, std::string("cannot read ") + path);
+    char line[256];
+    std::vector<TuneEntry> got;
+    int ln = 0;
+    bbc_status rc = BBC_OK;
+    while (fgets(line, sizeof line, f)) {
+        ++ln;
+        if (ln == 1) {
+            if (strcmp(line, "bbc-tune 1 gfx950\n") != 0 && strcmp(line, "bbc-tune 1 gfx950") != 0) {
+                rc = fail(ctx, BBC_EINVAL, std::string(path) + ":1: not a tuning file for gfx950");
+                break;
+            }
+            continue;
+        }
+        TuneEntry e;
+        double ms = 0;
+        char extra = 0;
+        int n = sscanf(line, "%d %d %d %d %d %lf %c", &e.ns_bits, &e.deg_bits, &e.band_words, &e.wg_size, &e.wg_per_cu,
+                       &ms, &extra);
+        if (n != 6 || e.ns_bits < 0 || e.ns_bits > 64 || e.deg_bits < 0 || e.deg_bits > 64 || e.wg_per_cu < 0 ||
+            e.band_words <= 0 || e.wg_size <= 0 || !wedge_shape_ok(e.band_words, e.wg_size)) {
+            rc = fail(ctx, BBC_EINVAL, std::string(path) + ":" + std::to_string(ln) + ": malformed tuning entry");
+            break;
+        }
+        e.ms = (float)ms;
+        got.push_back(e);
+    }
+    if (rc == BBC_OK && ln == 0) rc = fail(ctx, BBC_EINVAL, std::string(path) + ": empty file");
+    fclose(f);
+    if (rc != BBC_OK) return rc;
+    for (const TuneEntry& e : got) tune_store(ctx, e);
+    return BBC_OK;
 }
 
 }  // extern "C"

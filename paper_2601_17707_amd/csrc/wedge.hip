@@ -599,6 +599,17 @@ bool wedge_shape_ok(int band_words, int wg) { return shape_index(band_words, wg)
 
 int wedge_block(int band_words, int wg, bool full) { return full ? kFullWG : kShapes[shape_index(band_words, wg)].wg; }
 
+int wedge_band(int band_words, int wg, bool full) {
+    return full ? kFullBW : kShapes[shape_index(band_words, wg)].band_words;
+}
+
+int wedge_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
+
+void wedge_shape(int i, int* wg, int* band_words) {
+    *wg = kShapes[i].wg;
+    *band_words = kShapes[i].band_words;
+}
+
 template <int WG, int BW, bool FULL>
 static int occupancy() {
     int n = 0;
