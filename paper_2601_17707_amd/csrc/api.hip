@@ -18,6 +18,7 @@ void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const
                            const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
                            uint32_t* ea, uint32_t* ec, uint8_t* en, hipStream_t s);
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st, hipStream_t s);
+void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
@@ -38,6 +39,9 @@ void launch_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s, cons
                        const int32_t* cidx, int8_t* mats, const DevStatus* st, hipStream_t s);
 void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles, const int8_t* mats, uint32_t* tabs,
                   DevStatus* st, hipStream_t s);
+void launch_bidx(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int64_t n_c, int gs,
+                 uint32_t* nb, uint32_t* ioff, uint32_t* idx, int2* meta, uint32_t* partials, const DevStatus* st,
+                 hipStream_t s);
 bool wedge_shape_ok(int band_words, int wg);
 int wedge_block(int band_words, int wg, bool full);
 int wedge_blocks_per_cu(int band_words, int wg, bool full);
@@ -45,7 +49,8 @@ int wedge_band(int band_words, int wg, bool full);
 int wedge_shape_count();
 void wedge_shape(int i, int* wg, int* band_words);
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
-                  const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
+                  const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* bidx,
+                  const int2* bmeta, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
                   unsigned long long* gtotals, const HybridView& hv, hipStream_t s);
@@ -188,6 +193,8 @@ struct Plan {
     DevTile* dtiles;
     int8_t* mats;
     uint32_t* tabs;
+    uint32_t *bnb, *bioff, *bidx;  // band-boundary index of the centre lists
+    int2* bmeta;
 
     size_t carve(char* base, const Job& J) {
         Carve c(base);
@@ -240,6 +247,11 @@ struct Plan {
         dtiles = c.take<DevTile>(J.n_tiles);
         mats = c.take<int8_t>(J.mat_bytes);
         tabs = c.take<uint32_t>(J.tab_words);
+        const bool idx = J.pv == nullptr;
+        bnb = c.take<uint32_t>(idx ? n_c : 0);
+        bioff = c.take<uint32_t>(idx ? n_c + 1 : 0);
+        bidx = c.take<uint32_t>(idx ? m : 0);
+        bmeta = c.take<int2>(idx ? n_c : 0);
         return c.used;
     }
 };
@@ -270,10 +282,18 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
 
     // degrees and ranks (Definition 6: degree, then id; ascending; a batch
     // orders by graph first)
-    fill_u32(P.deg_s, 0u, n_s, s);
-    fill_u32(P.deg_c, 0u, n_c, s);
-    launch_hist(ea, m, P.deg_s, st, s);
-    launch_hist(ec, m, P.deg_c, st, s);
+    if (J.batched) {
+        fill_u32(P.deg_s, 0u, n_s, s);
+        fill_u32(P.deg_c, 0u, n_c, s);
+        launch_hist(ea, m, P.deg_s, st, s);
+        launch_hist(ec, m, P.deg_c, st, s);
+    } else {  // the U side's degrees are the CSR row lengths
+        uint32_t* deg_u = J.s_is_u ? P.deg_s : P.deg_c;
+        uint32_t* deg_v = J.s_is_u ? P.deg_c : P.deg_s;
+        launch_row_degrees(J.off, J.n_u, deg_u, st, s);
+        fill_u32(deg_v, 0u, J.n_v, s);
+        launch_hist(J.s_is_u ? ec : ea, m, deg_v, st, s);
+    }
     const uint32_t *rk_k = nullptr, *inv = nullptr;
     radix_sort(P.deg_s, P.rk_ka, P.rk_kb, nullptr, nullptr, nullptr, nullptr, P.rk_va, P.rk_vb, n_s,
                bits_for((uint64_t)(m > 0 ? m : 1)), P.hist, P.hist_scan, P.partials, s, &rk_k, nullptr, &inv);
@@ -305,6 +325,11 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     scan_exclusive_u32(P.deg_c, P.coff, n_c, P.partials, s);
     launch_back(perm, m, P.back, s);
     if (J.checks & BBC_CHECK_DUPLICATES) launch_check_dup(ckey, packed, m, st, s);
+    if (!J.pv) {  // band ends of the count-mode wedge kernel fall on multiples of its granule
+        int gs = 0;
+        while ((2 << gs) < wedge_band(J.band_words, J.wg_size, false)) ++gs;
+        launch_bidx(ckey, P.coff, packed, m, n_c, gs, P.bnb, P.bioff, P.bidx, P.bmeta, P.partials, st, s);
+    }
     HybridView hv{nullptr, nullptr, nullptr, nullptr, nullptr};
     if (hybrid) {
         hv = HybridView{P.ablk1, P.cblk, P.cpos, P.dblocks, P.tabs};
@@ -331,7 +356,8 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
         if (ev) (void)hipEventRecord(ev[5], s);
     }
     if (n_s >= 2 && m > 0)
-        launch_wedge(J.band_words, J.wg_size, J.grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, order,
+        launch_wedge(J.band_words, J.wg_size, J.grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, P.bidx,
+                     P.bmeta, order,
                      (int32_t)n_s, st, J.pv, inv, J.s_is_u ? 0 : J.n_u, J.s_is_u ? J.n_u : 0, n_c,
                      J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
                      J.batched ? J.totals : nullptr, hv, s);

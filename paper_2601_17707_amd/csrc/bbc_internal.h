@@ -27,6 +27,9 @@ struct DevStatus {
 
 enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8, kBadBlocks = 16 };
 
+// Band-boundary index: meta.x of a centre list that has no index entries.
+constexpr int32_t kBidxNone = INT32_MIN;
+
 // One dense block as the device sees it.
 struct DevBlock {
     // matrix and table exist only for blocks with n_r >= 2 and n_k >= 1

@@ -120,6 +120,12 @@ __global__ void k_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevS
     GRID_STRIDE(i, n) atomicAdd(&deg[ids[i]], 1u);
 }
 
+// Degrees of the CSR rows (U) straight from the offsets.
+__global__ void k_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st) {
+    const bool bad = input_bad(st);
+    GRID_STRIDE(i, n_u) deg[i] = bad ? 0u : (uint32_t)(off[i + 1] - off[i]);
+}
+
 // graph id of every anchor of a batch (one workgroup per graph)
 __global__ void k_anchor_graph(const DevGraph* gr, uint32_t* agid) {
     const DevGraph g = gr[blockIdx.x];
@@ -189,6 +195,7 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t* aoff, const int32_
     const int lane = lane_id();
     int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     int64_t nwv = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    __shared__ unsigned long long red[256 / kWave];
     unsigned long long all = 0, walked = 0;
     for (int64_t r = wv; r < n_s; r += nwv) {
         uint32_t a0 = aoff[r], a1 = aoff[r + 1];
@@ -209,8 +216,73 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t* aoff, const int32_
         all += w;
         walked += wk;
     }
-    if (lane == 0 && all) atomicAdd(&st->wedges, all);
-    if (lane == 0 && walked) atomicAdd(&st->walked, walked);
+    // one pair of global atomics per workgroup (every lane holds its wave's sums)
+    all = block_sum<256>(lane == 0 ? all : 0ull, red);
+    walked = block_sum<256>(lane == 0 ? walked : 0ull, red);
+    if (threadIdx.x == 0 && all) atomicAdd(&st->wedges, all);
+    if (threadIdx.x == 0 && walked) atomicAdd(&st->walked, walked);
+}
+
+// ------------------------------------------------------ band-boundary index
+//
+// The wedge kernel walks each centre list in bands of endpoint ranks whose
+// ends are multiples of a granule G = 2^gs.  For every centre c it needs
+// pos(c, k) = the first position of its list with rank >= k G.  Below the
+// granule of the list's first entry that is the list start, above the
+// granule of its last entry the list end; the positions in between,
+// klo = (first rank >> gs) + 1 <= k <= khi = last rank >> gs, are stored
+// once per call as idx[ioff[c] + k - klo] -- but only for lists with at
+// least as many entries as boundaries (khi - klo + 1 <= length), so the
+// index never exceeds m entries.  Shorter lists spread over many granules
+// are not indexed: the kernel finds their band ends by stepping forward
+// from its cursor (each entry is passed once per anchor).
+
+// Number of index entries of list c: its boundary count, or 0 if the list
+// is shorter than that (or the input is bad).
+__device__ __forceinline__ uint32_t bidx_entries(const uint32_t* coff, const uint32_t* packed, int64_t c, int gs) {
+    const uint32_t a = coff[c], b = coff[c + 1];
+    if (a == b) return 0u;
+    const uint32_t nbr = ((packed[b - 1] >> 1) >> gs) - ((packed[a] >> 1) >> gs);
+    return nbr <= b - a ? nbr : 0u;
+}
+
+__global__ void k_bidx_count(const uint32_t* coff, const uint32_t* packed, int64_t n_c, int gs, uint32_t* nb,
+                             const DevStatus* st) {
+    const bool bad = input_bad(st);
+    GRID_STRIDE(c, n_c) nb[c] = bad ? 0u : bidx_entries(coff, packed, c, gs);
+}
+
+// One thread per list entry q > list start of an indexed list: the granule
+// boundaries that fall between the previous entry's rank and its own point
+// at q.
+__global__ void k_bidx_fill(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int gs,
+                            const uint32_t* ioff, uint32_t* idx, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(q, m) {
+        const uint32_t c = ckey[q];
+        const uint32_t q0 = coff[c];
+        if ((uint32_t)q == q0 || ioff[c + 1] == ioff[c]) continue;  // list start, or list not indexed
+        const uint32_t g = (packed[q] >> 1) >> gs, gp = (packed[q - 1] >> 1) >> gs;
+        const uint32_t klo = ((packed[q0] >> 1) >> gs) + 1u;
+        for (uint32_t k = gp + 1; k <= g; ++k) idx[ioff[c] + (k - klo)] = (uint32_t)q;
+    }
+}
+
+// Per centre: (x, khi) with pos(c, k) = k > khi ? list end : idx[x + k] for
+// every k >= klo; x = kBidxNone for a list without index entries.
+__global__ void k_bidx_meta(const uint32_t* coff, const uint32_t* packed, const uint32_t* ioff, int64_t n_c, int gs,
+                            int2* meta, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(c, n_c) {
+        const uint32_t a = coff[c], b = coff[c + 1];
+        int2 v{kBidxNone, -1};
+        if (a != b) {
+            const int32_t klo = (int32_t)(((packed[a] >> 1) >> gs) + 1u);
+            v.y = (int32_t)((packed[b - 1] >> 1) >> gs);
+            if (ioff[c + 1] != ioff[c]) v.x = (int32_t)ioff[c] - klo;
+        }
+        meta[c] = v;
+    }
 }
 
 // ------------------------------------------------------------ host launchers
@@ -243,6 +315,11 @@ void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const
 
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256)), dim3(256), 0, s, ids, n, deg, st);
+}
+
+void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s) {
+    if (n_u > 0)
+        hipLaunchKernelGGL(k_row_degrees, dim3(grid_for(n_u, 256)), dim3(256), 0, s, off, n_u, deg, st);
 }
 
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s) {
@@ -280,8 +357,20 @@ void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, D
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
                  uint32_t* key, DevStatus* st, const HybridView& hv, hipStream_t s) {
     if (n_s > 0)
-        hipLaunchKernelGGL(k_work, dim3(grid_for((int64_t)n_s * kWave, 256)), dim3(256), 0, s, aoff, acent, back,
-                           coff, n_s, key, st, hv);
+        hipLaunchKernelGGL(k_work, dim3(grid_for((int64_t)n_s * kWave, 256, 4096)), dim3(256), 0, s, aoff, acent,
+                           back, coff, n_s, key, st, hv);
+}
+
+void launch_bidx(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int64_t n_c, int gs,
+                 uint32_t* nb, uint32_t* ioff, uint32_t* idx, int2* meta, uint32_t* partials, const DevStatus* st,
+                 hipStream_t s) {
+    if (n_c <= 0) return;
+    hipLaunchKernelGGL(k_bidx_count, dim3(grid_for(n_c, 256)), dim3(256), 0, s, coff, packed, n_c, gs, nb, st);
+    scan_exclusive_u32(nb, ioff, n_c, partials, s);
+    if (m > 0)
+        hipLaunchKernelGGL(k_bidx_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, ckey, coff, packed, m, gs, ioff, idx,
+                           st);
+    hipLaunchKernelGGL(k_bidx_meta, dim3(grid_for(n_c, 256)), dim3(256), 0, s, coff, packed, ioff, n_c, gs, meta, st);
 }
 
 }  // namespace bbc

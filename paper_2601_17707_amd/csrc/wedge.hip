@@ -132,12 +132,21 @@ constexpr uint32_t inverse_odd(uint32_t m) {
 constexpr uint32_t kSlotInv = inverse_odd(kSlotMul);
 static_assert(kSlotMul * kSlotInv == 1u, "slot scatter must be invertible");
 
+// Low 32 bits of a 24 x 24-bit product (full rate; the compiler drops the
+// masks that would let it pick this form, since only the low bits are used).
+__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // LDS word and increment for endpoint slot `slot` (rank - band start) and
 // wedge type t (0 = signs agree, 1 = disagree).
 template <int MODE, int BAND_WORDS>
 __device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& word, uint32_t& inc) {
     constexpr uint32_t mask = band_capacity<MODE, BAND_WORDS>() - 1u;  // slot <= mask already
-    slot = ((slot & mask) * kSlotMul) & mask;
+    static_assert(mask < (1u << 24), "band slots must fit a 24-bit multiply");
+    slot = mul_u24(slot & mask, kSlotMul) & mask;
     if constexpr (MODE == 0) {
         word = slot >> 2;
         inc = 1u << (((slot & 3u) << 3) + (t << 2));
@@ -200,13 +209,15 @@ constexpr int kUnroll = 8;
 
 template <int WG, int BAND_WORDS, bool FULL>
 struct WedgeShared {
-    uint32_t cnt[BAND_WORDS + kWave];  // counters, then one spare word per lane for padding
+    alignas(16) uint32_t cnt[BAND_WORDS + kWave];  // counters, then one spare word per lane for padding
     uint32_t bmp[BAND_WORDS / 32];
-    uint32_t c_cur[WG];     // slice start of each centre | negative-edge bit << 31
-    int32_t c_end[WG];      // slice end (exclusive) in the current band
+    uint32_t c_cur[WG];     // cursor of each centre: next list position | negative-edge bit << 31
     int32_t c_ce[WG];       // end of the centre's whole list
     uint32_t w_start[WG];   // non-empty slices only: start | negative-edge bit << 31
     int32_t w_pre[WG + 1];  // their exclusive prefix of lengths
+    // band-boundary index of each centre: pos(k) = k > c_khi ? c_ce : idx[c_base + k]
+    int32_t c_base[FULL ? 1 : WG];
+    int32_t c_khi[FULL ? 1 : WG];
     long long scan_tmp[WG / kWave + 1];
     // per-vertex mode only
     int32_t c_id[FULL ? WG : 1];                // centre id of each chunk entry
@@ -223,7 +234,8 @@ template <bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                                              const int32_t* __restrict__ acent, const uint8_t* __restrict__ aneg,
                                              const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
-                                             int32_t a0, int32_t k0, int32_t nk, int32_t blk, const HybridView& hv) {
+                                             const int2* __restrict__ bmeta, int32_t a0, int32_t k0, int32_t nk,
+                                             int32_t blk, const HybridView& hv) {
     const int tid = threadIdx.x;
     if (tid < nk) {
         const int32_t p = a0 + k0 + tid;
@@ -237,6 +249,10 @@ __device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS, FULL>& 
         if constexpr (FULL) {
             sh.c_id[tid] = c;
             sh.c_sum[tid] = 0;
+        } else {
+            const int2 bm = bmeta[c];
+            sh.c_base[tid] = bm.x;
+            sh.c_khi[tid] = bm.y;
         }
     }
 }
@@ -254,11 +270,22 @@ __device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FU
 }
 
 // Counts the wedges of the centres in the slice tables whose endpoint rank
-// lies in [lo, hi).  Slice starts are in c_cur; when `seek_start` they are
-// first advanced to the first rank >= lo.  `self` is the anchor's own rank
-// (its entries are skipped in the per-vertex centre walk).  `phases`: bit 0
-// counts the wedges, bit 1 runs the per-vertex centre walk, which needs the
-// band's counters complete over every centre of the anchor.
+// lies in [lo, hi).  Slices start at the cursors in c_cur; when
+// `seek_start` they are first advanced to the first rank >= lo.  Cursors
+// move to the slice ends.  `self` is the anchor's own rank (its entries are
+// skipped in the per-vertex centre walk).  `phases`: bit 0 counts the
+// wedges, bit 1 runs the per-vertex centre walk, which needs the band's
+// counters complete over every centre of the anchor.
+//
+// Slice ends: in count mode every band but the last ends on a multiple of
+// the granule 2^gs, so the end is one read of the band-boundary index (lo,
+// when seeking, is such a multiple too); per-vertex mode searches the list
+// with one wave per centre.
+//
+// A band holding at least BAND_WORDS / 8 wedges is "dense": its increments
+// need no return value (no touched-word bitmap) and the reduction scans the
+// whole band; sparser bands mark touched words.  Returns whether the band
+// was dense.
 //
 // The non-empty slices are compacted and flattened into rows of 64 wedges;
 // each wave owns a contiguous run of rows and each lane keeps a cursor on
@@ -266,13 +293,16 @@ __device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FU
 // (and a short advance when the lane crosses into the next slice).  Lanes
 // of a wave read consecutive entries of a list: coalesced 4-byte loads.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
-__device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
-                                          int32_t nk, int64_t lo, int64_t hi, bool seek_start, bool last,
-                                          int32_t self, int phases) {
+__device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
+                                          const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
+                                          int64_t hi, bool seek_start, bool last, int32_t self, int phases,
+                                          int32_t& pre, bool use_pre, int64_t next_hi) {
     constexpr int NW = WG / kWave;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
     const uint32_t band = (uint32_t)(hi - lo);
-    if (seek_start || !last) {
+    // slice of each centre: start in w_start (scratch until the compaction),
+    // end as the new cursor in c_cur
+    if constexpr (FULL) {
         for (int32_t k = wave; k < nk; k += NW) {
             const uint32_t cur = sh.c_cur[k];
             int32_t st = (int32_t)(cur & 0x7fffffffu);
@@ -280,18 +310,41 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
             if (seek_start) st = wave_lower_bound(packed, st, ce, (uint32_t)lo);
             const int32_t en = last ? ce : wave_lower_bound(packed, st, ce, (uint32_t)hi);
             if (lane == 0) {
-                sh.c_cur[k] = (uint32_t)st | (cur & 0x80000000u);
-                sh.c_end[k] = en;
+                sh.w_start[k] = (uint32_t)st | (cur & 0x80000000u);
+                sh.c_cur[k] = (uint32_t)en | (cur & 0x80000000u);
             }
         }
     } else if (tid < nk) {
-        sh.c_end[tid] = sh.c_ce[tid];
+        // thread k owns centre k from here to the compaction: no barrier
+        const uint32_t cur = sh.c_cur[tid];
+        int32_t st = (int32_t)(cur & 0x7fffffffu);
+        const int32_t ce = sh.c_ce[tid], base = sh.c_base[tid], khi = sh.c_khi[tid];
+        // first position at or after q with rank >= bound (a granule
+        // multiple above the anchor's own entry, so bound >> gs is at least
+        // the first indexed granule of every list holding the anchor)
+        auto seek = [&](int32_t q, int64_t bound) {
+            const int32_t kk = (int32_t)(bound >> gs);
+            if (kk > khi) return ce;
+            if (base != kBidxNone) return max(q, (int32_t)bidx[base + kk]);
+            while (q < ce && (int64_t)(packed[q] >> 1) < bound) ++q;  // short list: step forward
+            return q;
+        };
+        if (seek_start) st = seek(st, lo);
+        int32_t en = ce;
+        if (!last) en = (use_pre && base != kBidxNone) ? max(st, pre) : seek(st, hi);
+        // the end of the next band of an indexed list, read now and used one band later
+        if (next_hi >= 0 && base != kBidxNone) {
+            const int32_t kk = (int32_t)(next_hi >> gs);
+            pre = kk > khi ? ce : (int32_t)bidx[base + kk];
+        }
+        sh.w_start[tid] = (uint32_t)st | (cur & 0x80000000u);
+        sh.c_cur[tid] = (uint32_t)en | (cur & 0x80000000u);
     }
-    __syncthreads();
+    if constexpr (FULL) __syncthreads();
 
     // compact the non-empty slices: one scan carries (length, count << 40)
-    const uint32_t cur = tid < nk ? sh.c_cur[tid] : 0u;
-    const int32_t len = tid < nk ? sh.c_end[tid] - (int32_t)(cur & 0x7fffffffu) : 0;
+    const uint32_t cur = tid < nk ? sh.w_start[tid] : 0u;
+    const int32_t len = tid < nk ? (int32_t)(sh.c_cur[tid] & 0x7fffffffu) - (int32_t)(cur & 0x7fffffffu) : 0;
     long long tot;
     const long long ex =
         block_exclusive_scan<WG>((long long)len + ((long long)(len > 0) << 40), sh.scan_tmp, &tot);
@@ -306,6 +359,7 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
     if (tid == 0) sh.w_pre[nkc] = total;
     __syncthreads();
 
+    const bool dense = total >= BAND_WORDS / 8;
     const int32_t rows = (total + kWave - 1) / kWave;
     const int32_t rpw = (rows + NW - 1) / NW;
     const int32_t r0 = wave * rpw, r1 = min(rows, r0 + rpw);
@@ -356,11 +410,18 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                     inc[u] = 0;
                 }
             }
+            if (dense) {  // no return value needed: the reduction scans the band
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) old[u] = atomicAdd(&sh.cnt[word[u]], inc[u]);
+                for (int u = 0; u < kUnroll; ++u)
+                    (void)__hip_atomic_fetch_add(&sh.cnt[word[u]], inc[u], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[word[u] >> 5], 1u << (word[u] & 31u));
+                for (int u = 0; u < kUnroll; ++u) old[u] = atomicAdd(&sh.cnt[word[u]], inc[u]);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[word[u] >> 5], 1u << (word[u] & 31u));
+            }
         }
     }
     __syncthreads();
@@ -396,17 +457,18 @@ __device__ __forceinline__ void walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         }
         __syncthreads();
     }
+    return dense;
 }
 
 // Sum of the pair terms of every touched counter word, and clears them.
-// Slots are scattered over the whole band capacity, so the bitmap is
-// scanned in full (BAND_WORDS / 32 words).  In per-vertex mode the anchor's
-// own slot (w = u), if in [lo, hi), is left out.  For an anchor of a dense
-// block the cross term of endpoints in the same block is added.  Ends with
-// a barrier.
+// A dense band is scanned word by word; otherwise the touched-word bitmap
+// is scanned in full (slots are scattered over the whole band capacity).
+// In per-vertex mode the anchor's own slot (w = u), if in [lo, hi), is left
+// out.  For an anchor of a dense block the cross term of endpoints in the
+// same block is added.  Ends with a barrier.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, int64_t lo,
-                                                          int64_t hi, int32_t self, const CrossRow& cr) {
+                                                          int64_t hi, int32_t self, const CrossRow& cr, bool dense) {
     const bool cross = cr.row && lo < cr.rank0 + cr.n_r && hi > cr.rank0;
     uint32_t sw0 = 0xffffffffu, sm0 = 0, sw1 = 0xffffffffu, sm1 = 0;
     if constexpr (FULL) {
@@ -420,22 +482,39 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
         }
     }
     unsigned long long acc = 0;
-    for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
-        uint32_t bits = sh.bmp[b];
-        if (bits) {
-            sh.bmp[b] = 0;
-            while (bits) {
-                const uint32_t i = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                const uint32_t wd = (b << 5) + i;
-                uint32_t v = sh.cnt[wd];
-                sh.cnt[wd] = 0;
-                if constexpr (FULL) {
-                    if (wd == sw0) v &= ~sm0;
-                    if (wd == sw1) v &= ~sm1;
+    auto word_terms = [&](uint32_t wd, uint32_t v) {
+        if constexpr (FULL) {
+            if (wd == sw0) v &= ~sm0;
+            if (wd == sw1) v &= ~sm1;
+        }
+        if (has_pairs<MODE>(v)) acc += word_pairs<MODE>(v);
+        if (cross && v) acc += cross_term<MODE, BAND_WORDS>(wd, v, lo, cr);
+    };
+    if (dense) {  // every word, four at a time
+        for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
+            uint4* p = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
+            const uint4 v = *p;
+            if (v.x | v.y | v.z | v.w) {
+                *p = uint4{0u, 0u, 0u, 0u};
+                word_terms(w4 * 4u + 0u, v.x);
+                word_terms(w4 * 4u + 1u, v.y);
+                word_terms(w4 * 4u + 2u, v.z);
+                word_terms(w4 * 4u + 3u, v.w);
+            }
+        }
+    } else {
+        for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
+            uint32_t bits = sh.bmp[b];
+            if (bits) {
+                sh.bmp[b] = 0;
+                while (bits) {
+                    const uint32_t i = __ffs(bits) - 1;
+                    bits &= bits - 1u;
+                    const uint32_t wd = (b << 5) + i;
+                    const uint32_t v = sh.cnt[wd];
+                    sh.cnt[wd] = 0;
+                    word_terms(wd, v);
                 }
-                if (has_pairs<MODE>(v)) acc += word_pairs<MODE>(v);
-                if (cross) acc += cross_term<MODE, BAND_WORDS>(wd, v, lo, cr);
             }
         }
     }
@@ -443,19 +522,34 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
     return acc;
 }
 
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// Granule of band ends in count mode: the band capacity of the widest
+// counters, so every band capacity is a multiple of it.
+template <int BAND_WORDS>
+constexpr int granule_shift() { return ilog2(BAND_WORDS) - 1; }
+
 // All bands of anchor r (rank), list start a0, deg entries.  Anchors with
 // at most WG centres keep one slice cursor per centre across bands (each
 // band starts where the previous one ended); wider anchors re-load their
-// centres per chunk and seek the band start.  Returns this thread's share
-// of the anchor's pair terms.
+// centres per chunk and seek the band start.  In count mode the first band
+// is [r + 1, the last granule multiple <= r + 1 + capacity), the next ones
+// start and end on granule multiples.  Returns this thread's share of the
+// anchor's pair terms.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh, const int32_t* __restrict__ acent,
                                            const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
+                                           const uint32_t* __restrict__ bidx, const int2* __restrict__ bmeta,
                                            int32_t a0, int32_t deg, int32_t r, int64_t n_s,
                                            unsigned long long* __restrict__ pv, int64_t centre_base,
                                            unsigned long long& bands, const HybridView& hv) {
     constexpr int64_t band_slots = band_capacity<MODE, BAND_WORDS>();
+    constexpr int gs = granule_shift<BAND_WORDS>();
+    auto band_end = [&](int64_t lo) {
+        const int64_t hi = FULL ? lo + band_slots : ((lo + band_slots) >> gs) << gs;
+        return hi < n_s ? hi : n_s;
+    };
     const int64_t lo0 = FULL ? 0 : (int64_t)r + 1;
     unsigned long long acc = 0;
     int32_t blk = -1;
@@ -470,14 +564,16 @@ __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh
         }
     }
     if (deg <= WG) {
-        load_centres<FULL>(sh, acent, aneg, back, coff, a0, 0, deg, blk, hv);
+        load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, 0, deg, blk, hv);
         __syncthreads();
-        for (int64_t lo = lo0; lo < n_s; lo += band_slots) {
-            const int64_t hi = min(n_s, lo + band_slots);
-            walk_band<MODE, FULL>(sh, packed, deg, lo, hi, false, hi == n_s, r, FULL ? 3 : 1);
-            if (threadIdx.x < deg)
-                sh.c_cur[threadIdx.x] = (uint32_t)sh.c_end[threadIdx.x] | (sh.c_cur[threadIdx.x] & 0x80000000u);
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr);
+        int32_t pre = 0;  // prefetched end of the band after the current one
+        for (int64_t lo = lo0, hi; lo < n_s; lo = hi) {
+            hi = band_end(lo);
+            // the next band's end is a granule multiple unless it is the last band
+            const int64_t nh = hi < n_s ? band_end(hi) : -1;
+            const bool dense = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
+                                                     FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
             ++bands;
         }
         if constexpr (FULL) {
@@ -485,27 +581,31 @@ __device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh
                 atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
         }
     } else {
-        for (int64_t lo = lo0; lo < n_s; lo += band_slots) {
-            const int64_t hi = min(n_s, lo + band_slots);
+        for (int64_t lo = lo0, hi; lo < n_s; lo = hi) {
+            hi = band_end(lo);
             const bool first = lo == lo0;
+            bool dense = false;  // any chunk dense: the band is reduced by a full scan
             for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                 const int32_t nk = min(WG, deg - k0);
-                load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk, blk, hv);
+                load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
                 __syncthreads();
-                walk_band<MODE, FULL>(sh, packed, nk, lo, hi, !first, hi == n_s, r, 1);
+                int32_t pre = 0;
+                dense |= walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 1, pre, false,
+                                               -1);
             }
             if constexpr (FULL) {
                 // second pass over the chunks once every wedge of the band is counted
                 for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                     const int32_t nk = min(WG, deg - k0);
-                    load_centres<FULL>(sh, acent, aneg, back, coff, a0, k0, nk, blk, hv);
+                    load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
                     __syncthreads();
-                    walk_band<MODE, FULL>(sh, packed, nk, lo, hi, !first, hi == n_s, r, 2);
+                    int32_t pre = 0;
+                    walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 2, pre, false, -1);
                     if (threadIdx.x < nk && sh.c_sum[threadIdx.x])
                         atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
                 }
             }
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
             ++bands;
         }
     }
@@ -519,6 +619,7 @@ template <int WG, int BAND_WORDS, bool FULL>
 __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
+                                              const uint32_t* __restrict__ bidx, const int2* __restrict__ bmeta,
                                               const uint32_t* __restrict__ order, int32_t n_s, DevStatus* st,
                                               unsigned long long* __restrict__ pv, const uint32_t* __restrict__ inv,
                                               int64_t anchor_base, int64_t centre_base,
@@ -544,17 +645,17 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
         if (deg < 2 || (!FULL && r >= n_end - 1)) continue;
         unsigned long long a;
         if (deg <= 15)
-            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
-                                        hv);
+            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                        centre_base, bands, hv);
         else if (deg <= 255)
-            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
-                                        hv);
+            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                        centre_base, bands, hv);
         else if (deg <= 65535)
-            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
-                                        hv);
+            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                        centre_base, bands, hv);
         else
-            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, a0, deg, r, n_end, pv, centre_base, bands,
-                                        hv);
+            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                        centre_base, bands, hv);
         if constexpr (FULL) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
             if (tid == 0) pv[anchor_base + inv[r]] = s;
@@ -631,12 +732,14 @@ int wedge_blocks_per_cu(int band_words, int wg, bool full) {
 }
 
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
-                  const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* order,
+                  const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* bidx,
+                  const int2* bmeta, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
                   unsigned long long* gtotals, const HybridView& hv, hipStream_t s) {
 #define BBC_LAUNCH(W, B, F)                                                                                      \
-    hipLaunchKernelGGL((k_wedge<W, B, F>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, order, \
+    hipLaunchKernelGGL((k_wedge<W, B, F>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, bidx, \
+                       bmeta, order,                                                                           \
                        n_s, st, pv, inv, anchor_base, centre_base, agraph, rank_end, gtotals, hv)
     if (pv) {
         BBC_LAUNCH(kFullWG, kFullBW, true);

@@ -341,3 +341,20 @@ def test_per_vertex_structured(ctx, case):
         assert t == t_want, side
         assert np.array_equal(pv, want), side
         assert int(pv[: g.n_u].sum()) == 2 * t == int(pv[g.n_u:].sum())
+
+
+@pytest.mark.parametrize("side", ["auto", "u", "v"])
+def test_stats_wedge_counts(ctx, side):
+    """The wedge count the benchmark divides by: sum over centres of
+    C(deg, 2), computed here from the degrees, for every kernel shape."""
+    g = synth.chung_lu_graph(50_000, 20_000, 400_000, 2.1, 2.0, 2_000, 800, seed=77)
+    u, v, _ = g.edges()
+    s_is_u = side == "u" or (side == "auto" and g.n_u < g.n_v)
+    d = np.bincount(v if s_is_u else u, minlength=g.n_v if s_is_u else g.n_u).astype(np.int64)
+    want_w = int((d * (d - 1) // 2).sum())
+    for bw, wg in SHAPES:
+        gpu_count(ctx, g, side, band_words=bw, wg_size=wg)
+        st = ctx.stats()
+        assert st["wedges"] == want_w and st["wedges_all"] == want_w, (bw, wg)
+        assert st["n_anchor"] == (g.n_u if s_is_u else g.n_v)
+        assert st["n_edges"] == g.m

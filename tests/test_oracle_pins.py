@@ -292,6 +292,73 @@ def test_anchor_ranges_partition_the_count():
         assert sum(w for _, w in parts) == int((deg_c.astype(np.int64) * (deg_c - 1) // 2).sum())
 
 
+def _signed_matrix(g):
+    A = np.zeros((g.n_u, g.n_v), np.int64)
+    u, v, s = g.edges()
+    A[u, v] = s
+    return A
+
+
+def _pair_terms(a, b):
+    """sum over unordered anchor pairs of C(a,2) + C(b,2) (upper triangle)."""
+    iu = np.triu_indices(a.shape[0], 1)
+    a, b = a[iu], b[iu]
+    return int((a * (a - 1) // 2 + b * (b - 1) // 2).sum())
+
+
+def test_lemma1_matrix_form():
+    """Lemma 1 as matrix products: with S the signed adjacency seen from the
+    anchor side, S S^T = a - b and |S| |S|^T = a + b for every anchor pair;
+    the pair terms sum to the oracle's count, on either side."""
+    rng = np.random.default_rng(31)
+    for _ in range(40):
+        g = synth.random_graph(rng, int(rng.integers(2, 30)), int(rng.integers(2, 30)), 0.5, 0.4)
+        A = _signed_matrix(g)
+        for M in (A.T, A):  # anchors on V, then on U
+            D, P = M @ M.T, np.abs(M) @ np.abs(M).T
+            assert np.all((P + D) % 2 == 0)
+            assert _pair_terms((P + D) // 2, (P - D) // 2) == oracle.count(g)
+
+
+def test_dense_block_split_identity():
+    """The split the dense-block path relies on: with the edges between a
+    block's anchors R and centres C called dense, a wedge is dense when both
+    its edges are; a_D (from the dense part's matrix products) vanishes unless
+    both anchors lie in the same block (blocks disjoint on both sides), and
+    C(a,2) = C(a_D,2) + C(a_S,2) + a_D a_S with a_S = a - a_D.  Summed, the
+    three parts give the oracle's count; leaving out the cross term does not."""
+    rng = np.random.default_rng(32)
+    for trial in range(30):
+        n_u, n_v = int(rng.integers(20, 60)), int(rng.integers(15, 50))
+        g = synth.random_graph(rng, n_u, n_v, float(rng.uniform(0.2, 0.7)), 0.35)
+        A = _signed_matrix(g).T  # anchors on V
+        pu, pv = rng.permutation(n_u), rng.permutation(n_v)
+        mask = np.zeros_like(A)
+        blocks, ou, ov = [], 0, 0
+        for _ in range(int(rng.integers(1, 4))):
+            nr, nc = int(rng.integers(1, n_v // 3 + 1)), int(rng.integers(1, n_u // 3 + 1))
+            R, C = pv[ov:ov + nr], pu[ou:ou + nc]
+            ov, ou = ov + nr, ou + nc
+            mask[np.ix_(R, C)] = 1
+            blocks.append(R)
+        Dm = A * mask
+        aD, bD = (np.abs(Dm) @ np.abs(Dm).T + Dm @ Dm.T) // 2, (np.abs(Dm) @ np.abs(Dm).T - Dm @ Dm.T) // 2
+        a, b = (np.abs(A) @ np.abs(A).T + A @ A.T) // 2, (np.abs(A) @ np.abs(A).T - A @ A.T) // 2
+        # every other wedge (both edges outside the blocks, or one edge in) is sparse
+        aS, bS = a - aD, b - bD
+        assert aS.min() >= 0 and bS.min() >= 0
+        same = np.zeros((n_v, n_v), bool)
+        for R in blocks:
+            same[np.ix_(R, R)] = True
+        assert not np.any((aD + bD)[~same & ~np.eye(n_v, dtype=bool)])
+        iu = np.triu_indices(n_v, 1)
+        cross = int((aD * aS + bD * bS)[iu].sum())
+        want = oracle.count(g)
+        assert _pair_terms(aD, bD) + _pair_terms(aS, bS) + cross == want
+        if cross:
+            assert _pair_terms(aD, bD) + _pair_terms(aS, bS) != want
+
+
 def test_malformed_input_rejected():
     g = synth.complete_graph(3, 3)
     bad = synth.Graph(3, 3, g.offsets, g.adj.copy(), g.signs, {})
