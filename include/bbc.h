@@ -123,8 +123,10 @@ bbc_status bbc_destroy(bbc_ctx* ctx);
  *                        per-vertex reading).  Overwritten, not accumulated.
  *   opts                 host or NULL (defaults).  band_words / wg_size must
  *                        name an instantiated kernel shape (BBC_EINVAL
- *                        otherwise): 16384/512 (default), 16384/256,
- *                        8192/256, 8192/512, 32768/1024, 16384/1024.
+ *                        otherwise), as words/threads: 8192/256
+ *                        (default), 16384/512, 16384/256, 8192/512,
+ *                        32768/1024, 16384/1024, 4096/128, 8192/128,
+ *                        4096/256.
  * Synchronous with respect to *total: returns after the stream has
  * produced it.  Errors: BBC_EINVAL, BBC_EOFFSETS, BBC_ERANGE, BBC_ESIGN,
  * BBC_EDUP, BBC_ENOMEM, BBC_EDEVICE, BBC_ETOOBIG. */

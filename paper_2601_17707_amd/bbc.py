@@ -18,7 +18,8 @@ OK, EINVAL, EOFFSETS, ERANGE, ESIGN, EDUP, ENOMEM, EDEVICE, ETOOBIG = range(9)
 SIDE_AUTO, SIDE_U, SIDE_V = 0, 1, 2
 CHECK_SIGNS, CHECK_DUPLICATES, CHECK_ALL = 1, 2, 3
 # instantiated wedge-kernel shapes (band_words, wg_size); the first is the default
-WEDGE_SHAPES = [(16384, 512), (16384, 256), (8192, 256), (8192, 512), (32768, 1024), (16384, 1024)]
+WEDGE_SHAPES = [(8192, 256), (16384, 512), (16384, 256), (8192, 512), (32768, 1024), (16384, 1024),
+                (4096, 128), (8192, 128), (4096, 256)]
 _SIDES = {"auto": SIDE_AUTO, "u": SIDE_U, "v": SIDE_V, SIDE_AUTO: SIDE_AUTO, SIDE_U: SIDE_U, SIDE_V: SIDE_V}
 
 

@@ -369,10 +369,18 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         int32_t nb = sh.w_pre[k + 1];
         uint32_t st = sh.w_start[k];
         int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+        // the next batch, loaded early while this one is counted when it lies
+        // inside every lane's current slice
+        uint32_t y[kUnroll], ymask = 0;
+        bool have_next = false;
         for (int32_t r = r0; r < r1; r += kUnroll) {
             uint32_t x[kUnroll];
             uint32_t ngmask;  // bit u: the anchor edge of wedge u is negative
-            if (r + kUnroll <= r1 && __all(j + (kUnroll - 1) * kWave < nb)) {
+            if (have_next) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) x[u] = y[u];
+                ngmask = ymask;
+            } else if (r + kUnroll <= r1 && __all(j + (kUnroll - 1) * kWave < nb)) {
                 // whole block inside each lane's current slice: one address,
                 // immediate offsets
                 const uint32_t* row = packed + (uint32_t)(base + j);
@@ -399,6 +407,13 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                 ngmask = ngm;
             }
             j += kUnroll * kWave;
+            have_next = r + 2 * kUnroll <= r1 && __all(j + (kUnroll - 1) * kWave < nb);
+            if (have_next) {
+                const uint32_t* row = packed + (uint32_t)(base + j);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) y[u] = row[u * kWave];
+                ymask = (st >> 31) ? 0xffffffffu : 0u;
+            }
             uint32_t word[kUnroll], inc[kUnroll], old[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -680,13 +695,53 @@ __global__ void k_halve(unsigned long long* pv, int64_t n) {
 
 // ------------------------------------------------------------------ launch
 
+struct WedgeArgs {
+    const uint32_t* aoff;
+    const int32_t* acent;
+    const uint8_t* aneg;
+    const int32_t* back;
+    const uint32_t* coff;
+    const uint32_t* packed;
+    const uint32_t* bidx;
+    const int2* bmeta;
+    const uint32_t* order;
+    int32_t n_s;
+    DevStatus* st;
+    unsigned long long* pv;
+    const uint32_t* inv;
+    int64_t anchor_base, centre_base;
+    const int32_t* agraph;
+    const int64_t* rank_end;
+    unsigned long long* gtotals;
+    HybridView hv;
+};
+
+template <int WG, int BW, bool FULL>
+static void launch_shape(const WedgeArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_wedge<WG, BW, FULL>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back, a.coff,
+                       a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base, a.centre_base,
+                       a.agraph, a.rank_end, a.gtotals, a.hv);
+}
+
+template <int WG, int BW, bool FULL>
+static int occupancy() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL>, WG, 0) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
+}
+
 // Instantiated shapes: (threads per workgroup, counter words per band).
 // The first is the default.  Per-vertex mode uses one shape of its own.
 struct WedgeShape {
     int wg, band_words;
+    int (*occ)();
+    void (*launch)(const WedgeArgs&, int, hipStream_t);
 };
-static const WedgeShape kShapes[] = {{512, 16384}, {256, 16384}, {256, 8192}, {512, 8192}, {1024, 32768},
-                                     {1024, 16384}};
+#define BBC_SHAPE(W, B) {W, B, occupancy<W, B, false>, launch_shape<W, B, false>}
+static const WedgeShape kShapes[] = {BBC_SHAPE(256, 8192),  BBC_SHAPE(512, 16384), BBC_SHAPE(256, 16384),
+                                     BBC_SHAPE(512, 8192),  BBC_SHAPE(1024, 32768), BBC_SHAPE(1024, 16384),
+                                     BBC_SHAPE(128, 4096),  BBC_SHAPE(128, 8192),   BBC_SHAPE(256, 4096)};
+#undef BBC_SHAPE
 constexpr int kFullWG = 256, kFullBW = 16384;
 
 static int shape_index(int band_words, int wg) {
@@ -711,38 +766,22 @@ void wedge_shape(int i, int* wg, int* band_words) {
     *band_words = kShapes[i].band_words;
 }
 
-template <int WG, int BW, bool FULL>
-static int occupancy() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL>, WG, 0) != hipSuccess) return 1;
-    return n > 0 ? n : 1;
-}
-
 int wedge_blocks_per_cu(int band_words, int wg, bool full) {
     if (full) return occupancy<kFullWG, kFullBW, true>();
-    switch (shape_index(band_words, wg)) {
-        case 0: return occupancy<512, 16384, false>();
-        case 1: return occupancy<256, 16384, false>();
-        case 2: return occupancy<256, 8192, false>();
-        case 3: return occupancy<512, 8192, false>();
-        case 4: return occupancy<1024, 32768, false>();
-        case 5: return occupancy<1024, 16384, false>();
-    }
-    return 1;
+    const int i = shape_index(band_words, wg);
+    return i >= 0 ? kShapes[i].occ() : 1;
 }
 
 void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg,
                   const int32_t* back, const uint32_t* coff, const uint32_t* packed, const uint32_t* bidx,
-                  const int2* bmeta, const uint32_t* order,
-                  int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
-                  int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
-                  unsigned long long* gtotals, const HybridView& hv, hipStream_t s) {
-#define BBC_LAUNCH(W, B, F)                                                                                      \
-    hipLaunchKernelGGL((k_wedge<W, B, F>), dim3(grid), dim3(W), 0, s, aoff, acent, aneg, back, coff, packed, bidx, \
-                       bmeta, order,                                                                           \
-                       n_s, st, pv, inv, anchor_base, centre_base, agraph, rank_end, gtotals, hv)
+                  const int2* bmeta, const uint32_t* order, int32_t n_s, DevStatus* st, unsigned long long* pv,
+                  const uint32_t* inv, int64_t anchor_base, int64_t centre_base, int64_t n_centre,
+                  const int32_t* agraph, const int64_t* rank_end, unsigned long long* gtotals, const HybridView& hv,
+                  hipStream_t s) {
+    const WedgeArgs a{aoff, acent, aneg, back, coff, packed, bidx, bmeta, order, n_s, st, pv, inv,
+                      anchor_base, centre_base, agraph, rank_end, gtotals, hv};
     if (pv) {
-        BBC_LAUNCH(kFullWG, kFullBW, true);
+        launch_shape<kFullWG, kFullBW, true>(a, grid, s);
         if (n_centre > 0) {
             int64_t g = (n_centre + 255) / 256;
             hipLaunchKernelGGL(k_halve, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, s, pv + centre_base,
@@ -750,15 +789,8 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
         }
         return;
     }
-    switch (shape_index(band_words, wg)) {
-        case 0: BBC_LAUNCH(512, 16384, false); break;
-        case 1: BBC_LAUNCH(256, 16384, false); break;
-        case 2: BBC_LAUNCH(256, 8192, false); break;
-        case 3: BBC_LAUNCH(512, 8192, false); break;
-        case 4: BBC_LAUNCH(1024, 32768, false); break;
-        case 5: BBC_LAUNCH(1024, 16384, false); break;
-    }
-#undef BBC_LAUNCH
+    const int i = shape_index(band_words, wg);
+    if (i >= 0) kShapes[i].launch(a, grid, s);
 }
 
 }  // namespace bbc

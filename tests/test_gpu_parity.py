@@ -128,7 +128,7 @@ def test_band_boundaries(ctx, n_s):
     assert gpu_count(ctx, g, "v") == want
 
 
-SHAPES = [(16384, 512), (16384, 256), (8192, 256), (8192, 512), (32768, 1024), (16384, 1024)]
+SHAPES = bbc.WEDGE_SHAPES
 
 
 @pytest.mark.parametrize("bw,wg", SHAPES)
