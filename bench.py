@@ -36,8 +36,8 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix throughput, 5.0 POPS
 # write x 1.000).  Valid only for the kernel sources it was taken on: the
 # bench reports null once their hash differs.
 KERNEL_SOURCES = ["paper_2601_17707_amd/csrc/wedge.hip", "paper_2601_17707_amd/csrc/bbc_internal.h"]
-MEASURED_TRAFFIC = dict(kernel="k_wedge", workload=WORKLOAD, bytes=61169353644,
-                        sources_sha256="2d98a993de77db1fd59e86eb5e9fb9b08f6547075a847712099ef0fb52a022aa",
+MEASURED_TRAFFIC = dict(kernel="k_wedge", workload=WORKLOAD, bytes=52550971748,
+                        sources_sha256="556442fed7d5f4af30018bc74d59e3cb8860f0ef77db30c89761b7a26417e8a3",
                         summary="profiles/k_wedge_powerlaw-1m-500k-20m_pmc.md")
 
 

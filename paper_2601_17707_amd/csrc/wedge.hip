@@ -292,14 +292,16 @@ __device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FU
 // the slice holding its wedge, so moving to the next row costs a compare
 // (and a short advance when the lane crosses into the next slice).  Lanes
 // of a wave read consecutive entries of a list: coalesced 4-byte loads.
-template <int MODE, bool FULL, int WG, int BAND_WORDS>
-__device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
-                                          const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
-                                          int64_t hi, bool seek_start, bool last, int32_t self, int phases,
-                                          int32_t& pre, bool use_pre, int64_t next_hi) {
+// Slices of the current band (search and compaction).  Leaves the
+// compacted slice table in w_start / w_pre and ends with a barrier;
+// *total and *nkc receive the band's wedges and non-empty slices.
+template <bool FULL, int WG, int BAND_WORDS>
+__device__ __forceinline__ void compact_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
+                                             const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
+                                             int64_t hi, bool seek_start, bool last, int32_t& pre, bool use_pre,
+                                             int64_t next_hi, int32_t& total_out, int32_t& nkc_out) {
     constexpr int NW = WG / kWave;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    const uint32_t band = (uint32_t)(hi - lo);
     // slice of each centre: start in w_start (scratch until the compaction),
     // end as the new cursor in c_cur
     if constexpr (FULL) {
@@ -358,86 +360,162 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
     }
     if (tid == 0) sh.w_pre[nkc] = total;
     __syncthreads();
+    total_out = total;
+    nkc_out = nkc;
+}
 
-    const bool dense = total >= BAND_WORDS / 8;
+// One wave's walk over its rows of the compacted band: row range, the
+// per-lane slice cursor and the batch loaded ahead.
+struct RowWalk {
+    int32_t r, r1;      // next row, end of the wave's rows
+    int32_t total;      // wedges in the band
+    int32_t j, k, nb;   // this lane's next wedge, its slice and the slice end
+    uint32_t st;        // slice start | negative-edge bit << 31
+    int32_t base;       // list position of wedge j is base + j
+};
+
+// A batch of kUnroll rows (one element per lane and row) and the signs of
+// its anchor edges (bit u: the anchor edge of row u is negative).
+struct Batch {
+    uint32_t x[kUnroll];
+    uint32_t ngmask;
+};
+
+// Loads the batch of kUnroll rows at row w.r into x (lanes past the slices
+// get 0xffffffff, outside every band).  Advances the slice cursor, not w.j.
+template <int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ Batch load_batch(const WedgeShared<WG, BAND_WORDS, FULL>& sh,
+                                            const uint32_t* __restrict__ packed, RowWalk& w) {
+    Batch bt;
+    uint32_t(&x)[kUnroll] = bt.x;
+    if (w.r + kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb)) {
+        // whole batch inside each lane's current slice: one address,
+        // immediate offsets
+        const uint32_t* row = packed + (uint32_t)(w.base + w.j);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) x[u] = row[u * kWave];
+        bt.ngmask = (w.st >> 31) ? 0xffffffffu : 0u;
+    } else {
+        uint32_t ngm = 0;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int32_t jj = w.j + u * kWave;
+            x[u] = 0xffffffffu;
+            if (w.r + u < w.r1 && jj < w.total) {
+                while (jj >= w.nb) {  // stays below nkc: w_pre[nkc] = total > jj
+                    ++w.k;
+                    w.nb = sh.w_pre[w.k + 1];
+                    w.st = sh.w_start[w.k];
+                    w.base = (int32_t)(w.st & 0x7fffffffu) - sh.w_pre[w.k];
+                }
+                x[u] = packed[(uint32_t)(w.base + jj)];
+                ngm |= (w.st >> 31) << u;
+            }
+        }
+        bt.ngmask = ngm;
+    }
+    return bt;
+}
+
+// Sets up this wave's rows of a compacted band (contiguous runs of rows per
+// wave) and issues the loads of its first batch.
+template <int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void walk_start(const WedgeShared<WG, BAND_WORDS, FULL>& sh,
+                                           const uint32_t* __restrict__ packed, int32_t total, int32_t nkc,
+                                           RowWalk& w, Batch& next, bool& have_next) {
+    constexpr int NW = WG / kWave;
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    const int32_t rows = (total + kWave - 1) / kWave;
+    const int32_t rpw = (rows + NW - 1) / NW;
+    w.r = wave * rpw;
+    w.r1 = min(rows, w.r + rpw);
+    w.total = total;
+    have_next = false;
+    if (w.r < w.r1) {
+        w.j = w.r * kWave + lane;
+        w.k = slice_of(sh, nkc, min(w.j, total - 1));
+        w.nb = sh.w_pre[w.k + 1];
+        w.st = sh.w_start[w.k];
+        w.base = (int32_t)(w.st & 0x7fffffffu) - sh.w_pre[w.k];
+        next = load_batch(sh, packed, w);
+        have_next = true;
+    }
+}
+
+// Counts the wedges of this wave's rows whose endpoint rank lies in
+// [lo, lo + band).  The batch after the current one is loaded before the
+// current one is counted when it lies inside every lane's slice.
+template <int MODE, int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
+                                          int64_t lo, uint32_t band, bool dense, RowWalk& w, Batch& next,
+                                          bool& have_next) {
+    const int lane = lane_id();
+    for (; w.r < w.r1; w.r += kUnroll) {
+        const Batch cur = have_next ? next : load_batch(sh, packed, w);
+        const uint32_t(&x)[kUnroll] = cur.x;
+        const uint32_t ngmask = cur.ngmask;
+        w.j += kUnroll * kWave;
+        have_next = w.r + 2 * kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb);
+        if (have_next) {
+            const uint32_t* row = packed + (uint32_t)(w.base + w.j);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) next.x[u] = row[u * kWave];
+            next.ngmask = (w.st >> 31) ? 0xffffffffu : 0u;
+        }
+        uint32_t word[kUnroll], inc[kUnroll], old[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t slot = (x[u] >> 1) - (uint32_t)lo;
+            if (slot < band) {  // padding lanes fall through to a spare word
+                slot_word<MODE, BAND_WORDS>(slot, (x[u] ^ (ngmask >> u)) & 1u, word[u], inc[u]);
+            } else {
+                word[u] = BAND_WORDS + lane;
+                inc[u] = 0;
+            }
+        }
+        if (dense) {  // no return value needed: the reduction scans the band
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                (void)__hip_atomic_fetch_add(&sh.cnt[word[u]], inc[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) old[u] = atomicAdd(&sh.cnt[word[u]], inc[u]);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[word[u] >> 5], 1u << (word[u] & 31u));
+        }
+    }
+}
+
+// A band holding at least BAND_WORDS / 8 wedges is "dense": its increments
+// need no return value (no touched-word bitmap) and the reduction scans the
+// whole band; sparser bands mark touched words.
+template <int BAND_WORDS>
+__device__ __forceinline__ bool dense_band(int32_t total) { return total >= BAND_WORDS / 8; }
+
+// One band in one call: compaction, walk, and in per-vertex mode the centre
+// walk (phases: bit 0 counts the wedges, bit 1 runs the centre walk, which
+// needs the band's counters complete over every centre of the anchor).
+// Returns whether the band was dense.
+template <int MODE, bool FULL, int WG, int BAND_WORDS>
+__device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
+                                          const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
+                                          int64_t hi, bool seek_start, bool last, int32_t self, int phases,
+                                          int32_t& pre, bool use_pre, int64_t next_hi) {
+    constexpr int NW = WG / kWave;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    int32_t total, nkc;
+    compact_band(sh, packed, bidx, gs, nk, lo, hi, seek_start, last, pre, use_pre, next_hi, total, nkc);
+    const bool dense = dense_band<BAND_WORDS>(total);
     const int32_t rows = (total + kWave - 1) / kWave;
     const int32_t rpw = (rows + NW - 1) / NW;
     const int32_t r0 = wave * rpw, r1 = min(rows, r0 + rpw);
-    if ((phases & 1) && r0 < r1) {
-        int32_t j = r0 * kWave + lane;
-        int32_t k = slice_of(sh, nkc, min(j, total - 1));
-        int32_t nb = sh.w_pre[k + 1];
-        uint32_t st = sh.w_start[k];
-        int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
-        // the next batch, loaded early while this one is counted when it lies
-        // inside every lane's current slice
-        uint32_t y[kUnroll], ymask = 0;
-        bool have_next = false;
-        for (int32_t r = r0; r < r1; r += kUnroll) {
-            uint32_t x[kUnroll];
-            uint32_t ngmask;  // bit u: the anchor edge of wedge u is negative
-            if (have_next) {
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) x[u] = y[u];
-                ngmask = ymask;
-            } else if (r + kUnroll <= r1 && __all(j + (kUnroll - 1) * kWave < nb)) {
-                // whole block inside each lane's current slice: one address,
-                // immediate offsets
-                const uint32_t* row = packed + (uint32_t)(base + j);
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) x[u] = row[u * kWave];
-                ngmask = (st >> 31) ? 0xffffffffu : 0u;
-            } else {
-                uint32_t ngm = 0;
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int32_t jj = j + u * kWave;
-                    x[u] = 0xffffffffu;
-                    if (r + u < r1 && jj < total) {
-                        while (jj >= nb) {  // stays below nkc: w_pre[nkc] = total > jj
-                            ++k;
-                            nb = sh.w_pre[k + 1];
-                            st = sh.w_start[k];
-                            base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
-                        }
-                        x[u] = packed[(uint32_t)(base + jj)];
-                        ngm |= (st >> 31) << u;
-                    }
-                }
-                ngmask = ngm;
-            }
-            j += kUnroll * kWave;
-            have_next = r + 2 * kUnroll <= r1 && __all(j + (kUnroll - 1) * kWave < nb);
-            if (have_next) {
-                const uint32_t* row = packed + (uint32_t)(base + j);
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) y[u] = row[u * kWave];
-                ymask = (st >> 31) ? 0xffffffffu : 0u;
-            }
-            uint32_t word[kUnroll], inc[kUnroll], old[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t slot = (x[u] >> 1) - (uint32_t)lo;
-                if (slot < band) {  // padding lanes fall through to a spare word
-                    slot_word<MODE, BAND_WORDS>(slot, (x[u] ^ (ngmask >> u)) & 1u, word[u], inc[u]);
-                } else {
-                    word[u] = BAND_WORDS + lane;
-                    inc[u] = 0;
-                }
-            }
-            if (dense) {  // no return value needed: the reduction scans the band
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    (void)__hip_atomic_fetch_add(&sh.cnt[word[u]], inc[u], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-            } else {
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) old[u] = atomicAdd(&sh.cnt[word[u]], inc[u]);
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[word[u] >> 5], 1u << (word[u] & 31u));
-            }
-        }
+    if (phases & 1) {
+        RowWalk w;
+        Batch next;
+        bool have_next;
+        walk_start(sh, packed, total, nkc, w, next, have_next);
+        walk_rows<MODE>(sh, packed, lo, (uint32_t)(hi - lo), dense, w, next, have_next);
     }
     __syncthreads();
 
@@ -552,7 +630,7 @@ constexpr int granule_shift() { return ilog2(BAND_WORDS) - 1; }
 // start and end on granule multiples.  Returns this thread's share of the
 // anchor's pair terms.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
-__device__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh, const int32_t* __restrict__ acent,
+__device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh, const int32_t* __restrict__ acent,
                                            const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
                                            const uint32_t* __restrict__ bidx, const int2* __restrict__ bmeta,
