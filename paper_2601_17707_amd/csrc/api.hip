@@ -23,9 +23,10 @@ void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, h
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
                   const uint32_t* agid, int32_t* agraph, hipStream_t s);
-void launch_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
-                       const uint32_t* aoff, uint32_t* fill, int64_t n_s, int32_t* acent, uint8_t* aneg,
-                       uint32_t* apack, const DevStatus* st, hipStream_t s);
+void launch_edge_keys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
+                      uint32_t* key, uint32_t* pay, const DevStatus* st, hipStream_t s);
+void launch_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, int32_t* acent, uint8_t* aneg,
+                         uint32_t* apack, const DevStatus* st, hipStream_t s);
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
 void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
@@ -176,7 +177,7 @@ struct Plan {
     uint32_t *deg_s, *deg_c;
     uint32_t *rk_ka, *rk_kb, *rk_va, *rk_vb;  // rank sort
     int32_t* rank;
-    uint32_t *adeg, *aoff, *fill, *coff;
+    uint32_t *adeg, *aoff, *coff;
     int32_t* acent;
     uint8_t* aneg;
     uint32_t *apack, *k_a, *k_b, *v0_a, *v0_b, *v1_a, *v1_b;
@@ -211,7 +212,6 @@ struct Plan {
         rank = c.take<int32_t>(n_s);
         adeg = c.take<uint32_t>(n_s + 1);
         aoff = c.take<uint32_t>(n_s + 1);
-        fill = c.take<uint32_t>(n_s);
         coff = c.take<uint32_t>(n_c + 1);
         acent = c.take<int32_t>(m);
         aneg = c.take<uint8_t>(m);
@@ -315,9 +315,16 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     launch_ranks(inv, P.deg_s, n_s, P.rank, P.adeg, J.batched ? P.agid : nullptr, J.batched ? P.agraph : nullptr, s);
     scan_exclusive_u32(P.adeg, P.aoff, n_s, P.partials, s);
 
-    // anchor lists, then centre lists by a stable sort on the centre id of
-    // the rank-ordered anchor entries (each centre list comes out rank-sorted)
-    launch_fill_edges(ea, ec, en, m, P.rank, P.aoff, P.fill, n_s, P.acent, P.aneg, P.apack, st, s);
+    // anchor lists by a stable sort of the edges on their anchor's rank, then
+    // centre lists by a stable sort on the centre id of the rank-ordered
+    // anchor entries (each centre list comes out rank-sorted)
+    launch_edge_keys(ea, ec, en, m, P.rank, P.k_b, P.v0_b, st, s);
+    {
+        const uint32_t *sk = nullptr, *sp = nullptr;
+        radix_sort(P.k_b, P.k_a, P.k_b, P.v0_b, P.v0_a, P.v0_b, nullptr, nullptr, nullptr, m,
+                   bits_for(n_s > 0 ? (uint64_t)(n_s - 1) : 0), P.hist, P.hist_scan, P.partials, s, &sk, &sp, nullptr);
+        launch_unpack_edges(sk, sp, m, P.acent, P.aneg, P.apack, st, s);
+    }
     const uint32_t *ckey = nullptr, *packed = nullptr, *perm = nullptr;
     radix_sort((const uint32_t*)P.acent, P.k_a, P.k_b, P.apack, P.v0_a, P.v0_b, nullptr, P.v1_a, P.v1_b, m,
                bits_for(n_c > 0 ? (uint64_t)(n_c - 1) : 0), P.hist, P.hist_scan, P.partials, s, &ckey, &packed,

@@ -151,18 +151,27 @@ __global__ void k_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s,
 
 // ------------------------------------------------------------- anchor lists
 
-// Every edge into its anchor's list (rank order), placed by an atomic fill
-// counter (the order inside an anchor list is free).
-__global__ void k_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m,
-                             const int32_t* rank, const uint32_t* aoff, uint32_t* fill, int32_t* acent,
-                             uint8_t* aneg, uint32_t* apack, const DevStatus* st) {
+// Sort key (anchor rank) and payload (centre id | negative << 31) of every
+// edge; a stable sort on the key lays out the anchor lists in rank order.
+__global__ void k_edge_keys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m,
+                            const int32_t* rank, uint32_t* key, uint32_t* pay, const DevStatus* st) {
     if (input_bad(st)) return;
     GRID_STRIDE(e, m) {
-        const int32_t r = rank[ea[e]];
-        const uint32_t slot = aoff[r] + atomicAdd(&fill[r], 1u);
-        acent[slot] = (int32_t)ec[e];
-        aneg[slot] = en[e];
-        apack[slot] = ((uint32_t)r << 1) | en[e];
+        key[e] = (uint32_t)rank[ea[e]];
+        pay[e] = ec[e] | ((uint32_t)en[e] << 31);
+    }
+}
+
+// Anchor lists from the rank-sorted edges: centre id, sign, and the packed
+// rank << 1 | neg that goes into the centre lists.
+__global__ void k_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, int32_t* acent, uint8_t* aneg,
+                               uint32_t* apack, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(p, m) {
+        const uint32_t c = pay[p];
+        acent[p] = (int32_t)(c & 0x7fffffffu);
+        aneg[p] = (uint8_t)(c >> 31);
+        apack[p] = (key[p] << 1) | (c >> 31);
     }
 }
 
@@ -337,13 +346,17 @@ void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32
                            agraph);
 }
 
-void launch_fill_edges(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
-                       const uint32_t* aoff, uint32_t* fill, int64_t n_s, int32_t* acent, uint8_t* aneg,
-                       uint32_t* apack, const DevStatus* st, hipStream_t s) {
-    fill_u32(fill, 0u, n_s, s);
+void launch_edge_keys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
+                      uint32_t* key, uint32_t* pay, const DevStatus* st, hipStream_t s) {
     if (m > 0)
-        hipLaunchKernelGGL(k_fill_edges, dim3(grid_for(m, 256)), dim3(256), 0, s, ea, ec, en, m, rank, aoff, fill,
-                           acent, aneg, apack, st);
+        hipLaunchKernelGGL(k_edge_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, ea, ec, en, m, rank, key, pay, st);
+}
+
+void launch_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, int32_t* acent, uint8_t* aneg,
+                         uint32_t* apack, const DevStatus* st, hipStream_t s) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_unpack_edges, dim3(grid_for(m, 256)), dim3(256), 0, s, key, pay, m, acent, aneg, apack,
+                           st);
 }
 
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s) {

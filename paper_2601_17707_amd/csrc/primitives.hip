@@ -152,46 +152,62 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* keys, in
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile.  Items are visited in rounds of 256 (round,
-// then wave, then lane is the input order).  Within a wave, the lanes that
-// share a digit are found with eight ballots; a lane's place among them is
-// the number of such lanes below it.  Wave counts are turned into offsets
-// per round by the thread that owns the digit.
+// Stable scatter of one tile, staged through LDS so that global writes are
+// runs of consecutive positions.  Items are visited in rounds of 256
+// (round, then wave, then lane is the input order).  Within a wave, the
+// lanes that share a digit are found with eight ballots; a lane's place
+// among them is the number of such lanes below it.  Wave counts are turned
+// into offsets per round by the thread that owns the digit.  Each item
+// first goes to its place in the tile sorted by digit (in LDS); the sorted
+// tile is then written out in order, every digit's run at its global
+// offset.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys, uint32_t* keys_out,
                                                            const uint32_t* v0, uint32_t* v0_out,
                                                            const uint32_t* v1, uint32_t* v1_out, int v1_iota,
-                                                           int64_t n, int shift, const uint32_t* hist_scan,
-                                                           int64_t nblk) {
+                                                           int64_t n, int shift, const uint32_t* hist,
+                                                           const uint32_t* hist_scan, int64_t nblk) {
+    __shared__ uint32_t s_key[kRsTile];
+    __shared__ uint32_t s_v0[kRsTile];
+    __shared__ uint32_t s_v1[kRsTile];
     __shared__ uint32_t running[256];
+    __shared__ uint32_t lstart[256];  // first place of each digit in the sorted tile
+    __shared__ uint32_t gstart[256];  // global position of that place
     __shared__ uint32_t wcnt[kRsWaves][256];
     __shared__ uint32_t woff[kRsWaves][256];
+    __shared__ uint32_t scan_tmp[kRsWaves + 1];
     const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-    running[t] = hist_scan[(int64_t)t * nblk + blockIdx.x];
+    const uint32_t cnt = hist[(int64_t)t * nblk + blockIdx.x];
+    uint32_t tot;
+    const uint32_t ls = block_exclusive_scan<kRsThreads>(cnt, scan_tmp, &tot);
+    lstart[t] = ls;
+    running[t] = ls;
+    gstart[t] = hist_scan[(int64_t)t * nblk + blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kRsWaves; ++k) wcnt[k][t] = 0;
     __syncthreads();
+    const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
     for (int r = 0; r < kRsRounds; ++r) {
-        int64_t i = base + (int64_t)r * kRsThreads + t;
-        bool valid = i < n;
-        uint32_t key = valid ? keys[i] : 0u;
-        uint32_t d = (key >> shift) & 255u;
+        const int64_t i = base + (int64_t)r * kRsThreads + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            int bit = (d >> b) & 1u;
-            unsigned long long m = __ballot(bit);
+            const int bit = (d >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        uint32_t rk = (uint32_t)__popcll(peers & below);
+        const uint32_t rk = (uint32_t)__popcll(peers & below);
         if (valid && rk == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         {
             uint32_t run = running[t];
 #pragma unroll
             for (int k = 0; k < kRsWaves; ++k) {
-                uint32_t c = wcnt[k][t];
+                const uint32_t c = wcnt[k][t];
                 woff[k][t] = run;
                 run += c;
                 wcnt[k][t] = 0;
@@ -200,11 +216,21 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
         }
         __syncthreads();
         if (valid) {
-            uint32_t pos = woff[w][d] + rk;
-            keys_out[pos] = key;
-            if (v0) v0_out[pos] = v0[i];
-            if (v1_out) v1_out[pos] = v1_iota ? (uint32_t)i : v1[i];
+            const uint32_t pos = woff[w][d] + rk;  // place in the sorted tile
+            s_key[pos] = key;
+            if (with_v0) s_v0[pos] = v0[i];
+            if (with_v1) s_v1[pos] = v1_iota ? (uint32_t)i : v1[i];
         }
+    }
+    __syncthreads();
+    const uint32_t tile_n = (uint32_t)min((int64_t)kRsTile, n - base);
+    for (uint32_t p = t; p < tile_n; p += kRsThreads) {
+        const uint32_t key = s_key[p];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t g = gstart[d] + (p - lstart[d]);
+        keys_out[g] = key;
+        if (with_v0) v0_out[g] = s_v0[p];
+        if (with_v1) v1_out[g] = s_v1[p];
     }
 }
 
@@ -224,7 +250,7 @@ void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, n, shift, hist, nblk);
         scan_exclusive_u32(hist, hist_scan, 256 * nblk, partials, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, kd, v0s, v0d, v1s, v1d,
-                           v1_iota, n, shift, (const uint32_t*)hist_scan, nblk);
+                           v1_iota, n, shift, (const uint32_t*)hist, (const uint32_t*)hist_scan, nblk);
         ks = kd;
         v0s = v0d;
         v1s = v1d;
