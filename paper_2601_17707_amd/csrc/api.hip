@@ -29,8 +29,9 @@ void launch_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, in
                          uint32_t* apack, const DevStatus* st, hipStream_t s);
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
-void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
-                 uint32_t* key, DevStatus* st, const HybridView& hv, hipStream_t s);
+void launch_work(const uint32_t* apack, const int32_t* acent, const int32_t* back, const uint32_t* coff, int64_t m,
+                 int64_t n_s, unsigned long long* work, uint32_t* key, DevStatus* st, const HybridView& hv,
+                 hipStream_t s);
 void launch_block_mark(const DevBlock* blocks, int32_t n_blocks, int64_t max_ids, int32_t n_s, int32_t n_c,
                        uint32_t* agrp, int32_t* cblk, int32_t* cidx, DevStatus* st, hipStream_t s);
 void launch_block_cpos(const int32_t* cblk, int32_t n_c, const DevBlock* blocks, const uint32_t* coff,
@@ -183,6 +184,7 @@ struct Plan {
     uint32_t *apack, *k_a, *k_b, *v0_a, *v0_b, *v1_a, *v1_b;
     int32_t* back;
     uint32_t *wkey, *ord_a, *ord_b, *ord_va, *ord_vb;
+    unsigned long long* work;  // per-anchor work (wedges walked)
     uint32_t *hist, *hist_scan, *partials;
     uint32_t* agid;    // batch: graph of each anchor id
     int32_t* agraph;   // batch: graph of each rank
@@ -224,6 +226,7 @@ struct Plan {
         v1_b = c.take<uint32_t>(m);
         back = c.take<int32_t>(m);
         wkey = c.take<uint32_t>(n_s);
+        work = c.take<unsigned long long>(n_s);
         ord_a = c.take<uint32_t>(n_s);
         ord_b = c.take<uint32_t>(n_s);
         ord_va = c.take<uint32_t>(n_s);
@@ -349,7 +352,7 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     }
 
     // schedule: anchors by descending work
-    launch_work(P.aoff, P.acent, P.back, P.coff, (int32_t)n_s, P.wkey, st, hv, s);
+    launch_work(P.apack, P.acent, P.back, P.coff, m, n_s, P.work, P.wkey, st, hv, s);
     const uint32_t *ok = nullptr, *order = nullptr;
     radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, nullptr, P.ord_va, P.ord_vb, n_s, 32, P.hist,
                P.hist_scan, P.partials, s, &ok, nullptr, &order);

@@ -193,43 +193,60 @@ __global__ void k_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_
 // Per-anchor work: the number of wedges the anchor walks, i.e. the suffix
 // lengths of its centres' lists (ranked-above endpoints; an anchor of a
 // dense block starts past the block's anchors in the block's centres).  One
-// wave per anchor.  key = bitwise complement of the clamped work, so an
-// ascending sort orders anchors by descending work (heavy anchors start
-// first, as in the fanout ordering of Algorithm 4).  st->wedges receives the
-// sum over centres of C(deg, 2), st->walked the wedges the walk visits.
-__global__ __launch_bounds__(256) void k_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back,
-                                              const uint32_t* coff, int32_t n_s, uint32_t* key, DevStatus* st,
-                                              HybridView hv) {
+// thread per anchor-list entry; the entries of an anchor are contiguous, so
+// a wave sums runs of equal rank with a segmented scan and adds each run
+// once.  st->wedges receives the sum over centres of C(deg, 2), st->walked
+// the wedges the walk visits.
+__global__ __launch_bounds__(256) void k_work(const uint32_t* apack, const int32_t* acent, const int32_t* back,
+                                              const uint32_t* coff, int64_t m, unsigned long long* work,
+                                              DevStatus* st, HybridView hv) {
     if (input_bad(st)) return;
-    const int lane = lane_id();
-    int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    int64_t nwv = ((int64_t)gridDim.x * blockDim.x) / kWave;
     __shared__ unsigned long long red[256 / kWave];
+    const int lane = lane_id();
     unsigned long long all = 0, walked = 0;
-    for (int64_t r = wv; r < n_s; r += nwv) {
-        uint32_t a0 = aoff[r], a1 = aoff[r + 1];
-        const int32_t blk = hv.ablk1 ? (int32_t)hv.ablk1[r] - 1 : -1;
-        unsigned long long w = 0, wk = 0;
-        for (uint32_t p = a0 + lane; p < a1; p += kWave) {
-            int32_t c = acent[p];
+    // whole waves walk the entries, so the scan below sees every lane
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < m; p0 += stride) {
+        const int64_t p = p0 + threadIdx.x;
+        const bool valid = p < m;
+        uint32_t r = 0xffffffffu;
+        unsigned long long wk = 0;
+        if (valid) {
+            r = apack[p] >> 1;
+            const int32_t c = acent[p];
             const uint32_t suffix = coff[c + 1] - (uint32_t)back[p] - 1u;
-            w += suffix;
-            wk += (blk >= 0 && hv.cblk[c] == blk) ? coff[c + 1] - (uint32_t)hv.cpos[c] : suffix;
+            all += suffix;
+            wk = suffix;
+            if (hv.ablk1) {
+                const int32_t blk = (int32_t)hv.ablk1[r] - 1;
+                if (blk >= 0 && hv.cblk[c] == blk) wk = coff[c + 1] - (uint32_t)hv.cpos[c];
+            }
+            walked += wk;
         }
-        w = wave_sum(w);
-        wk = wave_sum(wk);
-        if (lane == 0) {
-            uint32_t cl = wk > 0xffffffffull ? 0xffffffffu : (uint32_t)wk;
-            key[r] = ~cl;
+        // inclusive segmented sum over lanes of equal rank
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const unsigned long long y = __shfl_up(wk, o, kWave);
+            const uint32_t ry = __shfl_up(r, o, kWave);
+            if (lane >= o && ry == r) wk += y;
         }
-        all += w;
-        walked += wk;
+        const uint32_t rn = __shfl_down(r, 1, kWave);
+        if (valid && (lane == kWave - 1 || rn != r) && wk) atomicAdd(&work[r], wk);
     }
-    // one pair of global atomics per workgroup (every lane holds its wave's sums)
-    all = block_sum<256>(lane == 0 ? all : 0ull, red);
-    walked = block_sum<256>(lane == 0 ? walked : 0ull, red);
+    all = block_sum<256>(all, red);
+    walked = block_sum<256>(walked, red);
     if (threadIdx.x == 0 && all) atomicAdd(&st->wedges, all);
     if (threadIdx.x == 0 && walked) atomicAdd(&st->walked, walked);
+}
+
+// Sort key of each anchor: the bitwise complement of its clamped work, so an
+// ascending sort orders anchors by descending work (heavy anchors start
+// first, as in the fanout ordering of Algorithm 4).
+__global__ void k_work_keys(const unsigned long long* work, int64_t n_s, uint32_t* key) {
+    GRID_STRIDE(r, n_s) {
+        const unsigned long long w = work[r];
+        key[r] = ~(w > 0xffffffffull ? 0xffffffffu : (uint32_t)w);
+    }
 }
 
 // ------------------------------------------------------ band-boundary index
@@ -367,11 +384,15 @@ void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, D
     if (m > 1) hipLaunchKernelGGL(k_check_dup, dim3(grid_for(m, 256)), dim3(256), 0, s, ckey, packed, m, st);
 }
 
-void launch_work(const uint32_t* aoff, const int32_t* acent, const int32_t* back, const uint32_t* coff, int32_t n_s,
-                 uint32_t* key, DevStatus* st, const HybridView& hv, hipStream_t s) {
-    if (n_s > 0)
-        hipLaunchKernelGGL(k_work, dim3(grid_for((int64_t)n_s * kWave, 256, 4096)), dim3(256), 0, s, aoff, acent,
-                           back, coff, n_s, key, st, hv);
+void launch_work(const uint32_t* apack, const int32_t* acent, const int32_t* back, const uint32_t* coff, int64_t m,
+                 int64_t n_s, unsigned long long* work, uint32_t* key, DevStatus* st, const HybridView& hv,
+                 hipStream_t s) {
+    if (n_s <= 0) return;
+    fill_bytes(work, n_s * 8, s);
+    if (m > 0)
+        hipLaunchKernelGGL(k_work, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, apack, acent, back, coff, m, work,
+                           st, hv);
+    hipLaunchKernelGGL(k_work_keys, dim3(grid_for(n_s, 256)), dim3(256), 0, s, work, n_s, key);
 }
 
 void launch_bidx(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int64_t n_c, int gs,
