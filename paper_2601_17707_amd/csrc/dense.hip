@@ -24,7 +24,9 @@
 // centre order (padded to 64).  |S| is S & 1 per byte, formed in registers.
 // Each workgroup computes one 128 x 128 tile of the upper triangle with
 // v_mfma_i32_32x32x32_i8: four waves, each 64 x 64 (2 x 2 MFMA tiles, two
-// products), operands staged through LDS 64 bytes of K at a time.
+// products), operands staged through two LDS buffers 64 bytes of K at a
+// time (the next slice is loaded while the current one computes); two
+// workgroups per CU.
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -111,12 +113,14 @@ constexpr int kDRow = kDK + 16;  // LDS row pitch in bytes (padding spreads bank
 // l % 32, row 8 * (i / 4) + 4 * (l / 32) + i % 4.
 __device__ __forceinline__ int mfma_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
 
-__global__ __launch_bounds__(256) void k_dense(const DevBlock* __restrict__ blocks, const DevTile* __restrict__ tiles,
-                                               const int8_t* __restrict__ mats, uint32_t* __restrict__ tabs,
-                                               DevStatus* st) {
+__global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ blocks,
+                                                  const DevTile* __restrict__ tiles, const int8_t* __restrict__ mats,
+                                                  uint32_t* __restrict__ tabs, DevStatus* st) {
     if (status_bad(st)) return;
-    __shared__ __align__(16) int8_t As[kDTile * kDRow];
-    __shared__ __align__(16) int8_t Bs[kDTile * kDRow];
+    // two LDS stages: the next K slice is stored into one while the other
+    // feeds the matrix cores
+    __shared__ __align__(16) int8_t As[2][kDTile * kDRow];
+    __shared__ __align__(16) int8_t Bs[2][kDTile * kDRow];
     const DevTile T = tiles[blockIdx.x];
     const DevBlock B = blocks[T.blk];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -133,24 +137,37 @@ __global__ __launch_bounds__(256) void k_dense(const DevBlock* __restrict__ bloc
             accP[i][j] = v16i{};
         }
 
-    // staging: 128 rows x 64 bytes per matrix = 512 16-byte pieces, two per thread
+    // staging: 128 rows x 64 bytes per matrix = 512 16-byte pieces, two per
+    // thread and matrix, held in registers while the previous slice computes
     const int lr = tid >> 2, lc = (tid & 3) * 16;
-    for (int k0 = 0; k0 < B.kpad; k0 += kDK) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = lr + 64 * h;
-            *(int4*)&As[r * kDRow + lc] = *(const int4*)&arow[(int64_t)r * B.kpad + k0 + lc];
-            *(int4*)&Bs[r * kDRow + lc] = *(const int4*)&brow[(int64_t)r * B.kpad + k0 + lc];
+    const int8_t* pa0 = arow + (int64_t)lr * B.kpad + lc;
+    const int8_t* pa1 = pa0 + (int64_t)64 * B.kpad;
+    const int8_t* pb0 = brow + (int64_t)lr * B.kpad + lc;
+    const int8_t* pb1 = pb0 + (int64_t)64 * B.kpad;
+    const int so0 = lr * kDRow + lc, so1 = (lr + 64) * kDRow + lc;
+    int4 ga0 = *(const int4*)pa0, ga1 = *(const int4*)pa1, gb0 = *(const int4*)pb0, gb1 = *(const int4*)pb1;
+    *(int4*)&As[0][so0] = ga0;
+    *(int4*)&As[0][so1] = ga1;
+    *(int4*)&Bs[0][so0] = gb0;
+    *(int4*)&Bs[0][so1] = gb1;
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < B.kpad; k0 += kDK, buf ^= 1) {
+        const bool more = k0 + kDK < B.kpad;
+        if (more) {
+            ga0 = *(const int4*)(pa0 + k0 + kDK);
+            ga1 = *(const int4*)(pa1 + k0 + kDK);
+            gb0 = *(const int4*)(pb0 + k0 + kDK);
+            gb1 = *(const int4*)(pb1 + k0 + kDK);
         }
-        __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < kDK; ks += 32) {
             v4i a[2], b[2], aa[2], ba[2];
             const int kk = ks + 16 * (lane >> 5);
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a[i] = *(const v4i*)&As[(wr * 64 + i * 32 + (lane & 31)) * kDRow + kk];
-                b[i] = *(const v4i*)&Bs[(wc * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                a[i] = *(const v4i*)&As[buf][(wr * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                b[i] = *(const v4i*)&Bs[buf][(wc * 64 + i * 32 + (lane & 31)) * kDRow + kk];
                 aa[i] = a[i] & 0x01010101;
                 ba[i] = b[i] & 0x01010101;
             }
@@ -162,27 +179,36 @@ __global__ __launch_bounds__(256) void k_dense(const DevBlock* __restrict__ bloc
                     accP[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[i], ba[j], accP[i][j], 0, 0, 0);
                 }
         }
+        // the other stage was last read before the previous barrier
+        if (more) {
+            *(int4*)&As[buf ^ 1][so0] = ga0;
+            *(int4*)&As[buf ^ 1][so1] = ga1;
+            *(int4*)&Bs[buf ^ 1][so0] = gb0;
+            *(int4*)&Bs[buf ^ 1][so1] = gb1;
+        }
         __syncthreads();
     }
 
-    // epilogue: pair terms of the upper triangle and the (a, b) table
+    // epilogue: pair terms of the upper triangle and the (a, b) table;
+    // a, b <= 65535, so a (a - 1) / 2 fits 32 bits
     unsigned long long acc = 0;
     uint32_t* tab = tabs + B.tab_off;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
+            const int gw = T.tj * kDTile + wc * 64 + j * 32 + (lane & 31);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int gu = T.ti * kDTile + wr * 64 + i * 32 + mfma_row(e, lane);
-                const int gw = T.tj * kDTile + wc * 64 + j * 32 + (lane & 31);
                 if (gu < gw && gw < B.n_r) {
-                    const int32_t P = accP[i][j][e], D = accD[i][j][e];
-                    const unsigned long long a = (uint32_t)(P + D) >> 1, b = (uint32_t)(P - D) >> 1;
-                    acc += a * (a - (a > 0)) / 2 + b * (b - (b > 0)) / 2;
-                    tab[(int64_t)gu * B.rpad + gw] = (uint32_t)a | ((uint32_t)b << 16);
+                    const uint32_t P = (uint32_t)accP[i][j][e], D = (uint32_t)accD[i][j][e];
+                    const uint32_t a = (P + D) >> 1, b = (P - D) >> 1;
+                    acc += (unsigned long long)(a * (a - (a > 0u)) >> 1) + (b * (b - (b > 0u)) >> 1);
+                    tab[(int64_t)gu * B.rpad + gw] = a | (b << 16);
                 }
             }
+        }
     acc = wave_sum(acc);
     if (lane == 0 && acc) atomicAdd(&st->total, acc);
 }
