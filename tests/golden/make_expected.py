@@ -5,12 +5,15 @@ Calls only the CPU oracle (oracle/) and the seeded generator; no value here
 comes from the GPU library.  Each entry records the generator's SHA-256 of
 the graph so a test can tell that it regenerated the same input.
 
-    python tests/golden/make_expected.py [workload:seed ...]
+    python tests/golden/make_expected.py [--procs N] [workload:seed ...]
 
 The full-size oracle runs take minutes (the 20M-edge graph) to tens of
-minutes (the 200M-edge graph) on one core.
+minutes (the 200M-edge graphs) on one core.  With --procs N the total is
+the sum of the oracle's counts over N x 4 anchor-id ranges run in N forked
+processes (the ranges partition the anchors, so the sum is the total).
 """
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -26,7 +29,25 @@ from paper_2601_17707_amd import synth  # noqa: E402
 
 OUT = os.path.join(HERE, "expected_counts.json")
 DEFAULT = ["uniform-2k-1k-20k:1", "uniform-2k-1k-20k:2", "uniform-2k-1k-20k:3", "powerlaw-1m-500k-20m:1",
-           "skewed-5m-200k-200m:1"]
+           "skewed-5m-200k-200m:1", "hybrid-2m-1m-50m-16x4096:1"]
+_G = None  # the graph shared with forked workers
+
+
+def _range_count(bounds):
+    lo, hi = bounds
+    return oracle.count_anchors(_G, lo, hi)[0]
+
+
+def parallel_total(g, procs):
+    """Sum of the oracle's anchor-range counts over a partition of the anchors."""
+    global _G
+    _G = g
+    n_s = g.n_u if g.n_u < g.n_v else g.n_v
+    cuts = np.linspace(0, n_s, procs * 4 + 1).astype(np.int64)
+    with mp.get_context("fork").Pool(procs) as pool:
+        parts = pool.map(_range_count, list(zip(cuts[:-1].tolist(), cuts[1:].tolist())), chunksize=1)
+    _G = None
+    return int(sum(parts))
 N_VERTEX_SAMPLES = 48
 
 
@@ -40,7 +61,7 @@ def vertex_sample(g, seed):
     return sorted(picks)
 
 
-def main(keys):
+def main(keys, procs=1):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for key in keys:
         name, seed = key.split(":")
@@ -49,7 +70,7 @@ def main(keys):
         g = synth.workload(name, seed)
         sha = g.sha256()
         t1 = time.time()
-        total = oracle.count(g)
+        total = oracle.count(g) if procs <= 1 else parallel_total(g, procs)
         t2 = time.time()
         xs = vertex_sample(g, seed)
         vc = oracle.vertices(g, xs)
@@ -65,4 +86,8 @@ def main(keys):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or DEFAULT)
+    args = sys.argv[1:]
+    procs = 1
+    if args[:1] == ["--procs"]:
+        procs, args = int(args[1]), args[2:]
+    main(args or DEFAULT, procs)

@@ -51,3 +51,18 @@ def test_full_size(ctx, key):
     assert np.array_equal(got[ids], want)
     # each butterfly holds two vertices of each side
     assert int(got[: g.n_u].sum()) == 2 * t == int(got[g.n_u:].sum())
+
+
+@pytest.mark.parametrize("key", [k for k in sorted(EXPECTED) if k.startswith("hybrid")])
+def test_full_size_dense_blocks(ctx, key):
+    """The planted-block workload at full size with its 16 blocks on the
+    matrix cores: the oracle's total, in the launch the benchmark times."""
+    e = EXPECTED[key]
+    print("full size with blocks", key, flush=True)
+    g = synth.workload(e["workload"], e["seed"])
+    assert g.sha256() == e["sha256"], "generator output changed"
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    blocks = [(torch.from_numpy(c).cuda(), torch.from_numpy(r).cuda()) for r, c in g.meta["blocks"]]
+    assert ctx.count(off, adj, sg, g.n_v, opts=bbc.options(blocks=blocks)) == int(e["total"])
+    st = ctx.stats()
+    assert st["n_blocks"] == 16 and st["wedges"] < st["wedges_all"]
