@@ -70,43 +70,43 @@ __device__ __forceinline__ int32_t wave_lower_bound(const uint32_t* __restrict__
     return lo;
 }
 
-// Whether any counter field of a word is >= 2 (only those close butterflies;
-// most endpoint pairs share a single wedge).
+// Pair terms of the counter fields of LDS words: sum over fields x of
+// C(x,2) = (x^2 - x) / 2.  The sums of x^2 and of x over a word are single
+// packed dot-product instructions (the word with itself, and with a word of
+// ones), so no field is unpacked; x^2 - x is even, so halving the
+// difference is exact.  Modes 0 and 1 keep 32-bit partial sums per band and
+// thread (at most 64 words per thread and band, each below 2^18); modes 2
+// and 3 widen per word.
 template <int MODE>
-__device__ __forceinline__ bool has_pairs(uint32_t v) {
-    if constexpr (MODE == 0) return (v & 0xEEEEEEEEu) != 0;
-    else if constexpr (MODE == 1) return (v & 0xFEFEFEFEu) != 0;
-    else if constexpr (MODE == 2) return (v & 0xFFFEFFFEu) != 0;
-    else return v > 1u;
-}
-
-// Sum of C(x,2) over the counter fields of one LDS word.
-template <int MODE>
-__device__ __forceinline__ unsigned long long word_pairs(uint32_t v) {
-    if constexpr (MODE == 0) {  // eight 4-bit fields
-        uint32_t s = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            uint32_t x = (v >> (4 * i)) & 15u;
-            s += x * (x - 1u) / 2u;
+struct PairSum {
+    uint32_t sq = 0, lin = 0;
+    unsigned long long wide = 0;
+    __device__ __forceinline__ void add(uint32_t v) {
+        if constexpr (MODE == 0) {  // eight 4-bit fields
+            sq = __builtin_amdgcn_udot8(v, v, sq, false);
+            lin = __builtin_amdgcn_udot8(v, 0x11111111u, lin, false);
+        } else if constexpr (MODE == 1) {  // four 8-bit fields
+            sq = __builtin_amdgcn_udot4(v, v, sq, false);
+            lin = __builtin_amdgcn_udot4(v, 0x01010101u, lin, false);
+        } else if constexpr (MODE == 2) {  // a and b of one endpoint, a + b <= 65535: the squares fit 32 bits
+            typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+            const u16x2 h = __builtin_bit_cast(u16x2, v);
+            const uint32_t q = __builtin_amdgcn_udot2(h, h, 0u, false);
+            wide += (q - ((v & 0xffffu) + (v >> 16))) >> 1;
+        } else {  // one 32-bit field
+            const unsigned long long a = v;
+            wide += a * (a - (a > 0)) / 2;
         }
-        return s;
-    } else if constexpr (MODE == 1) {  // four 8-bit fields
-        uint32_t s = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t x = (v >> (8 * i)) & 255u;
-            s += x * (x - 1u) / 2u;
-        }
-        return s;
-    } else if constexpr (MODE == 2) {  // two 16-bit fields
-        unsigned long long a = v & 0xffffu, b = v >> 16;
-        return a * (a - (a > 0)) / 2 + b * (b - (b > 0)) / 2;
-    } else {  // one 32-bit field
-        unsigned long long a = v;
-        return a * (a - (a > 0)) / 2;
     }
-}
+    // The pair terms added so far, and restarts.
+    __device__ __forceinline__ unsigned long long take() {
+        unsigned long long r = wide;
+        if constexpr (MODE <= 1) r += (sq - lin) >> 1;
+        sq = lin = 0;
+        wide = 0;
+        return r;
+    }
+};
 
 // Band capacity in endpoint slots for a counter mode (a power of two).
 template <int MODE, int BAND_WORDS>
@@ -117,10 +117,12 @@ __host__ __device__ constexpr uint32_t band_capacity() {
 // Multiplier of the slot scatter.  Centre lists are sorted by rank, so the
 // lanes of a wave read endpoints at a near-regular stride; mapped straight
 // onto LDS words that stride lands on a few banks.  Any bijection between
-// endpoint slots and counter fields is valid (the reduction sums every
-// touched field), so slots are scattered by an odd multiplier modulo the
-// power-of-two capacity.
-constexpr uint32_t kSlotMul = 0x9E3779u;  // < 2^24: a full-rate 24-bit multiply
+// the endpoint ranks of a band and counter fields is valid (the reduction
+// sums every touched field), so an endpoint's slot is its rank times an odd
+// multiplier modulo the power-of-two band capacity: a band never spans more
+// ranks than its capacity, and distinct residues stay distinct under the
+// multiplication.
+constexpr uint32_t kSlotMul = 0x9E377u;  // times 8 still below 2^24: a full-rate 24-bit multiply
 
 // Inverse of an odd number modulo 2^32 (Newton iteration; each step doubles
 // the number of correct low bits).
@@ -131,35 +133,53 @@ constexpr uint32_t inverse_odd(uint32_t m) {
 }
 constexpr uint32_t kSlotInv = inverse_odd(kSlotMul);
 static_assert(kSlotMul * kSlotInv == 1u, "slot scatter must be invertible");
+static_assert(kSlotMul * 8u < (1u << 24), "scaled multipliers must fit a 24-bit multiply");
 
 // Low 32 bits of a 24 x 24-bit product (full rate; the compiler drops the
 // masks that would let it pick this form, since only the low bits are used).
+// The low k <= 24 bits of the product depend only on the low k bits of the
+// operands, so ranks above 2^24 map correctly modulo the band capacity.
 __device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) {
     uint32_t r;
     asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 
-// LDS word and increment for endpoint slot `slot` (rank - band start) and
-// wedge type t (0 = signs agree, 1 = disagree).
+// Counter field of endpoint rank `rank` and wedge type t (0 = signs agree,
+// 1 = disagree): byte offset of its LDS word in the band and bit shift of
+// the field.  Slot = rank * kSlotMul mod capacity; fields per word: mode 0
+// four slots of (a, b) nibbles, mode 1 two slots of (a, b) bytes, mode 2 one
+// slot of (a, b) halves, mode 3 one 32-bit word per slot and type.  The
+// multiplier is pre-scaled so that the product lands at the byte offset.
 template <int MODE, int BAND_WORDS>
-__device__ __forceinline__ void slot_word(uint32_t slot, uint32_t t, uint32_t& word, uint32_t& inc) {
-    constexpr uint32_t mask = band_capacity<MODE, BAND_WORDS>() - 1u;  // slot <= mask already
-    static_assert(mask < (1u << 24), "band slots must fit a 24-bit multiply");
-    slot = mul_u24(slot & mask, kSlotMul) & mask;
+__device__ __forceinline__ void slot_field(uint32_t rank, uint32_t t, uint32_t& byte, uint32_t& shift) {
+    static_assert(band_capacity<MODE, BAND_WORDS>() <= (1u << 24), "band slots must fit a 24-bit multiply");
+    constexpr uint32_t wmask = (uint32_t)(BAND_WORDS - 1) << 2;
     if constexpr (MODE == 0) {
-        word = slot >> 2;
-        inc = 1u << (((slot & 3u) << 3) + (t << 2));
+        const uint32_t p = mul_u24(rank, kSlotMul);  // slot = p mod 4 BW; word = slot / 4
+        byte = p & wmask;
+        shift = ((p & 3u) << 3) | (t << 2);
     } else if constexpr (MODE == 1) {
-        word = slot >> 1;
-        inc = 1u << (((slot & 1u) << 4) + (t << 3));
+        const uint32_t p = mul_u24(rank, kSlotMul * 2u);  // slot = p / 2 mod 2 BW; word = slot / 2
+        byte = p & wmask;
+        shift = ((p & 2u) << 3) | (t << 3);
     } else if constexpr (MODE == 2) {
-        word = slot;
-        inc = 1u << (t << 4);
+        const uint32_t p = mul_u24(rank, kSlotMul * 4u);  // slot = p / 4 mod BW; word = slot
+        byte = p & wmask;
+        shift = t << 4;
     } else {
-        word = (slot << 1) + t;
-        inc = 1u;
+        const uint32_t p = mul_u24(rank, kSlotMul * 8u);  // slot = p / 8 mod BW / 2; word = 2 slot + t
+        byte = (p & ((uint32_t)(BAND_WORDS / 2 - 1) << 3)) | (t << 2);
+        shift = 0;
     }
+}
+
+// Endpoint rank of slot `slot` in the band starting at lo (the inverse of
+// the scatter: the one rank in [lo, lo + capacity) with that residue).
+template <int MODE, int BAND_WORDS>
+__device__ __forceinline__ int64_t slot_rank(uint32_t slot, int64_t lo) {
+    constexpr uint32_t mask = band_capacity<MODE, BAND_WORDS>() - 1u;
+    return lo + (int64_t)((slot * kSlotInv - (uint32_t)lo) & mask);
 }
 
 // The dense-block table row of an anchor inside a block (row == null
@@ -175,11 +195,9 @@ struct CrossRow {
 // of a field is recovered by inverting the scatter.
 template <int MODE, int BAND_WORDS>
 __device__ __forceinline__ unsigned long long cross_term(uint32_t wd, uint32_t v, int64_t lo, const CrossRow& cr) {
-    constexpr uint32_t mask = band_capacity<MODE, BAND_WORDS>() - 1u;
     unsigned long long acc = 0;
     if constexpr (MODE == 3) {  // word = slot * 2 + type
-        const uint32_t slot = ((wd >> 1) * kSlotInv) & mask;
-        const int64_t i = lo + slot - cr.rank0;
+        const int64_t i = slot_rank<MODE, BAND_WORDS>(wd >> 1, lo) - cr.rank0;
         if ((uint64_t)i < (uint64_t)cr.n_r) {
             const uint32_t t = cr.row[i];
             acc = (unsigned long long)v * ((wd & 1u) ? (t >> 16) : (t & 0xffffu));
@@ -193,8 +211,7 @@ __device__ __forceinline__ unsigned long long cross_term(uint32_t wd, uint32_t v
             const uint32_t x = v >> (f * FB);
             const uint32_t a = x & fm, b = (x >> (FB / 2)) & fm;
             if (a | b) {
-                const uint32_t slot = ((wd * (uint32_t)F + (uint32_t)f) * kSlotInv) & mask;
-                const int64_t i = lo + slot - cr.rank0;
+                const int64_t i = slot_rank<MODE, BAND_WORDS>(wd * (uint32_t)F + (uint32_t)f, lo) - cr.rank0;
                 if ((uint64_t)i < (uint64_t)cr.n_r) {
                     const uint32_t t = cr.row[i];
                     acc += (unsigned long long)a * (t & 0xffffu) + (unsigned long long)b * (t >> 16);
@@ -209,7 +226,7 @@ constexpr int kUnroll = 8;
 
 template <int WG, int BAND_WORDS, bool FULL>
 struct WedgeShared {
-    alignas(16) uint32_t cnt[BAND_WORDS + kWave];  // counters, then one spare word per lane for padding
+    alignas(16) uint32_t cnt[BAND_WORDS];  // counters
     uint32_t bmp[BAND_WORDS / 32];
     uint32_t c_cur[WG];     // cursor of each centre: next list position | negative-edge bit << 31
     int32_t c_ce[WG];       // end of the centre's whole list
@@ -282,7 +299,7 @@ __device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FU
 // when seeking, is such a multiple too); per-vertex mode searches the list
 // with one wave per centre.
 //
-// A band holding at least BAND_WORDS / 8 wedges is "dense": its increments
+// A band holding at least BAND_WORDS / 16 wedges is "dense": its increments
 // need no return value (no touched-word bitmap) and the reduction scans the
 // whole band; sparser bands mark touched words.  Returns whether the band
 // was dense.
@@ -375,14 +392,22 @@ struct RowWalk {
 };
 
 // A batch of kUnroll rows (one element per lane and row) and the signs of
-// its anchor edges (bit u: the anchor edge of row u is negative).
+// its anchor edges (bit u: the anchor edge of row u is negative).  A full
+// batch (the same for every lane of the wave) lies inside each lane's
+// current slice: every element is a wedge and ngmask is all ones or zero.
+// Otherwise only the first `rows` rows belong to the wave (the same for
+// every lane) and bit u of vmask says whether row u holds a wedge for this
+// lane (lanes past the band's last wedge hold none).
 struct Batch {
     uint32_t x[kUnroll];
     uint32_t ngmask;
+    uint32_t vmask;
+    int32_t rows;
+    bool full;
 };
 
-// Loads the batch of kUnroll rows at row w.r into x (lanes past the slices
-// get 0xffffffff, outside every band).  Advances the slice cursor, not w.j.
+// Loads the batch of kUnroll rows at row w.r into x.  Advances the slice
+// cursor, not w.j.
 template <int WG, int BAND_WORDS, bool FULL>
 __device__ __forceinline__ Batch load_batch(const WedgeShared<WG, BAND_WORDS, FULL>& sh,
                                             const uint32_t* __restrict__ packed, RowWalk& w) {
@@ -395,12 +420,16 @@ __device__ __forceinline__ Batch load_batch(const WedgeShared<WG, BAND_WORDS, FU
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) x[u] = row[u * kWave];
         bt.ngmask = (w.st >> 31) ? 0xffffffffu : 0u;
+        bt.vmask = (1u << kUnroll) - 1u;
+        bt.rows = kUnroll;
+        bt.full = true;
     } else {
-        uint32_t ngm = 0;
+        uint32_t ngm = 0, vm = 0;
+        const uint32_t spread = (uint32_t)lane_id() << 1;  // lanes with no wedge add zero to distinct words
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const int32_t jj = w.j + u * kWave;
-            x[u] = 0xffffffffu;
+            x[u] = spread;
             if (w.r + u < w.r1 && jj < w.total) {
                 while (jj >= w.nb) {  // stays below nkc: w_pre[nkc] = total > jj
                     ++w.k;
@@ -410,11 +439,50 @@ __device__ __forceinline__ Batch load_batch(const WedgeShared<WG, BAND_WORDS, FU
                 }
                 x[u] = packed[(uint32_t)(w.base + jj)];
                 ngm |= (w.st >> 31) << u;
+                vm |= 1u << u;
             }
         }
         bt.ngmask = ngm;
+        bt.vmask = vm;
+        bt.rows = min(kUnroll, w.r1 - w.r);
+        bt.full = false;
     }
     return bt;
+}
+
+// Counts the wedges of one batch: every loaded element lies in the current
+// band (slices are cut at the band's ends), so no range test is needed.
+// In MASKED batches rows past the wave's last row are skipped and lanes
+// holding no wedge add zero.  Dense bands increment without a return
+// value; sparse ones mark the first increment of a word in the
+// touched-word bitmap.
+template <int MODE, bool MASKED, int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void count_batch(WedgeShared<WG, BAND_WORDS, FULL>& sh, const Batch& b, bool dense) {
+    uint32_t byte[kUnroll], inc[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const uint32_t t = (b.x[u] ^ (MASKED ? b.ngmask >> u : b.ngmask)) & 1u;
+        uint32_t shift;
+        slot_field<MODE, BAND_WORDS>(b.x[u] >> 1, t, byte[u], shift);
+        const uint32_t one = MASKED ? (b.vmask >> u) & 1u : 1u;
+        inc[u] = MODE == 3 ? one : one << shift;
+    }
+    char* base = reinterpret_cast<char*>(sh.cnt);
+    if (dense) {  // no return value needed: the reduction scans the band
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (!MASKED || u < b.rows)
+                (void)__hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(base + byte[u]), inc[u], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        uint32_t old[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            old[u] = (!MASKED || u < b.rows) ? atomicAdd(reinterpret_cast<uint32_t*>(base + byte[u]), inc[u]) : 1u;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[byte[u] >> 7], 1u << ((byte[u] >> 2) & 31u));
+    }
 }
 
 // Sets up this wave's rows of a compacted band (contiguous runs of rows per
@@ -442,18 +510,14 @@ __device__ __forceinline__ void walk_start(const WedgeShared<WG, BAND_WORDS, FUL
     }
 }
 
-// Counts the wedges of this wave's rows whose endpoint rank lies in
-// [lo, lo + band).  The batch after the current one is loaded before the
-// current one is counted when it lies inside every lane's slice.
+// Counts the wedges of this wave's rows.  The batch after the current one
+// is loaded before the current one is counted when it lies inside every
+// lane's slice.
 template <int MODE, int WG, int BAND_WORDS, bool FULL>
 __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
-                                          int64_t lo, uint32_t band, bool dense, RowWalk& w, Batch& next,
-                                          bool& have_next) {
-    const int lane = lane_id();
+                                          bool dense, RowWalk& w, Batch& next, bool& have_next) {
     for (; w.r < w.r1; w.r += kUnroll) {
         const Batch cur = have_next ? next : load_batch(sh, packed, w);
-        const uint32_t(&x)[kUnroll] = cur.x;
-        const uint32_t ngmask = cur.ngmask;
         w.j += kUnroll * kWave;
         have_next = w.r + 2 * kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb);
         if (have_next) {
@@ -461,37 +525,20 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) next.x[u] = row[u * kWave];
             next.ngmask = (w.st >> 31) ? 0xffffffffu : 0u;
+            next.vmask = (1u << kUnroll) - 1u;
+            next.rows = kUnroll;
+            next.full = true;
         }
-        uint32_t word[kUnroll], inc[kUnroll], old[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t slot = (x[u] >> 1) - (uint32_t)lo;
-            if (slot < band) {  // padding lanes fall through to a spare word
-                slot_word<MODE, BAND_WORDS>(slot, (x[u] ^ (ngmask >> u)) & 1u, word[u], inc[u]);
-            } else {
-                word[u] = BAND_WORDS + lane;
-                inc[u] = 0;
-            }
-        }
-        if (dense) {  // no return value needed: the reduction scans the band
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                (void)__hip_atomic_fetch_add(&sh.cnt[word[u]], inc[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) old[u] = atomicAdd(&sh.cnt[word[u]], inc[u]);
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[word[u] >> 5], 1u << (word[u] & 31u));
-        }
+        if (cur.full) count_batch<MODE, false>(sh, cur, dense);
+        else count_batch<MODE, true>(sh, cur, dense);
     }
 }
 
-// A band holding at least BAND_WORDS / 8 wedges is "dense": its increments
+// A band holding at least BAND_WORDS / 16 wedges is "dense": its increments
 // need no return value (no touched-word bitmap) and the reduction scans the
 // whole band; sparser bands mark touched words.
 template <int BAND_WORDS>
-__device__ __forceinline__ bool dense_band(int32_t total) { return total >= BAND_WORDS / 8; }
+__device__ __forceinline__ bool dense_band(int32_t total) { return total >= BAND_WORDS / 16; }
 
 // One band in one call: compaction, walk, and in per-vertex mode the centre
 // walk (phases: bit 0 counts the wedges, bit 1 runs the centre walk, which
@@ -515,7 +562,7 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         Batch next;
         bool have_next;
         walk_start(sh, packed, total, nkc, w, next, have_next);
-        walk_rows<MODE>(sh, packed, lo, (uint32_t)(hi - lo), dense, w, next, have_next);
+        walk_rows<MODE>(sh, packed, dense, w, next, have_next);
     }
     __syncthreads();
 
@@ -541,9 +588,9 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                 }
                 const uint32_t x = packed[(uint32_t)(base + j)];
                 if ((int32_t)(x >> 1) != self) {
-                    uint32_t word, inc;
-                    slot_word<MODE, BAND_WORDS>((x >> 1) - (uint32_t)lo, (x ^ (st >> 31)) & 1u, word, inc);
-                    run += ((sh.cnt[word] >> (31 - __clz(inc))) & fmask) - 1u;
+                    uint32_t byte, shift;
+                    slot_field<MODE, BAND_WORDS>(x >> 1, (x ^ (st >> 31)) & 1u, byte, shift);
+                    run += ((sh.cnt[byte >> 2] >> shift) & fmask) - 1u;
                 }
             }
             if (run) atomicAdd(&sh.c_sum[sh.w_k[k]], run);
@@ -567,32 +614,40 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
     if constexpr (FULL) {
         if ((int64_t)self >= lo && (int64_t)self < hi) {
             constexpr uint32_t fmask = MODE == 0 ? 15u : MODE == 1 ? 255u : MODE == 2 ? 0xffffu : 0xffffffffu;
-            uint32_t inc0, inc1;
-            slot_word<MODE, BAND_WORDS>((uint32_t)(self - lo), 0u, sw0, inc0);
-            slot_word<MODE, BAND_WORDS>((uint32_t)(self - lo), 1u, sw1, inc1);
-            sm0 = fmask << (31 - __clz(inc0));
-            sm1 = fmask << (31 - __clz(inc1));
+            uint32_t sh0, sh1;
+            slot_field<MODE, BAND_WORDS>((uint32_t)self, 0u, sw0, sh0);
+            slot_field<MODE, BAND_WORDS>((uint32_t)self, 1u, sw1, sh1);
+            sw0 >>= 2;
+            sw1 >>= 2;
+            sm0 = fmask << sh0;
+            sm1 = fmask << sh1;
         }
     }
     unsigned long long acc = 0;
+    PairSum<MODE> ps;
     auto word_terms = [&](uint32_t wd, uint32_t v) {
         if constexpr (FULL) {
             if (wd == sw0) v &= ~sm0;
             if (wd == sw1) v &= ~sm1;
         }
-        if (has_pairs<MODE>(v)) acc += word_pairs<MODE>(v);
+        ps.add(v);
         if (cross && v) acc += cross_term<MODE, BAND_WORDS>(wd, v, lo, cr);
     };
     if (dense) {  // every word, four at a time
         for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
             uint4* p = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
             const uint4 v = *p;
-            if (v.x | v.y | v.z | v.w) {
-                *p = uint4{0u, 0u, 0u, 0u};
+            if (v.x | v.y | v.z | v.w) *p = uint4{0u, 0u, 0u, 0u};
+            if (FULL || cross) {
                 word_terms(w4 * 4u + 0u, v.x);
                 word_terms(w4 * 4u + 1u, v.y);
                 word_terms(w4 * 4u + 2u, v.z);
                 word_terms(w4 * 4u + 3u, v.w);
+            } else {  // zero words add nothing
+                ps.add(v.x);
+                ps.add(v.y);
+                ps.add(v.z);
+                ps.add(v.w);
             }
         }
     } else {
@@ -612,7 +667,7 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
         }
     }
     __syncthreads();
-    return acc;
+    return acc + ps.take();
 }
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
@@ -722,7 +777,7 @@ __global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff,
     if (*(volatile const int32_t*)&st->flags) return;  // input error: nothing to count
     __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
-    for (int i = tid; i < BAND_WORDS + kWave; i += WG) sh.cnt[i] = 0;
+    for (int i = tid; i < BAND_WORDS; i += WG) sh.cnt[i] = 0;
     for (int i = tid; i < BAND_WORDS / 32; i += WG) sh.bmp[i] = 0;
     unsigned long long acc = 0, bands = 0;
     for (;;) {
