@@ -224,17 +224,22 @@ __device__ __forceinline__ unsigned long long cross_term(uint32_t wd, uint32_t v
 
 constexpr int kUnroll = 8;
 
+// Compacted slices of one band: start | negative-edge bit << 31 of the
+// non-empty slices and the exclusive prefix of their lengths.
+template <int WG>
+struct SliceTable {
+    uint32_t start[WG];
+    int32_t pre[WG + 1];
+};
+
 template <int WG, int BAND_WORDS, bool FULL>
 struct WedgeShared {
     alignas(16) uint32_t cnt[BAND_WORDS];  // counters
     uint32_t bmp[BAND_WORDS / 32];
     uint32_t c_cur[WG];     // cursor of each centre: next list position | negative-edge bit << 31
-    int32_t c_ce[WG];       // end of the centre's whole list
-    uint32_t w_start[WG];   // non-empty slices only: start | negative-edge bit << 31
-    int32_t w_pre[WG + 1];  // their exclusive prefix of lengths
-    // band-boundary index of each centre: pos(k) = k > c_khi ? c_ce : idx[c_base + k]
-    int32_t c_base[FULL ? 1 : WG];
-    int32_t c_khi[FULL ? 1 : WG];
+    int32_t c_ce[FULL ? WG : 1];  // per-vertex mode: end of the centre's whole list
+    // count mode compacts the next band while the current one is reduced
+    SliceTable<WG> tab[FULL ? 1 : 2];
     long long scan_tmp[WG / kWave + 1];
     // per-vertex mode only
     int32_t c_id[FULL ? WG : 1];                // centre id of each chunk entry
@@ -243,17 +248,25 @@ struct WedgeShared {
     int32_t task;
 };
 
+// Per-centre values that stay in the registers of the thread owning the
+// centre in count mode: the end of its whole list and its band-boundary
+// index (pos(k) = k > khi ? ce : idx[base + k]).
+struct CentreMeta {
+    int32_t ce, base, khi;
+};
+
 // Loads the centres k0 .. k0+nk-1 of the anchor list starting at a0: the
 // slice start (just past the anchor's own entry in the centre list, the
 // ranked-above suffix; or the list start in per-vertex mode), the list end,
-// and the sign of the anchor edge.
+// and the sign of the anchor edge.  Thread k owns centre k.
 template <bool FULL, int WG, int BAND_WORDS>
-__device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS, FULL>& sh,
+__device__ __forceinline__ CentreMeta load_centres(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                                              const int32_t* __restrict__ acent, const uint8_t* __restrict__ aneg,
                                              const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
                                              const int2* __restrict__ bmeta, int32_t a0, int32_t k0, int32_t nk,
                                              int32_t blk, const HybridView& hv) {
     const int tid = threadIdx.x;
+    CentreMeta cm{0, kBidxNone, -1};
     if (tid < nk) {
         const int32_t p = a0 + k0 + tid;
         const int32_t c = acent[p];
@@ -262,25 +275,27 @@ __device__ __forceinline__ void load_centres(WedgeShared<WG, BAND_WORDS, FULL>& 
         // of the block's centres (those wedges are counted on matrix cores)
         if (!FULL && blk >= 0 && hv.cblk[c] == blk) start = (uint32_t)hv.cpos[c];
         sh.c_cur[tid] = start | ((uint32_t)aneg[p] << 31);
-        sh.c_ce[tid] = (int32_t)coff[c + 1];
+        cm.ce = (int32_t)coff[c + 1];
         if constexpr (FULL) {
+            sh.c_ce[tid] = cm.ce;
             sh.c_id[tid] = c;
             sh.c_sum[tid] = 0;
         } else {
             const int2 bm = bmeta[c];
-            sh.c_base[tid] = bm.x;
-            sh.c_khi[tid] = bm.y;
+            cm.base = bm.x;
+            cm.khi = bm.y;
         }
     }
+    return cm;
 }
 
 // Position of the first compacted slice holding flattened wedge jq.
-template <int WG, int BAND_WORDS, bool FULL>
-__device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FULL>& sh, int32_t nkc, int32_t jq) {
+template <int WG>
+__device__ __forceinline__ int32_t slice_of(const SliceTable<WG>& t, int32_t nkc, int32_t jq) {
     int32_t k = 0, b = nkc - 1;
     while (k < b) {
         const int32_t mid = (k + b + 1) >> 1;
-        if (sh.w_pre[mid] <= jq) k = mid;
+        if (t.pre[mid] <= jq) k = mid;
         else b = mid - 1;
     }
     return k;
@@ -310,17 +325,19 @@ __device__ __forceinline__ int32_t slice_of(const WedgeShared<WG, BAND_WORDS, FU
 // (and a short advance when the lane crosses into the next slice).  Lanes
 // of a wave read consecutive entries of a list: coalesced 4-byte loads.
 // Slices of the current band (search and compaction).  Leaves the
-// compacted slice table in w_start / w_pre and ends with a barrier;
-// *total and *nkc receive the band's wedges and non-empty slices.
+// compacted slice table in t and ends with a barrier; *total and *nkc
+// receive the band's wedges and non-empty slices.
 template <bool FULL, int WG, int BAND_WORDS>
-__device__ __forceinline__ void compact_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
-                                             const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
-                                             int64_t hi, bool seek_start, bool last, int32_t& pre, bool use_pre,
-                                             int64_t next_hi, int32_t& total_out, int32_t& nkc_out) {
+__device__ __forceinline__ void compact_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, SliceTable<WG>& t,
+                                             const uint32_t* __restrict__ packed, const uint32_t* __restrict__ bidx,
+                                             int gs, int32_t nk, int64_t lo, int64_t hi, bool seek_start, bool last,
+                                             int32_t& pre, bool use_pre, int64_t next_hi, const CentreMeta& cm,
+                                             int32_t& total_out, int32_t& nkc_out) {
     constexpr int NW = WG / kWave;
     const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
-    // slice of each centre: start in w_start (scratch until the compaction),
-    // end as the new cursor in c_cur
+    // slice of each centre: start (per-vertex mode: in t.start, scratch
+    // until the compaction), end as the new cursor in c_cur
+    uint32_t slice = 0;
     if constexpr (FULL) {
         for (int32_t k = wave; k < nk; k += NW) {
             const uint32_t cur = sh.c_cur[k];
@@ -329,15 +346,17 @@ __device__ __forceinline__ void compact_band(WedgeShared<WG, BAND_WORDS, FULL>& 
             if (seek_start) st = wave_lower_bound(packed, st, ce, (uint32_t)lo);
             const int32_t en = last ? ce : wave_lower_bound(packed, st, ce, (uint32_t)hi);
             if (lane == 0) {
-                sh.w_start[k] = (uint32_t)st | (cur & 0x80000000u);
+                t.start[k] = (uint32_t)st | (cur & 0x80000000u);
                 sh.c_cur[k] = (uint32_t)en | (cur & 0x80000000u);
             }
         }
+        __syncthreads();
+        if (tid < nk) slice = t.start[tid];
     } else if (tid < nk) {
         // thread k owns centre k from here to the compaction: no barrier
         const uint32_t cur = sh.c_cur[tid];
         int32_t st = (int32_t)(cur & 0x7fffffffu);
-        const int32_t ce = sh.c_ce[tid], base = sh.c_base[tid], khi = sh.c_khi[tid];
+        const int32_t ce = cm.ce, base = cm.base, khi = cm.khi;
         // first position at or after q with rank >= bound (a granule
         // multiple above the anchor's own entry, so bound >> gs is at least
         // the first indexed granule of every list holding the anchor)
@@ -356,13 +375,12 @@ __device__ __forceinline__ void compact_band(WedgeShared<WG, BAND_WORDS, FULL>& 
             const int32_t kk = (int32_t)(next_hi >> gs);
             pre = kk > khi ? ce : (int32_t)bidx[base + kk];
         }
-        sh.w_start[tid] = (uint32_t)st | (cur & 0x80000000u);
+        slice = (uint32_t)st | (cur & 0x80000000u);
         sh.c_cur[tid] = (uint32_t)en | (cur & 0x80000000u);
     }
-    if constexpr (FULL) __syncthreads();
 
     // compact the non-empty slices: one scan carries (length, count << 40)
-    const uint32_t cur = tid < nk ? sh.w_start[tid] : 0u;
+    const uint32_t cur = slice;
     const int32_t len = tid < nk ? (int32_t)(sh.c_cur[tid] & 0x7fffffffu) - (int32_t)(cur & 0x7fffffffu) : 0;
     long long tot;
     const long long ex =
@@ -371,14 +389,15 @@ __device__ __forceinline__ void compact_band(WedgeShared<WG, BAND_WORDS, FULL>& 
     const int32_t nkc = (int32_t)(tot >> 40);
     if (len > 0) {
         const int32_t idx = (int32_t)(ex >> 40);
-        sh.w_start[idx] = cur;
-        sh.w_pre[idx] = (int32_t)(ex & ((1ll << 40) - 1));
+        t.start[idx] = cur;
+        t.pre[idx] = (int32_t)(ex & ((1ll << 40) - 1));
         if constexpr (FULL) sh.w_k[idx] = tid;
     }
-    if (tid == 0) sh.w_pre[nkc] = total;
+    if (tid == 0) t.pre[nkc] = total;
     __syncthreads();
-    total_out = total;
-    nkc_out = nkc;
+    // the same for every lane: keep them in scalar registers
+    total_out = __builtin_amdgcn_readfirstlane(total);
+    nkc_out = __builtin_amdgcn_readfirstlane(nkc);
 }
 
 // One wave's walk over its rows of the compacted band: row range, the
@@ -408,9 +427,9 @@ struct Batch {
 
 // Loads the batch of kUnroll rows at row w.r into x.  Advances the slice
 // cursor, not w.j.
-template <int WG, int BAND_WORDS, bool FULL>
-__device__ __forceinline__ Batch load_batch(const WedgeShared<WG, BAND_WORDS, FULL>& sh,
-                                            const uint32_t* __restrict__ packed, RowWalk& w) {
+template <int WG>
+__device__ __forceinline__ Batch load_batch(const SliceTable<WG>& t, const uint32_t* __restrict__ packed,
+                                            RowWalk& w) {
     Batch bt;
     uint32_t(&x)[kUnroll] = bt.x;
     if (w.r + kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb)) {
@@ -431,11 +450,11 @@ __device__ __forceinline__ Batch load_batch(const WedgeShared<WG, BAND_WORDS, FU
             const int32_t jj = w.j + u * kWave;
             x[u] = spread;
             if (w.r + u < w.r1 && jj < w.total) {
-                while (jj >= w.nb) {  // stays below nkc: w_pre[nkc] = total > jj
+                while (jj >= w.nb) {  // stays below nkc: t.pre[nkc] = total > jj
                     ++w.k;
-                    w.nb = sh.w_pre[w.k + 1];
-                    w.st = sh.w_start[w.k];
-                    w.base = (int32_t)(w.st & 0x7fffffffu) - sh.w_pre[w.k];
+                    w.nb = t.pre[w.k + 1];
+                    w.st = t.start[w.k];
+                    w.base = (int32_t)(w.st & 0x7fffffffu) - t.pre[w.k];
                 }
                 x[u] = packed[(uint32_t)(w.base + jj)];
                 ngm |= (w.st >> 31) << u;
@@ -487,12 +506,11 @@ __device__ __forceinline__ void count_batch(WedgeShared<WG, BAND_WORDS, FULL>& s
 
 // Sets up this wave's rows of a compacted band (contiguous runs of rows per
 // wave) and issues the loads of its first batch.
-template <int WG, int BAND_WORDS, bool FULL>
-__device__ __forceinline__ void walk_start(const WedgeShared<WG, BAND_WORDS, FULL>& sh,
-                                           const uint32_t* __restrict__ packed, int32_t total, int32_t nkc,
-                                           RowWalk& w, Batch& next, bool& have_next) {
+template <int WG>
+__device__ __forceinline__ void walk_start(const SliceTable<WG>& t, const uint32_t* __restrict__ packed,
+                                           int32_t total, int32_t nkc, RowWalk& w, Batch& next, bool& have_next) {
     constexpr int NW = WG / kWave;
-    const int wave = threadIdx.x / kWave, lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
     const int32_t rows = (total + kWave - 1) / kWave;
     const int32_t rpw = (rows + NW - 1) / NW;
     w.r = wave * rpw;
@@ -501,11 +519,11 @@ __device__ __forceinline__ void walk_start(const WedgeShared<WG, BAND_WORDS, FUL
     have_next = false;
     if (w.r < w.r1) {
         w.j = w.r * kWave + lane;
-        w.k = slice_of(sh, nkc, min(w.j, total - 1));
-        w.nb = sh.w_pre[w.k + 1];
-        w.st = sh.w_start[w.k];
-        w.base = (int32_t)(w.st & 0x7fffffffu) - sh.w_pre[w.k];
-        next = load_batch(sh, packed, w);
+        w.k = slice_of(t, nkc, min(w.j, total - 1));
+        w.nb = t.pre[w.k + 1];
+        w.st = t.start[w.k];
+        w.base = (int32_t)(w.st & 0x7fffffffu) - t.pre[w.k];
+        next = load_batch(t, packed, w);
         have_next = true;
     }
 }
@@ -514,10 +532,11 @@ __device__ __forceinline__ void walk_start(const WedgeShared<WG, BAND_WORDS, FUL
 // is loaded before the current one is counted when it lies inside every
 // lane's slice.
 template <int MODE, int WG, int BAND_WORDS, bool FULL>
-__device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
-                                          bool dense, RowWalk& w, Batch& next, bool& have_next) {
+__device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh, const SliceTable<WG>& t,
+                                          const uint32_t* __restrict__ packed, bool dense, RowWalk& w, Batch& next,
+                                          bool& have_next) {
     for (; w.r < w.r1; w.r += kUnroll) {
-        const Batch cur = have_next ? next : load_batch(sh, packed, w);
+        const Batch cur = have_next ? next : load_batch(t, packed, w);
         w.j += kUnroll * kWave;
         have_next = w.r + 2 * kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb);
         if (have_next) {
@@ -548,11 +567,12 @@ template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
                                           const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
                                           int64_t hi, bool seek_start, bool last, int32_t self, int phases,
-                                          int32_t& pre, bool use_pre, int64_t next_hi) {
+                                          int32_t& pre, bool use_pre, int64_t next_hi, const CentreMeta& cm) {
     constexpr int NW = WG / kWave;
-    const int tid = threadIdx.x, wave = tid / kWave, lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
+    SliceTable<WG>& t = sh.tab[0];
     int32_t total, nkc;
-    compact_band(sh, packed, bidx, gs, nk, lo, hi, seek_start, last, pre, use_pre, next_hi, total, nkc);
+    compact_band(sh, t, packed, bidx, gs, nk, lo, hi, seek_start, last, pre, use_pre, next_hi, cm, total, nkc);
     const bool dense = dense_band<BAND_WORDS>(total);
     const int32_t rows = (total + kWave - 1) / kWave;
     const int32_t rpw = (rows + NW - 1) / NW;
@@ -561,8 +581,8 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         RowWalk w;
         Batch next;
         bool have_next;
-        walk_start(sh, packed, total, nkc, w, next, have_next);
-        walk_rows<MODE>(sh, packed, dense, w, next, have_next);
+        walk_start(t, packed, total, nkc, w, next, have_next);
+        walk_rows<MODE>(sh, t, packed, dense, w, next, have_next);
     }
     __syncthreads();
 
@@ -571,10 +591,10 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         if ((phases & 2) && r0 < r1) {
             constexpr uint32_t fmask = MODE == 0 ? 15u : MODE == 1 ? 255u : MODE == 2 ? 0xffffu : 0xffffffffu;
             int32_t j = r0 * kWave + lane;
-            int32_t k = slice_of(sh, nkc, min(j, total - 1));
-            int32_t nb = sh.w_pre[k + 1];
-            uint32_t st = sh.w_start[k];
-            int32_t base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+            int32_t k = slice_of(t, nkc, min(j, total - 1));
+            int32_t nb = t.pre[k + 1];
+            uint32_t st = t.start[k];
+            int32_t base = (int32_t)(st & 0x7fffffffu) - t.pre[k];
             unsigned long long run = 0;
             for (int32_t r = r0; r < r1; ++r, j += kWave) {
                 if (j >= total) continue;
@@ -582,9 +602,9 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
                     if (run) atomicAdd(&sh.c_sum[sh.w_k[k]], run);
                     run = 0;
                     ++k;
-                    nb = sh.w_pre[k + 1];
-                    st = sh.w_start[k];
-                    base = (int32_t)(st & 0x7fffffffu) - sh.w_pre[k];
+                    nb = t.pre[k + 1];
+                    st = t.start[k];
+                    base = (int32_t)(st & 0x7fffffffu) - t.pre[k];
                 }
                 const uint32_t x = packed[(uint32_t)(base + j)];
                 if ((int32_t)(x >> 1) != self) {
@@ -711,8 +731,57 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             cr.row = hv.tabs + B.tab_off + (int64_t)(r - B.rank0) * B.rpad;
         }
     }
-    if (deg <= WG) {
-        load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, 0, deg, blk, hv);
+    if (deg <= WG && !FULL) {
+        // count mode, one chunk of centres: the next band is compacted and
+        // its first loads are issued before the current band is reduced, so
+        // the loads travel while the counters are summed and cleared
+        const CentreMeta cm = load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, 0, deg, blk, hv);
+        __syncthreads();
+        int32_t pre = 0;  // prefetched end of the band after the current one
+        int64_t lo = lo0, hi = band_end(lo);
+        int buf = 0;
+        int32_t total, nkc;
+        RowWalk w;
+        Batch next;
+        bool have_next;
+        {
+            const int64_t nh = hi < n_s ? band_end(hi) : -1;
+            compact_band(sh, sh.tab[0], packed, bidx, gs, deg, lo, hi, false, hi == n_s, pre, false,
+                         nh < n_s ? nh : -1, cm, total, nkc);
+            walk_start(sh.tab[0], packed, total, nkc, w, next, have_next);
+        }
+        for (;;) {
+            const bool dense = dense_band<BAND_WORDS>(total);
+            walk_rows<MODE>(sh, sh.tab[buf], packed, dense, w, next, have_next);
+            __syncthreads();
+            const bool more = hi < n_s;
+            const int64_t lo2 = hi;
+            int64_t hi2 = hi;
+            int32_t total2 = 0, nkc2 = 0;
+            RowWalk w2;
+            Batch next2;
+            bool have_next2 = false;
+            if (more) {
+                hi2 = band_end(lo2);
+                const int64_t nh = hi2 < n_s ? band_end(hi2) : -1;
+                compact_band(sh, sh.tab[buf ^ 1], packed, bidx, gs, deg, lo2, hi2, false, hi2 == n_s, pre, true,
+                             nh < n_s ? nh : -1, cm, total2, nkc2);
+                walk_start(sh.tab[buf ^ 1], packed, total2, nkc2, w2, next2, have_next2);
+            }
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
+            ++bands;
+            if (!more) break;
+            lo = lo2;
+            hi = hi2;
+            total = total2;
+            nkc = nkc2;
+            w = w2;
+            next = next2;
+            have_next = have_next2;
+            buf ^= 1;
+        }
+    } else if (deg <= WG) {
+        const CentreMeta cm = load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, 0, deg, blk, hv);
         __syncthreads();
         int32_t pre = 0;  // prefetched end of the band after the current one
         for (int64_t lo = lo0, hi; lo < n_s; lo = hi) {
@@ -720,7 +789,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             // the next band's end is a granule multiple unless it is the last band
             const int64_t nh = hi < n_s ? band_end(hi) : -1;
             const bool dense = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
-                                                     FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1);
+                                                     FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
             acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
             ++bands;
         }
@@ -735,20 +804,23 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             bool dense = false;  // any chunk dense: the band is reduced by a full scan
             for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                 const int32_t nk = min(WG, deg - k0);
-                load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
+                const CentreMeta cm =
+                    load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
                 __syncthreads();
                 int32_t pre = 0;
                 dense |= walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 1, pre, false,
-                                               -1);
+                                               -1, cm);
             }
             if constexpr (FULL) {
                 // second pass over the chunks once every wedge of the band is counted
                 for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                     const int32_t nk = min(WG, deg - k0);
-                    load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
+                    const CentreMeta cm =
+                        load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
                     __syncthreads();
                     int32_t pre = 0;
-                    walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 2, pre, false, -1);
+                    walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 2, pre, false, -1,
+                                          cm);
                     if (threadIdx.x < nk && sh.c_sum[threadIdx.x])
                         atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
                 }
@@ -764,7 +836,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
 // each graph, n_graphs + 1 entries) and per-graph totals; an anchor's
 // endpoints then stop at the end of its graph's rank range.
 template <int WG, int BAND_WORDS, bool FULL>
-__global__ __launch_bounds__(WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
+__global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
                                               const uint32_t* __restrict__ bidx, const int2* __restrict__ bmeta,
