@@ -756,8 +756,9 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     }
     rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr, &db, &dt);
     if (rc != BBC_OK) return rc;
-    // per-vertex mode sums every anchor's pairs from both ends
-    *total = full ? (uint64_t)ctx->st_host->total / 2 : (uint64_t)ctx->st_host->total;
+    // the kernels sum twice the pair terms (per-vertex mode: every anchor's
+    // pairs, seen from both ends)
+    *total = (uint64_t)ctx->st_host->total / 2;
     return BBC_OK;
 }
 

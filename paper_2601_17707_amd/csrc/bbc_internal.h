@@ -17,7 +17,7 @@ struct DevStatus {
     int64_t bad_sign;
     int64_t bad_dup;
     int64_t bad_block;          // first offending dense-block vertex (block * 2^32 + position)
-    unsigned long long total;   // balanced butterflies
+    unsigned long long total;   // twice the balanced butterflies
     unsigned long long wedges;  // sum over centres of C(deg, 2)
     unsigned long long walked;  // wedges the sparse walk visits (dense-block wedges excluded)
     unsigned long long bands;   // counter bands processed

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
                 if (gu < gw && gw < B.n_r) {
                     const uint32_t P = (uint32_t)accP[i][j][e], D = (uint32_t)accD[i][j][e];
                     const uint32_t a = (P + D) >> 1, b = (P - D) >> 1;
-                    acc += (unsigned long long)(a * (a - (a > 0u)) >> 1) + (b * (b - (b > 0u)) >> 1);
+                    acc += (unsigned long long)(a * (a - (a > 0u))) + b * (b - (b > 0u));  // twice the pair terms
                     tab[(int64_t)gu * B.rpad + gw] = a | (b << 16);
                 }
             }

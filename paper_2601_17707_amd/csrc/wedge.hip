@@ -71,37 +71,42 @@ __device__ __forceinline__ int32_t wave_lower_bound(const uint32_t* __restrict__
 }
 
 // Pair terms of the counter fields of LDS words: sum over fields x of
-// C(x,2) = (x^2 - x) / 2.  The sums of x^2 and of x over a word are single
-// packed dot-product instructions (the word with itself, and with a word of
-// ones), so no field is unpacked; x^2 - x is even, so halving the
-// difference is exact.  Modes 0 and 1 keep 32-bit partial sums per band and
-// thread (at most 64 words per thread and band, each below 2^18); modes 2
-// and 3 widen per word.
-template <int MODE>
+// C(x,2) = (x^2 - x) / 2.  The sum of x^2 over a word is one packed
+// dot-product instruction (the word with itself), so no field is unpacked.
+// In count mode (TWICE) only the squares are summed: the band's sum of x is
+// its number of wedges, which the caller subtracts once, and the kernel
+// carries twice the pair terms.  Otherwise the sum of x is the dot product
+// with a word of ones and x^2 - x, always even, is halved per thread.
+// Modes 0 and 1 keep 32-bit partial sums per band and thread (at most 64
+// words per thread and band, each below 2^18); modes 2 and 3 widen per
+// word (in mode 2, a + b <= 65535, so a^2 + b^2 fits 32 bits).
+template <int MODE, bool TWICE>
 struct PairSum {
     uint32_t sq = 0, lin = 0;
     unsigned long long wide = 0;
     __device__ __forceinline__ void add(uint32_t v) {
         if constexpr (MODE == 0) {  // eight 4-bit fields
             sq = __builtin_amdgcn_udot8(v, v, sq, false);
-            lin = __builtin_amdgcn_udot8(v, 0x11111111u, lin, false);
+            if constexpr (!TWICE) lin = __builtin_amdgcn_udot8(v, 0x11111111u, lin, false);
         } else if constexpr (MODE == 1) {  // four 8-bit fields
             sq = __builtin_amdgcn_udot4(v, v, sq, false);
-            lin = __builtin_amdgcn_udot4(v, 0x01010101u, lin, false);
-        } else if constexpr (MODE == 2) {  // a and b of one endpoint, a + b <= 65535: the squares fit 32 bits
+            if constexpr (!TWICE) lin = __builtin_amdgcn_udot4(v, 0x01010101u, lin, false);
+        } else if constexpr (MODE == 2) {  // a and b of one endpoint
             typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
             const u16x2 h = __builtin_bit_cast(u16x2, v);
             const uint32_t q = __builtin_amdgcn_udot2(h, h, 0u, false);
-            wide += (q - ((v & 0xffffu) + (v >> 16))) >> 1;
+            if constexpr (TWICE) wide += q;
+            else wide += (q - ((v & 0xffffu) + (v >> 16))) >> 1;
         } else {  // one 32-bit field
             const unsigned long long a = v;
-            wide += a * (a - (a > 0)) / 2;
+            if constexpr (TWICE) wide += a * a;
+            else wide += a * (a - (a > 0)) / 2;
         }
     }
-    // The pair terms added so far, and restarts.
+    // The sums added so far, and restarts.
     __device__ __forceinline__ unsigned long long take() {
         unsigned long long r = wide;
-        if constexpr (MODE <= 1) r += (sq - lin) >> 1;
+        if constexpr (MODE <= 1) r += TWICE ? (unsigned long long)sq : (unsigned long long)((sq - lin) >> 1);
         sq = lin = 0;
         wide = 0;
         return r;
@@ -411,12 +416,13 @@ struct RowWalk {
 };
 
 // A batch of kUnroll rows (one element per lane and row) and the signs of
-// its anchor edges (bit u: the anchor edge of row u is negative).  A full
-// batch (the same for every lane of the wave) lies inside each lane's
-// current slice: every element is a wedge and ngmask is all ones or zero.
-// Otherwise only the first `rows` rows belong to the wave (the same for
-// every lane) and bit u of vmask says whether row u holds a wedge for this
-// lane (lanes past the band's last wedge hold none).
+// its anchor edges (bit u: the anchor edge of row u is negative); the signs
+// are applied when the batch is counted, so that the loads stay in flight
+// until then.  A full batch (the same for every lane of the wave) lies
+// inside each lane's current slice: every element is a wedge and ngmask is
+// all ones or zero.  Otherwise only the first `rows` rows belong to the
+// wave (the same for every lane) and bit u of vmask says whether row u
+// holds a wedge for this lane (lanes past the band's last wedge hold none).
 struct Batch {
     uint32_t x[kUnroll];
     uint32_t ngmask;
@@ -562,9 +568,9 @@ __device__ __forceinline__ bool dense_band(int32_t total) { return total >= BAND
 // One band in one call: compaction, walk, and in per-vertex mode the centre
 // walk (phases: bit 0 counts the wedges, bit 1 runs the centre walk, which
 // needs the band's counters complete over every centre of the anchor).
-// Returns whether the band was dense.
+// Returns the band's wedges.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
-__device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
+__device__ __forceinline__ int32_t walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
                                           const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
                                           int64_t hi, bool seek_start, bool last, int32_t self, int phases,
                                           int32_t& pre, bool use_pre, int64_t next_hi, const CentreMeta& cm) {
@@ -617,7 +623,7 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         }
         __syncthreads();
     }
-    return dense;
+    return total;
 }
 
 // Sum of the pair terms of every touched counter word, and clears them.
@@ -628,7 +634,8 @@ __device__ __forceinline__ bool walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh,
 // same block is added.  Ends with a barrier.
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, int64_t lo,
-                                                          int64_t hi, int32_t self, const CrossRow& cr, bool dense) {
+                                                          int64_t hi, int32_t self, const CrossRow& cr, bool dense,
+                                                          int32_t total) {
     const bool cross = cr.row && lo < cr.rank0 + cr.n_r && hi > cr.rank0;
     uint32_t sw0 = 0xffffffffu, sm0 = 0, sw1 = 0xffffffffu, sm1 = 0;
     if constexpr (FULL) {
@@ -644,7 +651,7 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
         }
     }
     unsigned long long acc = 0;
-    PairSum<MODE> ps;
+    PairSum<MODE, !FULL> ps;
     auto word_terms = [&](uint32_t wd, uint32_t v) {
         if constexpr (FULL) {
             if (wd == sw0) v &= ~sm0;
@@ -687,7 +694,10 @@ __device__ __forceinline__ unsigned long long reduce_band(WedgeShared<WG, BAND_W
         }
     }
     __syncthreads();
-    return acc + ps.take();
+    if constexpr (FULL) return acc + ps.take();
+    // count mode: twice the pair terms, the band's wedges subtracted once
+    // (modular arithmetic: only the workgroup's sum is meaningful)
+    return 2 * acc + ps.take() - (threadIdx.x == 0 ? (unsigned long long)total : 0ull);
 }
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
@@ -703,7 +713,8 @@ constexpr int granule_shift() { return ilog2(BAND_WORDS) - 1; }
 // centres per chunk and seek the band start.  In count mode the first band
 // is [r + 1, the last granule multiple <= r + 1 + capacity), the next ones
 // start and end on granule multiples.  Returns this thread's share of the
-// anchor's pair terms.
+// anchor's pair terms (twice the pair terms in count mode; the shares are
+// meaningful only summed over the workgroup).
 template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh, const int32_t* __restrict__ acent,
                                            const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
@@ -768,7 +779,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                              nh < n_s ? nh : -1, cm, total2, nkc2);
                 walk_start(sh.tab[buf ^ 1], packed, total2, nkc2, w2, next2, have_next2);
             }
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
             if (!more) break;
             lo = lo2;
@@ -788,9 +799,9 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             hi = band_end(lo);
             // the next band's end is a granule multiple unless it is the last band
             const int64_t nh = hi < n_s ? band_end(hi) : -1;
-            const bool dense = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
-                                                     FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
+            const int32_t total = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
+                                                        FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense_band<BAND_WORDS>(total), total);
             ++bands;
         }
         if constexpr (FULL) {
@@ -802,14 +813,17 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             hi = band_end(lo);
             const bool first = lo == lo0;
             bool dense = false;  // any chunk dense: the band is reduced by a full scan
+            int32_t total = 0;
             for (int32_t k0 = 0; k0 < deg; k0 += WG) {
                 const int32_t nk = min(WG, deg - k0);
                 const CentreMeta cm =
                     load_centres<FULL>(sh, acent, aneg, back, coff, bmeta, a0, k0, nk, blk, hv);
                 __syncthreads();
                 int32_t pre = 0;
-                dense |= walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 1, pre, false,
-                                               -1, cm);
+                const int32_t tc = walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 1,
+                                                         pre, false, -1, cm);
+                dense |= dense_band<BAND_WORDS>(tc);
+                total += tc;
             }
             if constexpr (FULL) {
                 // second pass over the chunks once every wedge of the band is counted
@@ -825,7 +839,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                         atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
                 }
             }
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense);
+            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
         }
     }
@@ -881,7 +895,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             if (tid == 0) pv[anchor_base + inv[r]] = s;
         } else if (gtotals) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
-            if (tid == 0 && s) atomicAdd(&gtotals[agraph[r]], s);
+            if (tid == 0 && s) atomicAdd(&gtotals[agraph[r]], s >> 1);  // twice the pair terms
         }
         acc += a;
     }
