@@ -17,7 +17,8 @@ void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* 
 void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
                            const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
                            uint32_t* ea, uint32_t* ec, uint8_t* en, hipStream_t s);
-void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st, hipStream_t s);
+void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,
+                 int64_t scratch_words, const DevStatus* st, hipStream_t s);
 void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
@@ -285,17 +286,15 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
 
     // degrees and ranks (Definition 6: degree, then id; ascending; a batch
     // orders by graph first)
+    // (histogram replicas live in k_a, free until the edge sort)
     if (J.batched) {
-        fill_u32(P.deg_s, 0u, n_s, s);
-        fill_u32(P.deg_c, 0u, n_c, s);
-        launch_hist(ea, m, P.deg_s, st, s);
-        launch_hist(ec, m, P.deg_c, st, s);
+        launch_hist(ea, m, P.deg_s, n_s, P.k_a, m, st, s);
+        launch_hist(ec, m, P.deg_c, n_c, P.k_a, m, st, s);
     } else {  // the U side's degrees are the CSR row lengths
         uint32_t* deg_u = J.s_is_u ? P.deg_s : P.deg_c;
         uint32_t* deg_v = J.s_is_u ? P.deg_c : P.deg_s;
         launch_row_degrees(J.off, J.n_u, deg_u, st, s);
-        fill_u32(deg_v, 0u, J.n_v, s);
-        launch_hist(J.s_is_u ? ec : ea, m, deg_v, st, s);
+        launch_hist(J.s_is_u ? ec : ea, m, deg_v, J.n_v, P.k_a, m, st, s);
     }
     const uint32_t *rk_k = nullptr, *inv = nullptr;
     radix_sort(P.deg_s, P.rk_ka, P.rk_kb, nullptr, nullptr, nullptr, nullptr, P.rk_va, P.rk_vb, n_s,

@@ -120,6 +120,25 @@ __global__ void k_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevS
     GRID_STRIDE(i, n) atomicAdd(&deg[ids[i]], 1u);
 }
 
+// The same histogram over nrep zeroed replicas: workgroup b adds into
+// replica b % nrep (consecutive workgroups run on different XCDs), which
+// spreads the atomics on the few ids of very high degree; k_hist_sum then
+// adds the replicas up into deg.
+__global__ void k_hist_rep(const uint32_t* ids, int64_t n, uint32_t* rep, int64_t n_bins, int nrep,
+                           const DevStatus* st) {
+    if (input_bad(st)) return;
+    uint32_t* h = rep + (int64_t)(blockIdx.x % nrep) * n_bins;
+    GRID_STRIDE(i, n) atomicAdd(&h[ids[i]], 1u);
+}
+
+__global__ void k_hist_sum(const uint32_t* rep, int64_t n_bins, int nrep, uint32_t* deg) {
+    GRID_STRIDE(v, n_bins) {
+        uint32_t s = 0;
+        for (int c = 0; c < nrep; ++c) s += rep[(int64_t)c * n_bins + v];
+        deg[v] = s;
+    }
+}
+
 // Degrees of the CSR rows (U) straight from the offsets.
 __global__ void k_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st) {
     const bool bad = input_bad(st);
@@ -339,8 +358,18 @@ void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const
                            vstart, n_graphs, m, check_sign, st, ea, ec, en);
 }
 
-void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, const DevStatus* st, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256)), dim3(256), 0, s, ids, n, deg, st);
+void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,
+                 int64_t scratch_words, const DevStatus* st, hipStream_t s) {
+    const int nrep = n_bins > 0 ? (int)std::min<int64_t>(8, scratch_words / n_bins) : 0;
+    if (nrep < 2) {  // no room for replicas: one histogram
+        fill_u32(deg, 0u, n_bins, s);
+        if (n > 0) hipLaunchKernelGGL(k_hist, dim3(grid_for(n, 256)), dim3(256), 0, s, ids, n, deg, st);
+        return;
+    }
+    fill_u32(scratch, 0u, (int64_t)nrep * n_bins, s);
+    if (n > 0)
+        hipLaunchKernelGGL(k_hist_rep, dim3(grid_for(n, 256)), dim3(256), 0, s, ids, n, scratch, n_bins, nrep, st);
+    hipLaunchKernelGGL(k_hist_sum, dim3(grid_for(n_bins, 256)), dim3(256), 0, s, scratch, n_bins, nrep, deg);
 }
 
 void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s) {
