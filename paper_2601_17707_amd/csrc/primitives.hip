@@ -153,14 +153,17 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* keys, in
 }
 
 // Stable scatter of one tile, staged through LDS so that global writes are
-// runs of consecutive positions.  Items are visited in rounds of 256
-// (round, then wave, then lane is the input order).  Within a wave, the
-// lanes that share a digit are found with eight ballots; a lane's place
-// among them is the number of such lanes below it.  Wave counts are turned
-// into offsets per round by the thread that owns the digit.  Each item
-// first goes to its place in the tile sorted by digit (in LDS); the sorted
-// tile is then written out in order, every digit's run at its global
-// offset.
+// runs of consecutive positions.  Wave w owns the tile's items
+// [w * 1024, (w + 1) * 1024), visited in 16 rounds of 64, so the input
+// order is (wave, round, lane).  Within a round the lanes that share a
+// digit are found with eight ballots; an item's place among its wave's
+// items of that digit is the wave's running count of the digit plus the
+// number of such lanes below it (the lowest of them then advances the
+// count; a wave's LDS operations complete in order).  After one barrier
+// every digit's places are offset by the counts of the waves before, each
+// item goes to its place in the tile sorted by digit (in LDS), and the
+// sorted tile is written out in order, every digit's run at its global
+// offset.  Items stay in registers between the phases.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys, uint32_t* keys_out,
                                                            const uint32_t* v0, uint32_t* v0_out,
                                                            const uint32_t* v1, uint32_t* v1_out, int v1_iota,
@@ -169,66 +172,75 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
     __shared__ uint32_t s_key[kRsTile];
     __shared__ uint32_t s_v0[kRsTile];
     __shared__ uint32_t s_v1[kRsTile];
-    __shared__ uint32_t running[256];
     __shared__ uint32_t lstart[256];  // first place of each digit in the sorted tile
     __shared__ uint32_t gstart[256];  // global position of that place
     __shared__ uint32_t wcnt[kRsWaves][256];
-    __shared__ uint32_t woff[kRsWaves][256];
     __shared__ uint32_t scan_tmp[kRsWaves + 1];
     const int t = threadIdx.x, w = t / kWave, lane = lane_id();
     const uint32_t cnt = hist[(int64_t)t * nblk + blockIdx.x];
     uint32_t tot;
     const uint32_t ls = block_exclusive_scan<kRsThreads>(cnt, scan_tmp, &tot);
     lstart[t] = ls;
-    running[t] = ls;
     gstart[t] = hist_scan[(int64_t)t * nblk + blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kRsWaves; ++k) wcnt[k][t] = 0;
     __syncthreads();
     const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * (kRsRounds * kWave);
+    uint32_t key[kRsRounds], a[kRsRounds], b[kRsRounds], place[kRsRounds];
+#pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kRsThreads + t;
+        const int64_t i = base + (int64_t)r * kWave + lane;
         const bool valid = i < n;
-        const uint32_t key = valid ? keys[i] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        key[r] = valid ? keys[i] : 0u;
+        a[r] = (valid && with_v0) ? v0[i] : 0u;
+        b[r] = (valid && with_v1) ? (v1_iota ? (uint32_t)i : v1[i]) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        const bool valid = base + (int64_t)r * kWave + lane < n;
+        const uint32_t d = (key[r] >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int bit = (d >> b) & 1u;
-            const unsigned long long m = __ballot(bit);
-            peers &= bit ? m : ~m;
+        for (int bit = 0; bit < 8; ++bit) {
+            const int on = (d >> bit) & 1u;
+            const unsigned long long m = __ballot(on);
+            peers &= on ? m : ~m;
         }
         const uint32_t rk = (uint32_t)__popcll(peers & below);
-        if (valid && rk == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {
-            uint32_t run = running[t];
+        const uint32_t run = wcnt[w][d];
+        place[r] = run + rk;
+        if (valid && rk == 0) wcnt[w][d] = run + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {  // digit t: offset of each wave's places
+        uint32_t off = lstart[t];
 #pragma unroll
-            for (int k = 0; k < kRsWaves; ++k) {
-                const uint32_t c = wcnt[k][t];
-                woff[k][t] = run;
-                run += c;
-                wcnt[k][t] = 0;
-            }
-            running[t] = run;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = woff[w][d] + rk;  // place in the sorted tile
-            s_key[pos] = key;
-            if (with_v0) s_v0[pos] = v0[i];
-            if (with_v1) s_v1[pos] = v1_iota ? (uint32_t)i : v1[i];
+        for (int k = 0; k < kRsWaves; ++k) {
+            const uint32_t c = wcnt[k][t];
+            wcnt[k][t] = off;
+            off += c;
         }
     }
     __syncthreads();
-    const uint32_t tile_n = (uint32_t)min((int64_t)kRsTile, n - base);
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        if (base + (int64_t)r * kWave + lane < n) {
+            const uint32_t pos = wcnt[w][(key[r] >> shift) & 255u] + place[r];
+            s_key[pos] = key[r];
+            if (with_v0) s_v0[pos] = a[r];
+            if (with_v1) s_v1[pos] = b[r];
+        }
+    }
+    __syncthreads();
+    const int64_t tbase = (int64_t)blockIdx.x * kRsTile;
+    const uint32_t tile_n = (uint32_t)min((int64_t)kRsTile, n - tbase);
     for (uint32_t p = t; p < tile_n; p += kRsThreads) {
-        const uint32_t key = s_key[p];
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t k = s_key[p];
+        const uint32_t d = (k >> shift) & 255u;
         const uint32_t g = gstart[d] + (p - lstart[d]);
-        keys_out[g] = key;
+        keys_out[g] = k;
         if (with_v0) v0_out[g] = s_v0[p];
         if (with_v1) v1_out[g] = s_v1[p];
     }
