@@ -183,6 +183,14 @@ def bench_hybrid(ctx, steps: int, warmup: int, seed: int) -> dict:
     dms = sum(dense_ms) / len(dense_ms)
     ctx.count(off, adj, sg, g.n_v, opts=opts_s)
     total_s, ms_s = timed_calls(opts_s, max(1, min(steps, 3)))
+    # the same graph with blocks found by the planner instead of the planted list
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    found = ctx.plan_blocks(off, adj, g.n_v)
+    plan_ms = 1000.0 * (time.perf_counter() - t)
+    opts_p = bbc.options(blocks=found)
+    ctx.count(off, adj, sg, g.n_v, opts=opts_p)
+    total_p, ms_p = timed_calls(opts_p, max(1, min(steps, 3)))
     tops = ops / (dms / 1e3) / 1e12
     return dict(workload=HYBRID_WORKLOAD, seed=seed, n_u=g.n_u, n_v=g.n_v, n_edges=g.m, blocks="16 x (4096 x 4096)",
                 wedges=int(st["wedges_all"]), wedges_sparse_walk=int(st["wedges"]),
@@ -191,7 +199,9 @@ def bench_hybrid(ctx, steps: int, warmup: int, seed: int) -> dict:
                 count_ms=sum(count_ms) / len(count_ms),
                 dense=dict(kernel="k_dense", ms=dms, int8_ops=ops, achieved=tops, peak=INT8_PEAK_TOPS, unit="TOP/s",
                            frac=tops / INT8_PEAK_TOPS, bound="mfma"),
-                balanced_butterflies=total_h, totals_match_sparse_only=bool(total_h == total_s))
+                balanced_butterflies=total_h, totals_match_sparse_only=bool(total_h == total_s),
+                planner=dict(ms=plan_ms, blocks=len(found), ms_per_call=ms_p, speedup_vs_sparse_only=ms_s / ms_p,
+                             totals_match=bool(total_p == total_s)))
 
 
 def main():

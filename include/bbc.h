@@ -235,6 +235,50 @@ bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path);
  * shape that is not instantiated; the table is unchanged on error. */
 bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path);
 
+/* Dense-block planner options.  Candidates are the vertices of degree >=
+ * min_degree.  A block grows from a seed anchor: C starts as the seed's
+ * candidate centres, then twice R = the candidate anchors linked to at
+ * least member_frac of C and C = the candidate centres linked to at least
+ * member_frac of R; it is kept when |R| >= min_anchors, |C| >= min_centres
+ * and |edges of R x C| >= min_density * |R| * |C|.  R is capped at 16,384
+ * and C at 65,535 vertices (the dense kernel's limits).  The search stops
+ * after max_tries seeds in a row give no block. */
+typedef struct {
+    uint32_t struct_size; /* sizeof(bbc_plan_options) */
+    int32_t side;         /* anchor side, BBC_SIDE_* as in bbc_options */
+    int32_t min_degree;   /* default 256 */
+    float member_frac;    /* default 0.3 */
+    float min_density;    /* default 0.25 */
+    int32_t min_anchors;  /* default 256 */
+    int32_t min_centres;  /* default 64 */
+    int32_t max_tries;    /* default 32 */
+} bbc_plan_options;
+
+/* Fills *opts with the defaults above. */
+bbc_status bbc_plan_options_init(bbc_plan_options* opts);
+
+/* Finds dense blocks for the int8 matrix-core path (bbc_options.blocks).
+ * The paper gives no planner (its counting is blocks-free); any choice of
+ * blocks keeps the count exact, so this heuristic only decides speed.
+ *   n_u, n_v, n_edges, offsets, adj  the graph as in bbc_count (device;
+ *                        signs are not needed)
+ *   opts                 host or NULL (defaults)
+ *   max_blocks           capacity of blocks
+ *   blocks               host, max_blocks entries: receive the blocks, ids
+ *                        pointing into `ids`
+ *   ids                  device, ids_cap int32: every block's U ids, then
+ *                        its V ids; the search stops before a block that
+ *                        would not fit
+ *   n_blocks             host: number of blocks written
+ * The blocks are pairwise disjoint and valid input for bbc_count with the
+ * same anchor side.  Synchronous.  Temporary device memory (about 17 bytes
+ * per edge) is allocated and freed inside the call.  Errors: BBC_EINVAL
+ * (null pointers, negative sizes, bad options), BBC_EOFFSETS, BBC_ERANGE,
+ * BBC_ENOMEM, BBC_EDEVICE, BBC_ETOOBIG. */
+bbc_status bbc_plan_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                           const int32_t* adj, const bbc_plan_options* opts, int32_t max_blocks,
+                           bbc_dense_block* blocks, int32_t* ids, int64_t ids_cap, int32_t* n_blocks, void* stream);
+
 /* Static strings; never NULL. */
 const char* bbc_status_string(bbc_status s);
 const char* bbc_last_error(const bbc_ctx* ctx);

@@ -54,6 +54,19 @@ class Options(ctypes.Structure):
     ]
 
 
+class PlanOptions(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("side", ctypes.c_int32),
+        ("min_degree", ctypes.c_int32),
+        ("member_frac", ctypes.c_float),
+        ("min_density", ctypes.c_float),
+        ("min_anchors", ctypes.c_int32),
+        ("min_centres", ctypes.c_int32),
+        ("max_tries", ctypes.c_int32),
+    ]
+
+
 class GraphDesc(ctypes.Structure):
     _fields_ = [
         ("n_u", ctypes.c_int32),
@@ -136,6 +149,11 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_tune_save.restype = ctypes.c_int
     lib.bbc_tune_load.argtypes = [vp, ctypes.c_char_p]
     lib.bbc_tune_load.restype = ctypes.c_int
+    lib.bbc_plan_options_init.argtypes = [ctypes.POINTER(PlanOptions)]
+    lib.bbc_plan_options_init.restype = ctypes.c_int
+    lib.bbc_plan_blocks.argtypes = [vp, i32, i32, i64, vp, vp, ctypes.POINTER(PlanOptions), i32,
+                                    ctypes.POINTER(DenseBlock), vp, i64, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.bbc_plan_blocks.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -165,6 +183,19 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
         o.n_blocks = len(blocks)
         o.blocks = ctypes.cast(arr, ctypes.POINTER(DenseBlock))
         o._keep = (arr, blocks)
+    return o
+
+
+def plan_options(side="auto", **kw) -> PlanOptions:
+    """Dense-block planner options (defaults from bbc_plan_options_init);
+    keyword arguments override fields by name."""
+    o = PlanOptions()
+    load_library().bbc_plan_options_init(ctypes.byref(o))
+    o.side = _SIDES[side]
+    for k, v in kw.items():
+        if k not in dict(PlanOptions._fields_):
+            raise TypeError(f"unknown plan option {k}")
+        setattr(o, k, v)
     return o
 
 
@@ -286,6 +317,32 @@ class Context:
         st = self._lib.bbc_tune_load(self._h, os.fsencode(path))
         if st != OK:
             raise BbcError(st, self.last_error())
+
+    def plan_blocks(self, offsets, adj, n_v: int, opts: PlanOptions | None = None, max_blocks: int = 64,
+                    stream=None) -> list:
+        """Dense blocks found by the planner, as (u_ids, v_ids) int32 device
+        tensors ready for ``options(blocks=...)``."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        n_u = offsets.numel() - 1
+        o = opts if opts is not None else plan_options()
+        cap = min(n_u + int(n_v), max_blocks * (16384 + 65535))
+        ids = torch.empty(max(cap, 1), dtype=torch.int32, device=offsets.device)
+        arr = (DenseBlock * max(max_blocks, 1))()
+        nb = ctypes.c_int32(0)
+        st = self._lib.bbc_plan_blocks(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj),
+                                       ctypes.byref(o), int(max_blocks), arr, ctypes.c_void_p(ids.data_ptr()),
+                                       cap, ctypes.byref(nb), _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        out, base = [], ids.data_ptr()
+        for i in range(nb.value):
+            b = arr[i]
+            pu, pv = (b.u_ids - base) // 4, (b.v_ids - base) // 4
+            out.append((ids[pu:pu + b.n_u_ids], ids[pv:pv + b.n_v_ids]))
+        return out
 
     def plan(self, batch: "Batch", opts: Options | None = None) -> "BatchPlan":
         return BatchPlan(self, batch, opts)

@@ -45,6 +45,18 @@ void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles,
 void launch_bidx(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int64_t n_c, int gs,
                  uint32_t* nb, uint32_t* ioff, uint32_t* idx, int2* meta, uint32_t* partials, const DevStatus* st,
                  hipStream_t s);
+void pl_scatter(const uint32_t* key, const uint32_t* val, int64_t m, const uint32_t* off, int64_t n_keys,
+                uint32_t* cur, uint32_t* out, hipStream_t s);
+void pl_cand_deg(const uint32_t* ea, const uint32_t* ec, int64_t m, const uint32_t* deg_a, const uint32_t* deg_c,
+                 uint32_t tau, uint32_t* cd, hipStream_t s);
+void pl_seed(const uint32_t* off_a, const uint32_t* adj_a, uint32_t seed, const uint32_t* deg_c, uint32_t tau,
+             const uint8_t* assigned_c, uint32_t* list, uint32_t* n, uint32_t cap, hipStream_t s);
+void pl_count(const uint32_t* list, const uint32_t* n, uint32_t cap, const uint32_t* off, const uint32_t* adj,
+              uint32_t* cnt, hipStream_t s);
+void pl_select(uint32_t* cnt, int64_t n, const uint32_t* deg, uint32_t tau, const uint8_t* assigned,
+               const uint32_t* n_other, uint32_t cap_other, float frac, uint32_t* out, uint32_t* n_out, uint32_t cap,
+               unsigned long long* edges, hipStream_t s);
+void pl_assign(const uint32_t* list, uint32_t n, uint8_t* assigned, hipStream_t s);
 bool wedge_shape_ok(int band_words, int wg);
 int wedge_block(int band_words, int wg, bool full);
 int wedge_blocks_per_cu(int band_words, int wg, bool full);
@@ -630,6 +642,21 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
 
 }  // namespace
 
+// Temporary device memory of one planner call, freed on every return path.
+struct PlanScratch {
+    std::vector<void*> ptrs;
+    ~PlanScratch() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    T* take(int64_t n) {
+        void* p = nullptr;
+        if (hipMalloc(&p, (size_t)(n > 0 ? n : 1) * sizeof(T)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return (T*)p;
+    }
+};
+
 extern "C" {
 
 void bbc_options_init(bbc_options* o) {
@@ -912,6 +939,164 @@ bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
         chosen->wg_size = best.wg_size;
         chosen->wg_per_cu = best.wg_per_cu;
     }
+    return BBC_OK;
+}
+
+bbc_status bbc_plan_options_init(bbc_plan_options* o) {
+    if (!o) return BBC_EINVAL;
+    *o = bbc_plan_options{sizeof(bbc_plan_options), BBC_SIDE_AUTO, 256, 0.3f, 0.25f, 256, 64, 32};
+    return BBC_OK;
+}
+
+bbc_status bbc_plan_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                           const int32_t* adj, const bbc_plan_options* opts_in, int32_t max_blocks,
+                           bbc_dense_block* blocks, int32_t* ids, int64_t ids_cap, int32_t* n_blocks, void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    if (!n_blocks) return fail(ctx, BBC_EINVAL, "n_blocks is NULL");
+    *n_blocks = 0;
+    bbc_plan_options o;
+    bbc_plan_options_init(&o);
+    if (opts_in) {
+        if (opts_in->struct_size != sizeof(bbc_plan_options))
+            return fail(ctx, BBC_EINVAL, "plan options: struct_size mismatch");
+        o = *opts_in;
+    }
+    if (o.side != BBC_SIDE_AUTO && o.side != BBC_SIDE_U && o.side != BBC_SIDE_V)
+        return fail(ctx, BBC_EINVAL, "plan options: bad side");
+    if (o.min_degree < 1 || !(o.member_frac > 0.f && o.member_frac <= 1.f) ||
+        !(o.min_density > 0.f && o.min_density <= 1.f) || o.min_anchors < 2 || o.min_centres < 1 ||
+        o.max_tries < 1)
+        return fail(ctx, BBC_EINVAL, "plan options out of range");
+    if (max_blocks < 0 || ids_cap < 0 || n_u < 0 || n_v < 0 || n_edges < 0)
+        return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    if (max_blocks > 0 && (!blocks || (ids_cap > 0 && !ids))) return fail(ctx, BBC_EINVAL, "output pointer is NULL");
+    if (!offsets || (n_edges > 0 && !adj)) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+    if (max_blocks == 0 || n_edges == 0) return BBC_OK;
+
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool su = side_is_u(o.side, n_u, n_v);
+    const int64_t m = n_edges, n_a = su ? n_u : n_v, n_c = su ? n_v : n_u;
+    const uint32_t tau = (uint32_t)o.min_degree;
+    constexpr uint32_t kCapR = 16384, kCapC = 65535;
+    PlanScratch P;
+    uint32_t* ea = P.take<uint32_t>(m);
+    uint32_t* ec = P.take<uint32_t>(m);
+    uint32_t* adj_a = P.take<uint32_t>(m);  // anchor -> centres
+    uint32_t* adj_c = P.take<uint32_t>(m);  // centre -> anchors
+    uint32_t* deg_a = P.take<uint32_t>(n_a);
+    uint32_t* deg_c = P.take<uint32_t>(n_c);
+    uint32_t* off_a = P.take<uint32_t>(n_a + 1);
+    uint32_t* off_c = P.take<uint32_t>(n_c + 1);
+    uint32_t* cur = P.take<uint32_t>(std::max(n_a, n_c));
+    uint32_t* cd = P.take<uint32_t>(n_a);
+    uint32_t* cnt_a = P.take<uint32_t>(n_a);
+    uint32_t* cnt_c = P.take<uint32_t>(n_c);
+    uint8_t* asg_a = P.take<uint8_t>(n_a);
+    uint8_t* asg_c = P.take<uint8_t>(n_c);
+    uint32_t* list_r = P.take<uint32_t>(kCapR);
+    uint32_t* list_c = P.take<uint32_t>(kCapC);
+    uint32_t* small = P.take<uint32_t>(8);  // [n_r, n_c] then edges (u64) at [2..3]
+    uint32_t* partials = P.take<uint32_t>((int64_t)scan_partials_size(std::max(n_a, n_c) + 8));
+    uint32_t* host = nullptr;  // pinned: the three counts read back per seed
+    if (!ea || !ec || !adj_a || !adj_c || !deg_a || !deg_c || !off_a || !off_c || !cur || !cd || !cnt_a || !cnt_c ||
+        !asg_a || !asg_c || !list_r || !list_c || !small || !partials)
+        return fail(ctx, BBC_ENOMEM, "plan: device memory");
+    if (hipHostMalloc((void**)&host, 4 * sizeof(uint32_t)) != hipSuccess)
+        return fail(ctx, BBC_ENOMEM, "plan: pinned host memory");
+    struct HostFree {
+        uint32_t* p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } host_free{host};
+
+    // edges as (anchor, centre) with the offset and id-range checks
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, ctx->st_dev);
+    launch_decode_single(offsets, adj, nullptr, n_u, n_v, m, su ? 1 : 0, 0, ctx->st_dev, ea, ec, nullptr, s);
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    bbc_status rc = status_result(ctx, *ctx->st_host);
+    if (rc != BBC_OK) return rc;
+
+    // both adjacency directions (degree histograms use adj_a as scratch before the scatter)
+    launch_hist(ea, m, deg_a, n_a, adj_a, m, ctx->st_dev, s);
+    launch_hist(ec, m, deg_c, n_c, adj_a, m, ctx->st_dev, s);
+    scan_exclusive_u32(deg_a, off_a, n_a, partials, s);
+    scan_exclusive_u32(deg_c, off_c, n_c, partials, s);
+    pl_scatter(ea, ec, m, off_a, n_a, cur, adj_a, s);
+    pl_scatter(ec, ea, m, off_c, n_c, cur, adj_c, s);
+    fill_u32(cd, 0u, n_a, s);
+    pl_cand_deg(ea, ec, m, deg_a, deg_c, tau, cd, s);
+    fill_u32(cnt_a, 0u, n_a, s);
+    fill_u32(cnt_c, 0u, n_c, s);
+    fill_bytes(asg_a, n_a, s);
+    fill_bytes(asg_c, n_c, s);
+
+    // seeds: candidate anchors by decreasing (candidate centres)^2 / degree
+    std::vector<uint32_t> h_deg(n_a), h_cd(n_a);
+    HIP_OR_FAIL(hipMemcpyAsync(h_deg.data(), deg_a, n_a * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipMemcpyAsync(h_cd.data(), cd, n_a * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    std::vector<std::pair<double, uint32_t>> seeds;
+    for (int64_t a = 0; a < n_a; ++a)
+        if (h_deg[a] >= tau && h_cd[a] >= (uint32_t)o.min_centres)
+            seeds.push_back({-(double)h_cd[a] * h_cd[a] / h_deg[a], (uint32_t)a});
+    std::sort(seeds.begin(), seeds.end());
+    std::vector<uint8_t> used(n_a, 0);
+
+    uint32_t* n_r = small;
+    uint32_t* n_cc = small + 1;
+    unsigned long long* edges = (unsigned long long*)(small + 2);
+    int32_t found = 0, tries = 0;
+    int64_t ids_used = 0;
+    std::vector<uint32_t> h_r;
+    for (const auto& sd : seeds) {
+        const uint32_t seed = sd.second;
+        if (used[seed]) continue;
+        fill_u32(small, 0u, 4, s);
+        pl_seed(off_a, adj_a, seed, deg_c, tau, asg_c, list_c, n_cc, kCapC, s);
+        for (int it = 0; it < 2; ++it) {
+            fill_u32(small, 0u, 1, s);
+            pl_count(list_c, n_cc, kCapC, off_c, adj_c, cnt_a, s);
+            pl_select(cnt_a, n_a, deg_a, tau, asg_a, n_cc, kCapC, o.member_frac, list_r, n_r, kCapR,
+                      edges, s);
+            fill_u32(small + 1, 0u, 3, s);
+            pl_count(list_r, n_r, kCapR, off_a, adj_a, cnt_c, s);
+            pl_select(cnt_c, n_c, deg_c, tau, asg_c, n_r, kCapR, o.member_frac, list_c, n_cc, kCapC, edges,
+                      s);
+        }
+        HIP_OR_FAIL(hipMemcpyAsync(host, small, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        const uint32_t nr = std::min(host[0], kCapR), nc = std::min(host[1], kCapC);
+        const unsigned long long e = (unsigned long long)host[2] | ((unsigned long long)host[3] << 32);
+        used[seed] = 1;
+        const bool keep = nr >= (uint32_t)o.min_anchors && nc >= (uint32_t)o.min_centres &&
+                          (double)e >= (double)o.min_density * nr * nc && ids_used + nr + nc <= ids_cap;
+        if (!keep) {
+            if (++tries >= o.max_tries) break;
+            continue;
+        }
+        tries = 0;
+        // U ids first, then V ids
+        const uint32_t* lu = su ? list_r : list_c;
+        const uint32_t* lv = su ? list_c : list_r;
+        const uint32_t nu = su ? nr : nc, nv = su ? nc : nr;
+        HIP_OR_FAIL(hipMemcpyAsync(ids + ids_used, lu, nu * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(ids + ids_used + nu, lv, nv * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        blocks[found] = bbc_dense_block{(int32_t)nu, (int32_t)nv, ids + ids_used, ids + ids_used + nu};
+        ids_used += nu + nv;
+        pl_assign(list_r, nr, asg_a, s);
+        pl_assign(list_c, nc, asg_c, s);
+        h_r.resize(nr);
+        HIP_OR_FAIL(hipMemcpyAsync(h_r.data(), list_r, nr * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        for (uint32_t r : h_r) used[r] = 1;
+        if (++found == max_blocks) break;
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    *n_blocks = found;
     return BBC_OK;
 }
 

@@ -77,12 +77,12 @@ __global__ void k_decode_single(const int32_t* off, const int32_t* adj, const in
     GRID_STRIDE(e, m) {
         const int32_t u = row_of(off, n_u, e);
         const int32_t v = adj[e];
-        const int8_t s = sg[e];
+        const int8_t s = sg ? sg[e] : (int8_t)1;  // no signs: the block planner
         if (v < 0 || v >= n_v) flag_bad(st, kBadRange, &st->bad_range, e);
         if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, e);
         ea[e] = (uint32_t)(s_is_u ? u : v);
         ec[e] = (uint32_t)(s_is_u ? v : u);
-        en[e] = s < 0 ? 1 : 0;
+        if (en) en[e] = s < 0 ? 1 : 0;
     }
 }
 

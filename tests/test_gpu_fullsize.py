@@ -66,3 +66,26 @@ def test_full_size_dense_blocks(ctx, key):
     assert ctx.count(off, adj, sg, g.n_v, opts=bbc.options(blocks=blocks)) == int(e["total"])
     st = ctx.stats()
     assert st["n_blocks"] == 16 and st["wedges"] < st["wedges_all"]
+
+
+@pytest.mark.parametrize("key", [k for k in sorted(EXPECTED) if k.startswith("hybrid")])
+def test_full_size_planned_blocks(ctx, key):
+    """The planner on the planted-block workload: it finds the 16 planted
+    blocks (Jaccard >= 0.9 on both sides) among 3M vertices (it may add
+    blocks of the background's densely linked hubs), and the count with its
+    blocks is the oracle's total."""
+    e = EXPECTED[key]
+    print("full size, planned blocks", key, flush=True)
+    g = synth.workload(e["workload"], e["seed"])
+    assert g.sha256() == e["sha256"], "generator output changed"
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    found = ctx.plan_blocks(off, adj, g.n_v)
+    print("planned", [(int(u.numel()), int(v.numel())) for u, v in found], flush=True)
+    assert len(found) >= 16
+    got = [(set(u.cpu().numpy().tolist()), set(v.cpu().numpy().tolist())) for u, v in found]
+    for r, c in g.meta["blocks"]:
+        rs, cs = set(r.tolist()), set(c.tolist())
+        best = max(got, key=lambda f: len(f[1] & rs))
+        assert len(best[1] & rs) / len(best[1] | rs) >= 0.9
+        assert len(best[0] & cs) / len(best[0] | cs) >= 0.9
+    assert ctx.count(off, adj, sg, g.n_v, opts=bbc.options(blocks=found)) == int(e["total"])
