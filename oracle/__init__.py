@@ -11,6 +11,8 @@ this package; it shares no code with the GPU library.
 * :func:`count_anchors` - the same over a range of anchors (timing samples);
 * :func:`brute` - Definitions 1 and 2 applied to every 2x2 vertex choice;
 * :func:`count_kinds` - balanced / unbalanced / all butterflies per pair;
+* :func:`count_classes` and :func:`brute_classes` - the six sign-pattern
+  classes of the case study (Table 8), by the walk and by brute force;
 * :func:`per_vertex`, :func:`vertex` and :func:`vertices` - balanced butterflies containing
   each vertex (the paper reports totals only; see the C header).
 
@@ -56,11 +58,13 @@ def _load():
         lib.oracle_per_vertex.argtypes = head + [ctypes.c_int, PU]
         lib.oracle_vertex.argtypes = head + [i64, PU]
         lib.oracle_brute.argtypes = head + [PU, PU, PU]
+        lib.oracle_count_classes.argtypes = head + [ctypes.c_int, PU]
+        lib.oracle_brute_classes.argtypes = head + [ctypes.c_int, PU]
         lib.oracle_count_anchors.argtypes = head + [ctypes.c_int, i32, i32, PU, PU]
         lib.oracle_vertices.argtypes = head + [ctypes.POINTER(ctypes.c_int64), i64, PU]
         lib.oracle_vertices.restype = ctypes.c_int
         for f in (lib.oracle_count_anchors, lib.oracle_count, lib.oracle_count_kinds, lib.oracle_per_vertex, lib.oracle_vertex,
-                  lib.oracle_brute):
+                  lib.oracle_brute, lib.oracle_count_classes, lib.oracle_brute_classes):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -153,3 +157,23 @@ def brute(g, per_vertex: bool = False):
     if per_vertex:
         return int(b.value), int(u.value), pv
     return int(b.value), int(u.value)
+
+
+CLASS_NAMES = ("pp_pp", "pp_mm", "mm_mm", "pm_pm", "pp_pm", "pm_mm")
+
+
+def count_classes(g, side: int = SIDE_AUTO) -> list:
+    """Six sign-pattern classes [++/++, ++/--, --/--, +-/+-, ++/+-, +-/--]
+    over pairs of the anchor side (see the C header)."""
+    keep, a = _args(g)
+    out = (ctypes.c_uint64 * 6)()
+    _check(_load().oracle_count_classes(*a, side, out))
+    return [int(x) for x in out]
+
+
+def brute_classes(g, side: int = SIDE_AUTO) -> list:
+    """The same classes by brute force over all 2 x 2 vertex choices."""
+    keep, a = _args(g)
+    out = (ctypes.c_uint64 * 6)()
+    _check(_load().oracle_brute_classes(*a, side, out))
+    return [int(x) for x in out]

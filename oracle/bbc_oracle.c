@@ -255,6 +255,103 @@ int oracle_count_kinds(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, 
     return 0;
 }
 
+/* Sign-pattern classes of the case study (Sec. "Case Study", Table 8):
+ * for an anchor pair {u, w} every shared centre c carries a pattern, ++
+ * (both edges positive, p of them), -- (both negative, n) or +- (the two
+ * edges differ, b); a butterfly is a pair of shared centres, so its class is
+ * the unordered pair of their patterns.  Per anchor pair:
+ *   out[0] ++/++ C(p,2)   out[1] ++/-- p*n   out[2] --/-- C(n,2)
+ *   out[3] +-/+- C(b,2)   out[4] ++/+- p*b   out[5] +-/-- n*b
+ * summed over the pairs of the anchor side (the case study pairs the drugs).
+ * Coherent (0-2) and incoherent (3) butterflies are balanced, mixed (4, 5)
+ * unbalanced (Lemma 1).  Algorithm 1's walk with three buckets per
+ * endpoint instead of two, pairs by plain id order. */
+int oracle_count_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                         const int8_t* sg, int side, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    uint32_t* P = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* N = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    uint64_t c[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t u = 0; u < g.n_s; ++u) {
+        int32_t nt = 0;
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            int32_t ctr = g.s_nbr[i];
+            for (int64_t j = g.c_off[ctr]; j < g.c_off[ctr + 1]; ++j) {
+                int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                if (P[w] == 0 && N[w] == 0 && B[w] == 0) touched[nt++] = w;
+                if (g.c_sgn[j] != g.s_sgn[i]) B[w]++;
+                else if (g.s_sgn[i] > 0) P[w]++;
+                else N[w]++;
+            }
+        }
+        for (int32_t k = 0; k < nt; ++k) {
+            int32_t w = touched[k];
+            uint64_t p = P[w], n = N[w], b = B[w];
+            c[0] += choose2(p);
+            c[1] += p * n;
+            c[2] += choose2(n);
+            c[3] += choose2(b);
+            c[4] += p * b;
+            c[5] += n * b;
+            P[w] = N[w] = B[w] = 0;
+        }
+    }
+    free(P);
+    free(N);
+    free(B);
+    free(touched);
+    sides_free(&g);
+    for (int k = 0; k < 6; ++k) out[k] = c[k];
+    return 0;
+}
+
+/* The same classes by brute force over every 2 x 2 vertex choice (tiny
+ * graphs): pairs on the anchor side, patterns read at the two centres. */
+int oracle_brute_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                         const int8_t* sg, int side, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    if ((int64_t)n_u * n_v > (1LL << 26)) return 1;
+    const int su = pick_side(n_u, n_v, side) == 1;
+    const int32_t n_s = su ? n_u : n_v, n_c = su ? n_v : n_u;
+    int8_t* M = (int8_t*)calloc((size_t)n_s * (size_t)n_c + 1, 1);  // M[anchor][centre]
+    for (int32_t u = 0; u < n_u; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            const int32_t a = su ? u : adj[e], c = su ? adj[e] : u;
+            M[(size_t)a * n_c + c] = sg[e];
+        }
+    uint64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t a1 = 0; a1 < n_s; ++a1)
+        for (int32_t a2 = a1 + 1; a2 < n_s; ++a2)
+            for (int32_t c1 = 0; c1 < n_c; ++c1) {
+                const int8_t x1 = M[(size_t)a1 * n_c + c1], y1 = M[(size_t)a2 * n_c + c1];
+                if (!x1 || !y1) continue;
+                for (int32_t c2 = c1 + 1; c2 < n_c; ++c2) {
+                    const int8_t x2 = M[(size_t)a1 * n_c + c2], y2 = M[(size_t)a2 * n_c + c2];
+                    if (!x2 || !y2) continue;
+                    /* pattern per centre: 0 = ++, 1 = --, 2 = +- */
+                    const int t1 = x1 != y1 ? 2 : (x1 > 0 ? 0 : 1);
+                    const int t2 = x2 != y2 ? 2 : (x2 > 0 ? 0 : 1);
+                    const int lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
+                    int k;
+                    if (lo == 0 && hi == 0) k = 0;
+                    else if (lo == 0 && hi == 1) k = 1;
+                    else if (lo == 1 && hi == 1) k = 2;
+                    else if (lo == 2) k = 3;
+                    else if (lo == 0) k = 4; /* ++ with +- */
+                    else k = 5;              /* -- with +- */
+                    ++cnt[k];
+                }
+            }
+    free(M);
+    for (int k = 0; k < 6; ++k) out[k] = cnt[k];
+    return 0;
+}
+
 /* Per-vertex counts.  For each anchor pair {u, w} with a symmetric and b
  * asymmetric wedges, the pair closes C(a,2) + C(b,2) balanced butterflies,
  * each containing u and w.  A centre c of a wedge u-c-w of one type lies in

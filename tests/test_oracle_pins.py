@@ -87,6 +87,86 @@ def test_table8_identity():
 # ----------------------------------------------------------------- brute force
 
 
+def py_classes(g, side):
+    """The six sign-pattern classes in pure Python, from the definition: a
+    butterfly is two anchor-side vertices and two centres; each centre's
+    pattern is ++, -- or +- (the two edges differ); its class is the
+    unordered pair of the two patterns."""
+    sign = {}
+    for u in range(g.n_u):
+        for e in range(g.offsets[u], g.offsets[u + 1]):
+            sign[(u, int(g.adj[e]))] = int(g.signs[e])
+    su = side == oracle.SIDE_U or (side == oracle.SIDE_AUTO and g.n_u < g.n_v)
+    n_s, n_c = (g.n_u, g.n_v) if su else (g.n_v, g.n_u)
+    key = (lambda a, c: (a, c)) if su else (lambda a, c: (c, a))
+    order = {("pp", "pp"): 0, ("mm", "pp"): 1, ("mm", "mm"): 2, ("pm", "pm"): 3, ("pm", "pp"): 4, ("mm", "pm"): 5}
+    out = [0] * 6
+    for a1, a2 in itertools.combinations(range(n_s), 2):
+        for c1, c2 in itertools.combinations(range(n_c), 2):
+            s = [sign.get(key(a, c)) for a in (a1, a2) for c in (c1, c2)]
+            if None in s:
+                continue
+            x1, x2, y1, y2 = s  # a1c1, a1c2, a2c1, a2c2
+            pat = sorted("pm" if x != y else ("pp" if x > 0 else "mm") for x, y in ((x1, y1), (x2, y2)))
+            out[order[tuple(pat)]] += 1
+    return out
+
+
+def test_classes_of_the_case_study_sample():
+    """The sample drug-target network (drugs on U, the case study's pair
+    side): the class split derived by hand from the figure, 5 coherent
+    (1 ++/++, 3 ++/--, 1 --/--), 1 incoherent, 2 mixed (one of each)."""
+    g, exp = load_graphs("drug_target_sample.txt")["drug_target"]
+    got = oracle.count_classes(g, oracle.SIDE_U)
+    assert got == [exp["class_" + n] for n in oracle.CLASS_NAMES]
+    assert got == oracle.brute_classes(g, oracle.SIDE_U) == py_classes(g, oracle.SIDE_U)
+    assert sum(got[:4]) == exp["balanced"] and sum(got[4:]) == exp["unbalanced"]
+    # pairs of targets instead: the same butterflies, other classes
+    assert oracle.count_classes(g, oracle.SIDE_V) == py_classes(g, oracle.SIDE_V)
+
+
+def test_class_order_matches_table8():
+    """The class order and kinds follow Table 8: coherent ++/++, ++/--,
+    --/--, incoherent +-/+- balanced; mixed ++/+- and +-/-- unbalanced."""
+    _, classes = load_table8()
+    assert [n.split("_", 1)[1] for n, _, _ in classes] == list(oracle.CLASS_NAMES)
+    assert [k for _, _, k in classes] == ["balanced"] * 4 + ["unbalanced"] * 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_classes_walk_matches_definitions(seed):
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(25):
+        n_u, n_v = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        A = rng.random((n_u, n_v)) < rng.random()
+        u, v = np.nonzero(A)
+        sg = np.where(rng.random(u.size) < rng.random(), -1, 1)
+        g = synth.from_edges(n_u, n_v, u, v, sg)
+        for side in (oracle.SIDE_AUTO, oracle.SIDE_U, oracle.SIDE_V):
+            got = oracle.count_classes(g, side)
+            assert got == oracle.brute_classes(g, side) == py_classes(g, side)
+            bal, unb, allb = oracle.count_kinds(g, side)
+            assert sum(got[:4]) == bal and sum(got[4:]) == unb and sum(got) == allb
+
+
+@pytest.mark.parametrize("s,c", [(2, 2), (3, 5), (6, 4)])
+def test_classes_closed_forms(s, c):
+    """K_{s,c} with the s vertices of U as the pair side: all positive ->
+    C(s,2) C(c,2) of ++/++; one negative edge at (u0, c0) -> the s - 1 pairs
+    holding u0 keep C(c-1,2) ++/++ and gain c - 1 ++/+- each."""
+    u, v = np.divmod(np.arange(s * c), c)
+    g = synth.from_edges(s, c, u, v, np.ones(s * c, np.int8))
+    assert oracle.count_classes(g, oracle.SIDE_U) == [comb(s, 2) * comb(c, 2), 0, 0, 0, 0, 0]
+    sg = np.ones(s * c, np.int8)
+    sg[0] = -1
+    g = synth.from_edges(s, c, u, v, sg)
+    pp = (s - 1) * comb(c - 1, 2) + comb(s - 1, 2) * comb(c, 2)
+    assert oracle.count_classes(g, oracle.SIDE_U) == [pp, 0, 0, 0, (s - 1) * (c - 1), 0]
+    # every sign negative: the mirror image
+    g = synth.from_edges(s, c, u, v, -np.ones(s * c, np.int8))
+    assert oracle.count_classes(g, oracle.SIDE_U) == [0, 0, comb(s, 2) * comb(c, 2), 0, 0, 0]
+
+
 def test_brute_matches_python_definition():
     rng = np.random.default_rng(11)
     for _ in range(150):
@@ -417,4 +497,51 @@ def test_pins_catch_planted_oracle_mistakes(name, tmp_path):
     for _ in range(50):
         g = synth.small_random_graph(rng, max_n=8)
         failures += mcount(g) != py_brute(g)[0]
+    assert failures > 0, f"mutant '{name}' passed every pin"
+
+
+CLASS_MUTANTS = {
+    "patterns p and n swapped": ("else if (g.s_sgn[i] > 0) P[w]++;", "else if (g.s_sgn[i] < 0) P[w]++;"),
+    "mixed ++/+- dropped": ("            c[4] += p * b;\n", ""),
+    "incoherent as a product": ("            c[3] += choose2(b);", "            c[3] += b * b;"),
+    "pair filter dropped": ("                if (w <= u) continue;\n                if (P[w] == 0", "                if (w == u) continue;\n                if (P[w] == 0"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLASS_MUTANTS))
+def test_class_pins_catch_planted_mistakes(name, tmp_path):
+    """Each plausible slip in the three-bucket class walk makes a pin fail."""
+    import ctypes
+
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "bbc_oracle.c")).read()
+    old, new = CLASS_MUTANTS[name]
+    assert src.count(old) >= 1
+    i = src.index("int oracle_count_classes(")
+    j = src.index("int oracle_brute_classes(")
+    body = src[i:j]
+    assert old in body
+    mut = tmp_path / "mut.c"
+    mut.write_text(src[:i] + body.replace(old, new) + src[j:])
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), str(mut)])
+    lib = ctypes.CDLL(str(so))
+    P32, P8 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)
+    lib.oracle_count_classes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P32, P32, P8,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+
+    def mclasses(g, side):
+        off = np.ascontiguousarray(g.offsets, np.int32)
+        adj = np.ascontiguousarray(g.adj, np.int32)
+        sg = np.ascontiguousarray(g.signs, np.int8)
+        out = (ctypes.c_uint64 * 6)()
+        lib.oracle_count_classes(g.n_u, g.n_v, adj.size, off.ctypes.data_as(P32), adj.ctypes.data_as(P32),
+                                 sg.ctypes.data_as(P8), side, out)
+        return [int(x) for x in out]
+
+    g, exp = load_graphs("drug_target_sample.txt")["drug_target"]
+    failures = int(mclasses(g, oracle.SIDE_U) != [exp["class_" + n] for n in oracle.CLASS_NAMES])
+    rng = np.random.default_rng(32)
+    for _ in range(40):
+        g = synth.small_random_graph(rng, max_n=7)
+        failures += mclasses(g, oracle.SIDE_U) != py_classes(g, oracle.SIDE_U)
     assert failures > 0, f"mutant '{name}' passed every pin"
