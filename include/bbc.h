@@ -235,6 +235,24 @@ bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path);
  * shape that is not instantiated; the table is unchanged on error. */
 bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path);
 
+/* Sign-pattern classes of the case study (Sec. "Case Study", Table 8).
+ * For a pair of anchor-side vertices (opts->side picks the side; the case
+ * study pairs the drugs) every shared centre carries a pattern: ++ (both
+ * edges positive), -- (both negative) or +- (the edges differ); a butterfly
+ * is a pair of shared centres and its class the unordered pair of their
+ * patterns.  classes (host, 6 uint64) receives, in Table 8's order:
+ *   [0] coherent ++/++  [1] coherent ++/--  [2] coherent --/--
+ *   [3] incoherent +-/+-  [4] mixed ++/+-  [5] mixed +-/--
+ * Coherent and incoherent butterflies are balanced, mixed ones unbalanced
+ * (Lemma 1), so [0] + [1] + [2] + [3] is bbc_count's total.  The same walk
+ * as bbc_count with three counters per endpoint (one kernel shape: 256
+ * threads, 8,192-word bands); dense blocks, per-vertex output and batches
+ * are not offered here (BBC_EINVAL for blocks).  Other arguments, errors and
+ * synchronisation as bbc_count. */
+bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                             const int32_t* adj, const int8_t* signs, uint64_t* classes, const bbc_options* opts,
+                             void* stream);
+
 /* Dense-block planner options.  Candidates are the vertices of degree >=
  * min_degree.  A block grows from a seed anchor: C starts as the seed's
  * candidate centres, then twice R = the candidate anchors linked to at

@@ -149,6 +149,9 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_tune_save.restype = ctypes.c_int
     lib.bbc_tune_load.argtypes = [vp, ctypes.c_char_p]
     lib.bbc_tune_load.restype = ctypes.c_int
+    lib.bbc_count_classes.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(Options), vp]
+    lib.bbc_count_classes.restype = ctypes.c_int
     lib.bbc_plan_options_init.argtypes = [ctypes.POINTER(PlanOptions)]
     lib.bbc_plan_options_init.restype = ctypes.c_int
     lib.bbc_plan_blocks.argtypes = [vp, i32, i32, i64, vp, vp, ctypes.POINTER(PlanOptions), i32,
@@ -282,6 +285,22 @@ class Context:
         if st != OK:
             raise BbcError(st, self.last_error())
         return int(out.value)
+
+    def count_classes(self, offsets, adj, signs, n_v: int, opts: Options | None = None, stream=None) -> list:
+        """The six sign-pattern classes [++/++, ++/--, --/--, +-/+-, ++/+-,
+        +-/--] over pairs of the anchor side (``options(side=...)``)."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        out = (ctypes.c_uint64 * 6)()
+        o = opts if opts is not None else options()
+        st = self._lib.bbc_count_classes(self._h, offsets.numel() - 1, int(n_v), adj.numel(), _ptr(offsets),
+                                         _ptr(adj), _ptr(signs), out, ctypes.byref(o), _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return [int(x) for x in out]
 
     def count_batched(self, batch: "Batch", opts: Options | None = None, stream=None):
         """Per-graph counts of a Batch; returns its totals tensor (int64, on device)."""

@@ -60,6 +60,8 @@ void pl_assign(const uint32_t* list, uint32_t n, uint8_t* assigned, hipStream_t 
 bool wedge_shape_ok(int band_words, int wg);
 int wedge_block(int band_words, int wg, bool full);
 int wedge_blocks_per_cu(int band_words, int wg, bool full);
+int wedge_class_blocks_per_cu();
+int wedge_class_band();
 int wedge_band(int band_words, int wg, bool full);
 int wedge_shape_count();
 void wedge_shape(int i, int* wg, int* band_words);
@@ -68,13 +70,14 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int2* bmeta, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
-                  unsigned long long* gtotals, const HybridView& hv, hipStream_t s);
+                  unsigned long long* gtotals, const HybridView& hv, bool classes, hipStream_t s);
 
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->flags = 0;
         st->bad_offset = st->bad_range = st->bad_sign = st->bad_dup = st->bad_block = INT64_MAX;
         st->total = 0;
+        for (int k = 0; k < 6; ++k) st->cls[k] = 0;
         st->wedges = 0;
         st->walked = 0;
         st->bands = 0;
@@ -179,6 +182,7 @@ struct Job {
     uint32_t checks = BBC_CHECK_ALL;
     int band_words = 0, wg_size = 0, grid = 0;
     bool tuned = false;  // shape taken from the tuning table
+    bool classes = false;  // the six sign-pattern classes instead of the total
     // dense blocks (single graph only)
     int32_t n_blocks = 0, n_tiles = 0;
     int64_t r_first = 0;  // first rank of the block anchors (they sit at the top)
@@ -348,7 +352,11 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     if (J.checks & BBC_CHECK_DUPLICATES) launch_check_dup(ckey, packed, m, st, s);
     if (!J.pv) {  // band ends of the count-mode wedge kernel fall on multiples of its granule
         int gs = 0;
-        while ((2 << gs) < wedge_band(J.band_words, J.wg_size, false)) ++gs;
+        if (J.classes) {  // the narrowest class band holds a quarter of the words
+            while ((4 << gs) < wedge_class_band()) ++gs;
+        } else {
+            while ((2 << gs) < wedge_band(J.band_words, J.wg_size, false)) ++gs;
+        }
         launch_bidx(ckey, P.coff, packed, m, n_c, gs, P.bnb, P.bioff, P.bidx, P.bmeta, P.partials, st, s);
     }
     HybridView hv{nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -381,7 +389,7 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
                      P.bmeta, order,
                      (int32_t)n_s, st, J.pv, inv, J.s_is_u ? 0 : J.n_u, J.s_is_u ? J.n_u : 0, n_c,
                      J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
-                     J.batched ? J.totals : nullptr, hv, s);
+                     J.batched ? J.totals : nullptr, hv, J.classes, s);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
@@ -785,6 +793,43 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     // the kernels sum twice the pair terms (per-vertex mode: every anchor's
     // pairs, seen from both ends)
     *total = (uint64_t)ctx->st_host->total / 2;
+    return BBC_OK;
+}
+
+bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                             const int32_t* adj, const int8_t* signs, uint64_t* classes, const bbc_options* opts_in,
+                             void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    bbc_options opts;
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
+    if (!classes) return fail(ctx, BBC_EINVAL, "classes is NULL");
+    if (opts.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with class counts");
+    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+
+    DeviceGuard guard(ctx->device);
+    Job J;
+    J.off = offsets;
+    J.adj = adj;
+    J.sg = signs;
+    J.n_u = n_u;
+    J.n_v = n_v;
+    J.s_is_u = side_is_u(opts.side, n_u, n_v);
+    J.m = n_edges;
+    J.n_s = J.s_is_u ? n_u : n_v;
+    J.n_c = J.s_is_u ? n_v : n_u;
+    J.checks = opts.checks;
+    J.classes = true;
+    J.band_words = wedge_class_band();
+    J.wg_size = 256;
+    J.grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_class_blocks_per_cu());
+    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
+    if (rc != BBC_OK) return rc;
+    for (int k = 0; k < 6; ++k) classes[k] = (uint64_t)ctx->st_host->cls[k];
     return BBC_OK;
 }
 

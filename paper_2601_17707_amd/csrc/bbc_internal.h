@@ -21,6 +21,7 @@ struct DevStatus {
     unsigned long long wedges;  // sum over centres of C(deg, 2)
     unsigned long long walked;  // wedges the sparse walk visits (dense-block wedges excluded)
     unsigned long long bands;   // counter bands processed
+    unsigned long long cls[6];  // sign-pattern classes (class mode)
     unsigned int queue;         // persistent work queue head
     unsigned int pad1;
 };

@@ -114,9 +114,14 @@ struct PairSum {
 };
 
 // Band capacity in endpoint slots for a counter mode (a power of two).
+// Modes 0-3 count two wedge types per slot (agree, disagree) in 4, 8, 16 or
+// 32-bit fields; modes 4-7 count three for the sign-pattern classes (both
+// edges positive, both negative, different) in a slot of four such fields.
 template <int MODE, int BAND_WORDS>
 __host__ __device__ constexpr uint32_t band_capacity() {
-    return MODE == 0 ? BAND_WORDS * 4u : MODE == 1 ? BAND_WORDS * 2u : MODE == 2 ? BAND_WORDS * 1u : BAND_WORDS / 2u;
+    constexpr uint32_t bw = BAND_WORDS;
+    return MODE == 0 ? bw * 4u : MODE == 1 ? bw * 2u : MODE == 2 ? bw : MODE == 3 ? bw / 2u
+         : MODE == 4 ? bw * 2u : MODE == 5 ? bw : MODE == 6 ? bw / 2u : bw / 4u;
 }
 
 // Multiplier of the slot scatter.  Centre lists are sorted by rank, so the
@@ -172,10 +177,25 @@ __device__ __forceinline__ void slot_field(uint32_t rank, uint32_t t, uint32_t& 
         const uint32_t p = mul_u24(rank, kSlotMul * 4u);  // slot = p / 4 mod BW; word = slot
         byte = p & wmask;
         shift = t << 4;
-    } else {
+    } else if constexpr (MODE == 3) {
         const uint32_t p = mul_u24(rank, kSlotMul * 8u);  // slot = p / 8 mod BW / 2; word = 2 slot + t
         byte = (p & ((uint32_t)(BAND_WORDS / 2 - 1) << 3)) | (t << 2);
         shift = 0;
+    } else {  // classes, t in {0, 1, 2}: field t of the slot's four
+        const uint32_t slot = mul_u24(rank, kSlotMul) & (band_capacity<MODE, BAND_WORDS>() - 1u);
+        if constexpr (MODE == 4) {  // 4-bit fields, two slots per word
+            byte = (slot >> 1) << 2;
+            shift = ((slot & 1u) << 4) | (t << 2);
+        } else if constexpr (MODE == 5) {  // 8-bit fields, a word per slot
+            byte = slot << 2;
+            shift = t << 3;
+        } else if constexpr (MODE == 6) {  // 16-bit fields, two words per slot
+            byte = (slot << 3) | ((t >> 1) << 2);
+            shift = (t & 1u) << 4;
+        } else {  // 32-bit fields, four words per slot
+            byte = (slot << 4) | (t << 2);
+            shift = 0;
+        }
     }
 }
 
@@ -486,11 +506,13 @@ __device__ __forceinline__ void count_batch(WedgeShared<WG, BAND_WORDS, FULL>& s
     uint32_t byte[kUnroll], inc[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t t = (b.x[u] ^ (MASKED ? b.ngmask >> u : b.ngmask)) & 1u;
+        const uint32_t ng = (MASKED ? b.ngmask >> u : b.ngmask) & 1u;
+        // agree / disagree; in class mode both positive 0, both negative 1, different 2
+        const uint32_t t = MODE >= 4 ? (((b.x[u] & 1u) != ng) ? 2u : ng) : (b.x[u] ^ ng) & 1u;
         uint32_t shift;
         slot_field<MODE, BAND_WORDS>(b.x[u] >> 1, t, byte[u], shift);
         const uint32_t one = MASKED ? (b.vmask >> u) & 1u : 1u;
-        inc[u] = MODE == 3 ? one : one << shift;
+        inc[u] = (MODE == 3 || MODE == 7) ? one : one << shift;
     }
     char* base = reinterpret_cast<char*>(sh.cnt);
     if (dense) {  // no return value needed: the reduction scans the band
@@ -562,8 +584,8 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
 // A band holding at least BAND_WORDS / 16 wedges is "dense": its increments
 // need no return value (no touched-word bitmap) and the reduction scans the
 // whole band; sparser bands mark touched words.
-template <int BAND_WORDS>
-__device__ __forceinline__ bool dense_band(int32_t total) { return total >= BAND_WORDS / 16; }
+template <int MODE, int BAND_WORDS>
+__device__ __forceinline__ bool dense_band(int32_t total) { return MODE >= 4 || total >= BAND_WORDS / 16; }
 
 // One band in one call: compaction, walk, and in per-vertex mode the centre
 // walk (phases: bit 0 counts the wedges, bit 1 runs the centre walk, which
@@ -579,7 +601,7 @@ __device__ __forceinline__ int32_t walk_band(WedgeShared<WG, BAND_WORDS, FULL>& 
     SliceTable<WG>& t = sh.tab[0];
     int32_t total, nkc;
     compact_band(sh, t, packed, bidx, gs, nk, lo, hi, seek_start, last, pre, use_pre, next_hi, cm, total, nkc);
-    const bool dense = dense_band<BAND_WORDS>(total);
+    const bool dense = dense_band<MODE, BAND_WORDS>(total);
     const int32_t rows = (total + kWave - 1) / kWave;
     const int32_t rpw = (rows + NW - 1) / NW;
     const int32_t r0 = wave * rpw, r1 = min(rows, r0 + rpw);
@@ -624,6 +646,53 @@ __device__ __forceinline__ int32_t walk_band(WedgeShared<WG, BAND_WORDS, FULL>& 
         __syncthreads();
     }
     return total;
+}
+
+// Sums of the six sign-pattern classes, per thread: for an endpoint with p
+// wedges whose edges are both positive, n both negative and b different,
+// ++/++ C(p,2), ++/-- p n, --/-- C(n,2), +-/+- C(b,2), ++/+- p b, +-/-- n b.
+struct ClassSums {
+    unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
+    __device__ __forceinline__ void add(uint32_t p, uint32_t n, uint32_t b) {
+        if (!(p | n | b)) return;
+        const unsigned long long P = p, N = n, B = b;
+        c[0] += P * (P - (P > 0)) / 2;
+        c[1] += P * N;
+        c[2] += N * (N - (N > 0)) / 2;
+        c[3] += B * (B - (B > 0)) / 2;
+        c[4] += P * B;
+        c[5] += N * B;
+    }
+};
+
+// Class mode: the sums of every slot of the band (a full scan, four words
+// at a time; slots never straddle them), clearing the counters.  Ends with
+// a barrier.
+template <int MODE, int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void reduce_classes(WedgeShared<WG, BAND_WORDS, FULL>& sh, ClassSums& cs) {
+    for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
+        uint4* q = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
+        const uint4 v = *q;
+        if (!(v.x | v.y | v.z | v.w)) continue;
+        *q = uint4{0u, 0u, 0u, 0u};
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        if constexpr (MODE == 4) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t x = w[k >> 1] >> ((k & 1) * 16);
+                cs.add(x & 15u, (x >> 4) & 15u, (x >> 8) & 15u);
+            }
+        } else if constexpr (MODE == 5) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cs.add(w[k] & 255u, (w[k] >> 8) & 255u, (w[k] >> 16) & 255u);
+        } else if constexpr (MODE == 6) {
+            cs.add(v.x & 0xffffu, v.x >> 16, v.y & 0xffffu);
+            cs.add(v.z & 0xffffu, v.z >> 16, v.w & 0xffffu);
+        } else {
+            cs.add(v.x, v.y, v.z);
+        }
+    }
+    __syncthreads();
 }
 
 // Sum of the pair terms of every touched counter word, and clears them.
@@ -707,6 +776,10 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 template <int BAND_WORDS>
 constexpr int granule_shift() { return ilog2(BAND_WORDS) - 1; }
 
+// In class mode the narrowest band holds BAND_WORDS / 4 slots.
+template <int MODE, int BAND_WORDS>
+constexpr int mode_granule_shift() { return MODE >= 4 ? ilog2(BAND_WORDS) - 2 : granule_shift<BAND_WORDS>(); }
+
 // All bands of anchor r (rank), list start a0, deg entries.  Anchors with
 // at most WG centres keep one slice cursor per centre across bands (each
 // band starts where the previous one ended); wider anchors re-load their
@@ -722,9 +795,9 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                                            const uint32_t* __restrict__ bidx, const int2* __restrict__ bmeta,
                                            int32_t a0, int32_t deg, int32_t r, int64_t n_s,
                                            unsigned long long* __restrict__ pv, int64_t centre_base,
-                                           unsigned long long& bands, const HybridView& hv) {
+                                           unsigned long long& bands, const HybridView& hv, ClassSums& cs) {
     constexpr int64_t band_slots = band_capacity<MODE, BAND_WORDS>();
-    constexpr int gs = granule_shift<BAND_WORDS>();
+    constexpr int gs = mode_granule_shift<MODE, BAND_WORDS>();
     auto band_end = [&](int64_t lo) {
         const int64_t hi = FULL ? lo + band_slots : ((lo + band_slots) >> gs) << gs;
         return hi < n_s ? hi : n_s;
@@ -762,7 +835,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             walk_start(sh.tab[0], packed, total, nkc, w, next, have_next);
         }
         for (;;) {
-            const bool dense = dense_band<BAND_WORDS>(total);
+            const bool dense = dense_band<MODE, BAND_WORDS>(total);
             walk_rows<MODE>(sh, sh.tab[buf], packed, dense, w, next, have_next);
             __syncthreads();
             const bool more = hi < n_s;
@@ -779,7 +852,8 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                              nh < n_s ? nh : -1, cm, total2, nkc2);
                 walk_start(sh.tab[buf ^ 1], packed, total2, nkc2, w2, next2, have_next2);
             }
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
+            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs);
+            else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
             if (!more) break;
             lo = lo2;
@@ -801,7 +875,8 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             const int64_t nh = hi < n_s ? band_end(hi) : -1;
             const int32_t total = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
                                                         FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense_band<BAND_WORDS>(total), total);
+            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs);
+            else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense_band<MODE, BAND_WORDS>(total), total);
             ++bands;
         }
         if constexpr (FULL) {
@@ -822,7 +897,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                 int32_t pre = 0;
                 const int32_t tc = walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 1,
                                                          pre, false, -1, cm);
-                dense |= dense_band<BAND_WORDS>(tc);
+                dense |= dense_band<MODE, BAND_WORDS>(tc);
                 total += tc;
             }
             if constexpr (FULL) {
@@ -839,7 +914,8 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                         atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
                 }
             }
-            acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
+            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs);
+            else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
         }
     }
@@ -849,7 +925,9 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
 // Batched launches pass agraph (graph of each rank), rank_end (first rank of
 // each graph, n_graphs + 1 entries) and per-graph totals; an anchor's
 // endpoints then stop at the end of its graph's rank range.
-template <int WG, int BAND_WORDS, bool FULL>
+// CLS: the six sign-pattern classes instead of the balanced total (count
+// mode only), summed into st->cls.
+template <int WG, int BAND_WORDS, bool FULL, bool CLS = false>
 __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
@@ -866,6 +944,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     for (int i = tid; i < BAND_WORDS; i += WG) sh.cnt[i] = 0;
     for (int i = tid; i < BAND_WORDS / 32; i += WG) sh.bmp[i] = 0;
     unsigned long long acc = 0, bands = 0;
+    ClassSums cs;
     for (;;) {
         __syncthreads();
         if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
@@ -877,19 +956,20 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
         const int64_t n_end = agraph ? rank_end[agraph[r] + 1] : (int64_t)n_s;
         // fewer than two centres: no endpoint pair shares two wedges
         if (deg < 2 || (!FULL && r >= n_end - 1)) continue;
+        constexpr int M0 = CLS ? 4 : 0;  // counter mode of degree class 0; classes use modes 4-7
         unsigned long long a;
         if (deg <= 15)
-            a = count_anchor<0, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                        centre_base, bands, hv);
+            a = count_anchor<M0 + 0, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                             centre_base, bands, hv, cs);
         else if (deg <= 255)
-            a = count_anchor<1, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                        centre_base, bands, hv);
+            a = count_anchor<M0 + 1, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                             centre_base, bands, hv, cs);
         else if (deg <= 65535)
-            a = count_anchor<2, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                        centre_base, bands, hv);
+            a = count_anchor<M0 + 2, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                             centre_base, bands, hv, cs);
         else
-            a = count_anchor<3, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                        centre_base, bands, hv);
+            a = count_anchor<M0 + 3, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
+                                             centre_base, bands, hv, cs);
         if constexpr (FULL) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
             if (tid == 0) pv[anchor_base + inv[r]] = s;
@@ -901,6 +981,13 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     }
     acc = wave_sum(acc);
     if (lane_id() == 0 && acc) atomicAdd(&st->total, acc);
+    if constexpr (CLS) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const unsigned long long v = wave_sum(cs.c[k]);
+            if (lane_id() == 0 && v) atomicAdd(&st->cls[k], v);
+        }
+    }
     if (tid == 0 && bands) atomicAdd(&st->bands, bands);
 }
 
@@ -935,17 +1022,17 @@ struct WedgeArgs {
     HybridView hv;
 };
 
-template <int WG, int BW, bool FULL>
+template <int WG, int BW, bool FULL, bool CLS = false>
 static void launch_shape(const WedgeArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_wedge<WG, BW, FULL>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back, a.coff,
+    hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back, a.coff,
                        a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base, a.centre_base,
                        a.agraph, a.rank_end, a.gtotals, a.hv);
 }
 
-template <int WG, int BW, bool FULL>
+template <int WG, int BW, bool FULL, bool CLS = false>
 static int occupancy() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL>, WG, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL, CLS>, WG, 0) != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 
@@ -962,6 +1049,7 @@ static const WedgeShape kShapes[] = {BBC_SHAPE(256, 8192),  BBC_SHAPE(512, 16384
                                      BBC_SHAPE(128, 4096),  BBC_SHAPE(128, 8192),   BBC_SHAPE(256, 4096)};
 #undef BBC_SHAPE
 constexpr int kFullWG = 256, kFullBW = 16384;
+constexpr int kClsWG = 256, kClsBW = 8192;  // sign-pattern classes: one shape
 
 static int shape_index(int band_words, int wg) {
     int n = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
@@ -985,6 +1073,10 @@ void wedge_shape(int i, int* wg, int* band_words) {
     *band_words = kShapes[i].band_words;
 }
 
+int wedge_class_blocks_per_cu() { return occupancy<kClsWG, kClsBW, false, true>(); }
+
+int wedge_class_band() { return kClsBW; }
+
 int wedge_blocks_per_cu(int band_words, int wg, bool full) {
     if (full) return occupancy<kFullWG, kFullBW, true>();
     const int i = shape_index(band_words, wg);
@@ -996,7 +1088,7 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int2* bmeta, const uint32_t* order, int32_t n_s, DevStatus* st, unsigned long long* pv,
                   const uint32_t* inv, int64_t anchor_base, int64_t centre_base, int64_t n_centre,
                   const int32_t* agraph, const int64_t* rank_end, unsigned long long* gtotals, const HybridView& hv,
-                  hipStream_t s) {
+                  bool classes, hipStream_t s) {
     const WedgeArgs a{aoff, acent, aneg, back, coff, packed, bidx, bmeta, order, n_s, st, pv, inv,
                       anchor_base, centre_base, agraph, rank_end, gtotals, hv};
     if (pv) {
@@ -1006,6 +1098,10 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
             hipLaunchKernelGGL(k_halve, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, s, pv + centre_base,
                                n_centre);
         }
+        return;
+    }
+    if (classes) {
+        launch_shape<kClsWG, kClsBW, false, true>(a, grid, s);
         return;
     }
     const int i = shape_index(band_words, wg);
