@@ -10,9 +10,10 @@ Prints one JSON line.  value = wedges/s, where the wedges are
 sum over centres c of C(deg c, 2): every wedge u - c - w with w ranked above
 u, walked exactly once.  The line also carries the batched measurement
 (graphs/s of 10,000 graphs of uneven size, one captured batch plan, against
-a loop of plain per-graph calls), the dense-block workload (hybrid int8
-matrix-core path against the sparse-only path), the roofline of the wedge
-kernel and the CPU oracle's rate.
+a loop of plain per-graph calls), the six sign-pattern classes on the same
+graph, the dense-block workload (hybrid int8 matrix-core path against the
+sparse-only path), the roofline of the wedge kernel and the CPU oracle's
+rate.
 """
 from __future__ import annotations
 
@@ -139,6 +140,32 @@ def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
                 totals_match_loop=bool(list(totals) == loop), balanced_butterflies=int(totals.sum()))
 
 
+def bench_classes(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps: int, warmup: int) -> dict:
+    """The six sign-pattern classes on the resident bench graph: the same
+    wedges walked with three counters per endpoint.  The four balanced
+    classes must add up to the balanced count."""
+    import torch
+
+    from paper_2601_17707_amd import bbc
+
+    opts, opts_t = bbc.options(), bbc.options(timing=True)
+    for _ in range(max(1, warmup)):
+        ctx.count_classes(off, adj, sg, n_v, opts=opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        cls = ctx.count_classes(off, adj, sg, n_v, opts=opts)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t) / steps
+    kern = []
+    for _ in range(3):
+        ctx.count_classes(off, adj, sg, n_v, opts=opts_t)
+        kern.append(ctx.stats()["ms_count"])
+    return dict(ms_per_call=ms, kernel_ms=sum(kern) / len(kern), wedges_per_s=wedges / (ms / 1e3) / 1e9, unit="G/s",
+                classes=dict(zip(("pp_pp", "pp_mm", "mm_mm", "pm_pm", "pp_pm", "pm_mm"), cls)),
+                balanced_matches_count=bool(sum(cls[:4]) == total))
+
+
 def bench_hybrid(ctx, steps: int, warmup: int, seed: int) -> dict:
     """The planted-block workload (power-law background, |U| = 2e6, |V| = 1e6,
     5e7 background edges, 16 blocks of 4096 x 4096 at density 0.5) counted
@@ -214,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-graph batch measurement")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the dense-block workload")
+    ap.add_argument("--no-classes", action="store_true", help="skip the sign-pattern class count")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -298,6 +326,9 @@ def main():
                       traffic=measured_traffic(args.workload), kernel="k_wedge", algorithmic_bytes=nbytes,
                       bands=int(st["bands"])),
     )
+    if not args.no_classes:
+        line["classes"] = bench_classes(ctx, off, adj, sg, g.n_v, wedges, total, max(1, min(args.steps, 5)),
+                                        args.warmup)
     if not args.no_batch and args.workload == WORKLOAD:
         line["batched"] = bench_batched(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
     if not args.no_hybrid and args.workload == WORKLOAD:

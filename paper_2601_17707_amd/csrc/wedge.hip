@@ -585,7 +585,7 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
 // need no return value (no touched-word bitmap) and the reduction scans the
 // whole band; sparser bands mark touched words.
 template <int MODE, int BAND_WORDS>
-__device__ __forceinline__ bool dense_band(int32_t total) { return MODE >= 4 || total >= BAND_WORDS / 16; }
+__device__ __forceinline__ bool dense_band(int32_t total) { return MODE >= 6 || total >= BAND_WORDS / 16; }
 
 // One band in one call: compaction, walk, and in per-vertex mode the centre
 // walk (phases: bit 0 counts the wedges, bit 1 runs the centre walk, which
@@ -665,31 +665,91 @@ struct ClassSums {
     }
 };
 
-// Class mode: the sums of every slot of the band (a full scan, four words
-// at a time; slots never straddle them), clearing the counters.  Ends with
-// a barrier.
+// Per-band class sums of narrow slots (4- and 8-bit fields) in 32 bits:
+// a thread visits at most 64 slots of a band, each adding at most 255^2
+// per class.  take() moves C(p,2) = (p^2 - p) / 2 and the products into the
+// 64-bit sums.
+struct NarrowClassSums {
+    uint32_t pp = 0, nn = 0, bb = 0, pn = 0, pb = 0, nb = 0, p1 = 0, n1 = 0, b1 = 0;
+    __device__ __forceinline__ void add(uint32_t p, uint32_t n, uint32_t b) {
+        pp += p * p;
+        nn += n * n;
+        bb += b * b;
+        pn += p * n;
+        pb += p * b;
+        nb += n * b;
+        p1 += p;
+        n1 += n;
+        b1 += b;
+    }
+    __device__ __forceinline__ void take(ClassSums& cs) const {
+        cs.c[0] += (pp - p1) >> 1;
+        cs.c[1] += pn;
+        cs.c[2] += (nn - n1) >> 1;
+        cs.c[3] += (bb - b1) >> 1;
+        cs.c[4] += pb;
+        cs.c[5] += nb;
+    }
+};
+
+// The slots of one counter word in the narrow class layouts: two 16-bit
+// slots of 4-bit fields, or one slot of 8-bit fields.
+template <int MODE>
+__device__ __forceinline__ void narrow_word(NarrowClassSums& ns, uint32_t w) {
+    if constexpr (MODE == 4) {
+        ns.add(w & 15u, (w >> 4) & 15u, (w >> 8) & 15u);
+        ns.add((w >> 16) & 15u, (w >> 20) & 15u, (w >> 24) & 15u);
+    } else {
+        ns.add(w & 255u, (w >> 8) & 255u, (w >> 16) & 255u);
+    }
+}
+
+// Class mode: the class sums of every touched slot of the band, clearing
+// the counters.  A dense band is scanned four words at a time (slots never
+// straddle them); a sparse one (narrow layouts only) through the
+// touched-word bitmap.  Ends with a barrier.
 template <int MODE, int WG, int BAND_WORDS, bool FULL>
-__device__ __forceinline__ void reduce_classes(WedgeShared<WG, BAND_WORDS, FULL>& sh, ClassSums& cs) {
-    for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
-        uint4* q = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
-        const uint4 v = *q;
-        if (!(v.x | v.y | v.z | v.w)) continue;
-        *q = uint4{0u, 0u, 0u, 0u};
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-        if constexpr (MODE == 4) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const uint32_t x = w[k >> 1] >> ((k & 1) * 16);
-                cs.add(x & 15u, (x >> 4) & 15u, (x >> 8) & 15u);
+__device__ __forceinline__ void reduce_classes(WedgeShared<WG, BAND_WORDS, FULL>& sh, ClassSums& cs, bool dense) {
+    if constexpr (MODE <= 5) {
+        NarrowClassSums ns;
+        if (dense) {
+            for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
+                uint4* q = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
+                const uint4 v = *q;
+                if (!(v.x | v.y | v.z | v.w)) continue;
+                *q = uint4{0u, 0u, 0u, 0u};
+                narrow_word<MODE>(ns, v.x);
+                narrow_word<MODE>(ns, v.y);
+                narrow_word<MODE>(ns, v.z);
+                narrow_word<MODE>(ns, v.w);
             }
-        } else if constexpr (MODE == 5) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) cs.add(w[k] & 255u, (w[k] >> 8) & 255u, (w[k] >> 16) & 255u);
-        } else if constexpr (MODE == 6) {
-            cs.add(v.x & 0xffffu, v.x >> 16, v.y & 0xffffu);
-            cs.add(v.z & 0xffffu, v.z >> 16, v.w & 0xffffu);
         } else {
-            cs.add(v.x, v.y, v.z);
+            for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
+                uint32_t bits = sh.bmp[b];
+                if (bits) {
+                    sh.bmp[b] = 0;
+                    while (bits) {
+                        const uint32_t wd = (b << 5) + (uint32_t)(__ffs(bits) - 1);
+                        bits &= bits - 1u;
+                        narrow_word<MODE>(ns, sh.cnt[wd]);
+                        sh.cnt[wd] = 0;
+                    }
+                }
+            }
+        }
+        ns.take(cs);
+    } else {
+        for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
+            uint4* q = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
+            const uint4 v = *q;
+            if (!(v.x | v.y | v.z | v.w)) continue;
+            *q = uint4{0u, 0u, 0u, 0u};
+            if constexpr (MODE == 6) {
+                cs.add(v.x & 0xffffu, v.x >> 16, v.y & 0xffffu);
+                cs.add(v.z & 0xffffu, v.z >> 16, v.w & 0xffffu);
+            } else {
+                cs.add(v.x, v.y, v.z);
+            }
         }
     }
     __syncthreads();
@@ -852,7 +912,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                              nh < n_s ? nh : -1, cm, total2, nkc2);
                 walk_start(sh.tab[buf ^ 1], packed, total2, nkc2, w2, next2, have_next2);
             }
-            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs);
+            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense);
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
             if (!more) break;
@@ -875,7 +935,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             const int64_t nh = hi < n_s ? band_end(hi) : -1;
             const int32_t total = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
                                                         FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
-            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs);
+            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense_band<MODE, BAND_WORDS>(total));
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense_band<MODE, BAND_WORDS>(total), total);
             ++bands;
         }
@@ -914,7 +974,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                         atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
                 }
             }
-            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs);
+            if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense);
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
         }
