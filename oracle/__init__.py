@@ -60,11 +60,14 @@ def _load():
         lib.oracle_brute.argtypes = head + [PU, PU, PU]
         lib.oracle_count_classes.argtypes = head + [ctypes.c_int, PU]
         lib.oracle_brute_classes.argtypes = head + [ctypes.c_int, PU]
+        lib.oracle_count_bicliques.argtypes = head + [ctypes.c_int, ctypes.c_int, PU]
+        lib.oracle_brute_bicliques.argtypes = head + [ctypes.c_int, ctypes.c_int, PU]
         lib.oracle_count_anchors.argtypes = head + [ctypes.c_int, i32, i32, PU, PU]
         lib.oracle_vertices.argtypes = head + [ctypes.POINTER(ctypes.c_int64), i64, PU]
         lib.oracle_vertices.restype = ctypes.c_int
         for f in (lib.oracle_count_anchors, lib.oracle_count, lib.oracle_count_kinds, lib.oracle_per_vertex, lib.oracle_vertex,
-                  lib.oracle_brute, lib.oracle_count_classes, lib.oracle_brute_classes):
+                  lib.oracle_brute, lib.oracle_count_classes, lib.oracle_brute_classes, lib.oracle_count_bicliques,
+                  lib.oracle_brute_bicliques):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -177,3 +180,25 @@ def brute_classes(g, side: int = SIDE_AUTO) -> list:
     out = (ctypes.c_uint64 * 6)()
     _check(_load().oracle_brute_classes(*a, side, out))
     return [int(x) for x in out]
+
+
+def count_bicliques(g, k: int, side: int = SIDE_AUTO) -> int:
+    """Balanced (2,k)-bicliques with the two vertices on `side` (Definition
+    5; Algorithm 1 with general k), exact in 128 bits.  OverflowError when
+    a term or the total does not fit 128 bits."""
+    keep, a = _args(g)
+    out = (ctypes.c_uint64 * 2)()
+    rc = _load().oracle_count_bicliques(*a, side, int(k), out)
+    if rc == 2:
+        raise OverflowError("(2,k)-biclique count does not fit 128 bits")
+    _check(rc)
+    return int(out[0]) | (int(out[1]) << 64)
+
+
+def brute_bicliques(g, k: int, side: int = SIDE_AUTO) -> int:
+    """The same by enumerating every pair and every k-subset of its common
+    neighbours (tiny graphs, at most 24 common neighbours per pair)."""
+    keep, a = _args(g)
+    out = _u64()
+    _check(_load().oracle_brute_bicliques(*a, side, int(k), ctypes.byref(out)))
+    return int(out.value)

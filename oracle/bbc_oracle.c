@@ -310,6 +310,141 @@ int oracle_count_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off
     return 0;
 }
 
+/* Balanced (2,k)-bicliques (Definition 5; the extension named in Sec.
+ * "Future Directions"): two vertices of the chosen side and k common
+ * neighbours on the other, all 2k edges present, with no unbalanced
+ * butterfly inside.  By Lemma 1 a butterfly of two shared centres is
+ * balanced exactly when both wedges are symmetric or both asymmetric, so
+ * the k centres must all be of one kind: per pair, C(a, k) + C(b, k), with
+ * a / b the symmetric / asymmetric wedge counts (Algorithm 1 with general
+ * k).  Unlike k = 2, the count depends on which side holds the two
+ * vertices; `side` picks it as elsewhere.
+ *
+ * Binomials come from Pascal's rule (a table of C(x, j), x <= the largest
+ * degree of the side, j <= k), saturating at 2^128; the total is summed in
+ * 128 bits.  Returns 2 when a term or the total does not fit 128 bits.
+ * out[0] / out[1] receive the low / high 64 bits.  1 <= k <= 64. */
+typedef unsigned __int128 u128;
+static const u128 U128_MAX = ~(u128)0;
+
+static int pascal_table(int32_t xmax, int k, u128** tab_out) {
+    /* tab[x * (k + 1) + j] = C(x, j); U128_MAX marks a saturated entry */
+    const size_t w = (size_t)k + 1;
+    u128* tab = (u128*)calloc(((size_t)xmax + 1) * w, sizeof(u128));
+    if (!tab) return 1;
+    tab[0] = 1;
+    for (int32_t x = 1; x <= xmax; ++x) {
+        tab[(size_t)x * w] = 1;
+        for (int j = 1; j <= k; ++j) {
+            const u128 p = tab[(size_t)(x - 1) * w + j - 1], q = tab[(size_t)(x - 1) * w + j];
+            tab[(size_t)x * w + j] = (p == U128_MAX || q == U128_MAX || p > U128_MAX - q) ? U128_MAX : p + q;
+        }
+    }
+    *tab_out = tab;
+    return 0;
+}
+
+int oracle_count_bicliques(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                           const int8_t* sg, int side, int k, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    if (k < 1 || k > 64) return 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    int32_t dmax = 0;
+    for (int32_t u = 0; u < g.n_s; ++u)
+        if (g.s_off[u + 1] - g.s_off[u] > dmax) dmax = (int32_t)(g.s_off[u + 1] - g.s_off[u]);
+    u128* tab;
+    if (pascal_table(dmax, k, &tab)) {
+        sides_free(&g);
+        return 1;
+    }
+    uint32_t* B1 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B2 = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    u128 total = 0;
+    int over = 0;
+    for (int32_t u = 0; u < g.n_s; ++u) {
+        int32_t nt = 0;
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            const int32_t c = g.s_nbr[i];
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                const int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                if (B1[w] == 0 && B2[w] == 0) touched[nt++] = w;
+                if (g.c_sgn[j] == g.s_sgn[i]) B1[w]++;
+                else B2[w]++;
+            }
+        }
+        for (int32_t t = 0; t < nt; ++t) {
+            const int32_t w = touched[t];
+            const u128 x = tab[(size_t)B1[w] * (k + 1) + k], y = tab[(size_t)B2[w] * (k + 1) + k];
+            if (x == U128_MAX || y == U128_MAX || x > U128_MAX - y || total > U128_MAX - (x + y)) over = 1;
+            else total += x + y;
+            B1[w] = B2[w] = 0;
+        }
+    }
+    free(B1);
+    free(B2);
+    free(touched);
+    free(tab);
+    sides_free(&g);
+    out[0] = (uint64_t)total;
+    out[1] = (uint64_t)(total >> 64);
+    return over ? 2 : 0;
+}
+
+/* The same by brute force (tiny graphs): every pair of the side, every
+ * k-subset of its common neighbours, kept when every butterfly inside (two
+ * of the k centres) has an even number of negative edges (Definitions 2
+ * and 5).  Common-neighbour sets of at most 24 vertices; 64-bit total. */
+int oracle_brute_bicliques(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                           const int8_t* sg, int side, int k, uint64_t* out) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    if (k < 1 || (int64_t)n_u * n_v > (1LL << 26)) return 1;
+    const int su = pick_side(n_u, n_v, side) == 1;
+    const int32_t n_s = su ? n_u : n_v, n_c = su ? n_v : n_u;
+    int8_t* M = (int8_t*)calloc((size_t)n_s * (size_t)n_c + 1, 1);
+    for (int32_t u = 0; u < n_u; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            const int32_t a = su ? u : adj[e], c = su ? adj[e] : u;
+            M[(size_t)a * n_c + c] = sg[e];
+        }
+    int32_t common[24];
+    uint64_t cnt = 0;
+    int rc = 0;
+    for (int32_t a1 = 0; a1 < n_s && !rc; ++a1)
+        for (int32_t a2 = a1 + 1; a2 < n_s && !rc; ++a2) {
+            int nc = 0;
+            for (int32_t c = 0; c < n_c; ++c)
+                if (M[(size_t)a1 * n_c + c] && M[(size_t)a2 * n_c + c]) {
+                    if (nc == 24) {
+                        rc = 1;
+                        break;
+                    }
+                    common[nc++] = c;
+                }
+            if (rc || nc < k) continue;
+            for (uint32_t mask = 0; mask < (1u << nc); ++mask) {
+                if (__builtin_popcount(mask) != k) continue;
+                int ok = 1;
+                for (int i = 0; i < nc && ok; ++i) {
+                    if (!(mask >> i & 1)) continue;
+                    for (int j = i + 1; j < nc && ok; ++j) {
+                        if (!(mask >> j & 1)) continue;
+                        const int32_t c1 = common[i], c2 = common[j];
+                        const int prod = M[(size_t)a1 * n_c + c1] * M[(size_t)a2 * n_c + c1] *
+                                         M[(size_t)a1 * n_c + c2] * M[(size_t)a2 * n_c + c2];
+                        if (prod < 0) ok = 0;
+                    }
+                }
+                cnt += (uint64_t)ok;
+            }
+        }
+    free(M);
+    *out = cnt;
+    return rc;
+}
+
 /* The same classes by brute force over every 2 x 2 vertex choice (tiny
  * graphs): pairs on the anchor side, patterns read at the two centres. */
 int oracle_brute_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,

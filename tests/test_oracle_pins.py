@@ -545,3 +545,147 @@ def test_class_pins_catch_planted_mistakes(name, tmp_path):
         g = synth.small_random_graph(rng, max_n=7)
         failures += mclasses(g, oracle.SIDE_U) != py_classes(g, oracle.SIDE_U)
     assert failures > 0, f"mutant '{name}' passed every pin"
+
+
+# --------------------------------------------- balanced (2,k)-bicliques
+
+def py_bicliques(g, k, side):
+    """Definition 5 by enumeration (pure Python, tiny graphs): pairs of the
+    side, k-subsets of their common neighbours with every butterfly inside
+    balanced (an even number of negative edges)."""
+    import itertools
+
+    su = side == oracle.SIDE_U or (side == oracle.SIDE_AUTO and g.n_u < g.n_v)
+    nbr = {}
+    for u in range(g.n_u):
+        for e in range(g.offsets[u], g.offsets[u + 1]):
+            a, c = (u, int(g.adj[e])) if su else (int(g.adj[e]), u)
+            nbr.setdefault(a, {})[c] = int(g.signs[e])
+    keys = sorted(nbr)
+    n = 0
+    for i, a1 in enumerate(keys):
+        for a2 in keys[i + 1:]:
+            common = sorted(set(nbr[a1]) & set(nbr[a2]))
+            for sub in itertools.combinations(common, k):
+                n += all(nbr[a1][c1] * nbr[a2][c1] * nbr[a1][c2] * nbr[a2][c2] > 0
+                         for c1, c2 in itertools.combinations(sub, 2))
+    return n
+
+
+def test_bicliques_walk_matches_definition():
+    """Algorithm 1 with general k against the definition, enumerated in C
+    and in Python, k = 1..5, both sides."""
+    rng = np.random.default_rng(41)
+    for t in range(150):
+        g = synth.small_random_graph(rng, max_n=8)
+        for side in (oracle.SIDE_U, oracle.SIDE_V):
+            for k in (1, 2, 3, 4, 5):
+                want = oracle.brute_bicliques(g, k, side)
+                assert oracle.count_bicliques(g, k, side) == want
+                if t < 40:
+                    assert py_bicliques(g, k, side) == want
+
+
+def test_bicliques_special_cases():
+    """k = 2 is the balanced butterfly count (either side); k = 1 counts the
+    wedges with both ends on the side, sum of C(deg, 2) over the other side;
+    k above every degree gives 0."""
+    rng = np.random.default_rng(42)
+    for _ in range(40):
+        g = synth.random_graph(rng, int(rng.integers(2, 30)), int(rng.integers(2, 30)), 0.4, 0.4)
+        t = oracle.count(g)
+        du = np.diff(g.offsets).astype(np.int64)
+        dv = np.bincount(g.adj, minlength=g.n_v).astype(np.int64)
+        for side, dc in ((oracle.SIDE_U, dv), (oracle.SIDE_V, du)):
+            assert oracle.count_bicliques(g, 2, side) == t
+            assert oracle.count_bicliques(g, 1, side) == int((dc * (dc - 1) // 2).sum())
+            dmax = int(max(du.max(initial=0), dv.max(initial=0)))
+            assert oracle.count_bicliques(g, dmax + 1, side) == 0
+
+
+@pytest.mark.parametrize("m,n", [(2, 3), (3, 5), (5, 7), (4, 12)])
+def test_bicliques_closed_forms(m, n):
+    """K_{m,n}: all positive, C(m,2) C(n,k) with pairs on U; one negative
+    edge (u0, v0): pairs with u0 have n-1 symmetric and 1 asymmetric wedge,
+    (m-1) (C(n-1,k) + C(1,k)) + C(m-1,2) C(n,k); pairs on V swap m and n."""
+    from math import comb
+
+    for k in range(1, n + 2):
+        g = synth.complete_graph(m, n)
+        assert oracle.count_bicliques(g, k, oracle.SIDE_U) == comb(m, 2) * comb(n, k)
+        assert oracle.count_bicliques(g, k, oracle.SIDE_V) == comb(n, 2) * comb(m, k)
+        s = np.ones(m * n, np.int8)
+        s[0] = -1  # edge (u0, v0): CSR row 0, first entry
+        g1 = synth.complete_graph(m, n, signs=s)
+        assert int(g1.adj[0]) == 0
+        assert oracle.count_bicliques(g1, k, oracle.SIDE_U) == \
+            (m - 1) * (comb(n - 1, k) + comb(1, k)) + comb(m - 1, 2) * comb(n, k)
+        assert oracle.count_bicliques(g1, k, oracle.SIDE_V) == \
+            (n - 1) * (comb(m - 1, k) + comb(1, k)) + comb(n - 1, 2) * comb(m, k)
+
+
+def test_bicliques_128_bit_range():
+    """One pair sharing n centres: C(n,k) exactly past 64 bits, and an
+    error once the count leaves 128 bits."""
+    from math import comb
+
+    for n, k in ((1000, 9), (1000, 16), (3000, 12)):
+        g = synth.complete_graph(2, n)
+        want = comb(n, k)
+        assert want >= 1 << 64
+        assert oracle.count_bicliques(g, k, oracle.SIDE_U) == want
+    g = synth.complete_graph(2, 20000)
+    assert comb(20000, 16) >= 1 << 128
+    with pytest.raises(OverflowError):
+        oracle.count_bicliques(g, 16, oracle.SIDE_U)
+
+
+BICLIQUE_MUTANTS = {
+    "buckets merged": ("const u128 x = tab[(size_t)B1[w] * (k + 1) + k], y = tab[(size_t)B2[w] * (k + 1) + k];",
+                       "const u128 x = tab[(size_t)(B1[w] + B2[w]) * (k + 1) + k], y = 0;"),
+    "k ignored (k = 2)": ("const u128 x = tab[(size_t)B1[w] * (k + 1) + k], y = tab[(size_t)B2[w] * (k + 1) + k];",
+                          "const u128 x = tab[(size_t)B1[w] * (k + 1) + 2], y = tab[(size_t)B2[w] * (k + 1) + 2];"),
+    "Pascal rule off by one": ("const u128 p = tab[(size_t)(x - 1) * w + j - 1], q = tab[(size_t)(x - 1) * w + j];",
+                               "const u128 p = tab[(size_t)(x - 1) * w + j - 1], q = tab[(size_t)(x - 1) * w + j - 1];"),
+    "pair filter dropped": ("                if (w <= u) continue;\n                if (B1[w] == 0 && B2[w] == 0)",
+                            "                if (w == u) continue;\n                if (B1[w] == 0 && B2[w] == 0)"),
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name", sorted(BICLIQUE_MUTANTS))
+def test_biclique_pins_catch_planted_mistakes(name, tmp_path):
+    """Each plausible slip in the general-k walk makes a pin fail."""
+    import ctypes
+
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "bbc_oracle.c")).read()
+    old, new = BICLIQUE_MUTANTS[name]
+    i = src.index("static int pascal_table(")
+    j = src.index("int oracle_brute_bicliques(")
+    body = src[i:j]
+    assert body.count(old) == 1
+    mut = tmp_path / "mut.c"
+    mut.write_text(src[:i] + body.replace(old, new) + src[j:])
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), str(mut)])
+    lib = ctypes.CDLL(str(so))
+    P32, P8 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)
+    lib.oracle_count_bicliques.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P32, P32, P8,
+                                           ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+
+    def mcount(g, k, side):
+        off = np.ascontiguousarray(g.offsets, np.int32)
+        adj = np.ascontiguousarray(g.adj, np.int32)
+        sg = np.ascontiguousarray(g.signs, np.int8)
+        out = (ctypes.c_uint64 * 2)()
+        lib.oracle_count_bicliques(g.n_u, g.n_v, adj.size, off.ctypes.data_as(P32), adj.ctypes.data_as(P32),
+                                   sg.ctypes.data_as(P8), side, k, out)
+        return int(out[0]) | (int(out[1]) << 64)
+
+    failures = 0
+    rng = np.random.default_rng(43)
+    for _ in range(30):
+        g = synth.small_random_graph(rng, max_n=7)
+        for k in (1, 3):
+            failures += mcount(g, k, oracle.SIDE_U) != py_bicliques(g, k, oracle.SIDE_U)
+    assert failures > 0, f"mutant '{name}' passed every pin"
