@@ -53,15 +53,22 @@ typedef enum {
     BBC_EDUP = 5,     /* a repeated (u, v) pair */
     BBC_ENOMEM = 6,   /* device memory could not be allocated */
     BBC_EDEVICE = 7,  /* HIP runtime error; bbc_last_error has the detail */
-    BBC_ETOOBIG = 8   /* sizes beyond the int32 CSR limits */
+    BBC_ETOOBIG = 8,  /* sizes beyond the int32 CSR limits */
+    BBC_EOVERFLOW = 9 /* the result does not fit its integer width (bbc_count_bicliques) */
 } bbc_status;
 
 typedef struct bbc_ctx bbc_ctx;
 
 /* anchor side: the paper starts from the smaller side, a tie keeping V
  * (Algorithm 2: S = V, replaced by U when |V| > |U|); the count is the same
- * from either side (Sec. "BB2K Algorithm"). */
-enum { BBC_SIDE_AUTO = 0, BBC_SIDE_U = 1, BBC_SIDE_V = 2 };
+ * from either side (Sec. "BB2K Algorithm").  BBC_SIDE_MIN_WEDGES takes the
+ * side whose walk has fewer wedges (sum of C(deg, 2) over the other side),
+ * the partition choice of the butterfly-counting prior art the paper cites
+ * (Sec. "Related Work"); it measures both on the device and waits for the
+ * stream once before the count, a tie following the AUTO rule.  bbc_count
+ * only: batches, the planner and the class counts (whose classes depend on
+ * the paired side) reject it with BBC_EINVAL. */
+enum { BBC_SIDE_AUTO = 0, BBC_SIDE_U = 1, BBC_SIDE_V = 2, BBC_SIDE_MIN_WEDGES = 3 };
 
 /* optional input checks (offsets and id ranges are always checked, since
  * the kernels index with them) */
@@ -252,6 +259,26 @@ bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path);
 bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                              const int32_t* adj, const int8_t* signs, uint64_t* classes, const bbc_options* opts,
                              void* stream);
+
+/* Balanced (2,k)-bicliques (Definition 5; the generalisation named in Sec.
+ * "Future Directions"): two vertices of the pair side and k common
+ * neighbours, all 2k edges present and no unbalanced butterfly inside.  By
+ * Lemma 1 the k centres of such a biclique give wedges of one kind, so the
+ * count is, over pairs {u, w} of the pair side, C(a_uw, k) + C(b_uw, k) with
+ * a / b the symmetric / asymmetric wedge counts (Algorithm 1 with general
+ * k).  k = 2 is bbc_count's total; k = 1 counts the wedges.  Unlike k = 2
+ * the result depends on the pair side: opts->side (BBC_SIDE_U or _V; AUTO
+ * takes the smaller side, a tie V; BBC_SIDE_MIN_WEDGES is rejected).
+ * count (host, 2 uint64) receives the exact 128-bit result, low word
+ * first; BBC_EOVERFLOW when it, or one pair's term, does not fit 128 bits.
+ * 1 <= k <= BBC_BICLIQUE_MAX_K, else BBC_EINVAL.  The same walk as
+ * bbc_count in one kernel shape (256 threads, 8,192-word bands); dense
+ * blocks, per-vertex output and batches are not offered (BBC_EINVAL for
+ * blocks).  Other arguments, errors and synchronisation as bbc_count. */
+#define BBC_BICLIQUE_MAX_K 16
+bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                               const int32_t* adj, const int8_t* signs, int32_t k, uint64_t* count,
+                               const bbc_options* opts, void* stream);
 
 /* Dense-block planner options.  Candidates are the vertices of degree >=
  * min_degree.  A block grows from a seed anchor: C starts as the seed's

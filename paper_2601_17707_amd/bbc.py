@@ -14,13 +14,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbbc.so")
 
-OK, EINVAL, EOFFSETS, ERANGE, ESIGN, EDUP, ENOMEM, EDEVICE, ETOOBIG = range(9)
-SIDE_AUTO, SIDE_U, SIDE_V = 0, 1, 2
+OK, EINVAL, EOFFSETS, ERANGE, ESIGN, EDUP, ENOMEM, EDEVICE, ETOOBIG, EOVERFLOW = range(10)
+SIDE_AUTO, SIDE_U, SIDE_V, SIDE_MIN_WEDGES = 0, 1, 2, 3
 CHECK_SIGNS, CHECK_DUPLICATES, CHECK_ALL = 1, 2, 3
 # instantiated wedge-kernel shapes (band_words, wg_size); the first is the default
 WEDGE_SHAPES = [(8192, 256), (16384, 512), (16384, 256), (8192, 512), (32768, 1024), (16384, 1024),
                 (4096, 128), (8192, 128), (4096, 256)]
-_SIDES = {"auto": SIDE_AUTO, "u": SIDE_U, "v": SIDE_V, SIDE_AUTO: SIDE_AUTO, SIDE_U: SIDE_U, SIDE_V: SIDE_V}
+_SIDES = {"auto": SIDE_AUTO, "u": SIDE_U, "v": SIDE_V, "min_wedges": SIDE_MIN_WEDGES, SIDE_AUTO: SIDE_AUTO,
+          SIDE_U: SIDE_U, SIDE_V: SIDE_V, SIDE_MIN_WEDGES: SIDE_MIN_WEDGES}
 
 
 class BbcError(RuntimeError):
@@ -152,6 +153,9 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_count_classes.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64),
                                       ctypes.POINTER(Options), vp]
     lib.bbc_count_classes.restype = ctypes.c_int
+    lib.bbc_count_bicliques.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_uint64),
+                                        ctypes.POINTER(Options), vp]
+    lib.bbc_count_bicliques.restype = ctypes.c_int
     lib.bbc_plan_options_init.argtypes = [ctypes.POINTER(PlanOptions)]
     lib.bbc_plan_options_init.restype = ctypes.c_int
     lib.bbc_plan_blocks.argtypes = [vp, i32, i32, i64, vp, vp, ctypes.POINTER(PlanOptions), i32,
@@ -301,6 +305,24 @@ class Context:
         if st != OK:
             raise BbcError(st, self.last_error())
         return [int(x) for x in out]
+
+    def count_bicliques(self, offsets, adj, signs, n_v: int, k: int, opts: Options | None = None,
+                        stream=None) -> int:
+        """Balanced (2,k)-bicliques with the pair on ``options(side=...)``,
+        exact (128-bit) as a Python int."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        out = (ctypes.c_uint64 * 2)()
+        o = opts if opts is not None else options()
+        st = self._lib.bbc_count_bicliques(self._h, offsets.numel() - 1, int(n_v), adj.numel(), _ptr(offsets),
+                                           _ptr(adj), _ptr(signs), int(k), out, ctypes.byref(o),
+                                           _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return int(out[0]) | (int(out[1]) << 64)
 
     def count_batched(self, batch: "Batch", opts: Options | None = None, stream=None):
         """Per-graph counts of a Batch; returns its totals tensor (int64, on device)."""

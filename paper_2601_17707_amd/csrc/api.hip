@@ -20,6 +20,8 @@ void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,
                  int64_t scratch_words, const DevStatus* st, hipStream_t s);
 void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s);
+void launch_side_wedges(const int32_t* off, int32_t n_u, const int32_t* adj, int64_t m, int32_t n_v, uint32_t* deg,
+                        unsigned long long* out, hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
@@ -70,7 +72,10 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int2* bmeta, const uint32_t* order,
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
-                  unsigned long long* gtotals, const HybridView& hv, bool classes, hipStream_t s);
+                  unsigned long long* gtotals, const HybridView& hv, int kind, int32_t bic_k,
+                  const unsigned long long* bic_tab, hipStream_t s);
+int wedge_bic_blocks_per_cu();
+void launch_choose_table(int32_t k, unsigned long long* tab, hipStream_t s);
 
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -183,6 +188,7 @@ struct Job {
     int band_words = 0, wg_size = 0, grid = 0;
     bool tuned = false;  // shape taken from the tuning table
     bool classes = false;  // the six sign-pattern classes instead of the total
+    int32_t bic_k = 0;     // > 0: balanced (2,k)-bicliques instead of the total
     // dense blocks (single graph only)
     int32_t n_blocks = 0, n_tiles = 0;
     int64_t r_first = 0;  // first rank of the block anchors (they sit at the top)
@@ -215,6 +221,7 @@ struct Plan {
     uint32_t* tabs;
     uint32_t *bnb, *bioff, *bidx;  // band-boundary index of the centre lists
     int2* bmeta;
+    unsigned long long* bic_tab;  // C(x, k) for x < 256 (biclique mode)
 
     size_t carve(char* base, const Job& J) {
         Carve c(base);
@@ -272,6 +279,7 @@ struct Plan {
         bioff = c.take<uint32_t>(idx ? n_c + 1 : 0);
         bidx = c.take<uint32_t>(idx ? m : 0);
         bmeta = c.take<int2>(idx ? n_c : 0);
+        bic_tab = c.take<unsigned long long>(J.bic_k > 0 ? 512 : 0);
         return c.used;
     }
 };
@@ -384,12 +392,14 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
         launch_dense(P.dblocks, P.dtiles, J.n_tiles, P.mats, P.tabs, st, s);
         if (ev) (void)hipEventRecord(ev[5], s);
     }
+    if (J.bic_k > 0) launch_choose_table(J.bic_k, P.bic_tab, s);
     if (n_s >= 2 && m > 0)
         launch_wedge(J.band_words, J.wg_size, J.grid, P.aoff, P.acent, P.aneg, P.back, P.coff, packed, P.bidx,
                      P.bmeta, order,
                      (int32_t)n_s, st, J.pv, inv, J.s_is_u ? 0 : J.n_u, J.s_is_u ? J.n_u : 0, n_c,
                      J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
-                     J.batched ? J.totals : nullptr, hv, J.classes, s);
+                     J.batched ? J.totals : nullptr, hv,
+                     J.classes ? kWedgeClasses : J.bic_k > 0 ? kWedgeBicliques : kWedgeCount, J.bic_k, P.bic_tab, s);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
@@ -416,7 +426,7 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
         if (in->struct_size != sizeof(bbc_options)) return fail(ctx, BBC_EINVAL, "bbc_options.struct_size");
         *o = *in;
     }
-    if (o->side < BBC_SIDE_AUTO || o->side > BBC_SIDE_V) return fail(ctx, BBC_EINVAL, "bad side option");
+    if (o->side < BBC_SIDE_AUTO || o->side > BBC_SIDE_MIN_WEDGES) return fail(ctx, BBC_EINVAL, "bad side option");
     if (!wedge_shape_ok(o->band_words, o->wg_size))
         return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
     if (o->wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
@@ -425,6 +435,30 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
 }
 
 bool side_is_u(int side, int32_t n_u, int32_t n_v) { return side == BBC_SIDE_U || (side == BBC_SIDE_AUTO && n_u < n_v); }
+
+// The anchor side of a single-graph call.  BBC_SIDE_MIN_WEDGES measures
+// both choices on the device (sum of C(deg, 2) over the centre side) and
+// takes the one with fewer wedges, the default rule breaking a tie; it
+// waits for the stream once.
+bbc_status resolve_side(bbc_ctx* ctx, int side, int32_t n_u, int32_t n_v, int64_t m, const int32_t* off,
+                        const int32_t* adj, hipStream_t s, bool* su) {
+    if (side != BBC_SIDE_MIN_WEDGES) {
+        *su = side_is_u(side, n_u, n_v);
+        return BBC_OK;
+    }
+    const size_t bytes = 32 + (size_t)n_v * 4;
+    bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, bytes);
+    if (rc != BBC_OK) return rc;
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(ctx->arena);
+    launch_side_wedges(off, n_u, adj, m, n_v, reinterpret_cast<uint32_t*>(ctx->arena + 32), out, s);
+    unsigned long long w[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(w, out, sizeof(w), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "side choice");
+    // w[0]: wedges with anchors on V (centres U); w[1]: anchors on U
+    *su = w[1] < w[0] || (w[1] == w[0] && side_is_u(BBC_SIDE_AUTO, n_u, n_v));
+    return BBC_OK;
+}
 
 void tune_class(int64_t n_s, int64_t m, int32_t* ns_bits, int32_t* deg_bits) {
     *ns_bits = bits_for((uint64_t)(n_s > 0 ? n_s : 0));
@@ -463,6 +497,8 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
     if (n_graphs < 0) return fail(ctx, BBC_EINVAL, "negative n_graphs");
     bbc_options o = o_in;
     if (o.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks apply to bbc_count only");
+    if (o.side == BBC_SIDE_MIN_WEDGES)
+        return fail(ctx, BBC_EINVAL, "BBC_SIDE_MIN_WEDGES applies to single-graph calls only");
     if (n_graphs > 0 && (!d || !off_cat || !totals)) return fail(ctx, BBC_EINVAL, "batch pointer is NULL");
     dg.resize((size_t)n_graphs);
     vstart.assign((size_t)n_graphs + 1, 0);
@@ -686,6 +722,7 @@ const char* bbc_status_string(bbc_status s) {
         case BBC_ENOMEM: return "out of device memory";
         case BBC_EDEVICE: return "HIP device error";
         case BBC_ETOOBIG: return "graph too large for int32 CSR";
+        case BBC_EOVERFLOW: return "result does not fit its integer width";
     }
     return "unknown status";
 }
@@ -769,7 +806,8 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     J.sg = signs;
     J.n_u = n_u;
     J.n_v = n_v;
-    J.s_is_u = side_is_u(opts.side, n_u, n_v);
+    rc = resolve_side(ctx, opts.side, n_u, n_v, n_edges, offsets, adj, (hipStream_t)stream, &J.s_is_u);
+    if (rc != BBC_OK) return rc;
     J.pv = (unsigned long long*)per_vertex;
     J.m = n_edges;
     J.n_s = J.s_is_u ? n_u : n_v;
@@ -806,6 +844,8 @@ bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_e
     if (rc != BBC_OK) return rc;
     if (!classes) return fail(ctx, BBC_EINVAL, "classes is NULL");
     if (opts.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with class counts");
+    if (opts.side == BBC_SIDE_MIN_WEDGES)
+        return fail(ctx, BBC_EINVAL, "class counts depend on the paired side: choose BBC_SIDE_U, _V or _AUTO");
     if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
     if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
         return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
@@ -830,6 +870,56 @@ bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_e
     rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
     if (rc != BBC_OK) return rc;
     for (int k = 0; k < 6; ++k) classes[k] = (uint64_t)ctx->st_host->cls[k];
+    return BBC_OK;
+}
+
+bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                               const int32_t* adj, const int8_t* signs, int32_t k, uint64_t* count,
+                               const bbc_options* opts_in, void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    bbc_options opts;
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
+    if (!count) return fail(ctx, BBC_EINVAL, "count is NULL");
+    if (k < 1 || k > BBC_BICLIQUE_MAX_K) return fail(ctx, BBC_EINVAL, "k outside [1, BBC_BICLIQUE_MAX_K]");
+    if (opts.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with biclique counts");
+    if (opts.side == BBC_SIDE_MIN_WEDGES)
+        return fail(ctx, BBC_EINVAL, "biclique counts depend on the side of the pair: choose BBC_SIDE_U, _V or _AUTO");
+    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+
+    DeviceGuard guard(ctx->device);
+    Job J;
+    J.off = offsets;
+    J.adj = adj;
+    J.sg = signs;
+    J.n_u = n_u;
+    J.n_v = n_v;
+    J.s_is_u = side_is_u(opts.side, n_u, n_v);
+    J.m = n_edges;
+    J.n_s = J.s_is_u ? n_u : n_v;
+    J.n_c = J.s_is_u ? n_v : n_u;
+    J.checks = opts.checks;
+    J.bic_k = k;
+    J.band_words = 8192;
+    J.wg_size = 256;
+    J.grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_bic_blocks_per_cu());
+    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
+    if (rc != BBC_OK) return rc;
+    // 32-bit limbs summed in 64 bits: carry them into the 128-bit result
+    const unsigned long long* l = ctx->st_host->cls;
+    unsigned long long c = 0, w[4];
+    for (int j = 0; j < 4; ++j) {
+        const unsigned long long t = l[j] + c;  // l[j] < 2^63 for any graph the kernel accepts
+        w[j] = t & 0xffffffffull;
+        c = t >> 32;
+    }
+    if (c != 0 || l[4] != 0) return fail(ctx, BBC_EOVERFLOW, "(2,k)-biclique count does not fit 128 bits");
+    count[0] = w[0] | (w[1] << 32);
+    count[1] = w[2] | (w[3] << 32);
     return BBC_OK;
 }
 

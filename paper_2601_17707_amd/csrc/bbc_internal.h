@@ -21,12 +21,16 @@ struct DevStatus {
     unsigned long long wedges;  // sum over centres of C(deg, 2)
     unsigned long long walked;  // wedges the sparse walk visits (dense-block wedges excluded)
     unsigned long long bands;   // counter bands processed
-    unsigned long long cls[6];  // sign-pattern classes (class mode)
+    unsigned long long cls[6];  // sign-pattern classes (class mode); biclique limbs and overflows
     unsigned int queue;         // persistent work queue head
     unsigned int pad1;
 };
 
 enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8, kBadBlocks = 16 };
+
+// What the wedge kernel sums: the balanced count, the six sign-pattern
+// classes, or balanced (2,k)-bicliques.
+enum : int { kWedgeCount = 0, kWedgeClasses = 1, kWedgeBicliques = 2 };
 
 // Band-boundary index: meta.x of a centre list that has no index entries.
 constexpr int32_t kBidxNone = INT32_MIN;

@@ -139,6 +139,38 @@ __global__ void k_hist_sum(const uint32_t* rep, int64_t n_bins, int nrep, uint32
     }
 }
 
+// Wedges of each anchor-side choice: the walk from anchors on one side
+// visits every pair of neighbours of every centre once, sum of C(deg, 2)
+// over the other side.  k_side_rows adds C(deg, 2) of the U rows into
+// out[0] (the walk from anchors on V); k_side_hist counts V degrees (ids
+// outside [0, n_v) are skipped: the count's own checks report them) and
+// k_side_bins adds their C(deg, 2) into out[1] (anchors on U).  Rows with
+// decreasing offsets count as empty here.
+__device__ __forceinline__ unsigned long long choose2_u64(long long d) {
+    return d > 1 ? (unsigned long long)d * (unsigned long long)(d - 1) / 2ull : 0ull;
+}
+
+__global__ void k_side_rows(const int32_t* off, int32_t n_u, unsigned long long* out) {
+    unsigned long long acc = 0;
+    GRID_STRIDE(i, n_u) acc += choose2_u64((long long)off[i + 1] - (long long)off[i]);
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(&out[0], acc);
+}
+
+__global__ void k_side_hist(const int32_t* adj, int64_t m, int32_t n_v, uint32_t* deg) {
+    GRID_STRIDE(i, m) {
+        const int32_t v = adj[i];
+        if (v >= 0 && v < n_v) atomicAdd(&deg[v], 1u);
+    }
+}
+
+__global__ void k_side_bins(const uint32_t* deg, int32_t n_v, unsigned long long* out) {
+    unsigned long long acc = 0;
+    GRID_STRIDE(i, n_v) acc += choose2_u64(deg[i]);
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(&out[1], acc);
+}
+
 // Degrees of the CSR rows (U) straight from the offsets.
 __global__ void k_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st) {
     const bool bad = input_bad(st);
@@ -370,6 +402,15 @@ void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, 
     if (n > 0)
         hipLaunchKernelGGL(k_hist_rep, dim3(grid_for(n, 256)), dim3(256), 0, s, ids, n, scratch, n_bins, nrep, st);
     hipLaunchKernelGGL(k_hist_sum, dim3(grid_for(n_bins, 256)), dim3(256), 0, s, scratch, n_bins, nrep, deg);
+}
+
+void launch_side_wedges(const int32_t* off, int32_t n_u, const int32_t* adj, int64_t m, int32_t n_v, uint32_t* deg,
+                        unsigned long long* out, hipStream_t s) {
+    fill_u32(reinterpret_cast<uint32_t*>(out), 0u, 4, s);
+    fill_u32(deg, 0u, n_v, s);
+    if (n_u > 0) hipLaunchKernelGGL(k_side_rows, dim3(grid_for(n_u, 256)), dim3(256), 0, s, off, n_u, out);
+    if (m > 0) hipLaunchKernelGGL(k_side_hist, dim3(grid_for(m, 256)), dim3(256), 0, s, adj, m, n_v, deg);
+    if (n_v > 0) hipLaunchKernelGGL(k_side_bins, dim3(grid_for(n_v, 256)), dim3(256), 0, s, deg, n_v, out);
 }
 
 void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s) {

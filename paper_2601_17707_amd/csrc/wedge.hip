@@ -755,6 +755,136 @@ __device__ __forceinline__ void reduce_classes(WedgeShared<WG, BAND_WORDS, FULL>
     __syncthreads();
 }
 
+// Balanced (2,k)-bicliques: per endpoint pair C(a, k) + C(b, k) as exact
+// 128-bit integers.  tab holds C(x, k) for x < 256 (low, high words);
+// larger counts use the multiplicative formula.
+struct BicView {
+    int32_t k;  // 1..16
+    const unsigned long long* __restrict__ tab;
+};
+
+// C(x, k) in four 32-bit limbs: after step i the limbs hold C(x, i + 1),
+// since C(x, i) (x - i) is divisible by i + 1.  ovf is set when a partial
+// product leaves 128 bits.
+__device__ inline void choose_u128(uint32_t x, int k, unsigned long long& lo, unsigned long long& hi, bool& ovf) {
+    uint32_t l[4] = {1u, 0u, 0u, 0u};
+    for (int i = 0; i < k; ++i) {
+        const unsigned long long f = x - (uint32_t)i;
+        unsigned long long carry = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned long long t = (unsigned long long)l[j] * f + carry;
+            l[j] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        if (carry) ovf = true;
+        const unsigned long long d = (unsigned long long)(i + 1);
+        unsigned long long r = 0;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const unsigned long long t = (r << 32) | l[j];
+            l[j] = (uint32_t)(t / d);
+            r = t % d;
+        }
+    }
+    lo = ((unsigned long long)l[1] << 32) | l[0];
+    hi = ((unsigned long long)l[3] << 32) | l[2];
+}
+
+// Biclique sums ride in a ClassSums: c[0..3] are 32-bit limbs of the 128-bit
+// sum kept in 64-bit registers (carried once per band), c[4] counts terms
+// that do not fit 128 bits.
+__device__ __forceinline__ void bic_field(ClassSums& cs, const BicView& bv, uint32_t x) {
+    if (x < (uint32_t)bv.k) return;
+    unsigned long long lo, hi;
+    if (x < 256u) {
+        lo = bv.tab[2 * x];
+        hi = bv.tab[2 * x + 1];
+    } else {
+        bool ovf = false;
+        choose_u128(x, bv.k, lo, hi, ovf);
+        if (ovf) {
+            cs.c[4] += 1;
+            return;
+        }
+    }
+    cs.c[0] += lo & 0xffffffffull;
+    cs.c[1] += lo >> 32;
+    cs.c[2] += hi & 0xffffffffull;
+    cs.c[3] += hi >> 32;
+}
+
+__device__ __forceinline__ void bic_carry(ClassSums& cs) {
+    cs.c[1] += cs.c[0] >> 32;
+    cs.c[0] &= 0xffffffffull;
+    cs.c[2] += cs.c[1] >> 32;
+    cs.c[1] &= 0xffffffffull;
+    cs.c[3] += cs.c[2] >> 32;
+    cs.c[2] &= 0xffffffffull;
+}
+
+// Fields of one counter word in the count layouts (a and b alike).
+template <int MODE>
+__device__ __forceinline__ void bic_word(ClassSums& cs, const BicView& bv, uint32_t v) {
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int f = 0; f < 8; ++f) bic_field(cs, bv, (v >> (4 * f)) & 15u);
+    } else if constexpr (MODE == 1) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) bic_field(cs, bv, (v >> (8 * f)) & 255u);
+    } else if constexpr (MODE == 2) {
+        bic_field(cs, bv, v & 0xffffu);
+        bic_field(cs, bv, v >> 16);
+    } else {
+        bic_field(cs, bv, v);
+    }
+}
+
+// Biclique mode: C(x, k) of every field of every touched word (a full scan
+// of a dense band, the touched-word bitmap otherwise), clearing the
+// counters.  Ends with a barrier.
+template <int MODE, int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void reduce_bic(WedgeShared<WG, BAND_WORDS, FULL>& sh, const BicView& bv, ClassSums& cs,
+                                           bool dense) {
+    if (dense) {
+        for (uint32_t w4 = threadIdx.x; w4 < (uint32_t)BAND_WORDS / 4u; w4 += WG) {
+            uint4* q = reinterpret_cast<uint4*>(&sh.cnt[w4 * 4u]);
+            const uint4 v = *q;
+            if (!(v.x | v.y | v.z | v.w)) continue;
+            *q = uint4{0u, 0u, 0u, 0u};
+            bic_word<MODE>(cs, bv, v.x);
+            bic_word<MODE>(cs, bv, v.y);
+            bic_word<MODE>(cs, bv, v.z);
+            bic_word<MODE>(cs, bv, v.w);
+        }
+    } else {
+        for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
+            uint32_t bits = sh.bmp[b];
+            if (bits) {
+                sh.bmp[b] = 0;
+                while (bits) {
+                    const uint32_t wd = (b << 5) + (uint32_t)(__ffs(bits) - 1);
+                    bits &= bits - 1u;
+                    bic_word<MODE>(cs, bv, sh.cnt[wd]);
+                    sh.cnt[wd] = 0;
+                }
+            }
+        }
+    }
+    bic_carry(cs);
+    __syncthreads();
+}
+
+// C(x, k) for x = 0..255 (one workgroup of 256 threads); x < k gives 0.
+__global__ void k_choose_table(int32_t k, unsigned long long* tab) {
+    const uint32_t x = threadIdx.x;
+    unsigned long long lo = 0, hi = 0;
+    bool ovf = false;
+    if (x >= (uint32_t)k) choose_u128(x, k, lo, hi, ovf);  // C(255, 16) < 2^81: no overflow here
+    tab[2 * x] = lo;
+    tab[2 * x + 1] = hi;
+}
+
 // Sum of the pair terms of every touched counter word, and clears them.
 // A dense band is scanned word by word; otherwise the touched-word bitmap
 // is scanned in full (slots are scattered over the whole band capacity).
@@ -848,14 +978,15 @@ constexpr int mode_granule_shift() { return MODE >= 4 ? ilog2(BAND_WORDS) - 2 : 
 // start and end on granule multiples.  Returns this thread's share of the
 // anchor's pair terms (twice the pair terms in count mode; the shares are
 // meaningful only summed over the workgroup).
-template <int MODE, bool FULL, int WG, int BAND_WORDS>
+template <int MODE, bool FULL, bool BIC, int WG, int BAND_WORDS>
 __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_WORDS, FULL>& sh, const int32_t* __restrict__ acent,
                                            const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
                                            const uint32_t* __restrict__ bidx, const int2* __restrict__ bmeta,
                                            int32_t a0, int32_t deg, int32_t r, int64_t n_s,
                                            unsigned long long* __restrict__ pv, int64_t centre_base,
-                                           unsigned long long& bands, const HybridView& hv, ClassSums& cs) {
+                                           unsigned long long& bands, const HybridView& hv, ClassSums& cs,
+                                           const BicView& bv) {
     constexpr int64_t band_slots = band_capacity<MODE, BAND_WORDS>();
     constexpr int gs = mode_granule_shift<MODE, BAND_WORDS>();
     auto band_end = [&](int64_t lo) {
@@ -913,6 +1044,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                 walk_start(sh.tab[buf ^ 1], packed, total2, nkc2, w2, next2, have_next2);
             }
             if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense);
+            else if constexpr (BIC) reduce_bic<MODE>(sh, bv, cs, dense);
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
             if (!more) break;
@@ -936,6 +1068,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             const int32_t total = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
                                                         FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
             if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense_band<MODE, BAND_WORDS>(total));
+            else if constexpr (BIC) reduce_bic<MODE>(sh, bv, cs, dense_band<MODE, BAND_WORDS>(total));
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense_band<MODE, BAND_WORDS>(total), total);
             ++bands;
         }
@@ -975,6 +1108,7 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                 }
             }
             if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense);
+            else if constexpr (BIC) reduce_bic<MODE>(sh, bv, cs, dense);
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
             ++bands;
         }
@@ -986,8 +1120,10 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
 // each graph, n_graphs + 1 entries) and per-graph totals; an anchor's
 // endpoints then stop at the end of its graph's rank range.
 // CLS: the six sign-pattern classes instead of the balanced total (count
-// mode only), summed into st->cls.
-template <int WG, int BAND_WORDS, bool FULL, bool CLS = false>
+// mode only), summed into st->cls.  BIC: balanced (2,k)-bicliques, the
+// 128-bit sum as 32-bit limbs in st->cls[0..3] and the count of terms
+// beyond 128 bits in st->cls[4].
+template <int WG, int BAND_WORDS, bool FULL, bool CLS = false, bool BIC = false>
 __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
@@ -997,7 +1133,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
                                               int64_t anchor_base, int64_t centre_base,
                                               const int32_t* __restrict__ agraph,
                                               const int64_t* __restrict__ rank_end,
-                                              unsigned long long* __restrict__ gtotals, HybridView hv) {
+                                              unsigned long long* __restrict__ gtotals, HybridView hv, BicView bv) {
     if (*(volatile const int32_t*)&st->flags) return;  // input error: nothing to count
     __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
@@ -1014,22 +1150,23 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
         const int32_t r = (int32_t)order[task];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
         const int64_t n_end = agraph ? rank_end[agraph[r] + 1] : (int64_t)n_s;
-        // fewer than two centres: no endpoint pair shares two wedges
-        if (deg < 2 || (!FULL && r >= n_end - 1)) continue;
+        // fewer than two centres (k in biclique mode): no endpoint pair
+        // shares enough wedges
+        if (deg < (BIC ? bv.k : 2) || (!FULL && r >= n_end - 1)) continue;
         constexpr int M0 = CLS ? 4 : 0;  // counter mode of degree class 0; classes use modes 4-7
         unsigned long long a;
         if (deg <= 15)
-            a = count_anchor<M0 + 0, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                             centre_base, bands, hv, cs);
+            a = count_anchor<M0 + 0, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
+                                                  pv, centre_base, bands, hv, cs, bv);
         else if (deg <= 255)
-            a = count_anchor<M0 + 1, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                             centre_base, bands, hv, cs);
+            a = count_anchor<M0 + 1, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
+                                                  pv, centre_base, bands, hv, cs, bv);
         else if (deg <= 65535)
-            a = count_anchor<M0 + 2, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                             centre_base, bands, hv, cs);
+            a = count_anchor<M0 + 2, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
+                                                  pv, centre_base, bands, hv, cs, bv);
         else
-            a = count_anchor<M0 + 3, FULL>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end, pv,
-                                             centre_base, bands, hv, cs);
+            a = count_anchor<M0 + 3, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
+                                                  pv, centre_base, bands, hv, cs, bv);
         if constexpr (FULL) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
             if (tid == 0) pv[anchor_base + inv[r]] = s;
@@ -1041,7 +1178,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     }
     acc = wave_sum(acc);
     if (lane_id() == 0 && acc) atomicAdd(&st->total, acc);
-    if constexpr (CLS) {
+    if constexpr (CLS || BIC) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const unsigned long long v = wave_sum(cs.c[k]);
@@ -1080,19 +1217,21 @@ struct WedgeArgs {
     const int64_t* rank_end;
     unsigned long long* gtotals;
     HybridView hv;
+    BicView bv;
 };
 
-template <int WG, int BW, bool FULL, bool CLS = false>
+template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
 static void launch_shape(const WedgeArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back, a.coff,
-                       a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base, a.centre_base,
-                       a.agraph, a.rank_end, a.gtotals, a.hv);
+    hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS, BIC>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back,
+                       a.coff, a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base,
+                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv);
 }
 
-template <int WG, int BW, bool FULL, bool CLS = false>
+template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
 static int occupancy() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL, CLS>, WG, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL, CLS, BIC>, WG, 0) != hipSuccess)
+        return 1;
     return n > 0 ? n : 1;
 }
 
@@ -1110,6 +1249,7 @@ static const WedgeShape kShapes[] = {BBC_SHAPE(256, 8192),  BBC_SHAPE(512, 16384
 #undef BBC_SHAPE
 constexpr int kFullWG = 256, kFullBW = 16384;
 constexpr int kClsWG = 256, kClsBW = 8192;  // sign-pattern classes: one shape
+constexpr int kBicWG = 256, kBicBW = 8192;  // (2,k)-bicliques: one shape, the count layouts
 
 static int shape_index(int band_words, int wg) {
     int n = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
@@ -1137,6 +1277,12 @@ int wedge_class_blocks_per_cu() { return occupancy<kClsWG, kClsBW, false, true>(
 
 int wedge_class_band() { return kClsBW; }
 
+int wedge_bic_blocks_per_cu() { return occupancy<kBicWG, kBicBW, false, false, true>(); }
+
+void launch_choose_table(int32_t k, unsigned long long* tab, hipStream_t s) {
+    hipLaunchKernelGGL(k_choose_table, dim3(1), dim3(256), 0, s, k, tab);
+}
+
 int wedge_blocks_per_cu(int band_words, int wg, bool full) {
     if (full) return occupancy<kFullWG, kFullBW, true>();
     const int i = shape_index(band_words, wg);
@@ -1148,9 +1294,9 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int2* bmeta, const uint32_t* order, int32_t n_s, DevStatus* st, unsigned long long* pv,
                   const uint32_t* inv, int64_t anchor_base, int64_t centre_base, int64_t n_centre,
                   const int32_t* agraph, const int64_t* rank_end, unsigned long long* gtotals, const HybridView& hv,
-                  bool classes, hipStream_t s) {
+                  int kind, int32_t bic_k, const unsigned long long* bic_tab, hipStream_t s) {
     const WedgeArgs a{aoff, acent, aneg, back, coff, packed, bidx, bmeta, order, n_s, st, pv, inv,
-                      anchor_base, centre_base, agraph, rank_end, gtotals, hv};
+                      anchor_base, centre_base, agraph, rank_end, gtotals, hv, BicView{bic_k, bic_tab}};
     if (pv) {
         launch_shape<kFullWG, kFullBW, true>(a, grid, s);
         if (n_centre > 0) {
@@ -1160,8 +1306,12 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
         }
         return;
     }
-    if (classes) {
+    if (kind == kWedgeClasses) {
         launch_shape<kClsWG, kClsBW, false, true>(a, grid, s);
+        return;
+    }
+    if (kind == kWedgeBicliques) {
+        launch_shape<kBicWG, kBicBW, false, false, true>(a, grid, s);
         return;
     }
     const int i = shape_index(band_words, wg);
