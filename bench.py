@@ -11,9 +11,9 @@ sum over centres c of C(deg c, 2): every wedge u - c - w with w ranked above
 u, walked exactly once.  The line also carries the batched measurement
 (graphs/s of 10,000 graphs of uneven size, one captured batch plan, against
 a loop of plain per-graph calls), the six sign-pattern classes on the same
-graph, the dense-block workload (hybrid int8 matrix-core path against the
-sparse-only path), the roofline of the wedge kernel and the CPU oracle's
-rate.
+graph, balanced (2,k)-bicliques for k = 2..4 on it, the dense-block
+workload (hybrid int8 matrix-core path against the sparse-only path), the
+roofline of the wedge kernel and the CPU oracle's rate.
 """
 from __future__ import annotations
 
@@ -166,6 +166,32 @@ def bench_classes(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps: i
                 balanced_matches_count=bool(sum(cls[:4]) == total))
 
 
+def bench_bicliques(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps: int, warmup: int) -> dict:
+    """Balanced (2,k)-bicliques on the resident bench graph, pairs on the
+    anchor side of the count, for k = 3 and 4 (exact 128-bit sums), and
+    k = 2 checked against the balanced count."""
+    import torch
+
+    from paper_2601_17707_amd import bbc
+
+    out = {}
+    for k in (2, 3, 4):
+        for _ in range(max(1, warmup)):
+            r = ctx.count_bicliques(off, adj, sg, n_v, k)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.count_bicliques(off, adj, sg, n_v, k)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t) / steps
+        ctx.count_bicliques(off, adj, sg, n_v, k, opts=bbc.options(timing=True))
+        out[f"k{k}"] = dict(count=str(r), ms_per_call=ms, kernel_ms=ctx.stats()["ms_count"],
+                            wedges_per_s=wedges / (ms / 1e3) / 1e9)
+    out["unit"] = "G/s"
+    out["k2_matches_count"] = bool(int(out["k2"]["count"]) == total)
+    return out
+
+
 def bench_hybrid(ctx, steps: int, warmup: int, seed: int) -> dict:
     """The planted-block workload (power-law background, |U| = 2e6, |V| = 1e6,
     5e7 background edges, 16 blocks of 4096 x 4096 at density 0.5) counted
@@ -242,6 +268,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-graph batch measurement")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the dense-block workload")
     ap.add_argument("--no-classes", action="store_true", help="skip the sign-pattern class count")
+    ap.add_argument("--no-bicliques", action="store_true", help="skip the (2,k)-biclique counts")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -329,6 +356,9 @@ def main():
     if not args.no_classes:
         line["classes"] = bench_classes(ctx, off, adj, sg, g.n_v, wedges, total, max(1, min(args.steps, 5)),
                                         args.warmup)
+    if not args.no_bicliques:
+        line["bicliques"] = bench_bicliques(ctx, off, adj, sg, g.n_v, wedges, total, max(1, min(args.steps, 3)),
+                                            args.warmup)
     if not args.no_batch and args.workload == WORKLOAD:
         line["batched"] = bench_batched(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
     if not args.no_hybrid and args.workload == WORKLOAD:
