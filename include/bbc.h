@@ -70,6 +70,15 @@ typedef struct bbc_ctx bbc_ctx;
  * the paired side) reject it with BBC_EINVAL. */
 enum { BBC_SIDE_AUTO = 0, BBC_SIDE_U = 1, BBC_SIDE_V = 2, BBC_SIDE_MIN_WEDGES = 3 };
 
+/* Work distribution of the wedge kernel over its persistent workgroups.
+ * Anchors are listed by descending work (Sec. "Optimization in GPU: Load
+ * balancing").  DYNAMIC (default): each workgroup takes the next anchor of
+ * a shared atomic queue.  STATIC: workgroup b takes positions b, b + G,
+ * b + 2G, ... of the list (G workgroups), a fixed deal with no queue, in the
+ * manner of the paper's fixed-tile kernel (G-BBC), which wins when anchors
+ * are few and heavy.  The autotuner tries both. */
+enum { BBC_SCHED_DYNAMIC = 0, BBC_SCHED_STATIC = 1 };
+
 /* optional input checks (offsets and id ranges are always checked, since
  * the kernels index with them) */
 enum { BBC_CHECK_SIGNS = 1, BBC_CHECK_DUPLICATES = 2, BBC_CHECK_ALL = 3 };
@@ -104,8 +113,9 @@ typedef struct {
     const bbc_dense_block* blocks; /* host array of n_blocks, or NULL */
     /* Nonzero: ignore the context's tuning table (see bbc_autotune).  The
      * table is consulted only when band_words, wg_size and wg_per_cu are all
-     * 0 and no per-vertex output is asked for. */
+     * 0, schedule is dynamic and no per-vertex output is asked for. */
     int32_t no_tuning;
+    int32_t schedule; /* BBC_SCHED_*: how wedge-kernel workgroups take anchors */
 } bbc_options;
 
 /* Fills *opts with the defaults: auto side, all checks, no timing. */
@@ -209,6 +219,7 @@ typedef struct {
     uint64_t wedges_all;  /* sum over centres of C(deg c, 2), dense blocks included */
     int32_t band_words;   /* LDS counter band of the wedge kernel, 32-bit words */
     int32_t tuned;        /* 1 if the kernel shape came from the tuning table */
+    int32_t schedule;     /* BBC_SCHED_* of the wedge kernel */
 } bbc_stats;
 
 bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out);
@@ -218,26 +229,27 @@ bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out);
  * Sec. "Optimization in GPU: Load balancing", Algorithm 4); here the wedge kernel's shape
  * (threads per workgroup, LDS band) and persistent grid (workgroups per
  * compute unit) are measured instead.  bbc_autotune counts the given
- * calibration graph (arguments as bbc_count) with every instantiated shape
- * and grid size, `reps` timed runs each (HIP events around the wedge
+ * calibration graph (arguments as bbc_count) with every instantiated shape,
+ * grid size and schedule (BBC_SCHED_*), `reps` timed runs each (HIP events around the wedge
  * kernel, best of reps; reps <= 0 means 2), and records the fastest in the
  * context's table under the graph's size class: (bit length of n_S, bit
  * length of m / n_S), n_S the anchor side of the default side rule.  Later
  * bbc_count and batched calls of the same class use that entry unless their
  * options fix the shape or set no_tuning.  *chosen (host, may be NULL)
- * receives options holding the chosen shape.  The count itself never
+ * receives options holding the chosen shape and schedule.  The count itself never
  * depends on the shape.  Errors: as bbc_count. */
 bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                         const int32_t* adj, const int8_t* signs, int32_t reps, bbc_options* chosen, void* stream);
 
 /* Writes the tuning table to a text file (path: host string).  One header
- * line "bbc-tune 1 gfx950", then one line per size class:
- * "ns_bits deg_bits band_words wg_size wg_per_cu ms".  BBC_EINVAL if the
- * file cannot be written. */
+ * line "bbc-tune 2 gfx950", then one line per size class:
+ * "ns_bits deg_bits band_words wg_size wg_per_cu schedule ms".  BBC_EINVAL
+ * if the file cannot be written. */
 bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path);
 
-/* Reads such a file and merges its entries into the table (an entry
- * replaces the one of the same class).  BBC_EINVAL, with the line number in
+/* Reads such a file (or a version-1 file, "bbc-tune 1 gfx950", whose lines
+ * have no schedule column and mean the dynamic schedule) and merges its
+ * entries into the table (an entry replaces the one of the same class).  BBC_EINVAL, with the line number in
  * bbc_last_error, for a missing file, a wrong header, a malformed line or a
  * shape that is not instantiated; the table is unchanged on error. */
 bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path);

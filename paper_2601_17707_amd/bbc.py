@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(HERE, "libbbc.so")
 
 OK, EINVAL, EOFFSETS, ERANGE, ESIGN, EDUP, ENOMEM, EDEVICE, ETOOBIG, EOVERFLOW = range(10)
 SIDE_AUTO, SIDE_U, SIDE_V, SIDE_MIN_WEDGES = 0, 1, 2, 3
+SCHED_DYNAMIC, SCHED_STATIC = 0, 1
+_SCHEDS = {"dynamic": SCHED_DYNAMIC, "static": SCHED_STATIC, SCHED_DYNAMIC: SCHED_DYNAMIC,
+           SCHED_STATIC: SCHED_STATIC}
 CHECK_SIGNS, CHECK_DUPLICATES, CHECK_ALL = 1, 2, 3
 # instantiated wedge-kernel shapes (band_words, wg_size); the first is the default
 WEDGE_SHAPES = [(8192, 256), (16384, 512), (16384, 256), (8192, 512), (32768, 1024), (16384, 1024),
@@ -52,6 +55,7 @@ class Options(ctypes.Structure):
         ("n_blocks", ctypes.c_int32),
         ("blocks", ctypes.POINTER(DenseBlock)),
         ("no_tuning", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
     ]
 
 
@@ -99,6 +103,7 @@ class Stats(ctypes.Structure):
         ("wedges_all", ctypes.c_uint64),
         ("band_words", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -170,9 +175,10 @@ def status_string(status: int) -> str:
 
 
 def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0,
-            blocks=None, no_tuning=False) -> Options:
+            blocks=None, no_tuning=False, schedule="dynamic") -> Options:
     """Options struct.  ``blocks``: list of (u_ids, v_ids) int32 device
-    tensors naming dense blocks (kept alive by the returned object)."""
+    tensors naming dense blocks (kept alive by the returned object).
+    ``schedule``: "dynamic" (shared queue) or "static" (fixed deal)."""
     o = Options()
     load_library().bbc_options_init(ctypes.byref(o))
     o.side = _SIDES[side]
@@ -182,6 +188,7 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
     o.wg_size = wg_size
     o.wg_per_cu = wg_per_cu
     o.no_tuning = 1 if no_tuning else 0
+    o.schedule = _SCHEDS[schedule]
     if blocks:
         arr = (DenseBlock * len(blocks))()
         for i, (uids, vids) in enumerate(blocks):
@@ -347,7 +354,8 @@ class Context:
                                     _ptr(signs), int(reps), ctypes.byref(chosen), _stream_ptr(stream, offsets))
         if st != OK:
             raise BbcError(st, self.last_error())
-        return dict(band_words=chosen.band_words, wg_size=chosen.wg_size, wg_per_cu=chosen.wg_per_cu)
+        return dict(band_words=chosen.band_words, wg_size=chosen.wg_size, wg_per_cu=chosen.wg_per_cu,
+                    schedule=chosen.schedule)
 
     def tune_save(self, path: str):
         st = self._lib.bbc_tune_save(self._h, os.fsencode(path))

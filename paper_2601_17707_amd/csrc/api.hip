@@ -1,6 +1,7 @@
 // C ABI of libbbc.so (declared in include/bbc.h): contexts, batch plans,
 // scratch arenas, the launch sequence and error mapping.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -73,7 +74,7 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
                   unsigned long long* gtotals, const HybridView& hv, int kind, int32_t bic_k,
-                  const unsigned long long* bic_tab, hipStream_t s);
+                  const unsigned long long* bic_tab, int sched, hipStream_t s);
 int wedge_bic_blocks_per_cu();
 void launch_choose_table(int32_t k, unsigned long long* tab, hipStream_t s);
 
@@ -94,6 +95,7 @@ __global__ void k_status_init(DevStatus* st) {
 struct TuneEntry {
     int32_t ns_bits, deg_bits;
     int32_t band_words, wg_size, wg_per_cu;
+    int32_t schedule;  // BBC_SCHED_*
     float ms;
 };
 }  // namespace bbc
@@ -186,6 +188,7 @@ struct Job {
     int64_t m = 0, n_s = 0, n_c = 0;
     uint32_t checks = BBC_CHECK_ALL;
     int band_words = 0, wg_size = 0, grid = 0;
+    int schedule = BBC_SCHED_DYNAMIC;
     bool tuned = false;  // shape taken from the tuning table
     bool classes = false;  // the six sign-pattern classes instead of the total
     int32_t bic_k = 0;     // > 0: balanced (2,k)-bicliques instead of the total
@@ -399,7 +402,8 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
                      (int32_t)n_s, st, J.pv, inv, J.s_is_u ? 0 : J.n_u, J.s_is_u ? J.n_u : 0, n_c,
                      J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
                      J.batched ? J.totals : nullptr, hv,
-                     J.classes ? kWedgeClasses : J.bic_k > 0 ? kWedgeBicliques : kWedgeCount, J.bic_k, P.bic_tab, s);
+                     J.classes ? kWedgeClasses : J.bic_k > 0 ? kWedgeBicliques : kWedgeCount, J.bic_k, P.bic_tab,
+                     J.schedule, s);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
@@ -430,6 +434,8 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
     if (!wedge_shape_ok(o->band_words, o->wg_size))
         return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
     if (o->wg_per_cu < 0) return fail(ctx, BBC_EINVAL, "negative wg_per_cu");
+    if (o->schedule != BBC_SCHED_DYNAMIC && o->schedule != BBC_SCHED_STATIC)
+        return fail(ctx, BBC_EINVAL, "bad schedule option");
     if (o->n_blocks < 0 || (o->n_blocks > 0 && !o->blocks)) return fail(ctx, BBC_EINVAL, "bad dense block list");
     return BBC_OK;
 }
@@ -468,7 +474,7 @@ void tune_class(int64_t n_s, int64_t m, int32_t* ns_bits, int32_t* deg_bits) {
 // Fills the kernel shape from the tuning table when the options leave it
 // open.  Returns whether an entry was used.
 bool apply_tuning(const bbc_ctx* ctx, bbc_options& o, int64_t n_s, int64_t m, bool full) {
-    if (o.no_tuning || full || o.band_words || o.wg_size || o.wg_per_cu) return false;
+    if (o.no_tuning || full || o.band_words || o.wg_size || o.wg_per_cu || o.schedule) return false;
     int32_t a, b;
     tune_class(n_s, m, &a, &b);
     for (const TuneEntry& e : ctx->tune)
@@ -476,6 +482,7 @@ bool apply_tuning(const bbc_ctx* ctx, bbc_options& o, int64_t n_s, int64_t m, bo
             o.band_words = e.band_words;
             o.wg_size = e.wg_size;
             o.wg_per_cu = e.wg_per_cu;
+            o.schedule = e.schedule;
             return true;
         }
     return false;
@@ -542,6 +549,7 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
     J.checks = o.checks;
     J.tuned = apply_tuning(ctx, o, ns, m, false);
     J.band_words = o.band_words;
+    J.schedule = o.schedule;
     J.wg_size = o.wg_size;
     J.grid = ctx->n_cu * (o.wg_per_cu > 0 ? o.wg_per_cu : wedge_blocks_per_cu(o.band_words, o.wg_size, false));
     return BBC_OK;
@@ -642,6 +650,7 @@ void fill_stats(bbc_ctx* ctx, const Job& J, const DevStatus& h, int block) {
     S.block = block;
     S.band_words = wedge_band(J.band_words, J.wg_size, J.pv != nullptr);
     S.tuned = J.tuned ? 1 : 0;
+    S.schedule = J.schedule;
 }
 
 bbc_status timed_stats(bbc_ctx* ctx) {
@@ -816,6 +825,7 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     const bool full = per_vertex != nullptr;
     J.tuned = apply_tuning(ctx, opts, J.n_s, n_edges, full);
     J.band_words = opts.band_words;
+    J.schedule = opts.schedule;
     J.wg_size = opts.wg_size;
     J.grid = ctx->n_cu *
              (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
@@ -865,6 +875,7 @@ bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_e
     J.checks = opts.checks;
     J.classes = true;
     J.band_words = wedge_class_band();
+    J.schedule = opts.schedule;
     J.wg_size = 256;
     J.grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_class_blocks_per_cu());
     rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
@@ -905,6 +916,7 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
     J.checks = opts.checks;
     J.bic_k = k;
     J.band_words = 8192;
+    J.schedule = opts.schedule;
     J.wg_size = 256;
     J.grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_bic_blocks_per_cu());
     rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
@@ -1031,20 +1043,22 @@ bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
     if (!ctx) return BBC_EINVAL;
     if (reps <= 0) reps = 2;
     uint64_t total = 0, first = 0;
-    TuneEntry best{0, 0, 0, 0, 0, 0.f};
+    TuneEntry best{0, 0, 0, 0, 0, 0, 0.f};
     bool have = false, counted = false;
     const int n_shapes = wedge_shape_count();
     for (int i = 0; i < n_shapes; ++i) {
         int wg, bw;
         wedge_shape(i, &wg, &bw);
         const int occ = wedge_blocks_per_cu(bw, wg, false);
-        for (int wpc = 1; wpc <= occ; ++wpc) {
+        for (int cfg = 0; cfg < 2 * occ; ++cfg) {
+            const int wpc = cfg / 2 + 1, sched = cfg & 1;  // both schedules at each grid
             if (wpc > 2 && wpc < occ) continue;  // 1, 2 and as many as fit
             bbc_options o;
             bbc_options_init(&o);
             o.band_words = bw;
             o.wg_size = wg;
             o.wg_per_cu = wpc;
+            o.schedule = sched;
             o.timing = 1;
             o.no_tuning = 1;
             float ms = 0.f;
@@ -1060,7 +1074,7 @@ bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
                 if (r > 0 && (r == 1 || ctx->stats.ms_count < ms)) ms = ctx->stats.ms_count;
             }
             if (!have || ms < best.ms) {
-                best = TuneEntry{0, 0, bw, wg, wpc, ms};
+                best = TuneEntry{0, 0, bw, wg, wpc, sched, ms};
                 have = true;
             }
         }
@@ -1073,6 +1087,7 @@ bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
         chosen->band_words = best.band_words;
         chosen->wg_size = best.wg_size;
         chosen->wg_per_cu = best.wg_per_cu;
+        chosen->schedule = best.schedule;
     }
     return BBC_OK;
 }
@@ -1239,10 +1254,10 @@ bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path) {
     if (!ctx || !path) return BBC_EINVAL;
     FILE* f = fopen(path, "w");
     if (!f) return fail(const_cast<bbc_ctx*>(ctx), BBC_EINVAL, std::string("cannot write ") + path);
-    bool ok = fprintf(f, "bbc-tune 1 gfx950\n") > 0;
+    bool ok = fprintf(f, "bbc-tune 2 gfx950\n") > 0;
     for (const TuneEntry& e : ctx->tune)
-        ok = ok && fprintf(f, "%d %d %d %d %d %.4f\n", e.ns_bits, e.deg_bits, e.band_words, e.wg_size, e.wg_per_cu,
-                           (double)e.ms) > 0;
+        ok = ok && fprintf(f, "%d %d %d %d %d %d %.4f\n", e.ns_bits, e.deg_bits, e.band_words, e.wg_size,
+                           e.wg_per_cu, e.schedule, (double)e.ms) > 0;
     ok = (fclose(f) == 0) && ok;
     return ok ? BBC_OK : fail(const_cast<bbc_ctx*>(ctx), BBC_EINVAL, std::string("write failed: ") + path);
 }
@@ -1253,24 +1268,43 @@ bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path) {
     if (!f) return fail(ctx, BBC_EINVAL, std::string("cannot read ") + path);
     char line[256];
     std::vector<TuneEntry> got;
-    int ln = 0;
+    int ln = 0, version = 0;
     bbc_status rc = BBC_OK;
     while (fgets(line, sizeof line, f)) {
         ++ln;
-        if (ln == 1) {
-            if (strcmp(line, "bbc-tune 1 gfx950\n") != 0 && strcmp(line, "bbc-tune 1 gfx950") != 0) {
+        if (ln == 1) {  // version 1 has no schedule column (dynamic)
+            if (strcmp(line, "bbc-tune 2 gfx950\n") == 0 || strcmp(line, "bbc-tune 2 gfx950") == 0) version = 2;
+            else if (strcmp(line, "bbc-tune 1 gfx950\n") == 0 || strcmp(line, "bbc-tune 1 gfx950") == 0) version = 1;
+            if (!version) {
                 rc = fail(ctx, BBC_EINVAL, std::string(path) + ":1: not a tuning file for gfx950");
                 break;
             }
             continue;
         }
         TuneEntry e;
+        e.schedule = BBC_SCHED_DYNAMIC;
         double ms = 0;
-        char extra = 0;
-        int n = sscanf(line, "%d %d %d %d %d %lf %c", &e.ns_bits, &e.deg_bits, &e.band_words, &e.wg_size, &e.wg_per_cu,
-                       &ms, &extra);
-        if (n != 6 || e.ns_bits < 0 || e.ns_bits > 64 || e.deg_bits < 0 || e.deg_bits > 64 || e.wg_per_cu < 0 ||
-            e.band_words <= 0 || e.wg_size <= 0 || !wedge_shape_ok(e.band_words, e.wg_size)) {
+        // whitespace-separated fields: integers, then the time; every field
+        // must parse in full
+        const int want = version == 1 ? 6 : 7;
+        int32_t* ints[6] = {&e.ns_bits, &e.deg_bits, &e.band_words, &e.wg_size, &e.wg_per_cu, &e.schedule};
+        int n = 0;
+        bool good = true;
+        char* save = nullptr;
+        for (char* tok = strtok_r(line, " \t\r\n", &save); tok; tok = strtok_r(nullptr, " \t\r\n", &save), ++n) {
+            char* end = nullptr;
+            if (n < want - 1) {
+                const long v = strtol(tok, &end, 10);
+                good = good && *end == 0 && v >= INT32_MIN && v <= INT32_MAX;
+                *ints[n] = (int32_t)v;
+            } else if (n == want - 1) {
+                ms = strtod(tok, &end);
+                good = good && *end == 0;
+            }
+        }
+        if (!good || n != want || e.ns_bits < 0 || e.ns_bits > 64 || e.deg_bits < 0 || e.deg_bits > 64 || e.wg_per_cu < 0 ||
+            e.band_words <= 0 || e.wg_size <= 0 || !wedge_shape_ok(e.band_words, e.wg_size) ||
+            (e.schedule != BBC_SCHED_DYNAMIC && e.schedule != BBC_SCHED_STATIC)) {
             rc = fail(ctx, BBC_EINVAL, std::string(path) + ":" + std::to_string(ln) + ": malformed tuning entry");
             break;
         }

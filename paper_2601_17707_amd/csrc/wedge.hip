@@ -1133,7 +1133,8 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
                                               int64_t anchor_base, int64_t centre_base,
                                               const int32_t* __restrict__ agraph,
                                               const int64_t* __restrict__ rank_end,
-                                              unsigned long long* __restrict__ gtotals, HybridView hv, BicView bv) {
+                                              unsigned long long* __restrict__ gtotals, HybridView hv, BicView bv,
+                                              int32_t sched_static) {
     if (*(volatile const int32_t*)&st->flags) return;  // input error: nothing to count
     __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
@@ -1141,11 +1142,16 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     for (int i = tid; i < BAND_WORDS / 32; i += WG) sh.bmp[i] = 0;
     unsigned long long acc = 0, bands = 0;
     ClassSums cs;
-    for (;;) {
+    for (int64_t it = 0;; ++it) {
         __syncthreads();
-        if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
-        __syncthreads();
-        const int32_t task = sh.task;
+        int64_t task;
+        if (sched_static) {  // fixed deal: workgroup b takes positions b, b + grid, b + 2 grid, ...
+            task = (int64_t)blockIdx.x + it * (int64_t)gridDim.x;
+        } else {  // dynamic: the next position of the shared queue
+            if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
+            __syncthreads();
+            task = sh.task;
+        }
         if (task >= n_s) break;
         const int32_t r = (int32_t)order[task];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
@@ -1218,13 +1224,14 @@ struct WedgeArgs {
     unsigned long long* gtotals;
     HybridView hv;
     BicView bv;
+    int32_t sched_static;
 };
 
 template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
 static void launch_shape(const WedgeArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS, BIC>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back,
                        a.coff, a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base,
-                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv);
+                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv, a.sched_static);
 }
 
 template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
@@ -1294,9 +1301,11 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int2* bmeta, const uint32_t* order, int32_t n_s, DevStatus* st, unsigned long long* pv,
                   const uint32_t* inv, int64_t anchor_base, int64_t centre_base, int64_t n_centre,
                   const int32_t* agraph, const int64_t* rank_end, unsigned long long* gtotals, const HybridView& hv,
-                  int kind, int32_t bic_k, const unsigned long long* bic_tab, hipStream_t s) {
-    const WedgeArgs a{aoff, acent, aneg, back, coff, packed, bidx, bmeta, order, n_s, st, pv, inv,
-                      anchor_base, centre_base, agraph, rank_end, gtotals, hv, BicView{bic_k, bic_tab}};
+                  int kind, int32_t bic_k, const unsigned long long* bic_tab, int sched, hipStream_t s) {
+    const WedgeArgs a{aoff,        acent,       aneg,   back,     coff,    packed, bidx,
+                      bmeta,       order,       n_s,    st,       pv,      inv,    anchor_base,
+                      centre_base, agraph,      rank_end, gtotals, hv,     BicView{bic_k, bic_tab},
+                      sched == 1 ? 1 : 0};
     if (pv) {
         launch_shape<kFullWG, kFullBW, true>(a, grid, s);
         if (n_centre > 0) {

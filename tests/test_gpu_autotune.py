@@ -32,6 +32,7 @@ def test_autotune_picks_an_instantiated_shape_and_keeps_the_count(ctx, tmp_path)
     st = ctx.stats()
     assert st["tuned"] == 1
     assert st["band_words"] == chosen["band_words"] and st["block"] == chosen["wg_size"]
+    assert st["schedule"] == chosen["schedule"] in (bbc.SCHED_DYNAMIC, bbc.SCHED_STATIC)
     # options that fix the shape, no_tuning, or per-vertex output bypass it
     assert ctx.count(off, adj, sg, g.n_v, opts=bbc.options(no_tuning=True)) == want
     assert ctx.stats()["tuned"] == 0
@@ -50,7 +51,7 @@ def test_autotune_picks_an_instantiated_shape_and_keeps_the_count(ctx, tmp_path)
     path = str(tmp_path / "tune.txt")
     ctx.tune_save(path)
     text = open(path).read().splitlines()
-    assert text[0] == "bbc-tune 1 gfx950" and len(text) == 2
+    assert text[0] == "bbc-tune 2 gfx950" and len(text) == 2
     c2 = bbc.Context(0)
     try:
         c2.tune_load(path)
@@ -95,7 +96,9 @@ def test_batched_calls_use_the_table(ctx):
 
 def test_tune_load_rejects_bad_files(ctx, tmp_path):
     cases = {
-        "header": "bbc-tune 2 gfx950\n1 2 16384 512 2 1.0\n",
+        "header": "bbc-tune 3 gfx950\n1 2 16384 512 2 1.0\n",
+        "v2 fields": "bbc-tune 2 gfx950\n19 6 16384 512 2 1.0\n",
+        "v2 schedule": "bbc-tune 2 gfx950\n19 6 16384 512 2 2 1.0\n",
         "arch": "bbc-tune 1 gfx942\n",
         "shape": "bbc-tune 1 gfx950\n19 6 12345 512 2 1.0\n",
         "fields": "bbc-tune 1 gfx950\n19 6 16384 512\n",
@@ -120,4 +123,10 @@ def test_tune_load_rejects_bad_files(ctx, tmp_path):
     out = str(tmp_path / "out.txt")
     ctx.tune_save(out)
     lines = open(out).read().splitlines()
-    assert lines == ["bbc-tune 1 gfx950", "3 4 16384 256 2 0.4000"]
+    assert lines == ["bbc-tune 2 gfx950", "3 4 16384 256 2 0 0.4000"]
+    # version 2 entries carry the schedule
+    with open(p, "w") as f:
+        f.write("bbc-tune 2 gfx950\n3 4 8192 256 1 1 0.3\n")
+    ctx.tune_load(p)
+    ctx.tune_save(out)
+    assert open(out).read().splitlines() == ["bbc-tune 2 gfx950", "3 4 8192 256 1 1 0.3000"]
