@@ -14,7 +14,13 @@ this package; it shares no code with the GPU library.
 * :func:`count_classes` and :func:`brute_classes` - the six sign-pattern
   classes of the case study (Table 8), by the walk and by brute force;
 * :func:`per_vertex`, :func:`vertex` and :func:`vertices` - balanced butterflies containing
-  each vertex (the paper reports totals only; see the C header).
+  each vertex (the paper reports totals only; see the C header);
+* :func:`count_bicliques` and :func:`brute_bicliques` - balanced
+  (2,k)-bicliques (Definition 5), by the general-k walk and by enumeration;
+* :func:`apply_updates` and :func:`update_delta` - dynamic graphs (Sec.
+  "Future Directions": edges added, removed or re-signed): the graph after
+  a batch of updates, and the change of the count as the difference of two
+  full counts.
 
 Graphs are passed as any object with ``n_u, n_v, offsets, adj, signs``
 (CSR over U, int32 / int32 / int8).
@@ -202,3 +208,43 @@ def brute_bicliques(g, k: int, side: int = SIDE_AUTO) -> int:
     out = _u64()
     _check(_load().oracle_brute_bicliques(*a, side, int(k), ctypes.byref(out)))
     return int(out.value)
+
+
+class _G:
+    """Minimal CSR graph (the attributes the oracle reads)."""
+
+    def __init__(self, n_u, n_v, offsets, adj, signs):
+        self.n_u, self.n_v, self.offsets, self.adj, self.signs = n_u, n_v, offsets, adj, signs
+
+
+def apply_updates(g, uu, vv, ss):
+    """The graph after a batch of edge updates: pair (uu[i], vv[i]) takes
+    sign ss[i] (+1 / -1), or is removed when ss[i] == 0.  Pairs are
+    distinct; removing an absent pair does nothing."""
+    deg = np.diff(np.asarray(g.offsets, np.int64))
+    state = {}
+    for u, v, s in zip(np.repeat(np.arange(g.n_u), deg).tolist(), np.asarray(g.adj).tolist(),
+                       np.asarray(g.signs).tolist()):
+        state[(u, v)] = s
+    seen = set()
+    for u, v, s in zip(np.asarray(uu).tolist(), np.asarray(vv).tolist(), np.asarray(ss).tolist()):
+        if (u, v) in seen:
+            raise ValueError("repeated pair in one update batch")
+        seen.add((u, v))
+        if s == 0:
+            state.pop((u, v), None)
+        else:
+            state[(u, v)] = s
+    keys = sorted(state)
+    u = np.array([k[0] for k in keys], np.int64)
+    v = np.array([k[1] for k in keys], np.int64)
+    s = np.array([state[k] for k in keys], np.int8)
+    off = np.zeros(g.n_u + 1, np.int64)
+    if u.size:
+        np.cumsum(np.bincount(u, minlength=g.n_u), out=off[1:])
+    return _G(g.n_u, g.n_v, off.astype(np.int32), v.astype(np.int32), s)
+
+
+def update_delta(g, uu, vv, ss) -> int:
+    """T(after) - T(before) for a batch of updates, from two full counts."""
+    return count(apply_updates(g, uu, vv, ss)) - count(g)

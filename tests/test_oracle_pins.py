@@ -689,3 +689,51 @@ def test_biclique_pins_catch_planted_mistakes(name, tmp_path):
         for k in (1, 3):
             failures += mcount(g, k, oracle.SIDE_U) != py_bicliques(g, k, oracle.SIDE_U)
     assert failures > 0, f"mutant '{name}' passed every pin"
+
+
+# ------------------------------------------------------------ dynamic updates
+
+@pytest.mark.parametrize("m,n", [(2, 2), (3, 4), (5, 7)])
+def test_update_delta_closed_forms(m, n):
+    """K_{m,n}, all positive: re-signing or removing one edge unbalances or
+    removes its (m-1)(n-1) butterflies; adding it back with + restores them
+    and with - adds only unbalanced ones; re-signing two edges of one U
+    vertex keeps the (m-1) butterflies holding both balanced."""
+    g = synth.complete_graph(m, n)
+    k = (m - 1) * (n - 1)
+    assert oracle.update_delta(g, [0], [0], [-1]) == -k
+    assert oracle.update_delta(g, [0], [0], [0]) == -k
+    assert oracle.update_delta(g, [0], [0], [1]) == 0  # same sign: nothing changes
+    h = oracle.apply_updates(g, [0], [0], [0])
+    assert oracle.count(h) == comb2(m) * comb2(n) - k
+    assert oracle.update_delta(h, [0], [0], [1]) == k
+    assert oracle.update_delta(h, [0], [0], [-1]) == 0
+    assert oracle.update_delta(h, [0], [0], [0]) == 0  # removing an absent pair
+    if n >= 2:
+        assert oracle.update_delta(g, [0, 0], [0, 1], [-1, -1]) == -2 * (m - 1) * (n - 2)
+
+
+def comb2(x):
+    return x * (x - 1) // 2
+
+
+def test_update_batch_equals_sequence():
+    """A batch equals its updates applied one after another, in any order,
+    including updates that share butterflies."""
+    rng = np.random.default_rng(51)
+    for _ in range(40):
+        g = synth.random_graph(rng, int(rng.integers(3, 12)), int(rng.integers(3, 12)), 0.5, 0.4)
+        q = int(rng.integers(1, 8))
+        pairs = rng.choice(g.n_u * g.n_v, size=min(q, g.n_u * g.n_v), replace=False)
+        uu, vv = pairs // g.n_v, pairs % g.n_v
+        ss = rng.choice([-1, 0, 1], size=uu.size)
+        batch = oracle.update_delta(g, uu, vv, ss)
+        for order in (np.arange(uu.size), rng.permutation(uu.size)):
+            h, total = g, 0
+            for i in order:
+                total += oracle.update_delta(h, uu[i:i + 1], vv[i:i + 1], ss[i:i + 1])
+                h = oracle.apply_updates(h, uu[i:i + 1], vv[i:i + 1], ss[i:i + 1])
+            assert total == batch
+        assert oracle.count(oracle.apply_updates(g, uu, vv, ss)) == py_brute(oracle.apply_updates(g, uu, vv, ss))[0]
+    with pytest.raises(ValueError):
+        oracle.apply_updates(synth.complete_graph(2, 2), [0, 0], [1, 1], [1, -1])
