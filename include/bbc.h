@@ -292,6 +292,31 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
                                const int32_t* adj, const int8_t* signs, int32_t k, uint64_t* count,
                                const bbc_options* opts, void* stream);
 
+/* Dynamic graphs (the setting named in Sec. "Future Directions": edges
+ * added, removed or re-signed).  For the graph G given as in bbc_count and a
+ * batch of n_updates updates - pair (upd_u[i], upd_v[i]) takes the state
+ * upd_state[i]: +1 / -1 (the edge is present with that sign; added if
+ * absent) or 0 (absent; removed if present) - *delta (host) receives
+ * T(G') - T(G), the change of the balanced butterfly count, G' being G with
+ * the whole batch applied.  Pairs within a batch must be distinct; an
+ * update that keeps a pair's state changes nothing.
+ * Only butterflies holding an updated pair can change; each is charged to
+ * the changed pair of lowest index it holds, and the walk of update i
+ * visits the butterflies through its pair before and after the batch,
+ * adding (balanced after) - (balanced before).  per_update (device, int64
+ * [n_updates], may be NULL) receives each update's share; the shares sum to
+ * *delta.  upd_u, upd_v (int32) and upd_state (int8) are device arrays.
+ * Work per update is about deg(v) x deg(u) binary searches.
+ * Errors: BBC_EINVAL (null pointers, negative sizes, a pair repeated in the
+ * batch), BBC_ERANGE / BBC_ESIGN (the graph's, or an update's id or state),
+ * BBC_EOFFSETS, BBC_EDUP, BBC_ENOMEM, BBC_EDEVICE, BBC_ETOOBIG.  Waits for
+ * the stream twice (after the checks, and for the result).  The graph is
+ * not modified. */
+bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                            const int32_t* adj, const int8_t* signs, int32_t n_updates, const int32_t* upd_u,
+                            const int32_t* upd_v, const int8_t* upd_state, int64_t* delta, int64_t* per_update,
+                            void* stream);
+
 /* Dense-block planner options.  Candidates are the vertices of degree >=
  * min_degree.  A block grows from a seed anchor: C starts as the seed's
  * candidate centres, then twice R = the candidate anchors linked to at

@@ -161,6 +161,9 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_count_bicliques.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_uint64),
                                         ctypes.POINTER(Options), vp]
     lib.bbc_count_bicliques.restype = ctypes.c_int
+    lib.bbc_update_delta.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
+                                     vp]
+    lib.bbc_update_delta.restype = ctypes.c_int
     lib.bbc_plan_options_init.argtypes = [ctypes.POINTER(PlanOptions)]
     lib.bbc_plan_options_init.restype = ctypes.c_int
     lib.bbc_plan_blocks.argtypes = [vp, i32, i32, i64, vp, vp, ctypes.POINTER(PlanOptions), i32,
@@ -330,6 +333,36 @@ class Context:
         if st != OK:
             raise BbcError(st, self.last_error())
         return int(out[0]) | (int(out[1]) << 64)
+
+    def update_delta(self, offsets, adj, signs, n_v: int, upd_u, upd_v, upd_state, per_update=None,
+                     stream=None) -> int:
+        """T(after) - T(before) for a batch of edge updates: pair (upd_u[i],
+        upd_v[i]) takes state upd_state[i] (+1 / -1, or 0 = absent).
+        ``per_update`` (int64 device tensor, optional) receives each
+        update's share."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        _check_tensor("upd_u", upd_u, torch.int32, torch)
+        _check_tensor("upd_v", upd_v, torch.int32, torch)
+        _check_tensor("upd_state", upd_state, torch.int8, torch)
+        q = upd_u.numel()
+        if upd_v.numel() != q or upd_state.numel() != q:
+            raise ValueError("update arrays differ in length")
+        if per_update is not None:
+            _check_tensor("per_update", per_update, torch.int64, torch)
+            if per_update.numel() < q:
+                raise ValueError("per_update holds fewer entries than updates")
+        out = ctypes.c_int64(0)
+        st = self._lib.bbc_update_delta(self._h, offsets.numel() - 1, int(n_v), adj.numel(), _ptr(offsets),
+                                        _ptr(adj), _ptr(signs), q, _ptr(upd_u), _ptr(upd_v), _ptr(upd_state),
+                                        ctypes.byref(out), _ptr(per_update) if per_update is not None else None,
+                                        _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return int(out.value)
 
     def count_batched(self, batch: "Batch", opts: Options | None = None, stream=None):
         """Per-graph counts of a Batch; returns its totals tensor (int64, on device)."""

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbc.so")
-SOURCES = ["api.hip", "build.hip", "dense.hip", "planner.hip", "primitives.hip", "wedge.hip"]
+SOURCES = ["api.hip", "build.hip", "dense.hip", "dynamic.hip", "planner.hip", "primitives.hip", "wedge.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

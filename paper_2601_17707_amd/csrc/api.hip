@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,20 @@ void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, 
 void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s);
 void launch_side_wedges(const int32_t* off, int32_t n_u, const int32_t* adj, int64_t m, int32_t n_v, uint32_t* deg,
                         unsigned long long* out, hipStream_t s);
+void dyn_check(const int32_t* uu, const int32_t* vv, const int8_t* ss, int32_t q, int32_t n_u, int32_t n_v,
+               DevStatus* st, hipStream_t s);
+void dyn_vkeys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, uint32_t* key, uint32_t* pay,
+               hipStream_t s);
+void dyn_ukeys(const uint32_t* vkey, const uint32_t* vpay, int64_t m, uint32_t* key, uint32_t* pay, hipStream_t s);
+void dyn_dup(const uint32_t* ukey, const uint32_t* urow, int64_t m, DevStatus* st, hipStream_t s);
+void dyn_key_init(const int32_t* a, int32_t q, uint32_t* key, hipStream_t s);
+void dyn_gather(const int32_t* src, const uint32_t* idx, int32_t q, uint32_t* key, hipStream_t s);
+void dyn_key64(const int32_t* hi, const int32_t* lo, const uint32_t* idx, int32_t q, unsigned long long* key,
+               uint32_t* pos, int check, DevStatus* st, hipStream_t s);
+void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, const uint32_t* vrow,
+               const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
+               const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
+               int32_t q, long long* per_update, DevStatus* st, hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
@@ -81,7 +96,7 @@ void launch_choose_table(int32_t k, unsigned long long* tab, hipStream_t s);
 __global__ void k_status_init(DevStatus* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->flags = 0;
-        st->bad_offset = st->bad_range = st->bad_sign = st->bad_dup = st->bad_block = INT64_MAX;
+        st->bad_offset = st->bad_range = st->bad_sign = st->bad_dup = st->bad_block = st->bad_update = INT64_MAX;
         st->total = 0;
         for (int k = 0; k < 6; ++k) st->cls[k] = 0;
         st->wedges = 0;
@@ -607,6 +622,14 @@ bbc_status block_job(bbc_ctx* ctx, const bbc_options& o, Job& J, std::vector<Dev
 // Maps the device status of a finished pass to a return code.
 bbc_status status_result(bbc_ctx* ctx, const DevStatus& h) {
     char buf[160];
+    if (h.flags & (kBadUpdRange | kBadUpdSign | kBadUpdDup)) {
+        const bbc_status st = (h.flags & kBadUpdRange) ? BBC_ERANGE : (h.flags & kBadUpdSign) ? BBC_ESIGN : BBC_EINVAL;
+        snprintf(buf, sizeof buf, "update batch: %s at update %lld",
+                 (h.flags & kBadUpdRange) ? "id out of range" : (h.flags & kBadUpdSign) ? "state not in {-1, 0, +1}"
+                                                                                       : "repeated pair",
+                 (long long)h.bad_update);
+        return fail(ctx, st, buf);
+    }
     if (h.flags & kBadOffsets) {
         snprintf(buf, sizeof buf, "offsets invalid at index %lld", (long long)h.bad_offset);
         return fail(ctx, BBC_EOFFSETS, buf);
@@ -932,6 +955,117 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
     if (c != 0 || l[4] != 0) return fail(ctx, BBC_EOVERFLOW, "(2,k)-biclique count does not fit 128 bits");
     count[0] = w[0] | (w[1] << 32);
     count[1] = w[2] | (w[3] << 32);
+    return BBC_OK;
+}
+
+bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                            const int32_t* adj, const int8_t* signs, int32_t n_updates, const int32_t* upd_u,
+                            const int32_t* upd_v, const int8_t* upd_state, int64_t* delta, int64_t* per_update,
+                            void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    if (!delta) return fail(ctx, BBC_EINVAL, "delta is NULL");
+    if (n_u < 0 || n_v < 0 || n_edges < 0 || n_updates < 0) return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    if (!offsets || (n_edges > 0 && (!adj || !signs)) || (n_updates > 0 && (!upd_u || !upd_v || !upd_state)))
+        return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+    *delta = 0;
+    if (n_updates == 0) return BBC_OK;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t m = n_edges, q = n_updates;
+    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(m, q), (int64_t)n_v + 1);
+    const int64_t hs = (int64_t)radix_hist_size(nmax);
+    // scratch: edge decode, two sorts of the edges, two of the updates
+    struct Dyn {
+        uint32_t *ea, *ec, *kin, *pin, *ka, *kb, *pa, *pb, *pa2, *pb2, *vdeg, *voff;
+        uint8_t* en;
+        uint32_t *qk, *qka, *qkb, *ia, *ib, *ia2, *ib2, *uv_pos, *vu_pos;
+        unsigned long long *uv_key, *vu_key;
+        int8_t* s_old;
+        uint32_t *hist, *hist_scan, *partials;
+        size_t carve(char* base, int64_t m, int64_t q, int32_t n_v, int64_t hs, int64_t nmax) {
+            Carve c(base);
+            ea = c.take<uint32_t>(m);
+            ec = c.take<uint32_t>(m);
+            en = c.take<uint8_t>(m);
+            kin = c.take<uint32_t>(m);
+            pin = c.take<uint32_t>(m);
+            ka = c.take<uint32_t>(m);
+            kb = c.take<uint32_t>(m);
+            pa = c.take<uint32_t>(m);
+            pb = c.take<uint32_t>(m);
+            pa2 = c.take<uint32_t>(m);
+            pb2 = c.take<uint32_t>(m);
+            vdeg = c.take<uint32_t>(n_v);
+            voff = c.take<uint32_t>((int64_t)n_v + 1);
+            qk = c.take<uint32_t>(q);
+            qka = c.take<uint32_t>(q);
+            qkb = c.take<uint32_t>(q);
+            ia = c.take<uint32_t>(q);
+            ib = c.take<uint32_t>(q);
+            ia2 = c.take<uint32_t>(q);
+            ib2 = c.take<uint32_t>(q);
+            uv_pos = c.take<uint32_t>(q);
+            vu_pos = c.take<uint32_t>(q);
+            uv_key = c.take<unsigned long long>(q);
+            vu_key = c.take<unsigned long long>(q);
+            s_old = c.take<int8_t>(q);
+            hist = c.take<uint32_t>(hs);
+            hist_scan = c.take<uint32_t>(hs + 1);
+            partials = c.take<uint32_t>((int64_t)scan_partials_size(hs + nmax + 8));
+            return c.used;
+        }
+    } D;
+    bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, D.carve(nullptr, m, q, n_v, hs, nmax));
+    if (rc != BBC_OK) return rc;
+    D.carve(ctx->arena, m, q, n_v, hs, nmax);
+    DevStatus* st = ctx->st_dev;
+    // checks first (the builds below index with the ids), one wait
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, st);
+    launch_decode_single(offsets, adj, signs, n_u, n_v, m, 1, 1, st, D.ea, D.ec, D.en, s);
+    dyn_check(upd_u, upd_v, upd_state, (int32_t)q, n_u, n_v, st, s);
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rc = status_result(ctx, *ctx->st_host);
+    if (rc != BBC_OK) return rc;
+    const int bits_u = bits_for(n_u > 0 ? (uint64_t)(n_u - 1) : 0), bits_v = bits_for(n_v > 0 ? (uint64_t)(n_v - 1) : 0);
+    // V rows: stable sort of the CSR-ordered edges by v (u ascending inside)
+    const uint32_t *vkey = nullptr, *vrow = nullptr, *ukey = nullptr, *urow = nullptr;
+    dyn_vkeys(D.ea, D.ec, D.en, m, D.kin, D.pin, s);
+    radix_sort(D.kin, D.ka, D.kb, D.pin, D.pa, D.pb, nullptr, nullptr, nullptr, m, bits_v, D.hist, D.hist_scan,
+               D.partials, s, &vkey, &vrow, nullptr);
+    launch_hist(D.ec, m, D.vdeg, n_v, nullptr, 0, st, s);
+    scan_exclusive_u32(D.vdeg, D.voff, n_v, D.partials, s);
+    // U rows sorted by v: stable sort of the V-ordered edges by u
+    dyn_ukeys(vkey, vrow, m, D.kin, D.pin, s);
+    radix_sort(D.kin, D.ka, D.kb, D.pin, D.pa2, D.pb2, nullptr, nullptr, nullptr, m, bits_u, D.hist, D.hist_scan,
+               D.partials, s, &ukey, &urow, nullptr);
+    dyn_dup(ukey, urow, m, st, s);
+    // updates by (u, v) and by (v, u): two stable sorts each, carrying the index
+    const uint32_t *k_out = nullptr, *i1 = nullptr, *i2 = nullptr;
+    dyn_key_init(upd_v, (int32_t)q, D.qk, s);
+    radix_sort(D.qk, D.qka, D.qkb, nullptr, nullptr, nullptr, nullptr, D.ia, D.ib, q, bits_v, D.hist, D.hist_scan,
+               D.partials, s, &k_out, nullptr, &i1);
+    dyn_gather(upd_u, i1, (int32_t)q, D.qk, s);
+    radix_sort(D.qk, D.qka, D.qkb, nullptr, nullptr, nullptr, i1, D.ia2, D.ib2, q, bits_u, D.hist, D.hist_scan,
+               D.partials, s, &k_out, nullptr, &i2);
+    dyn_key64(upd_u, upd_v, i2, (int32_t)q, D.uv_key, D.uv_pos, 1, st, s);
+    dyn_key_init(upd_u, (int32_t)q, D.qk, s);
+    radix_sort(D.qk, D.qka, D.qkb, nullptr, nullptr, nullptr, nullptr, D.ia, D.ib, q, bits_u, D.hist, D.hist_scan,
+               D.partials, s, &k_out, nullptr, &i1);
+    dyn_gather(upd_v, i1, (int32_t)q, D.qk, s);
+    radix_sort(D.qk, D.qka, D.qkb, nullptr, nullptr, nullptr, i1, D.ia2, D.ib2, q, bits_v, D.hist, D.hist_scan,
+               D.partials, s, &k_out, nullptr, &i2);
+    dyn_key64(upd_v, upd_u, i2, (int32_t)q, D.vu_key, D.vu_pos, 0, st, s);
+    dyn_delta(offsets, urow, D.voff, vrow, D.uv_key, D.uv_pos, D.vu_key, D.vu_pos, upd_u, upd_v, upd_state, D.s_old,
+              (int32_t)q, (long long*)per_update, st, s);
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    rc = status_result(ctx, *ctx->st_host);
+    if (rc != BBC_OK) return rc;
+    *delta = (int64_t)ctx->st_host->total;
     return BBC_OK;
 }
 

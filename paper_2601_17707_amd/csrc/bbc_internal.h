@@ -17,6 +17,7 @@ struct DevStatus {
     int64_t bad_sign;
     int64_t bad_dup;
     int64_t bad_block;          // first offending dense-block vertex (block * 2^32 + position)
+    int64_t bad_update;         // first offending update of a batch
     unsigned long long total;   // twice the balanced butterflies
     unsigned long long wedges;  // sum over centres of C(deg, 2)
     unsigned long long walked;  // wedges the sparse walk visits (dense-block wedges excluded)
@@ -26,7 +27,16 @@ struct DevStatus {
     unsigned int pad1;
 };
 
-enum : int32_t { kBadOffsets = 1, kBadRange = 2, kBadSign = 4, kBadDup = 8, kBadBlocks = 16 };
+enum : int32_t {
+    kBadOffsets = 1,
+    kBadRange = 2,
+    kBadSign = 4,
+    kBadDup = 8,
+    kBadBlocks = 16,
+    kBadUpdRange = 32,  // update batches: id out of range,
+    kBadUpdSign = 64,   // new state not in {-1, 0, +1},
+    kBadUpdDup = 128    // repeated pair
+};
 
 // What the wedge kernel sums: the balanced count, the six sign-pattern
 // classes, or balanced (2,k)-bicliques.
