@@ -11,7 +11,9 @@ sum over centres c of C(deg c, 2): every wedge u - c - w with w ranked above
 u, walked exactly once.  The line also carries the batched measurement
 (graphs/s of 10,000 graphs of uneven size, one captured batch plan, against
 a loop of plain per-graph calls), the six sign-pattern classes on the same
-graph, balanced (2,k)-bicliques for k = 2..4 on it, the dense-block
+graph, balanced (2,k)-bicliques for k = 2..4 on it, a batch of 100,000
+edge updates on it (the change of the count against a full recount), the
+dense-block
 workload (hybrid int8 matrix-core path against the sparse-only path), the
 roofline of the wedge kernel and the CPU oracle's rate.
 """
@@ -192,6 +194,42 @@ def bench_bicliques(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps:
     return out
 
 
+def bench_updates(ctx, g, off, adj, sg, count_ms: float, steps: int, warmup: int, seed: int,
+                  q: int = 100_000) -> dict:
+    """A batch of q edge updates on the resident bench graph (half re-sign
+    or remove existing edges, half add or leave absent pairs; states drawn
+    from {-1, 0, +1}): the change of the count by bbc_update_delta, against
+    the time of one full count.  The per-update shares must sum to it."""
+    import numpy as np
+    import torch
+
+    dev = off.device
+    rng = np.random.default_rng(seed + 100)
+    pick = rng.choice(g.m, q // 2, replace=False)
+    eu = np.searchsorted(g.offsets.astype(np.int64), pick, side="right") - 1
+    keys = set((eu.astype(np.int64) * g.n_v + g.adj[pick]).tolist())
+    while len(keys) < q:
+        keys.add(int(rng.integers(0, g.n_u)) * g.n_v + int(rng.integers(0, g.n_v)))
+    k = np.array(sorted(keys), np.int64)
+    rng.shuffle(k)
+    tu = torch.as_tensor((k // g.n_v).astype(np.int32), device=dev)
+    tv = torch.as_tensor((k % g.n_v).astype(np.int32), device=dev)
+    ts = torch.as_tensor(rng.choice([-1, 0, 1], size=q).astype(np.int8), device=dev)
+    shares = torch.empty(q, dtype=torch.int64, device=dev)
+    for _ in range(max(1, warmup)):
+        d = ctx.update_delta(off, adj, sg, g.n_v, tu, tv, ts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        d = ctx.update_delta(off, adj, sg, g.n_v, tu, tv, ts)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t) / steps
+    d2 = ctx.update_delta(off, adj, sg, g.n_v, tu, tv, ts, per_update=shares)
+    return dict(updates=q, ms_per_batch=ms, updates_per_s=q / (ms / 1e3), delta=d,
+                shares_sum_match=bool(int(shares.sum()) == d == d2), full_count_ms=count_ms,
+                speedup_vs_recount=count_ms / ms)
+
+
 def bench_hybrid(ctx, steps: int, warmup: int, seed: int) -> dict:
     """The planted-block workload (power-law background, |U| = 2e6, |V| = 1e6,
     5e7 background edges, 16 blocks of 4096 x 4096 at density 0.5) counted
@@ -269,6 +307,7 @@ def main():
     ap.add_argument("--no-hybrid", action="store_true", help="skip the dense-block workload")
     ap.add_argument("--no-classes", action="store_true", help="skip the sign-pattern class count")
     ap.add_argument("--no-bicliques", action="store_true", help="skip the (2,k)-biclique counts")
+    ap.add_argument("--no-updates", action="store_true", help="skip the dynamic-update batch")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -359,6 +398,9 @@ def main():
     if not args.no_bicliques:
         line["bicliques"] = bench_bicliques(ctx, off, adj, sg, g.n_v, wedges, total, max(1, min(args.steps, 3)),
                                             args.warmup)
+    if not args.no_updates:
+        line["updates"] = bench_updates(ctx, g, off, adj, sg, ms_step, max(1, min(args.steps, 5)), args.warmup,
+                                        args.seed)
     if not args.no_batch and args.workload == WORKLOAD:
         line["batched"] = bench_batched(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
     if not args.no_hybrid and args.workload == WORKLOAD:
