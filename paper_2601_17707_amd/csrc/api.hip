@@ -37,7 +37,7 @@ void dyn_key64(const int32_t* hi, const int32_t* lo, const uint32_t* idx, int32_
 void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, const uint32_t* vrow,
                const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
                const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
-               int32_t q, long long* per_update, DevStatus* st, hipStream_t s);
+               unsigned long long* wsum, int32_t n_v, int32_t q, long long* per_update, DevStatus* st, hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
@@ -982,7 +982,7 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
         uint32_t *ea, *ec, *kin, *pin, *ka, *kb, *pa, *pb, *pa2, *pb2, *vdeg, *voff;
         uint8_t* en;
         uint32_t *qk, *qka, *qkb, *ia, *ib, *ia2, *ib2, *uv_pos, *vu_pos;
-        unsigned long long *uv_key, *vu_key;
+        unsigned long long *uv_key, *vu_key, *wsum;
         int8_t* s_old;
         uint32_t *hist, *hist_scan, *partials;
         size_t carve(char* base, int64_t m, int64_t q, int32_t n_v, int64_t hs, int64_t nmax) {
@@ -1011,6 +1011,7 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
             vu_pos = c.take<uint32_t>(q);
             uv_key = c.take<unsigned long long>(q);
             vu_key = c.take<unsigned long long>(q);
+            wsum = c.take<unsigned long long>(n_v);
             s_old = c.take<int8_t>(q);
             hist = c.take<uint32_t>(hs);
             hist_scan = c.take<uint32_t>(hs + 1);
@@ -1060,7 +1061,7 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
                D.partials, s, &k_out, nullptr, &i2);
     dyn_key64(upd_v, upd_u, i2, (int32_t)q, D.vu_key, D.vu_pos, 0, st, s);
     dyn_delta(offsets, urow, D.voff, vrow, D.uv_key, D.uv_pos, D.vu_key, D.vu_pos, upd_u, upd_v, upd_state, D.s_old,
-              (int32_t)q, (long long*)per_update, st, s);
+              D.wsum, n_v, (int32_t)q, (long long*)per_update, st, s);
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rc = status_result(ctx, *ctx->st_host);

@@ -135,6 +135,7 @@ struct DynView {
     const int32_t* upd_v;
     const int8_t* s_new;  // by update index
     int8_t* s_old;        // state before the batch, filled by k_dyn_old
+    const unsigned long long* wsum;  // per V vertex v: sum of deg(w) over its neighbours w
     int32_t q;
 };
 
@@ -155,71 +156,242 @@ __global__ void k_dyn_old(DynView d, DevStatus* st) {
 
 __device__ __forceinline__ bool changed(const DynView& d, int32_t j) { return d.s_old[j] != d.s_new[j]; }
 
-// One workgroup per update (grid-stride over updates).  Candidates: w from
-// the V row of v (before) and from the updates on v that insert an edge;
-// x from the U row of u and from the updates on u that insert one.
-template <int WG>
+// wsum[v] = sum of deg(w) over the neighbours w of v (one wave per v): the
+// length of the walk v -> w -> x.
+__global__ void k_dyn_wsum(const uint32_t* voff, const uint32_t* vrow, const int32_t* uoff, int32_t n_v,
+                           unsigned long long* wsum) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t n_waves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t v = wave; v < n_v; v += n_waves) {
+        unsigned long long acc = 0;
+        for (uint32_t e = voff[v] + lane_id(); e < voff[v + 1]; e += kWave) {
+            const uint32_t w = vrow[e] >> 1;
+            acc += (unsigned long long)(uoff[w + 1] - uoff[w]);
+        }
+        acc = wave_sum(acc);
+        if (lane_id() == 0) wsum[v] = acc;
+    }
+}
+
+// Position of pair key in the sorted update keys [lo, hi), or -1.
+__device__ __forceinline__ int32_t find_in(const DynView& d, int32_t lo, int32_t hi, unsigned long long key) {
+    const int32_t end = hi;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (d.uv_key[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && d.uv_key[lo] == key) ? (int32_t)d.uv_pos[lo] : -1;
+}
+
+// Update range [lo, hi) of the pairs (a, *) in the (u, v)-sorted keys.
+__device__ __forceinline__ void update_row(const DynView& d, uint32_t a, int32_t& lo, int32_t& hi) {
+    lo = lower_bound64(d.uv_key, d.q, (unsigned long long)a << 32);
+    hi = lower_bound64(d.uv_key, d.q, (unsigned long long)(a + 1) << 32);
+}
+
+// Sign of (a, b) in a sorted row, searched from whichever side has the
+// shorter list: U row of a (entries v << 1 | neg) or V row of b (u << 1 | neg).
+__device__ __forceinline__ int32_t pair_state(const DynView& d, uint32_t a, uint32_t ua0, uint32_t ua1, uint32_t b,
+                                              uint32_t vb0, uint32_t vb1) {
+    return (ua1 - ua0 <= vb1 - vb0) ? row_state(d.urow, ua0, ua1, b) : row_state(d.vrow, vb0, vb1, a);
+}
+
+// LDS lists of one workgroup: candidates w (neighbours of v before or after
+// the batch) and x (of u), with what a pair needs besides the state of
+// (w, x).
+template <int CH>
+struct DynShared {
+    uint32_t a_w[CH], a_r0[CH], a_r1[CH];  // w, its U row bounds
+    int32_t a_lo[CH], a_hi[CH];           // updates on row w
+    int8_t a_s0[CH], a_s1[CH], a_ok[CH];   // (w, v) before / after; candidate kept
+    uint32_t b_x[CH], b_r0[CH], b_r1[CH];  // x, its V row bounds
+    int8_t b_s0[CH], b_s1[CH], b_ok[CH];   // (u, x) before / after; candidate kept
+    unsigned long long a_pre[CH];          // walk mode: first walk element of each w
+    unsigned long long scan_tmp[CH / kWave + 1];
+    long long tmp[CH / kWave + 1];
+};
+
+// Entry t of the w list: position a0 + t of [V row of v before the batch,
+// then the updates on v].  Kept when it is a neighbour of v before or after
+// (updates that do not insert add nothing new), is not u, and (w, v) is not
+// a changed pair of lower index than i.
+template <int CH>
+__device__ __forceinline__ void fill_w(const DynView& d, DynShared<CH>& sh, int32_t i, uint32_t u, uint32_t v,
+                                       uint32_t a_beg, uint32_t a_g, int32_t a_ub, uint32_t ia, uint32_t t) {
+    uint32_t w;
+    int32_t s0, s1, j2;
+    bool ok = true;
+    if (ia < a_g) {
+        const uint32_t e = d.vrow[a_beg + ia];
+        w = e >> 1;
+        s0 = (e & 1u) ? -1 : 1;
+        j2 = find_update(d, w, v);
+        s1 = j2 >= 0 ? d.s_new[j2] : s0;
+    } else {
+        j2 = (int32_t)d.vu_pos[a_ub + (int32_t)(ia - a_g)];
+        w = (uint32_t)d.upd_u[j2];
+        s0 = 0;
+        s1 = d.s_new[j2];
+        ok = d.s_old[j2] == 0 && s1 != 0;
+    }
+    ok = ok && w != u && !(j2 >= 0 && j2 < i && changed(d, j2));
+    sh.a_w[t] = w;
+    sh.a_s0[t] = (int8_t)s0;
+    sh.a_s1[t] = (int8_t)s1;
+    sh.a_ok[t] = ok;
+    if (ok) {
+        sh.a_r0[t] = (uint32_t)d.uoff[w];
+        sh.a_r1[t] = (uint32_t)d.uoff[w + 1];
+        int32_t lo, hi;
+        update_row(d, w, lo, hi);
+        sh.a_lo[t] = lo;
+        sh.a_hi[t] = hi;
+    }
+}
+
+// One workgroup per update (grid-stride over updates).  Two ways to visit
+// the butterflies through (u, v), the cheaper one taken per update:
+//   pairs: every (w, x) of the w list times the x list (neighbours of u and
+//          the updates on u that insert), the state of (w, x) by a binary
+//          search in the shorter of the two rows: deg(v) deg(u) searches;
+//   walk:  every w of the w list and every x of w's row (and of the updates
+//          on row w that insert), the state of (u, x) by a binary search in
+//          u's row: sum of deg(w) over w, which wsum[v] gives up front.
+// Both lists go through LDS in chunks; the walk flattens a chunk of w's row
+// lengths with a workgroup prefix sum.
+template <int WG, int CH>
 __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, long long* per_update, DevStatus* st) {
+    static_assert(CH >= WG, "one w per thread in walk mode");
     if (dyn_bad(st)) return;
-    __shared__ long long tmp[WG / kWave + 1];
+    __shared__ DynShared<CH> sh;
     for (int32_t i = blockIdx.x; i < d.q; i += gridDim.x) {
         long long acc = 0;
-        if (changed(d, i)) {
+        if (changed(d, i)) {  // uniform over the workgroup
             const uint32_t u = (uint32_t)d.upd_u[i], v = (uint32_t)d.upd_v[i];
             const int32_t s_uv0 = d.s_old[i], s_uv1 = d.s_new[i];
-            const uint32_t a_beg = d.voff[v], a_g = d.voff[v + 1] - a_beg;  // w before the batch
+            const uint32_t a_beg = d.voff[v], a_g = d.voff[v + 1] - a_beg;
             const int32_t a_ub = lower_bound64(d.vu_key, d.q, (unsigned long long)v << 32);
             const int32_t a_ue = lower_bound64(d.vu_key, d.q, (unsigned long long)(v + 1) << 32);
-            const uint32_t b_beg = (uint32_t)d.uoff[u], b_g = (uint32_t)d.uoff[u + 1] - b_beg;  // x before
-            const int32_t b_ub = lower_bound64(d.uv_key, d.q, (unsigned long long)u << 32);
-            const int32_t b_ue = lower_bound64(d.uv_key, d.q, (unsigned long long)(u + 1) << 32);
-            const uint64_t n_a = a_g + (uint64_t)(a_ue - a_ub), n_b = b_g + (uint64_t)(b_ue - b_ub);
-            const uint64_t n_p = n_a * n_b;
-            for (uint64_t p = threadIdx.x; p < n_p; p += WG) {
-                const uint64_t ia = p / n_b, ib = p - ia * n_b;
-                uint32_t w, x;
-                int32_t s_wv0, s_wv1, s_ux0, s_ux1, j2, j3;
-                if (ia < a_g) {
-                    const uint32_t e = d.vrow[a_beg + ia];
-                    w = e >> 1;
-                    s_wv0 = (e & 1u) ? -1 : 1;
-                    j2 = find_update(d, w, v);
-                    s_wv1 = j2 >= 0 ? d.s_new[j2] : s_wv0;
-                } else {
-                    j2 = (int32_t)d.vu_pos[a_ub + (int32_t)(ia - a_g)];
-                    if (d.s_old[j2] != 0 || d.s_new[j2] == 0) continue;  // only insertions are new w
-                    w = (uint32_t)d.upd_u[j2];
-                    s_wv0 = 0;
-                    s_wv1 = d.s_new[j2];
+            const uint32_t b_beg = (uint32_t)d.uoff[u], b_g = (uint32_t)d.uoff[u + 1] - b_beg;
+            int32_t b_ub, b_ue;
+            update_row(d, u, b_ub, b_ue);
+            const uint32_t n_a = a_g + (uint32_t)(a_ue - a_ub), n_b = b_g + (uint32_t)(b_ue - b_ub);
+            const bool walk = d.wsum[v] < (unsigned long long)n_a * n_b;
+            if (walk) {
+                for (uint32_t a0 = 0; a0 < n_a; a0 += WG) {
+                    const uint32_t na = min((uint32_t)WG, n_a - a0), t = threadIdx.x;
+                    unsigned long long cnt = 0;
+                    if (t < na) {
+                        fill_w(d, sh, i, u, v, a_beg, a_g, a_ub, a0 + t, t);
+                        if (sh.a_ok[t]) cnt = (sh.a_r1[t] - sh.a_r0[t]) + (unsigned long long)(sh.a_hi[t] - sh.a_lo[t]);
+                    }
+                    unsigned long long n_e;
+                    const unsigned long long pre = block_exclusive_scan<WG>(cnt, sh.scan_tmp, &n_e);
+                    sh.a_pre[t] = pre;
+                    __syncthreads();
+                    for (unsigned long long e = threadIdx.x; e < n_e; e += WG) {
+                        uint32_t lo = 0, hi = na - 1;  // last entry whose first element is <= e
+                        while (lo < hi) {
+                            const uint32_t mid = (lo + hi + 1) >> 1;
+                            if (sh.a_pre[mid] <= e) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const uint32_t ta = lo;
+                        const unsigned long long k = e - sh.a_pre[ta];
+                        const uint32_t w = sh.a_w[ta], deg_w = sh.a_r1[ta] - sh.a_r0[ta];
+                        uint32_t x;
+                        int32_t s_wx0, s_wx1, j4;
+                        if (k < deg_w) {
+                            const uint32_t ent = d.urow[sh.a_r0[ta] + (uint32_t)k];
+                            x = ent >> 1;
+                            s_wx0 = (ent & 1u) ? -1 : 1;
+                            j4 = sh.a_lo[ta] < sh.a_hi[ta]
+                                     ? find_in(d, sh.a_lo[ta], sh.a_hi[ta], ((unsigned long long)w << 32) | x)
+                                     : -1;
+                            s_wx1 = j4 >= 0 ? d.s_new[j4] : s_wx0;
+                        } else {
+                            j4 = (int32_t)d.uv_pos[sh.a_lo[ta] + (int32_t)(k - deg_w)];
+                            if (d.s_old[j4] != 0 || d.s_new[j4] == 0) continue;  // only insertions add an x
+                            x = (uint32_t)d.upd_v[j4];
+                            s_wx0 = 0;
+                            s_wx1 = d.s_new[j4];
+                        }
+                        if (x == v || (j4 >= 0 && j4 < i && changed(d, j4))) continue;
+                        const int32_t s_ux0 = row_state(d.urow, b_beg, b_beg + b_g, x);
+                        const int32_t j3 = b_ub < b_ue ? find_in(d, b_ub, b_ue, ((unsigned long long)u << 32) | x) : -1;
+                        const int32_t s_ux1 = j3 >= 0 ? d.s_new[j3] : s_ux0;
+                        if ((s_ux0 == 0 && s_ux1 == 0) || (j3 >= 0 && j3 < i && changed(d, j3))) continue;
+                        const int32_t b_before = s_uv0 * sh.a_s0[ta] * s_ux0 * s_wx0 > 0;
+                        const int32_t b_after = s_uv1 * sh.a_s1[ta] * s_ux1 * s_wx1 > 0;
+                        acc += b_after - b_before;
+                    }
+                    __syncthreads();  // the chunk is reloaded next
                 }
-                if (w == u) continue;
-                if (ib < b_g) {
-                    const uint32_t e = d.urow[b_beg + ib];
-                    x = e >> 1;
-                    s_ux0 = (e & 1u) ? -1 : 1;
-                    j3 = find_update(d, u, x);
-                    s_ux1 = j3 >= 0 ? d.s_new[j3] : s_ux0;
-                } else {
-                    j3 = (int32_t)d.uv_pos[b_ub + (int32_t)(ib - b_g)];
-                    if (d.s_old[j3] != 0 || d.s_new[j3] == 0) continue;
-                    x = (uint32_t)d.upd_v[j3];
-                    s_ux0 = 0;
-                    s_ux1 = d.s_new[j3];
+            } else {
+                for (uint32_t a0 = 0; a0 < n_a; a0 += CH) {
+                    const uint32_t na = min((uint32_t)CH, n_a - a0);
+                    for (uint32_t t = threadIdx.x; t < na; t += WG) fill_w(d, sh, i, u, v, a_beg, a_g, a_ub, a0 + t, t);
+                    for (uint32_t b0 = 0; b0 < n_b; b0 += CH) {
+                        const uint32_t nb = min((uint32_t)CH, n_b - b0);
+                        if (a0 == 0 || n_b > CH) {  // the x chunk is loaded once when it fits
+                            for (uint32_t t = threadIdx.x; t < nb; t += WG) {
+                                const uint32_t ib = b0 + t;
+                                uint32_t x;
+                                int32_t s0, s1, j3;
+                                bool ok = true;
+                                if (ib < b_g) {
+                                    const uint32_t e = d.urow[b_beg + ib];
+                                    x = e >> 1;
+                                    s0 = (e & 1u) ? -1 : 1;
+                                    j3 = b_ub < b_ue ? find_in(d, b_ub, b_ue, ((unsigned long long)u << 32) | x) : -1;
+                                    s1 = j3 >= 0 ? d.s_new[j3] : s0;
+                                } else {
+                                    j3 = (int32_t)d.uv_pos[b_ub + (int32_t)(ib - b_g)];
+                                    x = (uint32_t)d.upd_v[j3];
+                                    s0 = 0;
+                                    s1 = d.s_new[j3];
+                                    ok = d.s_old[j3] == 0 && s1 != 0;
+                                }
+                                ok = ok && x != v && !(j3 >= 0 && j3 < i && changed(d, j3));
+                                sh.b_x[t] = x;
+                                sh.b_s0[t] = (int8_t)s0;
+                                sh.b_s1[t] = (int8_t)s1;
+                                sh.b_ok[t] = ok;
+                                if (ok) {
+                                    sh.b_r0[t] = d.voff[x];
+                                    sh.b_r1[t] = d.voff[x + 1];
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        const uint32_t n_p = na * nb;
+                        for (uint32_t p = threadIdx.x; p < n_p; p += WG) {
+                            const uint32_t ja = p / nb, jb = p - ja * nb;
+                            if (!sh.a_ok[ja] || !sh.b_ok[jb]) continue;
+                            const uint32_t w = sh.a_w[ja], x = sh.b_x[jb];
+                            const int32_t s_wx0 =
+                                pair_state(d, w, sh.a_r0[ja], sh.a_r1[ja], x, sh.b_r0[jb], sh.b_r1[jb]);
+                            int32_t s_wx1 = s_wx0;
+                            if (sh.a_lo[ja] < sh.a_hi[ja]) {  // row w has updates: is (w, x) one of them?
+                                const int32_t j4 =
+                                    find_in(d, sh.a_lo[ja], sh.a_hi[ja], ((unsigned long long)w << 32) | x);
+                                if (j4 >= 0) {
+                                    if (j4 < i && changed(d, j4)) continue;  // charged to update j4
+                                    s_wx1 = d.s_new[j4];
+                                }
+                            }
+                            if (s_wx0 == 0 && s_wx1 == 0) continue;
+                            const int32_t b_before = s_uv0 * sh.a_s0[ja] * sh.b_s0[jb] * s_wx0 > 0;
+                            const int32_t b_after = s_uv1 * sh.a_s1[ja] * sh.b_s1[jb] * s_wx1 > 0;
+                            acc += b_after - b_before;
+                        }
+                        __syncthreads();  // the chunks are reloaded next
+                    }
                 }
-                if (x == v) continue;
-                const int32_t s_wx0 = row_state(d.urow, (uint32_t)d.uoff[w], (uint32_t)d.uoff[w + 1], x);
-                const int32_t j4 = find_update(d, w, x);
-                const int32_t s_wx1 = j4 >= 0 ? d.s_new[j4] : s_wx0;
-                if (s_wx0 == 0 && s_wx1 == 0) continue;
-                // charged to the changed pair of lowest index
-                if ((j2 >= 0 && j2 < i && changed(d, j2)) || (j3 >= 0 && j3 < i && changed(d, j3)) ||
-                    (j4 >= 0 && j4 < i && changed(d, j4)))
-                    continue;
-                const int32_t b0 = s_uv0 * s_wv0 * s_ux0 * s_wx0 > 0, b1 = s_uv1 * s_wv1 * s_ux1 * s_wx1 > 0;
-                acc += b1 - b0;
             }
         }
-        const long long sum = block_sum<WG>(acc, tmp);
+        const long long sum = block_sum<WG>(acc, sh.tmp);
         if (threadIdx.x == 0) {
             if (per_update) per_update[i] = sum;
             if (sum) atomicAdd(&st->total, (unsigned long long)sum);
@@ -264,11 +436,15 @@ void dyn_key64(const int32_t* hi, const int32_t* lo, const uint32_t* idx, int32_
 void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, const uint32_t* vrow,
                const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
                const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
-               int32_t q, long long* per_update, DevStatus* st, hipStream_t s) {
+               unsigned long long* wsum, int32_t n_v, int32_t q, long long* per_update, DevStatus* st, hipStream_t s) {
     if (q <= 0) return;
-    const DynView d{uoff, urow, voff, vrow, uv_key, uv_pos, vu_key, vu_pos, upd_u, upd_v, s_new, s_old, q};
+    const DynView d{uoff, urow, voff, vrow, uv_key, uv_pos, vu_key, vu_pos, upd_u, upd_v, s_new, s_old, wsum, q};
+    if (n_v > 0)
+        hipLaunchKernelGGL(k_dyn_wsum, dim3(dyn_grid((int64_t)n_v * kWave, 256)), dim3(256), 0, s, voff, vrow, uoff,
+                           n_v, wsum);
     hipLaunchKernelGGL(k_dyn_old, dim3(dyn_grid(q, 256)), dim3(256), 0, s, d, st);
-    hipLaunchKernelGGL(k_dyn_delta<256>, dim3((unsigned)(q < 65536 ? q : 65536)), dim3(256), 0, s, d, per_update, st);
+    hipLaunchKernelGGL((k_dyn_delta<256, 1024>), dim3((unsigned)(q < 65536 ? q : 65536)), dim3(256), 0, s, d,
+                       per_update, st);
 }
 
 }  // namespace bbc

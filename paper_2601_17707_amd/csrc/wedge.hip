@@ -1142,17 +1142,19 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     for (int i = tid; i < BAND_WORDS / 32; i += WG) sh.bmp[i] = 0;
     unsigned long long acc = 0, bands = 0;
     ClassSums cs;
-    for (int64_t it = 0;; ++it) {
+    uint32_t snext = blockIdx.x;  // static deal: positions b, b + grid, b + 2 grid, ... (< 2^31 + grid)
+    for (;;) {
         __syncthreads();
-        int64_t task;
-        if (sched_static) {  // fixed deal: workgroup b takes positions b, b + grid, b + 2 grid, ...
-            task = (int64_t)blockIdx.x + it * (int64_t)gridDim.x;
+        uint32_t task;
+        if (sched_static) {
+            task = snext;
+            snext += gridDim.x;
         } else {  // dynamic: the next position of the shared queue
             if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
             __syncthreads();
-            task = sh.task;
+            task = (uint32_t)sh.task;
         }
-        if (task >= n_s) break;
+        if (task >= (uint32_t)n_s) break;
         const int32_t r = (int32_t)order[task];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
         const int64_t n_end = agraph ? rank_end[agraph[r] + 1] : (int64_t)n_s;
