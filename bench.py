@@ -11,8 +11,9 @@ sum over centres c of C(deg c, 2): every wedge u - c - w with w ranked above
 u, walked exactly once.  The line also carries the batched measurement
 (graphs/s of 10,000 graphs of uneven size, one captured batch plan, against
 a loop of plain per-graph calls), the six sign-pattern classes on the same
-graph, balanced (2,k)-bicliques for k = 2..4 on it, a batch of 100,000
-edge updates on it (the change of the count against a full recount), the
+graph, balanced (2,k)-bicliques for k = 2..4 on it, batches of 1,000 and
+100,000 edge updates on it (the change of the count against a full
+recount), the
 dense-block
 workload (hybrid int8 matrix-core path against the sparse-only path), the
 roofline of the wedge kernel and the CPU oracle's rate.
@@ -399,8 +400,8 @@ def main():
         line["bicliques"] = bench_bicliques(ctx, off, adj, sg, g.n_v, wedges, total, max(1, min(args.steps, 3)),
                                             args.warmup)
     if not args.no_updates:
-        line["updates"] = bench_updates(ctx, g, off, adj, sg, ms_step, max(1, min(args.steps, 5)), args.warmup,
-                                        args.seed)
+        line["updates"] = [bench_updates(ctx, g, off, adj, sg, ms_step, max(1, min(args.steps, 5)), args.warmup,
+                                         args.seed, q=q) for q in (1_000, 100_000)]
     if not args.no_batch and args.workload == WORKLOAD:
         line["batched"] = bench_batched(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
     if not args.no_hybrid and args.workload == WORKLOAD:

@@ -37,7 +37,9 @@ void dyn_key64(const int32_t* hi, const int32_t* lo, const uint32_t* idx, int32_
 void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, const uint32_t* vrow,
                const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
                const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
-               unsigned long long* wsum, int32_t n_v, int32_t q, long long* per_update, DevStatus* st, hipStream_t s);
+               unsigned long long* wsum, int32_t n_v, int32_t q, uint32_t* n_tasks, uint32_t* task_off,
+               uint32_t* span, uint8_t* mode, uint32_t* partials, long long* per_update, DevStatus* st,
+               hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
@@ -981,7 +983,8 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
     struct Dyn {
         uint32_t *ea, *ec, *kin, *pin, *ka, *kb, *pa, *pb, *pa2, *pb2, *vdeg, *voff;
         uint8_t* en;
-        uint32_t *qk, *qka, *qkb, *ia, *ib, *ia2, *ib2, *uv_pos, *vu_pos;
+        uint32_t *qk, *qka, *qkb, *ia, *ib, *ia2, *ib2, *uv_pos, *vu_pos, *n_tasks, *task_off, *span;
+        uint8_t* mode;
         unsigned long long *uv_key, *vu_key, *wsum;
         int8_t* s_old;
         uint32_t *hist, *hist_scan, *partials;
@@ -1012,6 +1015,10 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
             uv_key = c.take<unsigned long long>(q);
             vu_key = c.take<unsigned long long>(q);
             wsum = c.take<unsigned long long>(n_v);
+            n_tasks = c.take<uint32_t>(q);
+            task_off = c.take<uint32_t>(q + 1);
+            span = c.take<uint32_t>(q);
+            mode = c.take<uint8_t>(q);
             s_old = c.take<int8_t>(q);
             hist = c.take<uint32_t>(hs);
             hist_scan = c.take<uint32_t>(hs + 1);
@@ -1061,7 +1068,8 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
                D.partials, s, &k_out, nullptr, &i2);
     dyn_key64(upd_v, upd_u, i2, (int32_t)q, D.vu_key, D.vu_pos, 0, st, s);
     dyn_delta(offsets, urow, D.voff, vrow, D.uv_key, D.uv_pos, D.vu_key, D.vu_pos, upd_u, upd_v, upd_state, D.s_old,
-              D.wsum, n_v, (int32_t)q, (long long*)per_update, st, s);
+              D.wsum, n_v, (int32_t)q, D.n_tasks, D.task_off, D.span, D.mode, D.partials, (long long*)per_update, st,
+              s);
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rc = status_result(ctx, *ctx->st_host);

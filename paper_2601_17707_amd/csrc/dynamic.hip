@@ -16,6 +16,8 @@
 // and by (v, u) as 64-bit keys, so that every edge state is a binary
 // search away.  One workgroup walks one update; its threads stride over the
 // (w, x) candidate pairs.
+#include <algorithm>
+
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -250,7 +252,56 @@ __device__ __forceinline__ void fill_w(const DynView& d, DynShared<CH>& sh, int3
     }
 }
 
-// One workgroup per update (grid-stride over updates).  Two ways to visit
+// Per-update scalars of the walk: the w list (V row of v, then the updates
+// on v) and the x list (U row of u, then the updates on u).
+struct DynUpd {
+    uint32_t u, v, a_beg, a_g, b_beg, b_g, n_a, n_b;
+    int32_t a_ub, b_ub, b_ue;
+};
+
+__device__ __forceinline__ DynUpd dyn_upd(const DynView& d, int32_t i) {
+    DynUpd r;
+    r.u = (uint32_t)d.upd_u[i];
+    r.v = (uint32_t)d.upd_v[i];
+    r.a_beg = d.voff[r.v];
+    r.a_g = d.voff[r.v + 1] - r.a_beg;
+    r.a_ub = lower_bound64(d.vu_key, d.q, (unsigned long long)r.v << 32);
+    const int32_t a_ue = lower_bound64(d.vu_key, d.q, (unsigned long long)(r.v + 1) << 32);
+    r.b_beg = (uint32_t)d.uoff[r.u];
+    r.b_g = (uint32_t)d.uoff[r.u + 1] - r.b_beg;
+    update_row(d, r.u, r.b_ub, r.b_ue);
+    r.n_a = r.a_g + (uint32_t)(a_ue - r.a_ub);
+    r.n_b = r.b_g + (uint32_t)(r.b_ue - r.b_ub);
+    return r;
+}
+
+// Work plan: every changed update is split into tasks, each a contiguous
+// span of its w list (a multiple of the walk's or the pairs' chunk), at most
+// max_tasks per update; unchanged updates get none.  mode[i] = 1 for the
+// walk.
+template <int WG, int CH>
+__global__ void k_dyn_plan(DynView d, uint32_t max_tasks, uint32_t* n_tasks, uint32_t* span, uint8_t* mode,
+                           const DevStatus* st) {
+    const bool bad = dyn_bad(st);
+    DYN_STRIDE(i, d.q) {
+        uint32_t c = 0, sp = 0;
+        uint8_t walk = 0;
+        if (!bad && changed(d, (int32_t)i)) {
+            const DynUpd r = dyn_upd(d, (int32_t)i);
+            walk = d.wsum[r.v] < (unsigned long long)r.n_a * r.n_b;
+            const uint32_t unit = walk ? WG : CH;
+            const uint32_t units = (r.n_a + unit - 1) / unit;
+            c = min(units, max_tasks);
+            sp = c ? ((units + c - 1) / c) * unit : 0;
+            c = sp ? (r.n_a + sp - 1) / sp : 0;
+        }
+        n_tasks[i] = c;
+        span[i] = sp;
+        mode[i] = walk;
+    }
+}
+
+// One workgroup per task (grid-stride over the tasks).  Two ways to visit
 // the butterflies through (u, v), the cheaper one taken per update:
 //   pairs: every (w, x) of the w list times the x list (neighbours of u and
 //          the updates on u that insert), the state of (w, x) by a binary
@@ -261,25 +312,34 @@ __device__ __forceinline__ void fill_w(const DynView& d, DynShared<CH>& sh, int3
 // Both lists go through LDS in chunks; the walk flattens a chunk of w's row
 // lengths with a workgroup prefix sum.
 template <int WG, int CH>
-__global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, long long* per_update, DevStatus* st) {
+__global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, const uint32_t* task_off, const uint32_t* span,
+                                                  const uint8_t* mode, long long* per_update, DevStatus* st) {
     static_assert(CH >= WG, "one w per thread in walk mode");
     if (dyn_bad(st)) return;
     __shared__ DynShared<CH> sh;
-    for (int32_t i = blockIdx.x; i < d.q; i += gridDim.x) {
+    const uint32_t n_tasks = task_off[d.q];
+    for (uint32_t task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int32_t i;
+        {  // the update of this task: last i with task_off[i] <= task
+            int32_t lo = 0, hi = d.q - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (task_off[mid] <= task) lo = mid;
+                else hi = mid - 1;
+            }
+            i = lo;
+        }
         long long acc = 0;
-        if (changed(d, i)) {  // uniform over the workgroup
-            const uint32_t u = (uint32_t)d.upd_u[i], v = (uint32_t)d.upd_v[i];
+        {
+            const DynUpd r = dyn_upd(d, i);
+            const uint32_t u = r.u, v = r.v, a_beg = r.a_beg, a_g = r.a_g, b_beg = r.b_beg, b_g = r.b_g;
+            const int32_t a_ub = r.a_ub, b_ub = r.b_ub, b_ue = r.b_ue;
+            const uint32_t n_b = r.n_b;
             const int32_t s_uv0 = d.s_old[i], s_uv1 = d.s_new[i];
-            const uint32_t a_beg = d.voff[v], a_g = d.voff[v + 1] - a_beg;
-            const int32_t a_ub = lower_bound64(d.vu_key, d.q, (unsigned long long)v << 32);
-            const int32_t a_ue = lower_bound64(d.vu_key, d.q, (unsigned long long)(v + 1) << 32);
-            const uint32_t b_beg = (uint32_t)d.uoff[u], b_g = (uint32_t)d.uoff[u + 1] - b_beg;
-            int32_t b_ub, b_ue;
-            update_row(d, u, b_ub, b_ue);
-            const uint32_t n_a = a_g + (uint32_t)(a_ue - a_ub), n_b = b_g + (uint32_t)(b_ue - b_ub);
-            const bool walk = d.wsum[v] < (unsigned long long)n_a * n_b;
-            if (walk) {
-                for (uint32_t a0 = 0; a0 < n_a; a0 += WG) {
+            const uint32_t a_lo_t = (task - task_off[i]) * span[i];  // this task's span of the w list
+            const uint32_t n_a = min(r.n_a, a_lo_t + span[i]);
+            if (mode[i]) {
+                for (uint32_t a0 = a_lo_t; a0 < n_a; a0 += WG) {
                     const uint32_t na = min((uint32_t)WG, n_a - a0), t = threadIdx.x;
                     unsigned long long cnt = 0;
                     if (t < na) {
@@ -329,12 +389,12 @@ __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, long long* per_upda
                     __syncthreads();  // the chunk is reloaded next
                 }
             } else {
-                for (uint32_t a0 = 0; a0 < n_a; a0 += CH) {
+                for (uint32_t a0 = a_lo_t; a0 < n_a; a0 += CH) {
                     const uint32_t na = min((uint32_t)CH, n_a - a0);
                     for (uint32_t t = threadIdx.x; t < na; t += WG) fill_w(d, sh, i, u, v, a_beg, a_g, a_ub, a0 + t, t);
                     for (uint32_t b0 = 0; b0 < n_b; b0 += CH) {
                         const uint32_t nb = min((uint32_t)CH, n_b - b0);
-                        if (a0 == 0 || n_b > CH) {  // the x chunk is loaded once when it fits
+                        if (a0 == a_lo_t || n_b > CH) {  // the x chunk is loaded once when it fits
                             for (uint32_t t = threadIdx.x; t < nb; t += WG) {
                                 const uint32_t ib = b0 + t;
                                 uint32_t x;
@@ -392,9 +452,9 @@ __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, long long* per_upda
             }
         }
         const long long sum = block_sum<WG>(acc, sh.tmp);
-        if (threadIdx.x == 0) {
-            if (per_update) per_update[i] = sum;
-            if (sum) atomicAdd(&st->total, (unsigned long long)sum);
+        if (threadIdx.x == 0 && sum) {
+            if (per_update) atomicAdd((unsigned long long*)&per_update[i], (unsigned long long)sum);
+            atomicAdd(&st->total, (unsigned long long)sum);
         }
     }
 }
@@ -436,15 +496,24 @@ void dyn_key64(const int32_t* hi, const int32_t* lo, const uint32_t* idx, int32_
 void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, const uint32_t* vrow,
                const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
                const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
-               unsigned long long* wsum, int32_t n_v, int32_t q, long long* per_update, DevStatus* st, hipStream_t s) {
+               unsigned long long* wsum, int32_t n_v, int32_t q, uint32_t* n_tasks, uint32_t* task_off,
+               uint32_t* span, uint8_t* mode, uint32_t* partials, long long* per_update, DevStatus* st,
+               hipStream_t s) {
     if (q <= 0) return;
+    constexpr int WG = 256, CH = 1024;
     const DynView d{uoff, urow, voff, vrow, uv_key, uv_pos, vu_key, vu_pos, upd_u, upd_v, s_new, s_old, wsum, q};
     if (n_v > 0)
         hipLaunchKernelGGL(k_dyn_wsum, dim3(dyn_grid((int64_t)n_v * kWave, 256)), dim3(256), 0, s, voff, vrow, uoff,
                            n_v, wsum);
     hipLaunchKernelGGL(k_dyn_old, dim3(dyn_grid(q, 256)), dim3(256), 0, s, d, st);
-    hipLaunchKernelGGL((k_dyn_delta<256, 1024>), dim3((unsigned)(q < 65536 ? q : 65536)), dim3(256), 0, s, d,
-                       per_update, st);
+    // at most 4096 tasks per update and 2^31 in all
+    const uint32_t max_tasks = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(4096, (int64_t)INT32_MAX / q));
+    hipLaunchKernelGGL((k_dyn_plan<WG, CH>), dim3(dyn_grid(q, 256)), dim3(256), 0, s, d, max_tasks, n_tasks, span,
+                       mode, (const DevStatus*)st);
+    scan_exclusive_u32(n_tasks, task_off, q, partials, s);
+    if (per_update) fill_bytes(per_update, (int64_t)q * 8, s);
+    hipLaunchKernelGGL((k_dyn_delta<WG, CH>), dim3(65536), dim3(WG), 0, s, d, (const uint32_t*)task_off,
+                       (const uint32_t*)span, (const uint8_t*)mode, per_update, st);
 }
 
 }  // namespace bbc
