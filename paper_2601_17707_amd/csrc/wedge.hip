@@ -266,6 +266,7 @@ struct WedgeShared {
     // count mode compacts the next band while the current one is reduced
     SliceTable<WG> tab[FULL ? 1 : 2];
     long long scan_tmp[WG / kWave + 1];
+    uint32_t ctab[16];  // biclique mode: C(x, k) for x < 16 (at most C(15, 7) = 6435)
     // per-vertex mode only
     int32_t c_id[FULL ? WG : 1];                // centre id of each chunk entry
     int32_t w_k[FULL ? WG : 1];                 // chunk entry of each compacted slice
@@ -823,12 +824,16 @@ __device__ __forceinline__ void bic_carry(ClassSums& cs) {
     cs.c[2] &= 0xffffffffull;
 }
 
-// Fields of one counter word in the count layouts (a and b alike).
+// Fields of one counter word in the count layouts (a and b alike).  4-bit
+// fields read C(x, k) from the small LDS table.
 template <int MODE>
-__device__ __forceinline__ void bic_word(ClassSums& cs, const BicView& bv, uint32_t v) {
+__device__ __forceinline__ void bic_word(ClassSums& cs, const BicView& bv, const uint32_t* ctab, uint32_t v) {
     if constexpr (MODE == 0) {
 #pragma unroll
-        for (int f = 0; f < 8; ++f) bic_field(cs, bv, (v >> (4 * f)) & 15u);
+        for (int f = 0; f < 8; ++f) {
+            const uint32_t x = (v >> (4 * f)) & 15u;
+            if (x >= (uint32_t)bv.k) cs.c[0] += ctab[x];
+        }
     } else if constexpr (MODE == 1) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) bic_field(cs, bv, (v >> (8 * f)) & 255u);
@@ -852,10 +857,10 @@ __device__ __forceinline__ void reduce_bic(WedgeShared<WG, BAND_WORDS, FULL>& sh
             const uint4 v = *q;
             if (!(v.x | v.y | v.z | v.w)) continue;
             *q = uint4{0u, 0u, 0u, 0u};
-            bic_word<MODE>(cs, bv, v.x);
-            bic_word<MODE>(cs, bv, v.y);
-            bic_word<MODE>(cs, bv, v.z);
-            bic_word<MODE>(cs, bv, v.w);
+            bic_word<MODE>(cs, bv, sh.ctab, v.x);
+            bic_word<MODE>(cs, bv, sh.ctab, v.y);
+            bic_word<MODE>(cs, bv, sh.ctab, v.z);
+            bic_word<MODE>(cs, bv, sh.ctab, v.w);
         }
     } else {
         for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
@@ -865,7 +870,7 @@ __device__ __forceinline__ void reduce_bic(WedgeShared<WG, BAND_WORDS, FULL>& sh
                 while (bits) {
                     const uint32_t wd = (b << 5) + (uint32_t)(__ffs(bits) - 1);
                     bits &= bits - 1u;
-                    bic_word<MODE>(cs, bv, sh.cnt[wd]);
+                    bic_word<MODE>(cs, bv, sh.ctab, sh.cnt[wd]);
                     sh.cnt[wd] = 0;
                 }
             }
@@ -1140,6 +1145,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     const int tid = threadIdx.x;
     for (int i = tid; i < BAND_WORDS; i += WG) sh.cnt[i] = 0;
     for (int i = tid; i < BAND_WORDS / 32; i += WG) sh.bmp[i] = 0;
+    if (BIC && tid < 16) sh.ctab[tid] = (uint32_t)bv.tab[2 * tid];
     unsigned long long acc = 0, bands = 0;
     ClassSums cs;
     uint32_t snext = blockIdx.x;  // static deal: positions b, b + grid, b + 2 grid, ... (< 2^31 + grid)
