@@ -15,6 +15,13 @@
  * Definition 6 (degree, then id).  Every step runs in the library's own HIP
  * kernels on the caller's stream; counts are exact integers.
  *
+ * Entry points: bbc_count (total, optional per-vertex counts and dense
+ * blocks), bbc_count_batched and the captured batch plans, bbc_plan_blocks
+ * (dense-block planner), bbc_autotune with bbc_tune_save / _load, and the
+ * extensions bbc_count_classes (the six sign-pattern classes of the case
+ * study), bbc_count_bicliques (balanced (2,k)-bicliques) and
+ * bbc_update_delta (the change of the count under edge updates).
+ *
  * Conventions for every entry point
  *   - Graphs are a CSR over U: offsets[n_u + 1] (int32, offsets[0] = 0,
  *     non-decreasing, offsets[n_u] = n_edges), adj[n_edges] (int32 V ids in
@@ -305,7 +312,7 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
  * visits the butterflies through its pair before and after the batch,
  * adding (balanced after) - (balanced before).  per_update (device, int64
  * [n_updates], may be NULL) receives each update's share; the shares sum to
- * *delta.  upd_u, upd_v (int32) and upd_state (int8) are device arrays.
+ * *delta (on error its content is unspecified).  upd_u, upd_v (int32) and upd_state (int8) are device arrays.
  * Work per update is about deg(v) x deg(u) binary searches.
  * Errors: BBC_EINVAL (null pointers, negative sizes, a pair repeated in the
  * batch), BBC_ERANGE / BBC_ESIGN (the graph's, or an update's id or state),

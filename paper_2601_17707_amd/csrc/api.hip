@@ -972,8 +972,10 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
         return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
     if (!offsets || (n_edges > 0 && (!adj || !signs)) || (n_updates > 0 && (!upd_u || !upd_v || !upd_state)))
         return fail(ctx, BBC_EINVAL, "input pointer is NULL");
-    *delta = 0;
-    if (n_updates == 0) return BBC_OK;
+    if (n_updates == 0) {
+        *delta = 0;
+        return BBC_OK;
+    }
     DeviceGuard guard(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     const int64_t m = n_edges, q = n_updates;
