@@ -694,15 +694,42 @@ struct NarrowClassSums {
 };
 
 // The slots of one counter word in the narrow class layouts: two 16-bit
-// slots of 4-bit fields, or one slot of 8-bit fields.
+// slots of 4-bit fields (p, n, b gathered into nibbles 0 and 4 of three
+// words, then nibble dot products), or one slot of 8-bit fields.
 template <int MODE>
 __device__ __forceinline__ void narrow_word(NarrowClassSums& ns, uint32_t w) {
     if constexpr (MODE == 4) {
-        ns.add(w & 15u, (w >> 4) & 15u, (w >> 8) & 15u);
-        ns.add((w >> 16) & 15u, (w >> 20) & 15u, (w >> 24) & 15u);
+        const uint32_t P = w & 0x000f000fu, N = (w >> 4) & 0x000f000fu, B = (w >> 8) & 0x000f000fu;
+        ns.pp = __builtin_amdgcn_udot8(P, P, ns.pp, false);
+        ns.nn = __builtin_amdgcn_udot8(N, N, ns.nn, false);
+        ns.bb = __builtin_amdgcn_udot8(B, B, ns.bb, false);
+        ns.pn = __builtin_amdgcn_udot8(P, N, ns.pn, false);
+        ns.pb = __builtin_amdgcn_udot8(P, B, ns.pb, false);
+        ns.nb = __builtin_amdgcn_udot8(N, B, ns.nb, false);
+        ns.p1 = __builtin_amdgcn_udot8(P, 0x11111111u, ns.p1, false);
+        ns.n1 = __builtin_amdgcn_udot8(N, 0x11111111u, ns.n1, false);
+        ns.b1 = __builtin_amdgcn_udot8(B, 0x11111111u, ns.b1, false);
     } else {
         ns.add(w & 255u, (w >> 8) & 255u, (w >> 16) & 255u);
     }
+}
+
+// Four slots of 8-bit fields (one per word): byte k of each word gathered
+// into one word by byte permutes, then byte dot products.
+__device__ __forceinline__ void narrow_quad8(NarrowClassSums& ns, const uint4& v) {
+    // v_perm_b32: selector byte s picks byte s of {hi, lo} (lo = bytes 0-3), 0x0c gives zero
+    const uint32_t P = __builtin_amdgcn_perm(v.y, v.x, 0x0c0c0400u) | __builtin_amdgcn_perm(v.w, v.z, 0x04000c0cu);
+    const uint32_t N = __builtin_amdgcn_perm(v.y, v.x, 0x0c0c0501u) | __builtin_amdgcn_perm(v.w, v.z, 0x05010c0cu);
+    const uint32_t B = __builtin_amdgcn_perm(v.y, v.x, 0x0c0c0602u) | __builtin_amdgcn_perm(v.w, v.z, 0x06020c0cu);
+    ns.pp = __builtin_amdgcn_udot4(P, P, ns.pp, false);
+    ns.nn = __builtin_amdgcn_udot4(N, N, ns.nn, false);
+    ns.bb = __builtin_amdgcn_udot4(B, B, ns.bb, false);
+    ns.pn = __builtin_amdgcn_udot4(P, N, ns.pn, false);
+    ns.pb = __builtin_amdgcn_udot4(P, B, ns.pb, false);
+    ns.nb = __builtin_amdgcn_udot4(N, B, ns.nb, false);
+    ns.p1 = __builtin_amdgcn_udot4(P, 0x01010101u, ns.p1, false);
+    ns.n1 = __builtin_amdgcn_udot4(N, 0x01010101u, ns.n1, false);
+    ns.b1 = __builtin_amdgcn_udot4(B, 0x01010101u, ns.b1, false);
 }
 
 // Class mode: the class sums of every touched slot of the band, clearing
@@ -719,10 +746,14 @@ __device__ __forceinline__ void reduce_classes(WedgeShared<WG, BAND_WORDS, FULL>
                 const uint4 v = *q;
                 if (!(v.x | v.y | v.z | v.w)) continue;
                 *q = uint4{0u, 0u, 0u, 0u};
-                narrow_word<MODE>(ns, v.x);
-                narrow_word<MODE>(ns, v.y);
-                narrow_word<MODE>(ns, v.z);
-                narrow_word<MODE>(ns, v.w);
+                if constexpr (MODE == 5) {
+                    narrow_quad8(ns, v);
+                } else {
+                    narrow_word<MODE>(ns, v.x);
+                    narrow_word<MODE>(ns, v.y);
+                    narrow_word<MODE>(ns, v.z);
+                    narrow_word<MODE>(ns, v.w);
+                }
             }
         } else {
             for (uint32_t b = threadIdx.x; b < (uint32_t)BAND_WORDS / 32u; b += WG) {
