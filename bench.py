@@ -40,8 +40,8 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix throughput, 5.0 POPS
 # write x 1.000).  Valid only for the kernel sources it was taken on: the
 # bench reports null once their hash differs.
 KERNEL_SOURCES = ["paper_2601_17707_amd/csrc/wedge.hip", "paper_2601_17707_amd/csrc/bbc_internal.h"]
-MEASURED_TRAFFIC = dict(kernel="k_wedge", workload=WORKLOAD, bytes=52683683910,
-                        sources_sha256="4e61f00e8f3a0dec57e40c5c252946e29e4edb5d5b5d74cf3dcce10e44ff9a85",
+MEASURED_TRAFFIC = dict(kernel="k_wedge", workload=WORKLOAD, bytes=52679925074,
+                        sources_sha256="43571c78d5f6824eb2c2e3030394371f4a6b4afda503f0d036c8bf6e0f7ceaff",
                         summary="profiles/k_wedge_powerlaw-1m-500k-20m_pmc.md")
 
 
