@@ -75,11 +75,13 @@ __global__ void k_dyn_dup(const uint32_t* ukey, const uint32_t* urow, int64_t m,
     }
 }
 
-// Update keys: a = first id, b = second id (as ints), index as payload.
+// Sort keys of the updates for the first (least significant) pass: one id
+// of every update, in update order.
 __global__ void k_dyn_ukey_init(const int32_t* a, int32_t q, uint32_t* key) {
     DYN_STRIDE(i, q) key[i] = (uint32_t)a[i];
 }
 
+// Keys of the second pass: the other id, in the order the first pass left.
 __global__ void k_dyn_gather(const int32_t* src, const uint32_t* idx, int32_t q, uint32_t* key) {
     DYN_STRIDE(i, q) key[i] = (uint32_t)src[idx[i]];
 }
