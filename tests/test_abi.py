@@ -46,11 +46,14 @@ def test_struct_layouts_match_header():
     lib.bbc_options_init(ctypes.byref(o))
     assert o.struct_size == ctypes.sizeof(bbc.Options)
     assert o.side == bbc.SIDE_AUTO and o.checks == bbc.CHECK_ALL and o.timing == 0
+    assert o.schedule == bbc.SCHED_DYNAMIC and o.no_tuning == 0 and o.n_blocks == 0
+    st = bbc.Stats()
+    assert ctypes.sizeof(st) > 0
 
 
 def test_status_strings():
     lib = _lib()
-    for s in range(9):
+    for s in range(10):
         txt = lib.bbc_status_string(s).decode()
         assert txt and txt != "unknown status"
     assert lib.bbc_status_string(99).decode() == "unknown status"
@@ -66,6 +69,17 @@ def test_host_argument_checks():
     assert lib.bbc_create(0, None) == bbc.EINVAL
     assert lib.bbc_last_stats(None, None) == bbc.EINVAL
     assert lib.bbc_last_error(None).decode() == "no context"
+    # the extension entry points reject a NULL context before touching anything
+    cls = (ctypes.c_uint64 * 6)(*range(6))
+    assert lib.bbc_count_classes(None, 1, 1, 0, None, None, None, cls, None, None) == bbc.EINVAL
+    assert list(cls) == list(range(6))
+    two = (ctypes.c_uint64 * 2)(5, 6)
+    assert lib.bbc_count_bicliques(None, 1, 1, 0, None, None, None, 3, two, None, None) == bbc.EINVAL
+    assert list(two) == [5, 6]
+    d = ctypes.c_int64(9)
+    assert lib.bbc_update_delta(None, 1, 1, 0, None, None, None, 0, None, None, None, ctypes.byref(d), None,
+                                None) == bbc.EINVAL
+    assert d.value == 9
 
 
 def test_no_gpu_means_device_error():
