@@ -341,6 +341,13 @@ __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, const uint32_t* tas
             const uint32_t a_lo_t = (task - task_off[i]) * span[i];  // this task's span of the w list
             const uint32_t n_a = min(r.n_a, a_lo_t + span[i]);
             if (mode[i]) {
+                // u's row, searched once per walk element, sits in LDS when it fits
+                // (the x list's slots are free in this mode)
+                const bool u_lds = b_g <= (uint32_t)CH;
+                if (u_lds) {
+                    for (uint32_t t = threadIdx.x; t < b_g; t += WG) sh.b_x[t] = d.urow[b_beg + t];
+                    __syncthreads();
+                }
                 for (uint32_t a0 = a_lo_t; a0 < n_a; a0 += WG) {
                     const uint32_t na = min((uint32_t)WG, n_a - a0), t = threadIdx.x;
                     unsigned long long cnt = 0;
@@ -380,7 +387,7 @@ __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, const uint32_t* tas
                             s_wx1 = d.s_new[j4];
                         }
                         if (x == v || (j4 >= 0 && j4 < i && changed(d, j4))) continue;
-                        const int32_t s_ux0 = row_state(d.urow, b_beg, b_beg + b_g, x);
+                        const int32_t s_ux0 = u_lds ? row_state(sh.b_x, 0, b_g, x) : row_state(d.urow, b_beg, b_beg + b_g, x);
                         const int32_t j3 = b_ub < b_ue ? find_in(d, b_ub, b_ue, ((unsigned long long)u << 32) | x) : -1;
                         const int32_t s_ux1 = j3 >= 0 ? d.s_new[j3] : s_ux0;
                         if ((s_ux0 == 0 && s_ux1 == 0) || (j3 >= 0 && j3 < i && changed(d, j3))) continue;
