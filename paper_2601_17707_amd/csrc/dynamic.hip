@@ -278,9 +278,13 @@ __device__ __forceinline__ DynUpd dyn_upd(const DynView& d, int32_t i) {
 }
 
 // Work plan: every changed update is split into tasks, each a contiguous
-// span of its w list (a multiple of the walk's or the pairs' chunk), at most
-// max_tasks per update; unchanged updates get none.  mode[i] = 1 for the
+// span of its w list, at most max_tasks per update; unchanged updates get
+// none.  Walk spans hold about kWalkBudget walk elements (from wsum), so a
+// hub's heavy neighbours spread over many workgroups; pairs spans are whole
+// chunks.  mode[i] = 1 for the
 // walk.
+constexpr unsigned long long kWalkBudget = 1ull << 15;
+
 template <int WG, int CH>
 __global__ void k_dyn_plan(DynView d, uint32_t max_tasks, uint32_t* n_tasks, uint32_t* span, uint8_t* mode,
                            const DevStatus* st) {
@@ -291,10 +295,16 @@ __global__ void k_dyn_plan(DynView d, uint32_t max_tasks, uint32_t* n_tasks, uin
         if (!bad && changed(d, (int32_t)i)) {
             const DynUpd r = dyn_upd(d, (int32_t)i);
             walk = d.wsum[r.v] < (unsigned long long)r.n_a * r.n_b;
-            const uint32_t unit = walk ? WG : CH;
-            const uint32_t units = (r.n_a + unit - 1) / unit;
-            c = min(units, max_tasks);
-            sp = c ? ((units + c - 1) / c) * unit : 0;
+            if (walk) {  // spans of w's holding about kWalkBudget walk elements each
+                const unsigned long long want = (d.wsum[r.v] + kWalkBudget - 1) / kWalkBudget;
+                c = (uint32_t)min(want, (unsigned long long)min(max_tasks, r.n_a));
+                if (c == 0 && r.n_a > 0) c = 1;
+                sp = c ? (r.n_a + c - 1) / c : 0;
+            } else {  // spans of whole CH-chunks of the w list
+                const uint32_t units = (r.n_a + CH - 1) / CH;
+                c = min(units, max_tasks);
+                sp = c ? ((units + c - 1) / c) * CH : 0;
+            }
             c = sp ? (r.n_a + sp - 1) / sp : 0;
         }
         n_tasks[i] = c;
