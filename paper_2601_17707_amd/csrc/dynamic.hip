@@ -277,11 +277,12 @@ __device__ __forceinline__ DynUpd dyn_upd(const DynView& d, int32_t i) {
     return r;
 }
 
-// Work plan: every changed update is split into tasks, each a contiguous
-// span of its w list, at most max_tasks per update; unchanged updates get
-// none.  Walk spans hold about kWalkBudget walk elements (from wsum), so a
-// hub's heavy neighbours spread over many workgroups; pairs spans are whole
-// chunks.  mode[i] = 1 for the
+// Work plan: every changed update is split into at most max_tasks tasks;
+// unchanged updates get none.  mode 1, the walk: spans of the w list
+// holding about kWalkBudget walk elements (from wsum), so a hub's heavy
+// neighbours spread over many workgroups; mode 2, pairs: one WG x WG tile
+// of (w, x) pairs per task (span = tiles per w chunk); mode 0, pairs when
+// the tiles are too many: spans of whole w chunks against every x chunk.  mode[i] = 1 for the
 // walk.
 constexpr unsigned long long kWalkBudget = 1ull << 15;
 
@@ -300,12 +301,20 @@ __global__ void k_dyn_plan(DynView d, uint32_t max_tasks, uint32_t* n_tasks, uin
                 c = (uint32_t)min(want, (unsigned long long)min(max_tasks, r.n_a));
                 if (c == 0 && r.n_a > 0) c = 1;
                 sp = c ? (r.n_a + c - 1) / c : 0;
-            } else {  // spans of whole CH-chunks of the w list
-                const uint32_t units = (r.n_a + CH - 1) / CH;
-                c = min(units, max_tasks);
-                sp = c ? ((units + c - 1) / c) * CH : 0;
+                c = sp ? (r.n_a + sp - 1) / sp : 0;
+            } else {
+                const uint32_t ca = (r.n_a + WG - 1) / WG, cb = (r.n_b + WG - 1) / WG;
+                if ((unsigned long long)ca * cb <= max_tasks) {  // one WG x WG tile of pairs per task
+                    walk = 2;
+                    c = ca * cb;
+                    sp = cb;
+                } else {  // spans of whole CH-chunks of the w list, every x chunk
+                    const uint32_t cc = (r.n_a + CH - 1) / CH;
+                    c = min(cc, max_tasks);
+                    sp = c ? ((cc + c - 1) / c) * CH : 0;
+                    c = sp ? (r.n_a + sp - 1) / sp : 0;
+                }
             }
-            c = sp ? (r.n_a + sp - 1) / sp : 0;
         }
         n_tasks[i] = c;
         span[i] = sp;
@@ -348,9 +357,19 @@ __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, const uint32_t* tas
             const int32_t a_ub = r.a_ub, b_ub = r.b_ub, b_ue = r.b_ue;
             const uint32_t n_b = r.n_b;
             const int32_t s_uv0 = d.s_old[i], s_uv1 = d.s_new[i];
-            const uint32_t a_lo_t = (task - task_off[i]) * span[i];  // this task's span of the w list
-            const uint32_t n_a = min(r.n_a, a_lo_t + span[i]);
-            if (mode[i]) {
+            // this task's part: w list [a_lo_t, n_a), x list [b_lo_t, b_hi_t)
+            const uint32_t k_t = task - task_off[i];
+            uint32_t a_lo_t, n_a, b_lo_t = 0, b_hi_t = n_b;
+            if (mode[i] == 2) {
+                a_lo_t = (k_t / span[i]) * WG;
+                n_a = min(r.n_a, a_lo_t + WG);
+                b_lo_t = (k_t % span[i]) * WG;
+                b_hi_t = min(n_b, b_lo_t + WG);
+            } else {
+                a_lo_t = k_t * span[i];
+                n_a = min(r.n_a, a_lo_t + span[i]);
+            }
+            if (mode[i] == 1) {
                 // u's row, searched once per walk element, sits in LDS when it fits
                 // (the x list's slots are free in this mode)
                 const bool u_lds = b_g <= (uint32_t)CH;
@@ -411,9 +430,9 @@ __global__ __launch_bounds__(WG) void k_dyn_delta(DynView d, const uint32_t* tas
                 for (uint32_t a0 = a_lo_t; a0 < n_a; a0 += CH) {
                     const uint32_t na = min((uint32_t)CH, n_a - a0);
                     for (uint32_t t = threadIdx.x; t < na; t += WG) fill_w(d, sh, i, u, v, a_beg, a_g, a_ub, a0 + t, t);
-                    for (uint32_t b0 = 0; b0 < n_b; b0 += CH) {
-                        const uint32_t nb = min((uint32_t)CH, n_b - b0);
-                        if (a0 == a_lo_t || n_b > CH) {  // the x chunk is loaded once when it fits
+                    for (uint32_t b0 = b_lo_t; b0 < b_hi_t; b0 += CH) {
+                        const uint32_t nb = min((uint32_t)CH, b_hi_t - b0);
+                        if (a0 == a_lo_t || b_hi_t - b_lo_t > CH) {  // the x chunk is loaded once when it fits
                             for (uint32_t t = threadIdx.x; t < nb; t += WG) {
                                 const uint32_t ib = b0 + t;
                                 uint32_t x;
