@@ -313,7 +313,9 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
  * adding (balanced after) - (balanced before).  per_update (device, int64
  * [n_updates], may be NULL) receives each update's share; the shares sum to
  * *delta (on error its content is unspecified).  upd_u, upd_v (int32) and upd_state (int8) are device arrays.
- * Work per update is about deg(v) x deg(u) binary searches.
+ * Work per update is the smaller of deg(u) deg(v) pair lookups and the
+ * walk v -> w -> x (the sum of deg(w) over the neighbours w of v), each a
+ * binary search, split into tasks that spread over the whole GPU.
  * Errors: BBC_EINVAL (null pointers, negative sizes, a pair repeated in the
  * batch), BBC_ERANGE / BBC_ESIGN (the graph's, or an update's id or state),
  * BBC_EOFFSETS, BBC_EDUP, BBC_ENOMEM, BBC_EDEVICE, BBC_ETOOBIG.  Waits for
