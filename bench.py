@@ -87,10 +87,136 @@ def cpu_baseline(g, wedges: int, budget_s: float = 15.0) -> dict:
     k = int(min(n_s, max(pilot, n_s * budget_s * rate / max(wedges, 1))))
     t2, w2 = timed(0, k)
     dt = max(t2 - t_setup, 1e-9)
-    return dict(value=w2 / dt / 1e9, unit="G/s", cores=1, kind="oracle",
+    h = host_info()
+    return dict(value=w2 / dt / 1e9, unit="G/s", cores=1, host_cores=h["cores"], host_model=h["model"], kind="oracle",
                 sample=f"anchors 0..{k - 1} of {n_s} ({w2} wedges, {100.0 * w2 / max(wedges, 1):.2f}% of the "
                        f"graph) counted in {dt:.1f} s; oracle transpose {t_setup:.1f} s excluded",
                 full_graph_estimate_s=wedges / (w2 / dt) + t_setup)
+
+
+def host_info() -> dict:
+    """Host cores (as this process sees them) and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(cores=n, logical_cpus=os.cpu_count(), model=model)
+
+
+def cpu_multicore(g, wedges: int, total: int) -> dict:
+    """The multicore CPU baseline in the manner of Algorithm 2 (M-BBC:
+    OpenMP over the smaller side's anchors, heaviest first, thread-local
+    buckets, priority pair filter) on the whole graph with every host core;
+    its total must equal the GPU's."""
+    import oracle
+
+    t0 = time.perf_counter()
+    t, threads = oracle.mbbc_count(g)
+    dt = time.perf_counter() - t0
+    h = host_info()
+    return dict(value=wedges / dt / 1e9, unit="G/s", seconds=dt, threads=threads, cores=h["cores"],
+                model=h["model"], kind="multicore (Algorithm 2 style, OpenMP)", total_matches=bool(t == total),
+                sample="whole graph, including its own CSR build and sorts")
+
+
+def bench_copy(mib: int = 4096, reps: int = 5) -> dict:
+    """Achievable HBM bandwidth on this device: a plain device-to-device
+    copy of `mib` MiB (read + write bytes per second), timed by HIP events."""
+    import torch
+
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * n / (ms / 1e3) / 1e9
+    return dict(bytes_per_copy=2 * n, ms=ms, achieved=gbs, unit="GB/s", frac_of_peak=gbs / HBM_PEAK_GBS)
+
+
+def bench_uniform(ctx, seed: int, calls: int = 200) -> dict:
+    """Latency of one bbc_count call on the small uniform graph (|U| =
+    2,000, |V| = 1,000, 20,000 edges, P(-) = 0.3): microseconds per call,
+    host wait included, and the kernels' span by HIP events."""
+    import torch
+
+    from paper_2601_17707_amd import bbc, synth
+
+    g = synth.workload("uniform-2k-1k-20k", seed)
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    for _ in range(10):
+        t = ctx.count(off, adj, sg, g.n_v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        t = ctx.count(off, adj, sg, g.n_v)
+    us = 1e6 * (time.perf_counter() - t0) / calls
+    span = []
+    for _ in range(10):
+        ctx.count(off, adj, sg, g.n_v, opts=bbc.options(timing=True))
+        span.append(ctx.stats()["ms_total"])
+    st = ctx.stats()
+    return dict(workload="uniform-2k-1k-20k", seed=seed, n_edges=g.m, us_per_call=us,
+                device_span_us=1e3 * sum(span) / len(span), kernel_us=1e3 * st["ms_count"], wedges=int(st["wedges"]),
+                balanced_butterflies=t)
+
+
+def bench_skewed(ctx, steps: int, warmup: int, seed: int) -> dict:
+    """The highly skewed workload (|U| = 5e6, |V| = 2e5, 2e8 edges, hub V
+    vertices near 430,000 edges): end-to-end, build and wedge-kernel times,
+    wedges/s and the kernel's roofline fraction on algorithmic bytes."""
+    import torch
+
+    from paper_2601_17707_amd import bbc, synth
+
+    t0 = time.perf_counter()
+    g = synth.workload("skewed-5m-200k-200m", seed)
+    gen_s = time.perf_counter() - t0
+    print(f"# skewed-5m-200k-200m: n_u={g.n_u} n_v={g.n_v} m={g.m} (generated in {gen_s:.1f} s)", file=sys.stderr,
+          flush=True)
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    n_v = g.n_v
+    del g
+    for _ in range(max(1, warmup)):
+        total = ctx.count(off, adj, sg, n_v)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        total = ctx.count(off, adj, sg, n_v)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t) / steps
+    kern, build = [], []
+    for _ in range(3):
+        ctx.count(off, adj, sg, n_v, opts=bbc.options(timing=True))
+        st = ctx.stats()
+        kern.append(st["ms_count"])
+        build.append(st["ms_checks"] + st["ms_build"])
+    kavg = sum(kern) / len(kern)
+    wedges = int(st["wedges"])
+    nbytes = algorithmic_bytes(st)
+    ach = nbytes / (kavg / 1e3) / 1e9
+    del off, adj, sg
+    torch.cuda.empty_cache()
+    return dict(workload="skewed-5m-200k-200m", seed=seed, n_edges=int(st["n_edges"]), wedges=wedges,
+                ms_per_call=ms, kernel_ms=kavg, build_ms=sum(build) / len(build),
+                wedges_per_s=wedges / (ms / 1e3) / 1e9, kernel_wedges_per_s=wedges / (kavg / 1e3) / 1e9, unit="G/s",
+                balanced_butterflies=total, bands=int(st["bands"]),
+                roofline=dict(bound="hbm", kernel="k_wedge", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=ach / HBM_PEAK_GBS, algorithmic_bytes=nbytes))
 
 
 def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
@@ -125,6 +251,14 @@ def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
     ms_batch = 1000.0 * (time.perf_counter() - t0) / steps
     ms_batch_ev = ev0.elapsed_time(ev1) / steps
 
+    # aggregate rate of the batch: every graph's wedges, and the wedge
+    # kernel's algorithmic bytes over its HIP-event time (one eager pass)
+    ctx.count_batched(batch, opts=bbc.options(timing=True))
+    bst = ctx.stats()
+    b_wedges = int(bst["wedges"])
+    b_bytes = algorithmic_bytes(bst)
+    b_kern = bst["ms_count"]
+
     # per-graph loop: plain bbc_count on each graph's slice of the same arrays
     loop = [0] * n
     torch.cuda.synchronize()
@@ -140,7 +274,12 @@ def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
     return dict(workload="batch-10k", graphs=n, edges=edges, ms_per_batch=ms_batch, ms_per_batch_events=ms_batch_ev,
                 graphs_per_s=n / (ms_batch / 1e3), per_graph_loop_s=loop_s, per_graph_loop_graphs_per_s=n / loop_s,
                 speedup_vs_loop=(n / (ms_batch / 1e3)) / (n / loop_s),
-                totals_match_loop=bool(list(totals) == loop), balanced_butterflies=int(totals.sum()))
+                totals_match_loop=bool(list(totals) == loop), balanced_butterflies=int(totals.sum()),
+                wedges=b_wedges, wedges_per_s=b_wedges / (ms_batch / 1e3) / 1e9, unit="G/s",
+                kernel_ms=b_kern, build_ms=bst["ms_checks"] + bst["ms_build"],
+                roofline=dict(bound="hbm", kernel="k_wedge", algorithmic_bytes=b_bytes,
+                              achieved=b_bytes / (b_kern / 1e3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=b_bytes / (b_kern / 1e3) / 1e9 / HBM_PEAK_GBS))
 
 
 def bench_classes(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps: int, warmup: int) -> dict:
@@ -170,9 +309,10 @@ def bench_classes(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps: i
 
 
 def bench_bicliques(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps: int, warmup: int) -> dict:
-    """Balanced (2,k)-bicliques on the resident bench graph, pairs on the
-    anchor side of the count, for k = 3 and 4 (exact 128-bit sums), and
-    k = 2 checked against the balanced count."""
+    """Balanced (2,k)-bicliques on the resident bench graph with the pair on
+    U, the size-two side the BB2K section fixes, for k = 3 and 4 (exact
+    128-bit sums), and k = 2 checked against the balanced count.  Wedges
+    are those of the U-anchored walk (sum of C(deg v, 2) over V)."""
     import torch
 
     from paper_2601_17707_amd import bbc
@@ -188,9 +328,12 @@ def bench_bicliques(ctx, off, adj, sg, n_v: int, wedges: int, total: int, steps:
         torch.cuda.synchronize()
         ms = 1000.0 * (time.perf_counter() - t) / steps
         ctx.count_bicliques(off, adj, sg, n_v, k, opts=bbc.options(timing=True))
-        out[f"k{k}"] = dict(count=str(r), ms_per_call=ms, kernel_ms=ctx.stats()["ms_count"],
-                            wedges_per_s=wedges / (ms / 1e3) / 1e9)
+        bst = ctx.stats()
+        w_k = int(bst["wedges"])
+        out[f"k{k}"] = dict(count=str(r), ms_per_call=ms, kernel_ms=bst["ms_count"], wedges=w_k,
+                            wedges_per_s=w_k / (ms / 1e3) / 1e9)
     out["unit"] = "G/s"
+    out["pair_side"] = "U"
     out["k2_matches_count"] = bool(int(out["k2"]["count"]) == total)
     return out
 
@@ -309,6 +452,10 @@ def main():
     ap.add_argument("--no-classes", action="store_true", help="skip the sign-pattern class count")
     ap.add_argument("--no-bicliques", action="store_true", help="skip the (2,k)-biclique counts")
     ap.add_argument("--no-updates", action="store_true", help="skip the dynamic-update batch")
+    ap.add_argument("--no-skewed", action="store_true", help="skip the 200M-edge skewed workload")
+    ap.add_argument("--no-uniform", action="store_true", help="skip the small-graph latency measurement")
+    ap.add_argument("--no-multicore", action="store_true", help="skip the multicore CPU baseline")
+    ap.add_argument("--no-copy", action="store_true", help="skip the device copy bandwidth measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -402,13 +549,24 @@ def main():
     if not args.no_updates:
         line["updates"] = [bench_updates(ctx, g, off, adj, sg, ms_step, max(1, min(args.steps, 5)), args.warmup,
                                          args.seed, q=q) for q in (1_000, 100_000)]
+    if not args.no_uniform and args.workload == WORKLOAD:
+        line["uniform"] = bench_uniform(ctx, args.seed)
     if not args.no_batch and args.workload == WORKLOAD:
         line["batched"] = bench_batched(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
-    if not args.no_hybrid and args.workload == WORKLOAD:
+    if args.workload == WORKLOAD and not (args.no_hybrid and args.no_skewed):
         del off, adj, sg
+        torch.cuda.empty_cache()
+    if not args.no_hybrid and args.workload == WORKLOAD:
         line["hybrid"] = bench_hybrid(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
+    if not args.no_skewed and args.workload == WORKLOAD:
+        line["skewed"] = bench_skewed(ctx, max(1, min(args.steps, 3)), args.warmup, args.seed)
+    if not args.no_copy:
+        line["hbm_copy"] = bench_copy()
+    line["host"] = host_info()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(g, wedges)
+    if not args.no_multicore:
+        line["cpu_multicore"] = cpu_multicore(g, wedges, total)
     ctx.close()
     print(json.dumps(line), flush=True)
 

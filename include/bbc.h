@@ -286,8 +286,10 @@ bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_e
  * count is, over pairs {u, w} of the pair side, C(a_uw, k) + C(b_uw, k) with
  * a / b the symmetric / asymmetric wedge counts (Algorithm 1 with general
  * k).  k = 2 is bbc_count's total; k = 1 counts the wedges.  Unlike k = 2
- * the result depends on the pair side: opts->side (BBC_SIDE_U or _V; AUTO
- * takes the smaller side, a tie V; BBC_SIDE_MIN_WEDGES is rejected).
+ * the result depends on the pair side: opts->side (BBC_SIDE_U or _V).
+ * The BB2K section under Algorithm 1 fixes the size-two side as U, so
+ * BBC_SIDE_AUTO means U here (not the smaller side); BBC_SIDE_MIN_WEDGES
+ * is rejected.
  * count (host, 2 uint64) receives the exact 128-bit result, low word
  * first; BBC_EOVERFLOW when it, or one pair's term, does not fit 128 bits.
  * 1 <= k <= BBC_BICLIQUE_MAX_K, else BBC_EINVAL.  The same walk as
@@ -312,7 +314,7 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
  * visits the butterflies through its pair before and after the batch,
  * adding (balanced after) - (balanced before).  per_update (device, int64
  * [n_updates], may be NULL) receives each update's share; the shares sum to
- * *delta (on error its content is unspecified).  upd_u, upd_v (int32) and upd_state (int8) are device arrays.
+ * *delta (on error it is left untouched).  upd_u, upd_v (int32) and upd_state (int8) are device arrays.
  * Work per update is the smaller of deg(u) deg(v) pair lookups and the
  * walk v -> w -> x (the sum of deg(w) over the neighbours w of v), each a
  * binary search, split into tasks that spread over the whole GPU.
@@ -325,6 +327,14 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
                             const int32_t* adj, const int8_t* signs, int32_t n_updates, const int32_t* upd_u,
                             const int32_t* upd_v, const int8_t* upd_state, int64_t* delta, int64_t* per_update,
                             void* stream);
+
+/* Caps the number of tasks one update of bbc_update_delta is split into
+ * (default 4,096; cap 0 restores the default).  With a smaller cap an
+ * update's pairs go to fewer, longer tasks: whole 1,024-entry chunks of
+ * its w list against every chunk of its x list once its 256 x 256 tiles
+ * outnumber the cap.  The result does not depend on it.  BBC_EINVAL for a
+ * NULL context or a negative cap. */
+bbc_status bbc_set_update_task_cap(bbc_ctx* ctx, int32_t cap);
 
 /* Dense-block planner options.  Candidates are the vertices of degree >=
  * min_degree.  A block grows from a seed anchor: C starts as the seed's

@@ -318,7 +318,9 @@ int oracle_count_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off
  * the k centres must all be of one kind: per pair, C(a, k) + C(b, k), with
  * a / b the symmetric / asymmetric wedge counts (Algorithm 1 with general
  * k).  Unlike k = 2, the count depends on which side holds the two
- * vertices; `side` picks it as elsewhere.
+ * vertices.  The BB2K section fixes the size-two side as U (its outer loop
+ * runs over u in U), so side 0 (automatic) means U here; side 2 puts the
+ * pair on V.
  *
  * Binomials come from Pascal's rule (a table of C(x, j), x <= the largest
  * degree of the side, j <= k), saturating at 2^128; the total is summed in
@@ -349,7 +351,7 @@ int oracle_count_bicliques(int32_t n_u, int32_t n_v, int64_t m, const int32_t* o
     if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
     if (k < 1 || k > 64) return 1;
     sides_t g;
-    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    build_sides(n_u, n_v, m, off, adj, sg, side == 2 ? 2 : 1, &g);
     int32_t dmax = 0;
     for (int32_t u = 0; u < g.n_s; ++u)
         if (g.s_off[u + 1] - g.s_off[u] > dmax) dmax = (int32_t)(g.s_off[u + 1] - g.s_off[u]);
@@ -401,7 +403,7 @@ int oracle_brute_bicliques(int32_t n_u, int32_t n_v, int64_t m, const int32_t* o
                            const int8_t* sg, int side, int k, uint64_t* out) {
     if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
     if (k < 1 || (int64_t)n_u * n_v > (1LL << 26)) return 1;
-    const int su = pick_side(n_u, n_v, side) == 1;
+    const int su = side != 2; /* the pair on U unless V is named, as in the walk */
     const int32_t n_s = su ? n_u : n_v, n_c = su ? n_v : n_u;
     int8_t* M = (int8_t*)calloc((size_t)n_s * (size_t)n_c + 1, 1);
     for (int32_t u = 0; u < n_u; ++u)

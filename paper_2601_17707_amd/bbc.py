@@ -164,6 +164,8 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_update_delta.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
                                      vp]
     lib.bbc_update_delta.restype = ctypes.c_int
+    lib.bbc_set_update_task_cap.argtypes = [vp, i32]
+    lib.bbc_set_update_task_cap.restype = ctypes.c_int
     lib.bbc_plan_options_init.argtypes = [ctypes.POINTER(PlanOptions)]
     lib.bbc_plan_options_init.restype = ctypes.c_int
     lib.bbc_plan_blocks.argtypes = [vp, i32, i32, i64, vp, vp, ctypes.POINTER(PlanOptions), i32,
@@ -293,9 +295,8 @@ class Context:
         sp = _stream_ptr(stream, offsets)
         out = ctypes.c_uint64(0)
         o = opts if opts is not None else options()
-        st = self._lib.bbc_count(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj), _ptr(signs),
-                                 ctypes.byref(out), _ptr(per_vertex) if per_vertex is not None else None,
-                                 ctypes.byref(o), sp)
+        st = self._lib.bbc_count(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj), _ptr(signs), ctypes.byref(out),
+                _ptr(per_vertex) if per_vertex is not None else None, ctypes.byref(o), sp)
         if st != OK:
             raise BbcError(st, self.last_error())
         return int(out.value)
@@ -363,6 +364,12 @@ class Context:
         if st != OK:
             raise BbcError(st, self.last_error())
         return int(out.value)
+
+    def set_update_task_cap(self, cap: int) -> None:
+        """Tasks per update of update_delta (0 = the default, 4,096)."""
+        st = self._lib.bbc_set_update_task_cap(self._h, int(cap))
+        if st != OK:
+            raise BbcError(st, self.last_error())
 
     def count_batched(self, batch: "Batch", opts: Options | None = None, stream=None):
         """Per-graph counts of a Batch; returns its totals tensor (int64, on device)."""

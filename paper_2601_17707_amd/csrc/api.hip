@@ -38,8 +38,8 @@ void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, 
                const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
                const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
                unsigned long long* wsum, int32_t n_v, int32_t q, uint32_t* n_tasks, uint32_t* task_off,
-               uint32_t* span, uint8_t* mode, uint32_t* partials, long long* per_update, DevStatus* st,
-               hipStream_t s);
+               uint32_t* span, uint8_t* mode, uint32_t* partials, long long* per_update, int32_t task_cap,
+               DevStatus* st, hipStream_t s);
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s);
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
@@ -130,6 +130,7 @@ struct bbc_ctx {
     bbc_stats stats = {};
     std::string err;
     std::vector<TuneEntry> tune;
+    int32_t update_task_cap = 0;  // bbc_update_delta: tasks per update (0: 4096)
 };
 
 struct bbc_batch_plan {
@@ -463,17 +464,24 @@ bool side_is_u(int side, int32_t n_u, int32_t n_v) { return side == BBC_SIDE_U |
 // both choices on the device (sum of C(deg, 2) over the centre side) and
 // takes the one with fewer wedges, the default rule breaking a tie; it
 // waits for the stream once.
+// The measurement runs in `buf` (cap bytes) when given, else in the
+// context's arena (grown to fit).
 bbc_status resolve_side(bbc_ctx* ctx, int side, int32_t n_u, int32_t n_v, int64_t m, const int32_t* off,
-                        const int32_t* adj, hipStream_t s, bool* su) {
+                        const int32_t* adj, hipStream_t s, bool* su, char* buf = nullptr, size_t cap = 0) {
     if (side != BBC_SIDE_MIN_WEDGES) {
         *su = side_is_u(side, n_u, n_v);
         return BBC_OK;
     }
     const size_t bytes = 32 + (size_t)n_v * 4;
-    bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, bytes);
-    if (rc != BBC_OK) return rc;
-    unsigned long long* out = reinterpret_cast<unsigned long long*>(ctx->arena);
-    launch_side_wedges(off, n_u, adj, m, n_v, reinterpret_cast<uint32_t*>(ctx->arena + 32), out, s);
+    if (buf) {
+        if (bytes > cap) return fail(ctx, BBC_ENOMEM, "side measurement exceeds the fixed scratch");
+    } else {
+        bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, bytes);
+        if (rc != BBC_OK) return rc;
+        buf = ctx->arena;
+    }
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(buf);
+    launch_side_wedges(off, n_u, adj, m, n_v, reinterpret_cast<uint32_t*>(buf + 32), out, s);
     unsigned long long w[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(w, out, sizeof(w), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -688,15 +696,14 @@ bbc_status timed_stats(bbc_ctx* ctx) {
     return BBC_OK;
 }
 
-// Runs a job on the context's arena and stream and waits for its status.
-bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStream_t s,
-                   const std::vector<DevGraph>* dg, const std::vector<int64_t>* vstart,
-                   const std::vector<int64_t>* rend, const std::vector<DevBlock>* db = nullptr,
-                   const std::vector<DevTile>* dt = nullptr) {
+// Runs a job whose buffers are carved from `arena` (large enough for it) on
+// stream s and waits for its status.
+bbc_status run_planned(bbc_ctx* ctx, const Job& J, char* arena, const bbc_options& opts, hipStream_t s,
+                       const std::vector<DevGraph>* dg, const std::vector<int64_t>* vstart,
+                       const std::vector<int64_t>* rend, const std::vector<DevBlock>* db,
+                       const std::vector<DevTile>* dt) {
     Plan P;
-    bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, P.carve(nullptr, J));
-    if (rc != BBC_OK) return rc;
-    P.carve(ctx->arena, J);
+    P.carve(arena, J);
     if (dg && !dg->empty()) {
         HIP_OR_FAIL(hipMemcpyAsync(P.graphs, dg->data(), dg->size() * sizeof(DevGraph), hipMemcpyHostToDevice, s));
         HIP_OR_FAIL(hipMemcpyAsync(P.vstart, vstart->data(), vstart->size() * 8, hipMemcpyHostToDevice, s));
@@ -712,10 +719,22 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
     HIP_OR_FAIL(hipGetLastError());
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
-    rc = status_result(ctx, *ctx->st_host);
+    const bbc_status rc = status_result(ctx, *ctx->st_host);
     if (rc != BBC_OK) return rc;
     fill_stats(ctx, J, *ctx->st_host, wedge_block(J.band_words, J.wg_size, J.pv != nullptr));
     return timing ? timed_stats(ctx) : BBC_OK;
+}
+
+// Runs a job on the context's arena (grown to fit) and stream and waits for
+// its status.
+bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStream_t s,
+                   const std::vector<DevGraph>* dg, const std::vector<int64_t>* vstart,
+                   const std::vector<int64_t>* rend, const std::vector<DevBlock>* db = nullptr,
+                   const std::vector<DevTile>* dt = nullptr) {
+    Plan P;
+    bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, P.carve(nullptr, J));
+    if (rc != BBC_OK) return rc;
+    return run_planned(ctx, J, ctx->arena, opts, s, dg, vstart, rend, db, dt);
 }
 
 }  // namespace
@@ -934,7 +953,7 @@ bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n
     J.sg = signs;
     J.n_u = n_u;
     J.n_v = n_v;
-    J.s_is_u = side_is_u(opts.side, n_u, n_v);
+    J.s_is_u = opts.side != BBC_SIDE_V;  // the size-two side is U unless V is named (BB2K)
     J.m = n_edges;
     J.n_s = J.s_is_u ? n_u : n_v;
     J.n_c = J.s_is_u ? n_v : n_u;
@@ -1070,13 +1089,20 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
                D.partials, s, &k_out, nullptr, &i2);
     dyn_key64(upd_v, upd_u, i2, (int32_t)q, D.vu_key, D.vu_pos, 0, st, s);
     dyn_delta(offsets, urow, D.voff, vrow, D.uv_key, D.uv_pos, D.vu_key, D.vu_pos, upd_u, upd_v, upd_state, D.s_old,
-              D.wsum, n_v, (int32_t)q, D.n_tasks, D.task_off, D.span, D.mode, D.partials, (long long*)per_update, st,
-              s);
+              D.wsum, n_v, (int32_t)q, D.n_tasks, D.task_off, D.span, D.mode, D.partials, (long long*)per_update,
+              ctx->update_task_cap, st, s);
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     rc = status_result(ctx, *ctx->st_host);
     if (rc != BBC_OK) return rc;
     *delta = (int64_t)ctx->st_host->total;
+    return BBC_OK;
+}
+
+bbc_status bbc_set_update_task_cap(bbc_ctx* ctx, int32_t cap) {
+    if (!ctx) return BBC_EINVAL;
+    if (cap < 0) return fail(ctx, BBC_EINVAL, "negative task cap");
+    ctx->update_task_cap = cap;
     return BBC_OK;
 }
 

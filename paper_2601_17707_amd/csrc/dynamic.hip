@@ -288,9 +288,12 @@ constexpr unsigned long long kWalkBudget = 1ull << 15;
 
 template <int WG, int CH>
 __global__ void k_dyn_plan(DynView d, uint32_t max_tasks, uint32_t* n_tasks, uint32_t* span, uint8_t* mode,
-                           const DevStatus* st) {
+                           long long* per_update, const DevStatus* st) {
     const bool bad = dyn_bad(st);
     DYN_STRIDE(i, d.q) {
+        // the shares start at zero only when the batch was accepted (every
+        // check ran earlier on the stream), so a rejected batch leaves them
+        if (per_update && !bad) per_update[i] = 0;
         uint32_t c = 0, sp = 0;
         uint8_t walk = 0;
         if (!bad && changed(d, (int32_t)i)) {
@@ -535,8 +538,8 @@ void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, 
                const unsigned long long* uv_key, const uint32_t* uv_pos, const unsigned long long* vu_key,
                const uint32_t* vu_pos, const int32_t* upd_u, const int32_t* upd_v, const int8_t* s_new, int8_t* s_old,
                unsigned long long* wsum, int32_t n_v, int32_t q, uint32_t* n_tasks, uint32_t* task_off,
-               uint32_t* span, uint8_t* mode, uint32_t* partials, long long* per_update, DevStatus* st,
-               hipStream_t s) {
+               uint32_t* span, uint8_t* mode, uint32_t* partials, long long* per_update, int32_t task_cap,
+               DevStatus* st, hipStream_t s) {
     if (q <= 0) return;
     constexpr int WG = 256, CH = 1024;
     const DynView d{uoff, urow, voff, vrow, uv_key, uv_pos, vu_key, vu_pos, upd_u, upd_v, s_new, s_old, wsum, q};
@@ -544,12 +547,12 @@ void dyn_delta(const int32_t* uoff, const uint32_t* urow, const uint32_t* voff, 
         hipLaunchKernelGGL(k_dyn_wsum, dim3(dyn_grid((int64_t)n_v * kWave, 256)), dim3(256), 0, s, voff, vrow, uoff,
                            n_v, wsum);
     hipLaunchKernelGGL(k_dyn_old, dim3(dyn_grid(q, 256)), dim3(256), 0, s, d, st);
-    // at most 4096 tasks per update and 2^31 in all
-    const uint32_t max_tasks = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(4096, (int64_t)INT32_MAX / q));
+    // at most task_cap (default 4096) tasks per update and 2^31 in all
+    const int64_t cap = task_cap > 0 ? task_cap : 4096;
+    const uint32_t max_tasks = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(cap, (int64_t)INT32_MAX / q));
     hipLaunchKernelGGL((k_dyn_plan<WG, CH>), dim3(dyn_grid(q, 256)), dim3(256), 0, s, d, max_tasks, n_tasks, span,
-                       mode, (const DevStatus*)st);
+                       mode, per_update, (const DevStatus*)st);
     scan_exclusive_u32(n_tasks, task_off, q, partials, s);
-    if (per_update) fill_bytes(per_update, (int64_t)q * 8, s);
     hipLaunchKernelGGL((k_dyn_delta<WG, CH>), dim3(65536), dim3(WG), 0, s, d, (const uint32_t*)task_off,
                        (const uint32_t*)span, (const uint8_t*)mode, per_update, st);
 }

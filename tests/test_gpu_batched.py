@@ -191,6 +191,41 @@ def test_plan_reports_input_errors(ctx):
     plan.close()
 
 
+def test_workload_batch_all(ctx):
+    """All 10,000 graphs of the batch workload, from one replay of a
+    captured plan, element by element against the oracle's stored totals
+    (tests/golden/batch10k_totals.json, written by make_expected.py from
+    the oracle alone), after checking the batch digest."""
+    import hashlib
+    import json
+    import os
+
+    import torch
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch10k_totals.json")
+    e = json.load(open(path))["batch-10k:1"]
+    graphs = synth.workload("batch-10k", 1)
+    h = hashlib.sha256()
+    for g in graphs:
+        h.update(bytes.fromhex(g.sha256()))
+    assert h.hexdigest() == e["sha256"], "generator output changed"
+    want = np.array([int(t) for t in e["totals"]], np.int64)
+    assert len(want) == len(graphs) == 10_000
+    b = bbc.Batch(graphs, "cuda:0")
+    plan = ctx.plan(b)
+    b.totals.fill_(-1)
+    plan.launch()
+    got = plan.wait().cpu().numpy()[: len(graphs)]
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} graphs differ, first {bad[:10].tolist()}"
+    # a second replay after eager work on the same stream gives the same totals
+    b.totals.fill_(-1)
+    torch.cuda.synchronize()
+    plan.launch()
+    assert np.array_equal(plan.wait().cpu().numpy()[: len(graphs)], want)
+    plan.close()
+
+
 def test_workload_batch_sample(ctx):
     """The first 200 members of the 10,000-graph batch workload."""
     graphs = synth.batch_graphs(200, seed=1)

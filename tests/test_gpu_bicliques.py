@@ -97,6 +97,20 @@ def test_one_pair_exact_and_overflow(ctx):
     assert e.value.status == bbc.EOVERFLOW
 
 
+@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("side", ["auto", "u", "v"])
+def test_band_crossing(ctx, k, side):
+    """70,000 V and 200,000 U vertices, 1.2M edges, hubs of about 3,000 on
+    both sides: anchors of either side fall in the 4-, 8- and 16-bit
+    layouts, whose bands (32,768, 16,384 and 8,192 endpoint ranks) the rank
+    ranges cross several times; the automatic side puts the pair on U."""
+    g = synth.chung_lu_graph(200_000, 70_000, 1_200_000, 2.1, 2.1, 4000, 4000, 11, p_neg=0.35)
+    got = check(ctx, g, k, side)
+    assert got > 0
+    if side == "auto":
+        assert got == oracle.count_bicliques(g, k, oracle.SIDE_U)
+
+
 def test_degenerate(ctx):
     for n_u, n_v, edges in [(1, 1, [(0, 0, 1)]), (3, 2, []), (2, 1, [(0, 0, 1), (1, 0, -1)]),
                             (2, 2, [(0, 0, 1), (0, 1, -1), (1, 0, -1), (1, 1, -1)])]:

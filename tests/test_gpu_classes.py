@@ -72,6 +72,28 @@ def test_every_counter_width(ctx):
     assert min(got) > 65535
 
 
+def band_graph():
+    """70,000 V and 200,000 U vertices, 1.2M edges, hubs of about 3,000 on
+    both sides: anchors on either side fall in the 4-, 8- and 16-bit class
+    layouts, and their rank ranges (70,000 or 200,000) span several bands of
+    every layout (16,384 slots at 4 bits, 8,192 at 8 bits, 4,096 at 16
+    bits), so band edges are crossed in an element-wise comparison."""
+    return synth.chung_lu_graph(200_000, 70_000, 1_200_000, 2.1, 2.1, 4000, 4000, 11, p_neg=0.35)
+
+
+@pytest.mark.parametrize("side", ["u", "v"])
+def test_band_crossing(ctx, side):
+    g = band_graph()
+    du = np.diff(g.offsets.astype(np.int64))
+    dv = np.bincount(g.adj, minlength=g.n_v)
+    d = du if side == "u" else dv
+    # anchors in every narrow layout, rank ranges of several bands
+    assert (d[d > 1] <= 15).sum() > 1000 and ((d > 15) & (d <= 255)).sum() > 1000 and (d > 255).sum() > 100
+    assert len(d) > 4 * 16384
+    got = check(ctx, g, side)
+    assert min(got) > 0
+
+
 def test_degenerate(ctx):
     for n_u, n_v, edges in [(1, 1, [(0, 0, 1)]), (3, 2, []), (2, 2, [(0, 0, 1), (0, 1, -1), (1, 0, -1), (1, 1, -1)])]:
         e = np.array(edges, np.int64).reshape(-1, 3)

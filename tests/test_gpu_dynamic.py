@@ -116,3 +116,51 @@ def test_rejected_inputs(ctx):
     with pytest.raises(bbc.BbcError) as e:
         gpu_delta(ctx, bad, [0], [0], [1])
     assert e.value.status == bbc.EDUP
+
+
+def test_rejected_inputs_leave_shares(ctx):
+    """A rejected batch (repeated pair, repeated edge, bad id or state)
+    leaves the per-update shares untouched."""
+    g = synth.complete_graph(3, 3)
+    bad = synth.Graph(2, 2, np.array([0, 2, 3], np.int32), np.array([1, 1, 0], np.int32),
+                      np.array([1, 1, 1], np.int8), {})
+    for h, (uu, vv, ss) in ((g, ([0, 0], [1, 1], [1, -1])), (bad, ([0], [0], [1])), (g, ([0], [3], [1])),
+                            (g, ([0], [0], [2]))):
+        off, adj, sg = bbc.graph_tensors(h, DEV)
+        pu = torch.full((len(uu),), 7, dtype=torch.int64, device=DEV)
+        with pytest.raises(bbc.BbcError):
+            ctx.update_delta(off, adj, sg, h.n_v, torch.as_tensor(np.asarray(uu, np.int32), device=DEV),
+                             torch.as_tensor(np.asarray(vv, np.int32), device=DEV),
+                             torch.as_tensor(np.asarray(ss, np.int8), device=DEV), per_update=pu)
+        assert torch.all(pu == 7)
+
+
+@pytest.mark.parametrize("cap", [1, 2, 3, 0])
+def test_task_caps(ctx, cap):
+    """Updates whose pairs mode outgrows the task cap: the w list (about
+    1,100 entries, two 1,024-entry chunks) is cut into spans of whole chunks
+    against every x chunk, one span per task when the cap allows; cap 0 is
+    the default tiling.  Rows of u are sparser than the average U row, so
+    the pairs mode is the cheaper one."""
+    rng = np.random.default_rng(21)
+    n_u, n_v = 1500, 1300
+    dens = np.where(np.arange(n_u) < 40, 0.3, 0.75)
+    present = rng.random((n_u, n_v)) < dens[:, None]
+    uu, vv = np.nonzero(present)
+    g = synth.from_edges(n_u, n_v, uu, vv, np.where(rng.random(uu.size) < 0.3, -1, 1))
+    q = 40
+    bu = np.arange(q)
+    bv = rng.choice(n_v, q, replace=False)
+    bs = rng.choice([-1, 0, 1], size=q)
+    want = oracle.update_delta(g, bu, bv, bs)
+    ctx.set_update_task_cap(cap)
+    try:
+        assert gpu_delta(ctx, g, bu, bv, bs, shares=True) == want
+    finally:
+        ctx.set_update_task_cap(0)
+
+
+def test_task_cap_rejects_negative(ctx):
+    with pytest.raises(bbc.BbcError) as e:
+        ctx.set_update_task_cap(-1)
+    assert e.value.status == bbc.EINVAL

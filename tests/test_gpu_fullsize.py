@@ -114,6 +114,28 @@ def test_full_size_classes(ctx, bench_graph):
     assert sum(cls) == ctx.count(off, adj, ones, g.n_v)
 
 
+@pytest.mark.parametrize("side", ["u", "v"])
+def test_full_size_classes_elementwise(ctx, bench_graph, side):
+    """Each of the six classes at full size, pairs on U and on V, against
+    the oracle's stored class totals."""
+    g, total = bench_graph
+    e = EXPECTED[BENCH_KEY]
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    got = ctx.count_classes(off, adj, sg, g.n_v, opts=bbc.options(side=side))
+    assert got == [int(x) for x in e[f"classes_{side}"]]
+
+
+@pytest.mark.parametrize("k", [3, 4])
+@pytest.mark.parametrize("side", ["u", "v"])
+def test_full_size_bicliques_k(ctx, bench_graph, k, side):
+    """(2,3) and (2,4)-bicliques at full size, pairs on U and on V, against
+    the oracle's stored counts."""
+    g, total = bench_graph
+    e = EXPECTED[BENCH_KEY]
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    assert ctx.count_bicliques(off, adj, sg, g.n_v, k, opts=bbc.options(side=side)) == int(e[f"bicliques_k{k}_{side}"])
+
+
 def test_full_size_bicliques(ctx, bench_graph):
     """k = 2 is the oracle's total on both pair sides; k = 1 counts the
     wedges, sum of C(deg, 2) over the other side."""

@@ -555,7 +555,7 @@ def py_bicliques(g, k, side):
     balanced (an even number of negative edges)."""
     import itertools
 
-    su = side == oracle.SIDE_U or (side == oracle.SIDE_AUTO and g.n_u < g.n_v)
+    su = side != oracle.SIDE_V  # the size-two side is U unless V is named (BB2K)
     nbr = {}
     for u in range(g.n_u):
         for e in range(g.offsets[u], g.offsets[u + 1]):
@@ -584,6 +584,23 @@ def test_bicliques_walk_matches_definition():
                 assert oracle.count_bicliques(g, k, side) == want
                 if t < 40:
                     assert py_bicliques(g, k, side) == want
+
+
+def test_bicliques_auto_side_is_u():
+    """The BB2K section fixes U as the size-two side: the automatic choice
+    pairs U vertices even when U is the larger side.  On K_{2,5} (U smaller)
+    and K_{5,2} (U larger) the (2,3) count is C(|U|,2) C(|V|,3) (pairs on U),
+    never C(|V|,2) C(|U|,3)."""
+    from math import comb
+
+    for m, n in ((2, 5), (5, 2), (4, 6), (6, 4)):
+        g = synth.complete_graph(m, n)
+        want = comb(m, 2) * comb(n, 3)
+        assert oracle.count_bicliques(g, 3, oracle.SIDE_AUTO) == want
+        assert oracle.count_bicliques(g, 3, oracle.SIDE_U) == want
+        assert oracle.brute_bicliques(g, 3, oracle.SIDE_AUTO) == want
+        assert py_bicliques(g, 3, oracle.SIDE_AUTO) == want
+        assert oracle.count_bicliques(g, 3, oracle.SIDE_V) == comb(n, 2) * comb(m, 3)
 
 
 def test_bicliques_special_cases():
