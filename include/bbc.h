@@ -123,6 +123,20 @@ typedef struct {
      * 0, schedule is dynamic and no per-vertex output is asked for. */
     int32_t no_tuning;
     int32_t schedule; /* BBC_SCHED_*: how wedge-kernel workgroups take anchors */
+    /* Regimes of the wedge kernel (the paper's warp / block split of
+     * Algorithm 4).  An anchor with at most wave_max_work wedges, at most 63
+     * centres and fewer than 2^20 vertices ranked above it in its graph is
+     * counted by one wavefront in a hashed LDS table of its own, with no
+     * workgroup barrier; these anchors are taken 64 per queue pop.  Every
+     * other anchor takes a whole workgroup, queue_chunk anchors per pop (in
+     * descending work order).  wave_max_work: 0 = the kernel shape's largest
+     * (1024 for the default shape; half of the table a wavefront gets from
+     * the band, at most 2048 slots), -1 = no wave regime, larger values are
+     * clamped to that largest.  queue_chunk: 0 = 1, at most 65536.  Only
+     * bbc_count without per-vertex output and the batched calls use the wave
+     * regime.  The counts never depend on either. */
+    int32_t queue_chunk;
+    int32_t wave_max_work;
 } bbc_options;
 
 /* Fills *opts with the defaults: auto side, all checks, no timing. */

@@ -56,6 +56,8 @@ class Options(ctypes.Structure):
         ("blocks", ctypes.POINTER(DenseBlock)),
         ("no_tuning", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
+        ("queue_chunk", ctypes.c_int32),
+        ("wave_max_work", ctypes.c_int32),
     ]
 
 
@@ -121,6 +123,11 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() or "
                           f"python -m paper_2601_17707_amd.build")
+    # torch first: it brings its own HIP runtime, and the library must bind
+    # to that same runtime (loaded after it, its libamdhip64 resolves to the
+    # copy already in the process) rather than start a second one
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.bbc_options_init.argtypes = [ctypes.POINTER(Options)]
@@ -180,10 +187,13 @@ def status_string(status: int) -> str:
 
 
 def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0,
-            blocks=None, no_tuning=False, schedule="dynamic") -> Options:
+            blocks=None, no_tuning=False, schedule="dynamic", queue_chunk=0, wave_max_work=0) -> Options:
     """Options struct.  ``blocks``: list of (u_ids, v_ids) int32 device
     tensors naming dense blocks (kept alive by the returned object).
-    ``schedule``: "dynamic" (shared queue) or "static" (fixed deal)."""
+    ``schedule``: "dynamic" (shared queue) or "static" (fixed deal).
+    ``queue_chunk``: workgroup-regime anchors per queue pop (0 = 1);
+    ``wave_max_work``: wave-regime threshold in wedges (0 = the shape's
+    largest, -1 = no wave regime)."""
     o = Options()
     load_library().bbc_options_init(ctypes.byref(o))
     o.side = _SIDES[side]
@@ -194,6 +204,8 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
     o.wg_per_cu = wg_per_cu
     o.no_tuning = 1 if no_tuning else 0
     o.schedule = _SCHEDS[schedule]
+    o.queue_chunk = int(queue_chunk)
+    o.wave_max_work = int(wave_max_work)
     if blocks:
         arr = (DenseBlock * len(blocks))()
         for i, (uids, vids) in enumerate(blocks):

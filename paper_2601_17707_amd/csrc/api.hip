@@ -51,8 +51,8 @@ void launch_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, in
 void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
 void launch_work(const uint32_t* apack, const int32_t* acent, const int32_t* back, const uint32_t* coff, int64_t m,
-                 int64_t n_s, unsigned long long* work, uint32_t* key, DevStatus* st, const HybridView& hv,
-                 hipStream_t s);
+                 int64_t n_s, unsigned long long* work, uint32_t* key, const uint32_t* aoff, const int32_t* agraph,
+                 const int64_t* rank_end, uint32_t light_w, DevStatus* st, const HybridView& hv, hipStream_t s);
 void launch_block_mark(const DevBlock* blocks, int32_t n_blocks, int64_t max_ids, int32_t n_s, int32_t n_c,
                        uint32_t* agrp, int32_t* cblk, int32_t* cidx, DevStatus* st, hipStream_t s);
 void launch_block_cpos(const int32_t* cblk, int32_t n_c, const DevBlock* blocks, const uint32_t* coff,
@@ -91,7 +91,9 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   int32_t n_s, DevStatus* st, unsigned long long* pv, const uint32_t* inv, int64_t anchor_base,
                   int64_t centre_base, int64_t n_centre, const int32_t* agraph, const int64_t* rank_end,
                   unsigned long long* gtotals, const HybridView& hv, int kind, int32_t bic_k,
-                  const unsigned long long* bic_tab, int sched, hipStream_t s);
+                  const unsigned long long* bic_tab, int sched, int32_t queue_chunk, int32_t light_chunk,
+                  hipStream_t s);
+int wedge_light_max(int band_words, int wg);
 int wedge_bic_blocks_per_cu();
 void launch_choose_table(int32_t k, unsigned long long* tab, hipStream_t s);
 
@@ -105,6 +107,7 @@ __global__ void k_status_init(DevStatus* st) {
         st->walked = 0;
         st->bands = 0;
         st->queue = 0;
+        st->n_light = 0;
     }
 }
 // One entry of the tuning table: the fastest wedge-kernel shape measured
@@ -208,6 +211,9 @@ struct Job {
     int band_words = 0, wg_size = 0, grid = 0;
     int schedule = BBC_SCHED_DYNAMIC;
     bool tuned = false;  // shape taken from the tuning table
+    int32_t queue_chunk = 1;    // workgroup-regime anchors per queue pop
+    int32_t light_w = 0;        // wave regime: anchors with at most this many wedges (0: none)
+    int32_t light_chunk = 64;   // wave-regime anchors per queue pop
     bool classes = false;  // the six sign-pattern classes instead of the total
     int32_t bic_k = 0;     // > 0: balanced (2,k)-bicliques instead of the total
     // dense blocks (single graph only)
@@ -400,7 +406,8 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     }
 
     // schedule: anchors by descending work
-    launch_work(P.apack, P.acent, P.back, P.coff, m, n_s, P.work, P.wkey, st, hv, s);
+    launch_work(P.apack, P.acent, P.back, P.coff, m, n_s, P.work, P.wkey, P.aoff, J.batched ? P.agraph : nullptr,
+                J.batched ? P.rank_end : nullptr, (uint32_t)J.light_w, st, hv, s);
     const uint32_t *ok = nullptr, *order = nullptr;
     radix_sort(P.wkey, P.ord_a, P.ord_b, nullptr, nullptr, nullptr, nullptr, P.ord_va, P.ord_vb, n_s, 32, P.hist,
                P.hist_scan, P.partials, s, &ok, nullptr, &order);
@@ -421,7 +428,7 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
                      J.batched ? P.agraph : nullptr, J.batched ? P.rank_end : nullptr,
                      J.batched ? J.totals : nullptr, hv,
                      J.classes ? kWedgeClasses : J.bic_k > 0 ? kWedgeBicliques : kWedgeCount, J.bic_k, P.bic_tab,
-                     J.schedule, s);
+                     J.schedule, J.queue_chunk, J.light_chunk, s);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
@@ -455,7 +462,16 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
     if (o->schedule != BBC_SCHED_DYNAMIC && o->schedule != BBC_SCHED_STATIC)
         return fail(ctx, BBC_EINVAL, "bad schedule option");
     if (o->n_blocks < 0 || (o->n_blocks > 0 && !o->blocks)) return fail(ctx, BBC_EINVAL, "bad dense block list");
+    if (o->queue_chunk < 0 || o->queue_chunk > 65536) return fail(ctx, BBC_EINVAL, "queue_chunk outside [0, 65536]");
+    if (o->wave_max_work < -1) return fail(ctx, BBC_EINVAL, "wave_max_work below -1");
     return BBC_OK;
+}
+
+// Regime knobs of a count-mode job (no wave regime with per-vertex output).
+void set_regimes(Job& J, const bbc_options& o, bool full) {
+    J.queue_chunk = o.queue_chunk > 0 ? o.queue_chunk : 1;
+    const int lmax = wedge_light_max(o.band_words, o.wg_size);
+    J.light_w = (full || o.wave_max_work < 0) ? 0 : o.wave_max_work == 0 ? lmax : std::min(o.wave_max_work, lmax);
 }
 
 bool side_is_u(int side, int32_t n_u, int32_t n_v) { return side == BBC_SIDE_U || (side == BBC_SIDE_AUTO && n_u < n_v); }
@@ -576,6 +592,7 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
     J.band_words = o.band_words;
     J.schedule = o.schedule;
     J.wg_size = o.wg_size;
+    set_regimes(J, o, false);
     J.grid = ctx->n_cu * (o.wg_per_cu > 0 ? o.wg_per_cu : wedge_blocks_per_cu(o.band_words, o.wg_size, false));
     return BBC_OK;
 }
@@ -871,6 +888,7 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
     J.band_words = opts.band_words;
     J.schedule = opts.schedule;
     J.wg_size = opts.wg_size;
+    set_regimes(J, opts, full);
     J.grid = ctx->n_cu *
              (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
     std::vector<DevBlock> db;

@@ -24,7 +24,7 @@ struct DevStatus {
     unsigned long long bands;   // counter bands processed
     unsigned long long cls[6];  // sign-pattern classes (class mode); biclique limbs and overflows
     unsigned int queue;         // persistent work queue head
-    unsigned int pad1;
+    unsigned int n_light;       // anchors of the wave regime (listed after every other anchor)
 };
 
 enum : int32_t {
@@ -41,6 +41,15 @@ enum : int32_t {
 // What the wedge kernel sums: the balanced count, the six sign-pattern
 // classes, or balanced (2,k)-bicliques.
 enum : int { kWedgeCount = 0, kWedgeClasses = 1, kWedgeBicliques = 2 };
+
+// Wave regime of the wedge kernel: an anchor with at most kLightMaxWork
+// wedges, at most kLightMaxDeg centres and fewer than 2^kLightKeyBits ranks
+// above it in its graph is counted by one wave in a hashed LDS table of its
+// own (20-bit endpoint key, two 6-bit counters per slot).  Such anchors are
+// listed after all others; the rest take a whole workgroup each.
+constexpr int kLightMaxDeg = 63;
+constexpr int kLightKeyBits = 20;
+constexpr int kLightMaxWork = 1024;
 
 // Band-boundary index: meta.x of a centre list that has no index entries.
 constexpr int32_t kBidxNone = INT32_MIN;

@@ -293,11 +293,34 @@ __global__ __launch_bounds__(256) void k_work(const uint32_t* apack, const int32
 // Sort key of each anchor: the bitwise complement of its clamped work, so an
 // ascending sort orders anchors by descending work (heavy anchors start
 // first, as in the fanout ordering of Algorithm 4).
-__global__ void k_work_keys(const unsigned long long* work, int64_t n_s, uint32_t* key) {
+// Sort keys of the schedule (ascending): anchors of the workgroup regime by
+// descending work in [0, 2^31), then the wave regime (light anchors, see
+// kLightMaxWork) in [2^31, 2^32): a batch keeps each graph's light anchors
+// together (key = graph), a single graph orders them by descending work.
+// light_w = 0 puts every anchor in the workgroup regime.  st->n_light
+// receives the number of light anchors (one atomic per workgroup).
+__global__ __launch_bounds__(256) void k_work_keys(const unsigned long long* work, int64_t n_s, uint32_t* key,
+                                                   const uint32_t* aoff, const int32_t* agraph,
+                                                   const int64_t* rank_end, const uint32_t* ablk1, uint32_t light_w,
+                                                   DevStatus* st) {
+    __shared__ unsigned long long red[256 / kWave];
+    unsigned long long n_light = 0;
     GRID_STRIDE(r, n_s) {
         const unsigned long long w = work[r];
-        key[r] = ~(w > 0xffffffffull ? 0xffffffffu : (uint32_t)w);
+        const uint32_t deg = aoff[r + 1] - aoff[r];
+        const int64_t n_end = agraph ? rank_end[agraph[r] + 1] : n_s;
+        const bool light = light_w > 0 && w <= light_w && deg <= (uint32_t)kLightMaxDeg && n_end - r <= (1ll << kLightKeyBits) &&
+                           !(ablk1 && ablk1[r]);
+        const uint32_t wc = w > 0x7fffffffull ? 0x7fffffffu : (uint32_t)w;
+        if (light) {
+            key[r] = 0x80000000u | (agraph ? (uint32_t)agraph[r] : 0x7fffffffu - wc);
+            ++n_light;
+        } else {
+            key[r] = 0x7fffffffu - wc;
+        }
     }
+    n_light = block_sum<256>(n_light, red);
+    if (threadIdx.x == 0 && n_light) atomicAdd(&st->n_light, (unsigned int)n_light);
 }
 
 // ------------------------------------------------------ band-boundary index
@@ -455,14 +478,15 @@ void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, D
 }
 
 void launch_work(const uint32_t* apack, const int32_t* acent, const int32_t* back, const uint32_t* coff, int64_t m,
-                 int64_t n_s, unsigned long long* work, uint32_t* key, DevStatus* st, const HybridView& hv,
-                 hipStream_t s) {
+                 int64_t n_s, unsigned long long* work, uint32_t* key, const uint32_t* aoff, const int32_t* agraph,
+                 const int64_t* rank_end, uint32_t light_w, DevStatus* st, const HybridView& hv, hipStream_t s) {
     if (n_s <= 0) return;
     fill_bytes(work, n_s * 8, s);
     if (m > 0)
         hipLaunchKernelGGL(k_work, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, apack, acent, back, coff, m, work,
                            st, hv);
-    hipLaunchKernelGGL(k_work_keys, dim3(grid_for(n_s, 256)), dim3(256), 0, s, work, n_s, key);
+    hipLaunchKernelGGL(k_work_keys, dim3(grid_for(n_s, 256)), dim3(256), 0, s, work, n_s, key, aoff, agraph,
+                       rank_end, hv.ablk1, light_w, st);
 }
 
 void launch_bidx(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int64_t n_c, int gs,

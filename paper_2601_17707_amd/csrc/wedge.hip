@@ -39,6 +39,7 @@
 // halved at the end.  No endpoint count is ever scattered.
 #include "bbc_internal.h"
 
+
 namespace bbc {
 
 // First position q in [lo, hi) of a rank-sorted list with rank(q) >= target
@@ -1152,6 +1153,114 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
     return acc;
 }
 
+// ------------------------------------------------------------ wave regime
+//
+// Light anchors (at most kLightMaxWork wedges and kLightMaxDeg centres; the
+// paper's warp regime, Algorithm 4) are counted by one wave each, with no
+// workgroup barrier: the wave's share of the counter band becomes a hashed
+// table of TW slots, a slot holding the endpoint key (rank - anchor rank,
+// 20 bits) above its two 6-bit counters (agree, disagree; both <= degree).
+// An anchor has at most TW / 2 wedges, so the table is never more than half
+// full and a linear probe always ends.  The pair terms are summed while
+// counting: raising a counter from x to x + 1 adds C(x+1,2) - C(x,2) = x, so
+// the value an increment returns is its share and no reduction pass is
+// needed; the table is then cleared.
+
+// Slot of `key` for wedge type t: claims an empty slot or increments the
+// key's counter; returns the counter's value before the increment.
+template <int TW>
+__device__ __forceinline__ uint32_t light_insert(uint32_t* __restrict__ tab, uint32_t key, uint32_t t) {
+    constexpr int kBits = ilog2(TW);
+    const uint32_t sh = 6u * t;
+    const uint32_t inc = 1u << sh;
+    uint32_t h = (key * 0x9E3779B1u) >> (32 - kBits);
+    for (;;) {
+        const uint32_t old = atomicCAS(&tab[h], 0u, (key << 12) | inc);
+        if (old == 0u) return 0u;
+        if ((old >> 12) == key) return (atomicAdd(&tab[h], inc) >> sh) & 63u;
+        h = (h + 1u) & (uint32_t)(TW - 1);
+    }
+}
+
+// Rows of 64 wedges loaded together by the wave regime.
+constexpr int kLightRows = 4;
+
+// Twice the pair terms of light anchor r, summed over the wave's lanes
+// (each lane returns its share).  cpre / cst: this wave's 64-entry slices
+// of LDS for the prefix of the slice lengths and the slice starts | sign.
+template <int TW>
+__device__ __forceinline__ uint32_t light_anchor(uint32_t* __restrict__ tab, int32_t* __restrict__ cpre,
+                                                 uint32_t* __restrict__ cst, const uint32_t* __restrict__ aoff,
+                                                 const int32_t* __restrict__ acent, const uint8_t* __restrict__ aneg,
+                                                 const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
+                                                 const uint32_t* __restrict__ packed, int32_t r) {
+    const int lane = lane_id();
+    const int32_t a0 = (int32_t)aoff[r];
+    const int32_t deg = (int32_t)aoff[r + 1] - a0;
+    if (deg < 2) return 0u;
+    // slice of centre `lane`: the suffix of its list above the anchor
+    int32_t len = 0;
+    uint32_t stv = 0;
+    if (lane < deg) {
+        const int32_t p = a0 + lane;
+        const uint32_t s0 = (uint32_t)back[p] + 1u;
+        len = (int32_t)(coff[acent[p] + 1] - s0);
+        stv = s0 | ((uint32_t)aneg[p] << 31);
+    }
+    const int32_t inc = wave_inclusive_scan(len);
+    const int32_t total = __shfl(inc, kWave - 1, kWave);
+    if (total < 2) return 0u;
+    if (lane < deg) {
+        cpre[lane] = inc - len;
+        cst[lane] = stv;
+    }
+    if (lane == 0) cpre[deg] = total;
+    __builtin_amdgcn_wave_barrier();
+    // per-lane cursor on the slice holding its wedge
+    int32_t k = 0, cb = 0, nb = cpre[1];
+    uint32_t cs = cst[0];
+    uint32_t acc = 0;  // at most kLightMaxWork increments of at most 63
+    for (int32_t j0 = 0; j0 < total; j0 += kWave * kLightRows) {
+        uint32_t x[kLightRows];
+        uint32_t ngm = 0, vm = 0;
+#pragma unroll
+        for (int u = 0; u < kLightRows; ++u) {
+            const int32_t j = j0 + u * kWave + lane;
+            x[u] = 0u;
+            if (j < total) {
+                while (j >= nb) {
+                    ++k;
+                    cb = nb;
+                    nb = cpre[k + 1];
+                    cs = cst[k];
+                }
+                x[u] = packed[(cs & 0x7fffffffu) + (uint32_t)(j - cb)];
+                ngm |= (cs >> 31) << u;
+                vm |= 1u << u;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kLightRows; ++u)
+            if ((vm >> u) & 1u)
+                acc += light_insert<TW>(tab, (x[u] >> 1) - (uint32_t)r, (x[u] ^ (ngm >> u)) & 1u);
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint4* t4 = reinterpret_cast<uint4*>(tab);
+    for (int i = lane; i < TW / 4; i += kWave) t4[i] = uint4{0u, 0u, 0u, 0u};
+    __builtin_amdgcn_wave_barrier();
+    return 2u * acc;
+}
+
+// How the persistent workgroups take work: positions [0, n_s - n_light) of
+// the schedule one anchor each (workgroup regime), queue_chunk anchors per
+// pop; the light positions after them light_chunk anchors per pop, dealt
+// to the waves of the workgroup.
+struct SchedArgs {
+    int32_t statik;       // nonzero: fixed deal of the tasks instead of the queue
+    int32_t queue_chunk;  // >= 1
+    int32_t light_chunk;  // >= 1
+};
+
 // Batched launches pass agraph (graph of each rank), rank_end (first rank of
 // each graph, n_graphs + 1 entries) and per-graph totals; an anchor's
 // endpoints then stop at the end of its graph's rank range.
@@ -1170,7 +1279,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
                                               const int32_t* __restrict__ agraph,
                                               const int64_t* __restrict__ rank_end,
                                               unsigned long long* __restrict__ gtotals, HybridView hv, BicView bv,
-                                              int32_t sched_static) {
+                                              SchedArgs sc) {
     if (*(volatile const int32_t*)&st->flags) return;  // input error: nothing to count
     __shared__ WedgeShared<WG, BAND_WORDS, FULL> sh;
     const int tid = threadIdx.x;
@@ -1179,25 +1288,24 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     if (BIC && tid < 16) sh.ctab[tid] = (uint32_t)bv.tab[2 * tid];
     unsigned long long acc = 0, bands = 0;
     ClassSums cs;
-    uint32_t snext = blockIdx.x;  // static deal: positions b, b + grid, b + 2 grid, ... (< 2^31 + grid)
-    for (;;) {
-        __syncthreads();
-        uint32_t task;
-        if (sched_static) {
-            task = snext;
-            snext += gridDim.x;
-        } else {  // dynamic: the next position of the shared queue
-            if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
-            __syncthreads();
-            task = (uint32_t)sh.task;
-        }
-        if (task >= (uint32_t)n_s) break;
-        const int32_t r = (int32_t)order[task];
+    constexpr bool kLight = !FULL && !CLS && !BIC;
+    constexpr int NW = WG / kWave;
+    constexpr int TW = BAND_WORDS / NW < 2048 ? BAND_WORDS / NW : 2048;  // light table slots per wave
+    const uint32_t n_light = kLight ? *(volatile const uint32_t*)&st->n_light : 0u;
+    const uint32_t n_heavy = (uint32_t)n_s - n_light;
+    // 32-bit task arithmetic: n_s < 2^31 and both chunks are at most 2^16
+    const uint32_t qc = (uint32_t)sc.queue_chunk, lc = (uint32_t)sc.light_chunk;
+    const uint32_t heavy_tasks = (n_heavy + qc - 1) / qc;
+    const uint32_t n_tasks = heavy_tasks + (n_light + lc - 1) / lc;
+
+    // one anchor of the workgroup regime (schedule position pos)
+    auto heavy = [&](uint32_t pos) {
+        const int32_t r = (int32_t)order[pos];
         const int32_t a0 = (int32_t)aoff[r], deg = (int32_t)aoff[r + 1] - a0;
         const int64_t n_end = agraph ? rank_end[agraph[r] + 1] : (int64_t)n_s;
         // fewer than two centres (k in biclique mode): no endpoint pair
         // shares enough wedges
-        if (deg < (BIC ? bv.k : 2) || (!FULL && r >= n_end - 1)) continue;
+        if (deg < (BIC ? bv.k : 2) || (!FULL && r >= n_end - 1)) return;
         constexpr int M0 = CLS ? 4 : 0;  // counter mode of degree class 0; classes use modes 4-7
         unsigned long long a;
         if (deg <= 15)
@@ -1220,6 +1328,57 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             if (tid == 0 && s) atomicAdd(&gtotals[agraph[r]], s >> 1);  // twice the pair terms
         }
         acc += a;
+    };
+
+    uint32_t snext = blockIdx.x;  // static deal: tasks b, b + grid, b + 2 grid, ... (< 2^32)
+    for (;;) {
+        __syncthreads();
+        uint32_t task;
+        if (sc.statik) {
+            task = snext;
+            snext += gridDim.x;
+        } else {  // dynamic: the next task of the shared queue
+            if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
+            __syncthreads();
+            task = (uint32_t)sh.task;
+        }
+        if (task >= n_tasks) break;
+        if (task < heavy_tasks) {
+            const uint32_t p1 = min(n_heavy, (task + 1) * qc);
+            for (uint32_t pos = task * qc; pos < p1; ++pos) {
+                if (pos > task * qc) __syncthreads();
+                heavy((uint32_t)pos);
+            }
+        } else if constexpr (kLight) {
+            // a chunk of light anchors, dealt round robin to the waves
+            const int wave = tid / kWave;
+            uint32_t* tab = sh.cnt + wave * TW;
+            int32_t* cpre = sh.tab[1].pre + wave * kWave;
+            uint32_t* cst = sh.tab[1].start + wave * kWave;
+            const uint32_t p0 = n_heavy + (task - heavy_tasks) * lc;
+            const uint32_t p1 = min((uint32_t)n_s, p0 + lc);
+            int32_t g_cur = -1;
+            uint32_t g_acc = 0;  // this lane's share of the current graph's total (batches)
+            for (uint32_t pos = p0 + wave; pos < p1; pos += NW) {
+                const int32_t r = (int32_t)order[pos];
+                if (gtotals) {
+                    const int32_t g = agraph[r];
+                    if (g != g_cur) {
+                        const uint32_t t = wave_sum(g_acc);
+                        if (lane_id() == 0 && t && g_cur >= 0) atomicAdd(&gtotals[g_cur], (unsigned long long)(t >> 1));
+                        g_cur = g;
+                        g_acc = 0;
+                    }
+                }
+                const uint32_t a = light_anchor<TW>(tab, cpre, cst, aoff, acent, aneg, back, coff, packed, r);
+                acc += a;
+                g_acc += a;
+            }
+            if (gtotals) {
+                const unsigned long long t = wave_sum((unsigned long long)g_acc);
+                if (lane_id() == 0 && t && g_cur >= 0) atomicAdd(&gtotals[g_cur], t >> 1);
+            }
+        }
     }
     acc = wave_sum(acc);
     if (lane_id() == 0 && acc) atomicAdd(&st->total, acc);
@@ -1263,14 +1422,14 @@ struct WedgeArgs {
     unsigned long long* gtotals;
     HybridView hv;
     BicView bv;
-    int32_t sched_static;
+    SchedArgs sc;
 };
 
 template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
 static void launch_shape(const WedgeArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS, BIC>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back,
                        a.coff, a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base,
-                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv, a.sched_static);
+                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv, a.sc);
 }
 
 template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
@@ -1314,6 +1473,16 @@ int wedge_band(int band_words, int wg, bool full) {
 
 int wedge_shape_count() { return (int)(sizeof(kShapes) / sizeof(kShapes[0])); }
 
+// Largest wedge count of a light anchor for a count-mode shape: half the
+// hashed table each wave carves from the band (at most 2048 slots).
+int wedge_light_max(int band_words, int wg) {
+    const int i = shape_index(band_words, wg);
+    if (i < 0) return 0;
+    int tw = kShapes[i].band_words / (kShapes[i].wg / kWave);
+    if (tw > 2048) tw = 2048;
+    return tw / 2;
+}
+
 void wedge_shape(int i, int* wg, int* band_words) {
     *wg = kShapes[i].wg;
     *band_words = kShapes[i].band_words;
@@ -1340,11 +1509,13 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                   const int2* bmeta, const uint32_t* order, int32_t n_s, DevStatus* st, unsigned long long* pv,
                   const uint32_t* inv, int64_t anchor_base, int64_t centre_base, int64_t n_centre,
                   const int32_t* agraph, const int64_t* rank_end, unsigned long long* gtotals, const HybridView& hv,
-                  int kind, int32_t bic_k, const unsigned long long* bic_tab, int sched, hipStream_t s) {
+                  int kind, int32_t bic_k, const unsigned long long* bic_tab, int sched, int32_t queue_chunk,
+                  int32_t light_chunk, hipStream_t s) {
     const WedgeArgs a{aoff,        acent,       aneg,   back,     coff,    packed, bidx,
                       bmeta,       order,       n_s,    st,       pv,      inv,    anchor_base,
                       centre_base, agraph,      rank_end, gtotals, hv,     BicView{bic_k, bic_tab},
-                      sched == 1 ? 1 : 0};
+                      SchedArgs{sched == 1 ? 1 : 0, queue_chunk > 0 ? queue_chunk : 1,
+                                light_chunk > 0 ? light_chunk : 1}};
     if (pv) {
         launch_shape<kFullWG, kFullBW, true>(a, grid, s);
         if (n_centre > 0) {
