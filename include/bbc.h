@@ -172,6 +172,29 @@ bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, co
                      const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
                      const bbc_options* opts, void* stream);
 
+/* Allocation-free variant of bbc_count, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid allocation.  Arguments, results, errors and
+ * synchronisation are those of bbc_count, except:
+ *   - the call allocates nothing (no hipMalloc / hipFree, no allocating
+ *     library routine).  Its scratch is a fixed device array of
+ *     BBC_NOALLOC_SCRATCH_BYTES bytes, one per GPU, held from the library's
+ *     first bbc_create on that GPU until the process ends;
+ *   - a graph whose scratch would exceed that size is rejected with
+ *     BBC_ETOOBIG, and bbc_last_error gives the bytes it needs (41 bytes
+ *     per edge, 60 per anchor-side and 24 per centre-side vertex, plus
+ *     sort histograms; 64 MiB holds about 1.3M edges);
+ *   - dense blocks are not accepted (BBC_EINVAL);
+ *   - every call on one GPU shares that GPU's array, whose contents persist
+ *     from call to call: calls that overlap on one GPU (several streams,
+ *     threads or contexts) race and must be serialised by the caller.
+ * The context (created beforehand, which may allocate) supplies the status
+ * word, pinned result memory and the tuning table. */
+#define BBC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+bbc_status bbc_count_noalloc(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                             const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
+                             const bbc_options* opts, void* stream);
+
 /* One graph of a batch.  Its offsets are local (offsets[0] = 0, n_u + 1
  * entries starting at offsets_cat[off_base]); its edges are adj_cat /
  * signs_cat[edge_base .. edge_base + n_edges).  Graphs may sit anywhere in

@@ -139,6 +139,8 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_count.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64), vp,
                               ctypes.POINTER(Options), vp]
     lib.bbc_count.restype = ctypes.c_int
+    lib.bbc_count_noalloc.argtypes = lib.bbc_count.argtypes
+    lib.bbc_count_noalloc.restype = ctypes.c_int
     PD = ctypes.POINTER(GraphDesc)
     lib.bbc_count_batched.argtypes = [vp, i32, PD, vp, vp, vp, vp, ctypes.POINTER(Options), vp]
     lib.bbc_count_batched.restype = ctypes.c_int
@@ -309,6 +311,30 @@ class Context:
         o = opts if opts is not None else options()
         st = self._lib.bbc_count(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj), _ptr(signs), ctypes.byref(out),
                 _ptr(per_vertex) if per_vertex is not None else None, ctypes.byref(o), sp)
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return int(out.value)
+
+    def count_noalloc(self, offsets, adj, signs, n_v: int, per_vertex=None, opts: Options | None = None,
+                      stream=None) -> int:
+        """As count(), through bbc_count_noalloc: the library allocates nothing
+        (its scratch is a fixed per-GPU array; larger graphs raise ETOOBIG)."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        n_u = offsets.numel() - 1
+        if per_vertex is not None:
+            _check_tensor("per_vertex", per_vertex, torch.int64, torch)
+            if per_vertex.numel() != n_u + n_v:
+                raise ValueError("per_vertex must hold n_u + n_v entries")
+        sp = _stream_ptr(stream, offsets)
+        out = ctypes.c_uint64(0)
+        o = opts if opts is not None else options()
+        st = self._lib.bbc_count_noalloc(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj), _ptr(signs),
+                                         ctypes.byref(out), _ptr(per_vertex) if per_vertex is not None else None,
+                                         ctypes.byref(o), sp)
         if st != OK:
             raise BbcError(st, self.last_error())
         return int(out.value)

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -134,6 +135,8 @@ struct bbc_ctx {
     std::string err;
     std::vector<TuneEntry> tune;
     int32_t update_task_cap = 0;  // bbc_update_delta: tasks per update (0: 4096)
+    char* fixed = nullptr;        // device address of this device's fixed scratch (bbc_count_noalloc)
+    hipError_t fixed_err = hipSuccess;
 };
 
 struct bbc_batch_plan {
@@ -144,6 +147,37 @@ struct bbc_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+// Fixed scratch of bbc_count_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never uses the array's
+// name as an address (it names a host-side stand-in): the device address
+// comes from hipGetSymbolAddress, looked up once per device with that device
+// current, and only that address reaches kernels.
+constexpr size_t kFixedScratchBytes = BBC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kFixedScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+char* g_fixed_ptr[kMaxDevices] = {};
+
+// Device address of the fixed scratch on `device`, which must be current.
+hipError_t fixed_scratch(int device, char** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    if (!g_fixed_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_fixed_ptr[device] = static_cast<char*>(p);
+    }
+    *out = g_fixed_ptr[device];
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -754,6 +788,75 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
     return run_planned(ctx, J, ctx->arena, opts, s, dg, vstart, rend, db, dt);
 }
 
+// bbc_count and bbc_count_noalloc: the same pipeline, its buffers carved
+// from the context's arena (grown on demand) or from the device's fixed
+// scratch (no allocation; sizes beyond it are rejected).
+bbc_status count_single(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                        const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
+                        const bbc_options* opts_in, void* stream, bool fixed) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    bbc_options opts;
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
+    if (!total) return fail(ctx, BBC_EINVAL, "total is NULL");
+    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+    if (fixed) {
+        if (opts.n_blocks > 0) return fail(ctx, BBC_EINVAL, "bbc_count_noalloc takes no dense blocks");
+        if (!ctx->fixed) return hip_fail(ctx, ctx->fixed_err, "fixed scratch lookup (hipGetSymbolAddress)");
+    }
+
+    DeviceGuard guard(ctx->device);
+    Job J;
+    J.off = offsets;
+    J.adj = adj;
+    J.sg = signs;
+    J.n_u = n_u;
+    J.n_v = n_v;
+    rc = resolve_side(ctx, opts.side, n_u, n_v, n_edges, offsets, adj, (hipStream_t)stream, &J.s_is_u,
+                      fixed ? ctx->fixed : nullptr, fixed ? kFixedScratchBytes : 0);
+    if (rc != BBC_OK) return rc;
+    J.pv = (unsigned long long*)per_vertex;
+    J.m = n_edges;
+    J.n_s = J.s_is_u ? n_u : n_v;
+    J.n_c = J.s_is_u ? n_v : n_u;
+    J.checks = opts.checks;
+    const bool full = per_vertex != nullptr;
+    J.tuned = apply_tuning(ctx, opts, J.n_s, n_edges, full);
+    J.band_words = opts.band_words;
+    J.schedule = opts.schedule;
+    J.wg_size = opts.wg_size;
+    set_regimes(J, opts, full);
+    J.grid = ctx->n_cu *
+             (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
+    std::vector<DevBlock> db;
+    std::vector<DevTile> dt;
+    if (opts.n_blocks > 0) {
+        if (full) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with per-vertex counts");
+        rc = block_job(ctx, opts, J, db, dt);
+        if (rc != BBC_OK) return rc;
+    }
+    if (fixed) {
+        Plan P;
+        const size_t need = P.carve(nullptr, J);
+        if (need > kFixedScratchBytes)
+            return fail(ctx, BBC_ETOOBIG, "bbc_count_noalloc: the graph needs " + std::to_string(need) +
+                                              " bytes of scratch, the fixed scratch holds " +
+                                              std::to_string(kFixedScratchBytes));
+        rc = run_planned(ctx, J, ctx->fixed, opts, (hipStream_t)stream, nullptr, nullptr, nullptr, nullptr, nullptr);
+    } else {
+        rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr, &db, &dt);
+    }
+    if (rc != BBC_OK) return rc;
+    // the kernels sum twice the pair terms (per-vertex mode: every anchor's
+    // pairs, seen from both ends)
+    *total = (uint64_t)ctx->st_host->total / 2;
+    return BBC_OK;
+}
+
 }  // namespace
 
 // Temporary device memory of one planner call, freed on every return path.
@@ -831,6 +934,10 @@ bbc_status bbc_create(int device, bbc_ctx** out) {
             bbc_destroy(ctx);
             return BBC_EDEVICE;
         }
+    // the fixed scratch of bbc_count_noalloc; a failure is reported by that
+    // entry point, the others do not need it
+    ctx->fixed_err = fixed_scratch(device, &ctx->fixed);
+    if (ctx->fixed_err != hipSuccess) (void)hipGetLastError();
     *out = ctx;
     return BBC_OK;
 }
@@ -858,52 +965,13 @@ bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out) {
 bbc_status bbc_count(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                      const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
                      const bbc_options* opts_in, void* stream) {
-    if (!ctx) return BBC_EINVAL;
-    ctx->err.clear();
-    bbc_options opts;
-    bbc_status rc = read_options(ctx, opts_in, &opts);
-    if (rc != BBC_OK) return rc;
-    if (!total) return fail(ctx, BBC_EINVAL, "total is NULL");
-    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
-    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
-        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
-    if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+    return count_single(ctx, n_u, n_v, n_edges, offsets, adj, signs, total, per_vertex, opts_in, stream, false);
+}
 
-    DeviceGuard guard(ctx->device);
-    Job J;
-    J.off = offsets;
-    J.adj = adj;
-    J.sg = signs;
-    J.n_u = n_u;
-    J.n_v = n_v;
-    rc = resolve_side(ctx, opts.side, n_u, n_v, n_edges, offsets, adj, (hipStream_t)stream, &J.s_is_u);
-    if (rc != BBC_OK) return rc;
-    J.pv = (unsigned long long*)per_vertex;
-    J.m = n_edges;
-    J.n_s = J.s_is_u ? n_u : n_v;
-    J.n_c = J.s_is_u ? n_v : n_u;
-    J.checks = opts.checks;
-    const bool full = per_vertex != nullptr;
-    J.tuned = apply_tuning(ctx, opts, J.n_s, n_edges, full);
-    J.band_words = opts.band_words;
-    J.schedule = opts.schedule;
-    J.wg_size = opts.wg_size;
-    set_regimes(J, opts, full);
-    J.grid = ctx->n_cu *
-             (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_blocks_per_cu(opts.band_words, opts.wg_size, full));
-    std::vector<DevBlock> db;
-    std::vector<DevTile> dt;
-    if (opts.n_blocks > 0) {
-        if (full) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with per-vertex counts");
-        rc = block_job(ctx, opts, J, db, dt);
-        if (rc != BBC_OK) return rc;
-    }
-    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr, &db, &dt);
-    if (rc != BBC_OK) return rc;
-    // the kernels sum twice the pair terms (per-vertex mode: every anchor's
-    // pairs, seen from both ends)
-    *total = (uint64_t)ctx->st_host->total / 2;
-    return BBC_OK;
+bbc_status bbc_count_noalloc(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                             const int32_t* adj, const int8_t* signs, uint64_t* total, uint64_t* per_vertex,
+                             const bbc_options* opts_in, void* stream) {
+    return count_single(ctx, n_u, n_v, n_edges, offsets, adj, signs, total, per_vertex, opts_in, stream, true);
 }
 
 bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
