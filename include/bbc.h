@@ -137,6 +137,11 @@ typedef struct {
      * regime.  The counts never depend on either. */
     int32_t queue_chunk;
     int32_t wave_max_work;
+    /* Largest scratch, in bytes, the call may need (the context's arena, or
+     * a batch plan's own); a call that needs more fails with BBC_ENOMEM
+     * before any work, its outputs and the arena untouched, and the context
+     * stays usable.  0 = no limit. */
+    int64_t scratch_limit;
 } bbc_options;
 
 /* Fills *opts with the defaults: auto side, all checks, no timing. */

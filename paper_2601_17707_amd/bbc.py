@@ -58,6 +58,7 @@ class Options(ctypes.Structure):
         ("schedule", ctypes.c_int32),
         ("queue_chunk", ctypes.c_int32),
         ("wave_max_work", ctypes.c_int32),
+        ("scratch_limit", ctypes.c_int64),
     ]
 
 
@@ -189,13 +190,15 @@ def status_string(status: int) -> str:
 
 
 def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0,
-            blocks=None, no_tuning=False, schedule="dynamic", queue_chunk=0, wave_max_work=0) -> Options:
+            blocks=None, no_tuning=False, schedule="dynamic", queue_chunk=0, wave_max_work=0,
+            scratch_limit=0) -> Options:
     """Options struct.  ``blocks``: list of (u_ids, v_ids) int32 device
     tensors naming dense blocks (kept alive by the returned object).
     ``schedule``: "dynamic" (shared queue) or "static" (fixed deal).
     ``queue_chunk``: workgroup-regime anchors per queue pop (0 = 1);
     ``wave_max_work``: wave-regime threshold in wedges (0 = the shape's
-    largest, -1 = no wave regime)."""
+    largest, -1 = no wave regime); ``scratch_limit``: bytes of scratch the
+    call may need (0 = no limit; beyond it the call fails with ENOMEM)."""
     o = Options()
     load_library().bbc_options_init(ctypes.byref(o))
     o.side = _SIDES[side]
@@ -208,6 +211,7 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
     o.schedule = _SCHEDS[schedule]
     o.queue_chunk = int(queue_chunk)
     o.wave_max_work = int(wave_max_work)
+    o.scratch_limit = int(scratch_limit)
     if blocks:
         arr = (DenseBlock * len(blocks))()
         for i, (uids, vids) in enumerate(blocks):

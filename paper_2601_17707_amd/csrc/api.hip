@@ -135,6 +135,7 @@ struct bbc_ctx {
     std::string err;
     std::vector<TuneEntry> tune;
     int32_t update_task_cap = 0;  // bbc_update_delta: tasks per update (0: 4096)
+    int64_t limit = 0;            // scratch_limit of the call in progress (0: none)
     char* fixed = nullptr;        // device address of this device's fixed scratch (bbc_count_noalloc)
     hipError_t fixed_err = hipSuccess;
 };
@@ -467,6 +468,9 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
 }
 
 bbc_status grow(bbc_ctx* ctx, char** arena, size_t* have, size_t bytes) {
+    if (ctx->limit > 0 && bytes > (size_t)ctx->limit)
+        return fail(ctx, BBC_ENOMEM, "the call needs " + std::to_string(bytes) + " bytes of scratch, above its "
+                                     "scratch_limit of " + std::to_string(ctx->limit));
     if (bytes <= *have) return BBC_OK;
     if (*arena) {
         (void)hipFree(*arena);
@@ -474,6 +478,7 @@ bbc_status grow(bbc_ctx* ctx, char** arena, size_t* have, size_t bytes) {
         *have = 0;
     }
     size_t want = bytes + bytes / 8 + (1u << 20);
+    if (ctx->limit > 0 && want > (size_t)ctx->limit) want = (size_t)ctx->limit;  // >= bytes
     if (hipMalloc((void**)arena, want) != hipSuccess) {
         *arena = nullptr;
         (void)hipGetLastError();
@@ -485,10 +490,13 @@ bbc_status grow(bbc_ctx* ctx, char** arena, size_t* have, size_t bytes) {
 
 bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
     bbc_options_init(o);
+    ctx->limit = 0;
     if (in) {
         if (in->struct_size != sizeof(bbc_options)) return fail(ctx, BBC_EINVAL, "bbc_options.struct_size");
         *o = *in;
     }
+    if (o->scratch_limit < 0) return fail(ctx, BBC_EINVAL, "negative scratch_limit");
+    ctx->limit = o->scratch_limit;
     if (o->side < BBC_SIDE_AUTO || o->side > BBC_SIDE_MIN_WEDGES) return fail(ctx, BBC_EINVAL, "bad side option");
     if (!wedge_shape_ok(o->band_words, o->wg_size))
         return fail(ctx, BBC_EINVAL, "no wedge kernel instance for this band_words / wg_size");
@@ -842,6 +850,9 @@ bbc_status count_single(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
     if (fixed) {
         Plan P;
         const size_t need = P.carve(nullptr, J);
+        if (ctx->limit > 0 && need > (size_t)ctx->limit)
+            return fail(ctx, BBC_ENOMEM, "the call needs " + std::to_string(need) + " bytes of scratch, above its "
+                                         "scratch_limit of " + std::to_string(ctx->limit));
         if (need > kFixedScratchBytes)
             return fail(ctx, BBC_ETOOBIG, "bbc_count_noalloc: the graph needs " + std::to_string(need) +
                                               " bytes of scratch, the fixed scratch holds " +
@@ -1071,6 +1082,7 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
                             void* stream) {
     if (!ctx) return BBC_EINVAL;
     ctx->err.clear();
+    ctx->limit = 0;
     if (!delta) return fail(ctx, BBC_EINVAL, "delta is NULL");
     if (n_u < 0 || n_v < 0 || n_edges < 0 || n_updates < 0) return fail(ctx, BBC_EINVAL, "negative size");
     if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
@@ -1243,6 +1255,11 @@ bbc_status bbc_batch_plan_create(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph
     p->ctx = ctx;
     Plan P;
     const size_t bytes = P.carve(nullptr, J);
+    if (opts.scratch_limit > 0 && bytes > (size_t)opts.scratch_limit) {
+        bbc_batch_plan_destroy(p);
+        return fail(ctx, BBC_ENOMEM, "the plan needs " + std::to_string(bytes) + " bytes of scratch, above its "
+                                     "scratch_limit of " + std::to_string(opts.scratch_limit));
+    }
     if (hipMalloc((void**)&p->arena, bytes) != hipSuccess ||
         hipMalloc((void**)&p->st_dev, sizeof(DevStatus)) != hipSuccess ||
         hipHostMalloc((void**)&p->st_host, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {

@@ -24,9 +24,9 @@
 // centre order (padded to 64).  |S| is S & 1 per byte, formed in registers.
 // Each workgroup computes one 128 x 128 tile of the upper triangle with
 // v_mfma_i32_32x32x32_i8: four waves, each 64 x 64 (2 x 2 MFMA tiles, two
-// products), operands staged through two LDS buffers 64 bytes of K at a
-// time (the next slice is loaded while the current one computes); two
-// workgroups per CU.
+// products), operands staged through two LDS buffers 128 bytes of K at a
+// time (the next slice is loaded while the current one computes, one
+// barrier per slice); two workgroups per CU.
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -106,8 +106,10 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kDTile = 128;  // output tile edge
-constexpr int kDK = 64;      // K bytes per LDS stage
+constexpr int kDK = 128;     // K bytes per LDS stage
 constexpr int kDRow = kDK + 16;  // LDS row pitch in bytes (padding spreads banks)
+constexpr int kDRowsPerPass = 256 * 16 / kDK;  // rows one pass of the workgroup's 16-byte loads covers
+constexpr int kDLoads = kDTile / kDRowsPerPass;  // 16-byte loads per thread and matrix per stage
 
 // Output element of accumulator i in lane l of a 32 x 32 MFMA tile: column
 // l % 32, row 8 * (i / 4) + 4 * (l / 32) + i % 4.
@@ -125,6 +127,10 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
     const DevBlock B = blocks[T.blk];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const int wr = wave >> 1, wc = wave & 1;
+    // on a diagonal tile the lower-left wave's outputs all lie below the
+    // diagonal (u > w): it loads and stores its share of the operands but
+    // issues no matrix instruction
+    const bool idle = T.ti == T.tj && wr > wc;
     const int8_t* arow = mats + B.mat_off + (int64_t)T.ti * kDTile * B.kpad;
     const int8_t* brow = mats + B.mat_off + (int64_t)T.tj * kDTile * B.kpad;
 
@@ -137,57 +143,62 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
             accP[i][j] = v16i{};
         }
 
-    // staging: 128 rows x 64 bytes per matrix = 512 16-byte pieces, two per
-    // thread and matrix, held in registers while the previous slice computes
-    const int lr = tid >> 2, lc = (tid & 3) * 16;
-    const int8_t* pa0 = arow + (int64_t)lr * B.kpad + lc;
-    const int8_t* pa1 = pa0 + (int64_t)64 * B.kpad;
-    const int8_t* pb0 = brow + (int64_t)lr * B.kpad + lc;
-    const int8_t* pb1 = pb0 + (int64_t)64 * B.kpad;
-    const int so0 = lr * kDRow + lc, so1 = (lr + 64) * kDRow + lc;
-    int4 ga0 = *(const int4*)pa0, ga1 = *(const int4*)pa1, gb0 = *(const int4*)pb0, gb1 = *(const int4*)pb1;
-    *(int4*)&As[0][so0] = ga0;
-    *(int4*)&As[0][so1] = ga1;
-    *(int4*)&Bs[0][so0] = gb0;
-    *(int4*)&Bs[0][so1] = gb1;
+    // staging: 128 rows x kDK bytes per matrix in 16-byte pieces, kDLoads
+    // per thread and matrix, held in registers while the previous slice
+    // computes; columns past kpad (a block whose K is not a multiple of kDK)
+    // are read as zero
+    const int lr = tid / (kDK / 16), lc = (tid % (kDK / 16)) * 16;
+    int4 ga[kDLoads], gb[kDLoads];
+    auto load_stage = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < kDLoads; ++i) {
+            const int64_t row = (int64_t)(lr + i * kDRowsPerPass) * B.kpad;
+            const bool in = k0 + lc < B.kpad;
+            ga[i] = in ? *(const int4*)(arow + row + k0 + lc) : int4{0, 0, 0, 0};
+            gb[i] = in ? *(const int4*)(brow + row + k0 + lc) : int4{0, 0, 0, 0};
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kDLoads; ++i) {
+            const int so = (lr + i * kDRowsPerPass) * kDRow + lc;
+            *(int4*)&As[buf][so] = ga[i];
+            *(int4*)&Bs[buf][so] = gb[i];
+        }
+    };
+    load_stage(0);
+    store_stage(0);
     __syncthreads();
     int buf = 0;
     for (int k0 = 0; k0 < B.kpad; k0 += kDK, buf ^= 1) {
         const bool more = k0 + kDK < B.kpad;
-        if (more) {
-            ga0 = *(const int4*)(pa0 + k0 + kDK);
-            ga1 = *(const int4*)(pa1 + k0 + kDK);
-            gb0 = *(const int4*)(pb0 + k0 + kDK);
-            gb1 = *(const int4*)(pb1 + k0 + kDK);
-        }
+        if (more) load_stage(k0 + kDK);
+        if (!idle) {
 #pragma unroll
-        for (int ks = 0; ks < kDK; ks += 32) {
-            v4i a[2], b[2], aa[2], ba[2];
-            const int kk = ks + 16 * (lane >> 5);
+            for (int ks = 0; ks < kDK; ks += 32) {
+                v4i a[2], b[2], aa[2], ba[2];
+                const int kk = ks + 16 * (lane >> 5);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                a[i] = *(const v4i*)&As[buf][(wr * 64 + i * 32 + (lane & 31)) * kDRow + kk];
-                b[i] = *(const v4i*)&Bs[buf][(wc * 64 + i * 32 + (lane & 31)) * kDRow + kk];
-                aa[i] = a[i] & 0x01010101;
-                ba[i] = b[i] & 0x01010101;
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    accD[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], accD[i][j], 0, 0, 0);
-                    accP[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[i], ba[j], accP[i][j], 0, 0, 0);
+                for (int i = 0; i < 2; ++i) {
+                    a[i] = *(const v4i*)&As[buf][(wr * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                    b[i] = *(const v4i*)&Bs[buf][(wc * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                    aa[i] = a[i] & 0x01010101;
+                    ba[i] = b[i] & 0x01010101;
                 }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        accD[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], accD[i][j], 0, 0, 0);
+                        accP[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[i], ba[j], accP[i][j], 0, 0, 0);
+                    }
+            }
         }
         // the other stage was last read before the previous barrier
-        if (more) {
-            *(int4*)&As[buf ^ 1][so0] = ga0;
-            *(int4*)&As[buf ^ 1][so1] = ga1;
-            *(int4*)&Bs[buf ^ 1][so0] = gb0;
-            *(int4*)&Bs[buf ^ 1][so1] = gb1;
-        }
+        if (more) store_stage(buf ^ 1);
         __syncthreads();
     }
+    if (idle) return;
 
     // epilogue: pair terms of the upper triangle and the (a, b) table;
     // a, b <= 65535, so a (a - 1) / 2 fits 32 bits
