@@ -137,6 +137,11 @@ typedef struct {
      * regime.  The counts never depend on either. */
     int32_t queue_chunk;
     int32_t wave_max_work;
+    /* Output tile edge of the int8 matrix kernel of dense blocks: 128
+     * (default) or 64 (less padding for small blocks); 0 = the tuning
+     * table's choice for the graph's size class (see bbc_autotune_blocks),
+     * else 128. */
+    int32_t dense_tile;
     /* Largest scratch, in bytes, the call may need (the context's arena, or
      * a batch plan's own); a call that needs more fails with BBC_ENOMEM
      * before any work, its outputs and the arena untouched, and the context
@@ -275,30 +280,46 @@ bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out);
 
 /* Autotuner.  The paper fixes its launch shape by hand (warp / partial-block
  * / full-block thresholds 32 and 512, blocks in proportion to the SM count;
- * Sec. "Optimization in GPU: Load balancing", Algorithm 4); here the wedge kernel's shape
- * (threads per workgroup, LDS band) and persistent grid (workgroups per
- * compute unit) are measured instead.  bbc_autotune counts the given
- * calibration graph (arguments as bbc_count) with every instantiated shape,
- * grid size and schedule (BBC_SCHED_*), `reps` timed runs each (HIP events around the wedge
- * kernel, best of reps; reps <= 0 means 2), and records the fastest in the
- * context's table under the graph's size class: (bit length of n_S, bit
- * length of m / n_S), n_S the anchor side of the default side rule.  Later
- * bbc_count and batched calls of the same class use that entry unless their
- * options fix the shape or set no_tuning.  *chosen (host, may be NULL)
- * receives options holding the chosen shape and schedule.  The count itself never
- * depends on the shape.  Errors: as bbc_count. */
+ * Sec. "Optimization in GPU: Load balancing", Algorithm 4); here the knobs
+ * are measured instead.  bbc_autotune counts the given calibration graph
+ * (arguments as bbc_count) in two stages, `reps` timed runs per
+ * configuration (HIP events around the wedge kernel, best of reps; reps <= 0
+ * means 2, one warm-up run before them): first every instantiated shape
+ * (threads per workgroup, LDS band), persistent grid (1, 2 and as many
+ * workgroups per CU as fit) and schedule (BBC_SCHED_*), then, with the
+ * fastest of those, queue_chunk in {1, 2, 4, 8} x wave_max_work in {the
+ * shape's largest, 256, -1}.  The winner is recorded in the context's table
+ * under the graph's size class: (bit length of n_S, bit length of
+ * m / n_S), n_S the anchor side of the default side rule.  Later bbc_count
+ * and batched calls of the same class use it unless their options fix the
+ * shape or set no_tuning (queue_chunk and wave_max_work only when they are
+ * 0).  *chosen (host, may be NULL) receives options holding the choice.
+ * Every configuration must give the same count (BBC_EDEVICE otherwise); the
+ * count never depends on them.  Errors: as bbc_count. */
 bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                         const int32_t* adj, const int8_t* signs, int32_t reps, bbc_options* chosen, void* stream);
 
+/* The same two-stage search on a batch (arguments as bbc_count_batched;
+ * totals receives the last run's counts), recorded under the batch's size
+ * class (n_S and m summed over its graphs), which bbc_count_batched and
+ * batch plans of the same layout then use.  Every configuration must give
+ * the same per-graph totals. */
+bbc_status bbc_autotune_batched(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* descs,
+                                const int32_t* offsets_cat, const int32_t* adj_cat, const int8_t* signs_cat,
+                                uint64_t* totals, int32_t reps, bbc_options* chosen, void* stream);
+
 /* Writes the tuning table to a text file (path: host string).  One header
- * line "bbc-tune 2 gfx950", then one line per size class:
- * "ns_bits deg_bits band_words wg_size wg_per_cu schedule ms".  BBC_EINVAL
- * if the file cannot be written. */
+ * line "bbc-tune 3 gfx950", then one line per size class: "ns_bits deg_bits
+ * band_words wg_size wg_per_cu schedule queue_chunk wave_max_work
+ * min_degree dense_tile ms" (band_words 0: the class has only dense-block
+ * choices; queue_chunk, min_degree and dense_tile 0: not tuned).
+ * BBC_EINVAL if the file cannot be written. */
 bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path);
 
-/* Reads such a file (or a version-1 file, "bbc-tune 1 gfx950", whose lines
- * have no schedule column and mean the dynamic schedule) and merges its
- * entries into the table (an entry replaces the one of the same class).  BBC_EINVAL, with the line number in
+/* Reads such a file (or an older one: version 2 lines end after the
+ * schedule column, version 1 lines after wg_per_cu and mean the dynamic
+ * schedule) and merges its entries into the table (an entry replaces the
+ * one of the same class).  BBC_EINVAL, with the line number in
  * bbc_last_error, for a missing file, a wrong header, a malformed line or a
  * shape that is not instantiated; the table is unchanged on error. */
 bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path);
@@ -389,7 +410,8 @@ bbc_status bbc_set_update_task_cap(bbc_ctx* ctx, int32_t cap);
 typedef struct {
     uint32_t struct_size; /* sizeof(bbc_plan_options) */
     int32_t side;         /* anchor side, BBC_SIDE_* as in bbc_options */
-    int32_t min_degree;   /* default 256 */
+    int32_t min_degree;   /* 0 (default) = the tuned threshold of the graph's size class
+                           * (bbc_autotune_blocks), else 256 */
     float member_frac;    /* default 0.3 */
     float min_density;    /* default 0.25 */
     int32_t min_anchors;  /* default 256 */
@@ -421,6 +443,21 @@ bbc_status bbc_plan_options_init(bbc_plan_options* opts);
 bbc_status bbc_plan_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                            const int32_t* adj, const bbc_plan_options* opts, int32_t max_blocks,
                            bbc_dense_block* blocks, int32_t* ids, int64_t ids_cap, int32_t* n_blocks, void* stream);
+
+/* Tunes the dense-block hybrid on a calibration graph (arguments as
+ * bbc_count): for the planner's degree threshold min_degree in {128, 256,
+ * 512, 1024} it plans blocks (bbc_plan_blocks, default options otherwise)
+ * and counts with them at both int8 tiles (dense_tile 64 and 128), each
+ * count equal to the sparse-only count (BBC_EDEVICE otherwise), and keeps
+ * the pair with the smallest planning time plus end-to-end count time (best
+ * of reps).  The pair is recorded under the graph's size class: planner
+ * calls with min_degree 0 and counts with dense_tile 0 of that class use
+ * it.  *chosen_plan and *chosen (host, may be NULL) receive options holding
+ * it.  Allocates a temporary id buffer (4 bytes per vertex).  Errors: as
+ * bbc_count and bbc_plan_blocks. */
+bbc_status bbc_autotune_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                               const int32_t* adj, const int8_t* signs, int32_t reps, bbc_plan_options* chosen_plan,
+                               bbc_options* chosen, void* stream);
 
 /* Static strings; never NULL. */
 const char* bbc_status_string(bbc_status s);

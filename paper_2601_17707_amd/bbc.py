@@ -58,6 +58,7 @@ class Options(ctypes.Structure):
         ("schedule", ctypes.c_int32),
         ("queue_chunk", ctypes.c_int32),
         ("wave_max_work", ctypes.c_int32),
+        ("dense_tile", ctypes.c_int32),
         ("scratch_limit", ctypes.c_int64),
     ]
 
@@ -161,6 +162,11 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_last_error.restype = ctypes.c_char_p
     lib.bbc_autotune.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, ctypes.POINTER(Options), vp]
     lib.bbc_autotune.restype = ctypes.c_int
+    lib.bbc_autotune_batched.argtypes = [vp, i32, PD, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp]
+    lib.bbc_autotune_batched.restype = ctypes.c_int
+    lib.bbc_autotune_blocks.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, ctypes.POINTER(PlanOptions),
+                                        ctypes.POINTER(Options), vp]
+    lib.bbc_autotune_blocks.restype = ctypes.c_int
     lib.bbc_tune_save.argtypes = [vp, ctypes.c_char_p]
     lib.bbc_tune_save.restype = ctypes.c_int
     lib.bbc_tune_load.argtypes = [vp, ctypes.c_char_p]
@@ -191,14 +197,15 @@ def status_string(status: int) -> str:
 
 def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0, wg_per_cu=0,
             blocks=None, no_tuning=False, schedule="dynamic", queue_chunk=0, wave_max_work=0,
-            scratch_limit=0) -> Options:
+            scratch_limit=0, dense_tile=0) -> Options:
     """Options struct.  ``blocks``: list of (u_ids, v_ids) int32 device
     tensors naming dense blocks (kept alive by the returned object).
     ``schedule``: "dynamic" (shared queue) or "static" (fixed deal).
     ``queue_chunk``: workgroup-regime anchors per queue pop (0 = 1);
     ``wave_max_work``: wave-regime threshold in wedges (0 = the shape's
     largest, -1 = no wave regime); ``scratch_limit``: bytes of scratch the
-    call may need (0 = no limit; beyond it the call fails with ENOMEM)."""
+    call may need (0 = no limit; beyond it the call fails with ENOMEM);
+    ``dense_tile``: int8 matrix output tile, 64 or 128 (0 = tuned, else 128)."""
     o = Options()
     load_library().bbc_options_init(ctypes.byref(o))
     o.side = _SIDES[side]
@@ -212,6 +219,7 @@ def options(side="auto", checks=CHECK_ALL, timing=False, band_words=0, wg_size=0
     o.queue_chunk = int(queue_chunk)
     o.wave_max_work = int(wave_max_work)
     o.scratch_limit = int(scratch_limit)
+    o.dense_tile = int(dense_tile)
     if blocks:
         arr = (DenseBlock * len(blocks))()
         for i, (uids, vids) in enumerate(blocks):
@@ -423,9 +431,15 @@ class Context:
             raise BbcError(st, self.last_error())
         return batch.totals
 
+    @staticmethod
+    def _chosen(o) -> dict:
+        return dict(band_words=o.band_words, wg_size=o.wg_size, wg_per_cu=o.wg_per_cu, schedule=o.schedule,
+                    queue_chunk=o.queue_chunk, wave_max_work=o.wave_max_work)
+
     def autotune(self, offsets, adj, signs, n_v: int, reps: int = 2, stream=None) -> dict:
-        """Times every wedge-kernel shape on this calibration graph and
-        records the fastest for its size class; returns the chosen shape."""
+        """Times the wedge kernel's shapes, grids, schedules, queue chunks and
+        wave-regime thresholds on this calibration graph and records the
+        fastest for its size class; returns the choice."""
         import torch
 
         _check_tensor("offsets", offsets, torch.int32, torch)
@@ -436,8 +450,35 @@ class Context:
                                     _ptr(signs), int(reps), ctypes.byref(chosen), _stream_ptr(stream, offsets))
         if st != OK:
             raise BbcError(st, self.last_error())
-        return dict(band_words=chosen.band_words, wg_size=chosen.wg_size, wg_per_cu=chosen.wg_per_cu,
-                    schedule=chosen.schedule)
+        return self._chosen(chosen)
+
+    def autotune_batched(self, batch: "Batch", reps: int = 2, stream=None) -> dict:
+        """The same search on a batch, recorded under the batch's size class
+        (used by count_batched and plans of that layout)."""
+        chosen = Options()
+        st = self._lib.bbc_autotune_batched(self._h, batch.n_graphs, batch.descs, _ptr(batch.offsets),
+                                            _ptr(batch.adj), _ptr(batch.signs), _ptr(batch.totals), int(reps),
+                                            ctypes.byref(chosen), _stream_ptr(stream, batch.offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return self._chosen(chosen)
+
+    def autotune_blocks(self, offsets, adj, signs, n_v: int, reps: int = 2, stream=None) -> dict:
+        """Times the planner's degree threshold and the int8 tile on this
+        graph (every hybrid count checked against the sparse-only one) and
+        records the fastest for its size class."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        cp, co = PlanOptions(), Options()
+        st = self._lib.bbc_autotune_blocks(self._h, offsets.numel() - 1, int(n_v), adj.numel(), _ptr(offsets),
+                                           _ptr(adj), _ptr(signs), int(reps), ctypes.byref(cp), ctypes.byref(co),
+                                           _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return dict(min_degree=cp.min_degree, dense_tile=co.dense_tile)
 
     def tune_save(self, path: str):
         st = self._lib.bbc_tune_save(self._h, os.fsencode(path))

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <string>
@@ -62,7 +63,7 @@ void launch_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s, cons
                        const uint32_t* aoff, const int32_t* acent, const uint8_t* aneg, const int32_t* cblk,
                        const int32_t* cidx, int8_t* mats, const DevStatus* st, hipStream_t s);
 void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles, const int8_t* mats, uint32_t* tabs,
-                  DevStatus* st, hipStream_t s);
+                  DevStatus* st, int tile, hipStream_t s);
 void launch_bidx(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int64_t n_c, int gs,
                  uint32_t* nb, uint32_t* ioff, uint32_t* idx, int2* meta, uint32_t* partials, const DevStatus* st,
                  hipStream_t s);
@@ -115,8 +116,12 @@ __global__ void k_status_init(DevStatus* st) {
 // for a size class (bit lengths of n_S and of m / n_S).
 struct TuneEntry {
     int32_t ns_bits, deg_bits;
-    int32_t band_words, wg_size, wg_per_cu;
-    int32_t schedule;  // BBC_SCHED_*
+    int32_t band_words, wg_size, wg_per_cu;  // band_words = 0: shape not tuned
+    int32_t schedule;       // BBC_SCHED_*
+    int32_t queue_chunk;    // 0: not tuned (1)
+    int32_t wave_max_work;  // 0: the shape's largest, -1: no wave regime
+    int32_t min_degree;     // planner threshold; 0: not tuned (256)
+    int32_t dense_tile;     // int8 matrix tile; 0: not tuned (128)
     float ms;
 };
 }  // namespace bbc
@@ -249,6 +254,7 @@ struct Job {
     int32_t queue_chunk = 1;    // workgroup-regime anchors per queue pop
     int32_t light_w = 0;        // wave regime: anchors with at most this many wedges (0: none)
     int32_t light_chunk = 64;   // wave-regime anchors per queue pop
+    int32_t dense_tile = 128;   // int8 matrix output tile (64 or 128)
     bool classes = false;  // the six sign-pattern classes instead of the total
     int32_t bic_k = 0;     // > 0: balanced (2,k)-bicliques instead of the total
     // dense blocks (single graph only)
@@ -452,7 +458,7 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     if (J.batched) fill_bytes(J.totals, (int64_t)J.n_graphs * 8, s);
     if (hybrid) {  // dense block products (int8 matrix cores), then the sparse walk reads their tables
         if (ev) (void)hipEventRecord(ev[4], s);
-        launch_dense(P.dblocks, P.dtiles, J.n_tiles, P.mats, P.tabs, st, s);
+        launch_dense(P.dblocks, P.dtiles, J.n_tiles, P.mats, P.tabs, st, J.dense_tile, s);
         if (ev) (void)hipEventRecord(ev[5], s);
     }
     if (J.bic_k > 0) launch_choose_table(J.bic_k, P.bic_tab, s);
@@ -506,11 +512,14 @@ bbc_status read_options(bbc_ctx* ctx, const bbc_options* in, bbc_options* o) {
     if (o->n_blocks < 0 || (o->n_blocks > 0 && !o->blocks)) return fail(ctx, BBC_EINVAL, "bad dense block list");
     if (o->queue_chunk < 0 || o->queue_chunk > 65536) return fail(ctx, BBC_EINVAL, "queue_chunk outside [0, 65536]");
     if (o->wave_max_work < -1) return fail(ctx, BBC_EINVAL, "wave_max_work below -1");
+    if (o->dense_tile != 0 && o->dense_tile != 64 && o->dense_tile != 128)
+        return fail(ctx, BBC_EINVAL, "dense_tile must be 0, 64 or 128");
     return BBC_OK;
 }
 
 // Regime knobs of a count-mode job (no wave regime with per-vertex output).
 void set_regimes(Job& J, const bbc_options& o, bool full) {
+    J.dense_tile = o.dense_tile ? o.dense_tile : 128;
     J.queue_chunk = o.queue_chunk > 0 ? o.queue_chunk : 1;
     const int lmax = wedge_light_max(o.band_words, o.wg_size);
     J.light_w = (full || o.wave_max_work < 0) ? 0 : o.wave_max_work == 0 ? lmax : std::min(o.wave_max_work, lmax);
@@ -554,21 +563,31 @@ void tune_class(int64_t n_s, int64_t m, int32_t* ns_bits, int32_t* deg_bits) {
     *deg_bits = bits_for((uint64_t)(m / (n_s > 0 ? n_s : 1)));
 }
 
-// Fills the kernel shape from the tuning table when the options leave it
-// open.  Returns whether an entry was used.
-bool apply_tuning(const bbc_ctx* ctx, bbc_options& o, int64_t n_s, int64_t m, bool full) {
-    if (o.no_tuning || full || o.band_words || o.wg_size || o.wg_per_cu || o.schedule) return false;
+const TuneEntry* tune_find(const bbc_ctx* ctx, int64_t n_s, int64_t m) {
     int32_t a, b;
     tune_class(n_s, m, &a, &b);
     for (const TuneEntry& e : ctx->tune)
-        if (e.ns_bits == a && e.deg_bits == b) {
-            o.band_words = e.band_words;
-            o.wg_size = e.wg_size;
-            o.wg_per_cu = e.wg_per_cu;
-            o.schedule = e.schedule;
-            return true;
-        }
-    return false;
+        if (e.ns_bits == a && e.deg_bits == b) return &e;
+    return nullptr;
+}
+
+// Fills what the options leave open from the tuning table: the kernel
+// shape, grid and schedule (when none of them is fixed), the queue chunk
+// and wave-regime threshold (when 0) and the dense tile (when 0).  Returns
+// whether the shape came from the table.
+bool apply_tuning(const bbc_ctx* ctx, bbc_options& o, int64_t n_s, int64_t m, bool full) {
+    if (o.no_tuning || full) return false;
+    const TuneEntry* e = tune_find(ctx, n_s, m);
+    if (!e) return false;
+    if (o.dense_tile == 0) o.dense_tile = e->dense_tile;
+    if (o.band_words || o.wg_size || o.wg_per_cu || o.schedule || e->band_words == 0) return false;
+    o.band_words = e->band_words;
+    o.wg_size = e->wg_size;
+    o.wg_per_cu = e->wg_per_cu;
+    o.schedule = e->schedule;
+    if (o.queue_chunk == 0) o.queue_chunk = e->queue_chunk;
+    if (o.wave_max_work == 0) o.wave_max_work = e->wave_max_work;
+    return true;
 }
 
 void tune_store(bbc_ctx* ctx, const TuneEntry& e) {
@@ -578,6 +597,16 @@ void tune_store(bbc_ctx* ctx, const TuneEntry& e) {
             return;
         }
     ctx->tune.push_back(e);
+}
+
+// The entry of a size class, created empty (nothing tuned) if absent.
+TuneEntry& tune_slot(bbc_ctx* ctx, int64_t n_s, int64_t m) {
+    int32_t a, b;
+    tune_class(n_s, m, &a, &b);
+    for (TuneEntry& x : ctx->tune)
+        if (x.ns_bits == a && x.deg_bits == b) return x;
+    ctx->tune.push_back(TuneEntry{a, b, 0, 0, 0, 0, 0, 0, 0, 0, 0.f});
+    return ctx->tune.back();
 }
 
 // Validates a batch on the host and fills the job and device descriptors.
@@ -644,7 +673,8 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
 // ranks, block by block.
 bbc_status block_job(bbc_ctx* ctx, const bbc_options& o, Job& J, std::vector<DevBlock>& db,
                      std::vector<DevTile>& dt) {
-    constexpr int32_t kMaxAnchors = 16384, kMaxCentres = 65535, kTile = 128, kK = 64;
+    constexpr int32_t kMaxAnchors = 16384, kMaxCentres = 65535, kK = 64;
+    const int32_t kTile = J.dense_tile;
     J.n_blocks = o.n_blocks;
     db.resize((size_t)o.n_blocks);
     int64_t n_anchors = 0;
@@ -794,6 +824,107 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
     bbc_status rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, P.carve(nullptr, J));
     if (rc != BBC_OK) return rc;
     return run_planned(ctx, J, ctx->arena, opts, s, dg, vstart, rend, db, dt);
+}
+
+// Autotuning of the wedge kernel, shared by the single-graph and the
+// batched tuner.  `run(options, &result)` performs one call (timing on)
+// and returns a result every configuration must reproduce.  Stage 1 times
+// every instantiated shape x grid (1, 2 and as many workgroups per CU as
+// fit) x schedule with the default regimes; stage 2 times the best of them
+// with queue_chunk in {1, 2, 4, 8} x wave_max_work in {shape's largest,
+// 256, off}.  Each configuration runs reps + 1 times (the first warms up);
+// its score is the best HIP-event time of the wedge kernel.
+template <class Run>
+bbc_status tune_wedge(bbc_ctx* ctx, int32_t reps, Run run, TuneEntry& best) {
+    if (reps <= 0) reps = 2;
+    uint64_t first = 0;
+    bool counted = false, have = false;
+    auto time_cfg = [&](bbc_options o, float* ms) -> bbc_status {
+        o.timing = 1;
+        o.no_tuning = 1;
+        float t = 0.f;
+        for (int r = 0; r <= reps; ++r) {
+            uint64_t res = 0;
+            const bbc_status rc = run(o, &res);
+            if (rc != BBC_OK) return rc;
+            if (!counted) {
+                first = res;
+                counted = true;
+            } else if (res != first) {
+                return fail(ctx, BBC_EDEVICE, "autotune: configurations disagree on the result");
+            }
+            if (r > 0 && (r == 1 || ctx->stats.ms_count < t)) t = ctx->stats.ms_count;
+        }
+        *ms = t;
+        return BBC_OK;
+    };
+    const int n_shapes = wedge_shape_count();
+    for (int i = 0; i < n_shapes; ++i) {
+        int wg, bw;
+        wedge_shape(i, &wg, &bw);
+        const int occ = wedge_blocks_per_cu(bw, wg, false);
+        for (int cfg = 0; cfg < 2 * occ; ++cfg) {
+            const int wpc = cfg / 2 + 1, sched = cfg & 1;  // both schedules at each grid
+            if (wpc > 2 && wpc < occ) continue;           // 1, 2 and as many as fit
+            bbc_options o;
+            bbc_options_init(&o);
+            o.band_words = bw;
+            o.wg_size = wg;
+            o.wg_per_cu = wpc;
+            o.schedule = sched;
+            float ms = 0.f;
+            const bbc_status rc = time_cfg(o, &ms);
+            if (rc != BBC_OK) return rc;
+            if (!have || ms < best.ms) {
+                best = TuneEntry{0, 0, bw, wg, wpc, sched, 1, 0, 0, 0, ms};
+                have = true;
+            }
+        }
+    }
+    const TuneEntry shape = best;
+    for (const int32_t qc : {1, 2, 4, 8})
+        for (const int32_t wm : {0, 256, -1}) {
+            if (qc == 1 && wm == 0) continue;  // timed in stage 1
+            bbc_options o;
+            bbc_options_init(&o);
+            o.band_words = shape.band_words;
+            o.wg_size = shape.wg_size;
+            o.wg_per_cu = shape.wg_per_cu;
+            o.schedule = shape.schedule;
+            o.queue_chunk = qc;
+            o.wave_max_work = wm;
+            float ms = 0.f;
+            const bbc_status rc = time_cfg(o, &ms);
+            if (rc != BBC_OK) return rc;
+            if (ms < best.ms) {
+                best.queue_chunk = qc;
+                best.wave_max_work = wm;
+                best.ms = ms;
+            }
+        }
+    return BBC_OK;
+}
+
+// Records a wedge-kernel tuning result under the size class (keeping the
+// class's dense-block fields) and reports it in *chosen (may be null).
+void tune_keep(bbc_ctx* ctx, int64_t n_s, int64_t m, const TuneEntry& best, bbc_options* chosen) {
+    TuneEntry& e = tune_slot(ctx, n_s, m);
+    e.band_words = best.band_words;
+    e.wg_size = best.wg_size;
+    e.wg_per_cu = best.wg_per_cu;
+    e.schedule = best.schedule;
+    e.queue_chunk = best.queue_chunk;
+    e.wave_max_work = best.wave_max_work;
+    e.ms = best.ms;
+    if (chosen) {
+        bbc_options_init(chosen);
+        chosen->band_words = best.band_words;
+        chosen->wg_size = best.wg_size;
+        chosen->wg_per_cu = best.wg_per_cu;
+        chosen->schedule = best.schedule;
+        chosen->queue_chunk = best.queue_chunk;
+        chosen->wave_max_work = best.wave_max_work;
+    }
 }
 
 // bbc_count and bbc_count_noalloc: the same pipeline, its buffers carved
@@ -1315,60 +1446,136 @@ bbc_status bbc_batch_wait(bbc_batch_plan* p, void* stream) {
 bbc_status bbc_autotune(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                         const int32_t* adj, const int8_t* signs, int32_t reps, bbc_options* chosen, void* stream) {
     if (!ctx) return BBC_EINVAL;
+    TuneEntry best{};
+    auto run = [&](const bbc_options& o, uint64_t* res) {
+        return bbc_count(ctx, n_u, n_v, n_edges, offsets, adj, signs, res, nullptr, &o, stream);
+    };
+    bbc_status rc = tune_wedge(ctx, reps, run, best);
+    if (rc != BBC_OK) return rc;
+    const bool su = side_is_u(BBC_SIDE_AUTO, n_u, n_v);
+    tune_keep(ctx, su ? n_u : n_v, n_edges, best, chosen);
+    return BBC_OK;
+}
+
+bbc_status bbc_autotune_batched(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* descs,
+                                const int32_t* offsets_cat, const int32_t* adj_cat, const int8_t* signs_cat,
+                                uint64_t* totals, int32_t reps, bbc_options* chosen, void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    if (n_graphs < 0 || (n_graphs > 0 && (!descs || !totals))) return fail(ctx, BBC_EINVAL, "bad batch arguments");
+    std::vector<uint64_t> host((size_t)(n_graphs > 0 ? n_graphs : 1));
+    // the result compared across configurations: the per-graph totals,
+    // folded with their positions
+    auto run = [&](const bbc_options& o, uint64_t* res) {
+        bbc_status rc = bbc_count_batched(ctx, n_graphs, descs, offsets_cat, adj_cat, signs_cat, totals, &o, stream);
+        if (rc != BBC_OK || n_graphs == 0) return rc;
+        DeviceGuard guard(ctx->device);
+        HIP_OR_FAIL(hipMemcpy(host.data(), totals, (size_t)n_graphs * 8, hipMemcpyDeviceToHost));
+        uint64_t h = 0;
+        for (int32_t g = 0; g < n_graphs; ++g) h = h * 1000003ull + host[(size_t)g] + 1;
+        *res = h;
+        return BBC_OK;
+    };
+    TuneEntry best{};
+    bbc_status rc = tune_wedge(ctx, reps, run, best);
+    if (rc != BBC_OK) return rc;
+    int64_t ns = 0, m = 0;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        m += descs[g].n_edges;
+        ns += side_is_u(BBC_SIDE_AUTO, descs[g].n_u, descs[g].n_v) ? descs[g].n_u : descs[g].n_v;
+    }
+    tune_keep(ctx, ns, m, best, chosen);
+    return BBC_OK;
+}
+
+bbc_status bbc_autotune_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                               const int32_t* adj, const int8_t* signs, int32_t reps, bbc_plan_options* chosen_plan,
+                               bbc_options* chosen, void* stream) {
+    if (!ctx) return BBC_EINVAL;
     if (reps <= 0) reps = 2;
-    uint64_t total = 0, first = 0;
-    TuneEntry best{0, 0, 0, 0, 0, 0, 0.f};
-    bool have = false, counted = false;
-    const int n_shapes = wedge_shape_count();
-    for (int i = 0; i < n_shapes; ++i) {
-        int wg, bw;
-        wedge_shape(i, &wg, &bw);
-        const int occ = wedge_blocks_per_cu(bw, wg, false);
-        for (int cfg = 0; cfg < 2 * occ; ++cfg) {
-            const int wpc = cfg / 2 + 1, sched = cfg & 1;  // both schedules at each grid
-            if (wpc > 2 && wpc < occ) continue;  // 1, 2 and as many as fit
+    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    constexpr int32_t kMaxBlocks = 1024;
+    constexpr int32_t kTaus[] = {128, 256, 512, 1024};
+    constexpr int32_t kTiles[] = {64, 128};
+    // the sparse-only count is the reference every configuration must match
+    uint64_t want = 0;
+    bbc_options o0;
+    bbc_options_init(&o0);
+    o0.no_tuning = 1;
+    bbc_status rc = bbc_count(ctx, n_u, n_v, n_edges, offsets, adj, signs, &want, nullptr, &o0, stream);
+    if (rc != BBC_OK) return rc;
+    int32_t* ids = nullptr;
+    {
+        DeviceGuard guard(ctx->device);
+        if (hipMalloc((void**)&ids, ((size_t)n_u + (size_t)n_v + 1) * sizeof(int32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, BBC_ENOMEM, "autotune: block id buffer");
+        }
+    }
+    std::vector<bbc_dense_block> blocks((size_t)kMaxBlocks);
+    double best_ms = -1.0;
+    int32_t best_tau = 256, best_tile = 128;
+    for (int32_t tau : kTaus) {
+        bbc_plan_options po;
+        bbc_plan_options_init(&po);
+        po.min_degree = tau;
+        int32_t nb = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = bbc_plan_blocks(ctx, n_u, n_v, n_edges, offsets, adj, &po, kMaxBlocks, blocks.data(), ids,
+                             (int64_t)n_u + n_v, &nb, stream);
+        const double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rc != BBC_OK) break;
+        for (int32_t tile : kTiles) {
             bbc_options o;
             bbc_options_init(&o);
-            o.band_words = bw;
-            o.wg_size = wg;
-            o.wg_per_cu = wpc;
-            o.schedule = sched;
+            o.n_blocks = nb;
+            o.blocks = blocks.data();
+            o.dense_tile = tile;
             o.timing = 1;
             o.no_tuning = 1;
             float ms = 0.f;
-            for (int r = 0; r <= reps; ++r) {  // the first run is a warm-up
-                bbc_status rc = bbc_count(ctx, n_u, n_v, n_edges, offsets, adj, signs, &total, nullptr, &o, stream);
-                if (rc != BBC_OK) return rc;
-                if (!counted) {
-                    first = total;
-                    counted = true;
-                } else if (total != first) {
-                    return fail(ctx, BBC_EDEVICE, "autotune: kernel shapes disagree on the count");
-                }
-                if (r > 0 && (r == 1 || ctx->stats.ms_count < ms)) ms = ctx->stats.ms_count;
+            for (int r = 0; r <= reps && rc == BBC_OK; ++r) {
+                uint64_t got = 0;
+                rc = bbc_count(ctx, n_u, n_v, n_edges, offsets, adj, signs, &got, nullptr, &o, stream);
+                if (rc == BBC_OK && got != want) rc = fail(ctx, BBC_EDEVICE, "autotune: dense blocks change the count");
+                if (r > 0 && (r == 1 || ctx->stats.ms_total < ms)) ms = ctx->stats.ms_total;
             }
-            if (!have || ms < best.ms) {
-                best = TuneEntry{0, 0, bw, wg, wpc, sched, ms};
-                have = true;
+            if (rc != BBC_OK) break;
+            const double score = plan_ms + ms;  // a one-off count plans once
+            if (best_ms < 0 || score < best_ms) {
+                best_ms = score;
+                best_tau = tau;
+                best_tile = tile;
             }
+            if (nb == 0) break;  // no blocks: the tile does not matter
         }
+        if (rc != BBC_OK) break;
     }
+    {
+        DeviceGuard guard(ctx->device);
+        (void)hipFree(ids);
+    }
+    if (rc != BBC_OK) return rc;
     const bool su = side_is_u(BBC_SIDE_AUTO, n_u, n_v);
-    tune_class(su ? n_u : n_v, n_edges, &best.ns_bits, &best.deg_bits);
-    tune_store(ctx, best);
+    TuneEntry& e = tune_slot(ctx, su ? n_u : n_v, n_edges);
+    e.min_degree = best_tau;
+    e.dense_tile = best_tile;
+    if (e.band_words == 0) e.ms = (float)best_ms;
+    if (chosen_plan) {
+        bbc_plan_options_init(chosen_plan);
+        chosen_plan->min_degree = best_tau;
+    }
     if (chosen) {
         bbc_options_init(chosen);
-        chosen->band_words = best.band_words;
-        chosen->wg_size = best.wg_size;
-        chosen->wg_per_cu = best.wg_per_cu;
-        chosen->schedule = best.schedule;
+        chosen->dense_tile = best_tile;
     }
     return BBC_OK;
 }
 
 bbc_status bbc_plan_options_init(bbc_plan_options* o) {
     if (!o) return BBC_EINVAL;
-    *o = bbc_plan_options{sizeof(bbc_plan_options), BBC_SIDE_AUTO, 256, 0.3f, 0.25f, 256, 64, 32};
+    *o = bbc_plan_options{sizeof(bbc_plan_options), BBC_SIDE_AUTO, 0, 0.3f, 0.25f, 256, 64, 32};
     return BBC_OK;
 }
 
@@ -1388,7 +1595,7 @@ bbc_status bbc_plan_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edg
     }
     if (o.side != BBC_SIDE_AUTO && o.side != BBC_SIDE_U && o.side != BBC_SIDE_V)
         return fail(ctx, BBC_EINVAL, "plan options: bad side");
-    if (o.min_degree < 1 || !(o.member_frac > 0.f && o.member_frac <= 1.f) ||
+    if (o.min_degree < 0 || !(o.member_frac > 0.f && o.member_frac <= 1.f) ||
         !(o.min_density > 0.f && o.min_density <= 1.f) || o.min_anchors < 2 || o.min_centres < 1 ||
         o.max_tries < 1)
         return fail(ctx, BBC_EINVAL, "plan options out of range");
@@ -1404,6 +1611,10 @@ bbc_status bbc_plan_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edg
     hipStream_t s = (hipStream_t)stream;
     const bool su = side_is_u(o.side, n_u, n_v);
     const int64_t m = n_edges, n_a = su ? n_u : n_v, n_c = su ? n_v : n_u;
+    if (o.min_degree == 0) {  // the tuned threshold of the graph's size class, else 256
+        const TuneEntry* e = tune_find(ctx, n_a, m);
+        o.min_degree = e && e->min_degree > 0 ? e->min_degree : 256;
+    }
     const uint32_t tau = (uint32_t)o.min_degree;
     constexpr uint32_t kCapR = 16384, kCapC = 65535;
     PlanScratch P;
@@ -1528,10 +1739,11 @@ bbc_status bbc_tune_save(const bbc_ctx* ctx, const char* path) {
     if (!ctx || !path) return BBC_EINVAL;
     FILE* f = fopen(path, "w");
     if (!f) return fail(const_cast<bbc_ctx*>(ctx), BBC_EINVAL, std::string("cannot write ") + path);
-    bool ok = fprintf(f, "bbc-tune 2 gfx950\n") > 0;
+    bool ok = fprintf(f, "bbc-tune 3 gfx950\n") > 0;
     for (const TuneEntry& e : ctx->tune)
-        ok = ok && fprintf(f, "%d %d %d %d %d %d %.4f\n", e.ns_bits, e.deg_bits, e.band_words, e.wg_size,
-                           e.wg_per_cu, e.schedule, (double)e.ms) > 0;
+        ok = ok && fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.4f\n", e.ns_bits, e.deg_bits, e.band_words, e.wg_size,
+                           e.wg_per_cu, e.schedule, e.queue_chunk, e.wave_max_work, e.min_degree, e.dense_tile,
+                           (double)e.ms) > 0;
     ok = (fclose(f) == 0) && ok;
     return ok ? BBC_OK : fail(const_cast<bbc_ctx*>(ctx), BBC_EINVAL, std::string("write failed: ") + path);
 }
@@ -1546,22 +1758,26 @@ bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path) {
     bbc_status rc = BBC_OK;
     while (fgets(line, sizeof line, f)) {
         ++ln;
-        if (ln == 1) {  // version 1 has no schedule column (dynamic)
-            if (strcmp(line, "bbc-tune 2 gfx950\n") == 0 || strcmp(line, "bbc-tune 2 gfx950") == 0) version = 2;
-            else if (strcmp(line, "bbc-tune 1 gfx950\n") == 0 || strcmp(line, "bbc-tune 1 gfx950") == 0) version = 1;
+        if (ln == 1) {  // version 1 has no schedule column (dynamic); versions 1 and 2 no regime or block columns
+            for (int v = 1; v <= 3; ++v) {
+                const std::string h = "bbc-tune " + std::to_string(v) + " gfx950";
+                if (h == line || h + "\n" == line) version = v;
+            }
             if (!version) {
                 rc = fail(ctx, BBC_EINVAL, std::string(path) + ":1: not a tuning file for gfx950");
                 break;
             }
             continue;
         }
-        TuneEntry e;
+        TuneEntry e{};
         e.schedule = BBC_SCHED_DYNAMIC;
         double ms = 0;
         // whitespace-separated fields: integers, then the time; every field
         // must parse in full
-        const int want = version == 1 ? 6 : 7;
-        int32_t* ints[6] = {&e.ns_bits, &e.deg_bits, &e.band_words, &e.wg_size, &e.wg_per_cu, &e.schedule};
+        const int want = version == 1 ? 6 : version == 2 ? 7 : 11;
+        int32_t* ints[10] = {&e.ns_bits,  &e.deg_bits,    &e.band_words,    &e.wg_size,    &e.wg_per_cu,
+                             &e.schedule, &e.queue_chunk, &e.wave_max_work, &e.min_degree, &e.dense_tile};
+        if (version == 1) ints[5] = nullptr;  // no schedule column: the time follows wg_per_cu
         int n = 0;
         bool good = true;
         char* save = nullptr;
@@ -1570,15 +1786,20 @@ bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path) {
             if (n < want - 1) {
                 const long v = strtol(tok, &end, 10);
                 good = good && *end == 0 && v >= INT32_MIN && v <= INT32_MAX;
-                *ints[n] = (int32_t)v;
+                if (ints[n]) *ints[n] = (int32_t)v;
             } else if (n == want - 1) {
                 ms = strtod(tok, &end);
                 good = good && *end == 0;
             }
         }
-        if (!good || n != want || e.ns_bits < 0 || e.ns_bits > 64 || e.deg_bits < 0 || e.deg_bits > 64 || e.wg_per_cu < 0 ||
-            e.band_words <= 0 || e.wg_size <= 0 || !wedge_shape_ok(e.band_words, e.wg_size) ||
-            (e.schedule != BBC_SCHED_DYNAMIC && e.schedule != BBC_SCHED_STATIC)) {
+        if (version == 1) e.schedule = BBC_SCHED_DYNAMIC;
+        const bool shape_ok = e.band_words == 0 ? (version == 3 && e.wg_size == 0 && e.wg_per_cu == 0)
+                                                : (e.wg_size > 0 && wedge_shape_ok(e.band_words, e.wg_size));
+        if (!good || n != want || e.ns_bits < 0 || e.ns_bits > 64 || e.deg_bits < 0 || e.deg_bits > 64 ||
+            e.wg_per_cu < 0 || e.band_words < 0 || !shape_ok ||
+            (e.schedule != BBC_SCHED_DYNAMIC && e.schedule != BBC_SCHED_STATIC) || e.queue_chunk < 0 ||
+            e.queue_chunk > 65536 || e.wave_max_work < -1 || e.min_degree < 0 ||
+            (e.dense_tile != 0 && e.dense_tile != 64 && e.dense_tile != 128)) {
             rc = fail(ctx, BBC_EINVAL, std::string(path) + ":" + std::to_string(ln) + ": malformed tuning entry");
             break;
         }

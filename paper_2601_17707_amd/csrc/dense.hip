@@ -26,7 +26,9 @@
 // v_mfma_i32_32x32x32_i8: four waves, each 64 x 64 (2 x 2 MFMA tiles, two
 // products), operands staged through two LDS buffers 128 bytes of K at a
 // time (the next slice is loaded while the current one computes, one
-// barrier per slice); two workgroups per CU.
+// barrier per slice); two workgroups per CU.  A 64 x 64 tile (one MFMA tile
+// per wave, four workgroups per CU) is the alternative the autotuner can
+// pick for small blocks.
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -105,24 +107,30 @@ __global__ void k_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kDTile = 128;  // output tile edge
-constexpr int kDK = 128;     // K bytes per LDS stage
+constexpr int kDK = 128;         // K bytes per LDS stage
 constexpr int kDRow = kDK + 16;  // LDS row pitch in bytes (padding spreads banks)
 constexpr int kDRowsPerPass = 256 * 16 / kDK;  // rows one pass of the workgroup's 16-byte loads covers
-constexpr int kDLoads = kDTile / kDRowsPerPass;  // 16-byte loads per thread and matrix per stage
 
 // Output element of accumulator i in lane l of a 32 x 32 MFMA tile: column
 // l % 32, row 8 * (i / 4) + 4 * (l / 32) + i % 4.
 __device__ __forceinline__ int mfma_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
 
-__global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ blocks,
-                                                  const DevTile* __restrict__ tiles, const int8_t* __restrict__ mats,
-                                                  uint32_t* __restrict__ tabs, DevStatus* st) {
+// One TILE x TILE output tile of the upper triangle of a block product per
+// workgroup (TILE = 128: four waves of 64 x 64, 2 x 2 MFMA tiles each;
+// TILE = 64: four waves of 32 x 32, one MFMA tile each).
+template <int TILE>
+__global__ __launch_bounds__(256, TILE == 128 ? 2 : 4) void k_dense(const DevBlock* __restrict__ blocks,
+                                                                    const DevTile* __restrict__ tiles,
+                                                                    const int8_t* __restrict__ mats,
+                                                                    uint32_t* __restrict__ tabs, DevStatus* st) {
+    constexpr int WT = TILE / 2;           // wave tile edge
+    constexpr int NT = WT / 32;            // MFMA tiles per wave tile edge
+    constexpr int kLoads = TILE / kDRowsPerPass;  // 16-byte loads per thread and matrix per stage
     if (status_bad(st)) return;
     // two LDS stages: the next K slice is stored into one while the other
     // feeds the matrix cores
-    __shared__ __align__(16) int8_t As[2][kDTile * kDRow];
-    __shared__ __align__(16) int8_t Bs[2][kDTile * kDRow];
+    __shared__ __align__(16) int8_t As[2][TILE * kDRow];
+    __shared__ __align__(16) int8_t Bs[2][TILE * kDRow];
     const DevTile T = tiles[blockIdx.x];
     const DevBlock B = blocks[T.blk];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -131,27 +139,27 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
     // diagonal (u > w): it loads and stores its share of the operands but
     // issues no matrix instruction
     const bool idle = T.ti == T.tj && wr > wc;
-    const int8_t* arow = mats + B.mat_off + (int64_t)T.ti * kDTile * B.kpad;
-    const int8_t* brow = mats + B.mat_off + (int64_t)T.tj * kDTile * B.kpad;
+    const int8_t* arow = mats + B.mat_off + (int64_t)T.ti * TILE * B.kpad;
+    const int8_t* brow = mats + B.mat_off + (int64_t)T.tj * TILE * B.kpad;
 
-    v16i accD[2][2], accP[2][2];
+    v16i accD[NT][NT], accP[NT][NT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NT; ++j) {
             accD[i][j] = v16i{};
             accP[i][j] = v16i{};
         }
 
-    // staging: 128 rows x kDK bytes per matrix in 16-byte pieces, kDLoads
+    // staging: TILE rows x kDK bytes per matrix in 16-byte pieces, kLoads
     // per thread and matrix, held in registers while the previous slice
     // computes; columns past kpad (a block whose K is not a multiple of kDK)
     // are read as zero
     const int lr = tid / (kDK / 16), lc = (tid % (kDK / 16)) * 16;
-    int4 ga[kDLoads], gb[kDLoads];
+    int4 ga[kLoads], gb[kLoads];
     auto load_stage = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < kDLoads; ++i) {
+        for (int i = 0; i < kLoads; ++i) {
             const int64_t row = (int64_t)(lr + i * kDRowsPerPass) * B.kpad;
             const bool in = k0 + lc < B.kpad;
             ga[i] = in ? *(const int4*)(arow + row + k0 + lc) : int4{0, 0, 0, 0};
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < kDLoads; ++i) {
+        for (int i = 0; i < kLoads; ++i) {
             const int so = (lr + i * kDRowsPerPass) * kDRow + lc;
             *(int4*)&As[buf][so] = ga[i];
             *(int4*)&Bs[buf][so] = gb[i];
@@ -176,19 +184,19 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
         if (!idle) {
 #pragma unroll
             for (int ks = 0; ks < kDK; ks += 32) {
-                v4i a[2], b[2], aa[2], ba[2];
+                v4i a[NT], b[NT], aa[NT], ba[NT];
                 const int kk = ks + 16 * (lane >> 5);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    a[i] = *(const v4i*)&As[buf][(wr * 64 + i * 32 + (lane & 31)) * kDRow + kk];
-                    b[i] = *(const v4i*)&Bs[buf][(wc * 64 + i * 32 + (lane & 31)) * kDRow + kk];
+                for (int i = 0; i < NT; ++i) {
+                    a[i] = *(const v4i*)&As[buf][(wr * WT + i * 32 + (lane & 31)) * kDRow + kk];
+                    b[i] = *(const v4i*)&Bs[buf][(wc * WT + i * 32 + (lane & 31)) * kDRow + kk];
                     aa[i] = a[i] & 0x01010101;
                     ba[i] = b[i] & 0x01010101;
                 }
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < NT; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
+                    for (int j = 0; j < NT; ++j) {
                         accD[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], accD[i][j], 0, 0, 0);
                         accP[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[i], ba[j], accP[i][j], 0, 0, 0);
                     }
@@ -205,13 +213,13 @@ __global__ __launch_bounds__(256, 2) void k_dense(const DevBlock* __restrict__ b
     unsigned long long acc = 0;
     uint32_t* tab = tabs + B.tab_off;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int gw = T.tj * kDTile + wc * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < NT; ++j) {
+            const int gw = T.tj * TILE + wc * WT + j * 32 + (lane & 31);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int gu = T.ti * kDTile + wr * 64 + i * 32 + mfma_row(e, lane);
+                const int gu = T.ti * TILE + wr * WT + i * 32 + mfma_row(e, lane);
                 if (gu < gw && gw < B.n_r) {
                     const uint32_t P = (uint32_t)accP[i][j][e], D = (uint32_t)accD[i][j][e];
                     const uint32_t a = (P + D) >> 1, b = (P - D) >> 1;
@@ -252,10 +260,14 @@ void launch_block_pack(const uint32_t* ablk1, int32_t r_first, int32_t n_s, cons
                        blocks, aoff, acent, aneg, cblk, cidx, mats, st);
 }
 
+// tile: 64 or 128 (the output tile edge the tile list was built for)
 void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles, const int8_t* mats, uint32_t* tabs,
-                  DevStatus* st, hipStream_t s) {
-    if (n_tiles > 0)
-        hipLaunchKernelGGL(k_dense, dim3((unsigned)n_tiles), dim3(256), 0, s, blocks, tiles, mats, tabs, st);
+                  DevStatus* st, int tile, hipStream_t s) {
+    if (n_tiles <= 0) return;
+    if (tile == 64)
+        hipLaunchKernelGGL(k_dense<64>, dim3((unsigned)n_tiles), dim3(256), 0, s, blocks, tiles, mats, tabs, st);
+    else
+        hipLaunchKernelGGL(k_dense<128>, dim3((unsigned)n_tiles), dim3(256), 0, s, blocks, tiles, mats, tabs, st);
 }
 
 }  // namespace bbc

@@ -27,6 +27,7 @@ def test_autotune_picks_an_instantiated_shape_and_keeps_the_count(ctx, tmp_path)
     chosen = ctx.autotune(off, adj, sg, g.n_v, reps=1)
     assert (chosen["band_words"], chosen["wg_size"]) in bbc.WEDGE_SHAPES
     assert chosen["wg_per_cu"] >= 1
+    assert chosen["queue_chunk"] in (1, 2, 4, 8) and chosen["wave_max_work"] in (0, 256, -1)
     # a default call of the same class now uses the entry
     assert ctx.count(off, adj, sg, g.n_v) == want
     st = ctx.stats()
@@ -51,7 +52,9 @@ def test_autotune_picks_an_instantiated_shape_and_keeps_the_count(ctx, tmp_path)
     path = str(tmp_path / "tune.txt")
     ctx.tune_save(path)
     text = open(path).read().splitlines()
-    assert text[0] == "bbc-tune 2 gfx950" and len(text) == 2
+    assert text[0] == "bbc-tune 3 gfx950" and len(text) == 2
+    f = text[1].split()
+    assert len(f) == 11 and int(f[6]) == chosen["queue_chunk"] and int(f[7]) == chosen["wave_max_work"]
     c2 = bbc.Context(0)
     try:
         c2.tune_load(path)
@@ -104,6 +107,11 @@ def test_tune_load_rejects_bad_files(ctx, tmp_path):
         "fields": "bbc-tune 1 gfx950\n19 6 16384 512\n",
         "trailing": "bbc-tune 1 gfx950\n19 6 16384 512 2 1.0 x\n",
         "negative": "bbc-tune 1 gfx950\n19 6 16384 512 -1 1.0\n",
+        "v3 fields": "bbc-tune 3 gfx950\n19 6 16384 512 2 1 1 0 0 1.0\n",
+        "v3 tile": "bbc-tune 3 gfx950\n19 6 16384 512 2 1 1 0 0 96 1.0\n",
+        "v3 chunk": "bbc-tune 3 gfx950\n19 6 16384 512 2 1 -3 0 0 0 1.0\n",
+        "v3 wave": "bbc-tune 3 gfx950\n19 6 16384 512 2 1 1 -2 0 0 1.0\n",
+        "v3 empty shape": "bbc-tune 3 gfx950\n19 6 0 512 2 1 1 0 0 0 1.0\n",
         "empty": "",
     }
     for name, text in cases.items():
@@ -123,10 +131,55 @@ def test_tune_load_rejects_bad_files(ctx, tmp_path):
     out = str(tmp_path / "out.txt")
     ctx.tune_save(out)
     lines = open(out).read().splitlines()
-    assert lines == ["bbc-tune 2 gfx950", "3 4 16384 256 2 0 0.4000"]
+    assert lines == ["bbc-tune 3 gfx950", "3 4 16384 256 2 0 0 0 0 0 0.4000"]
     # version 2 entries carry the schedule
     with open(p, "w") as f:
         f.write("bbc-tune 2 gfx950\n3 4 8192 256 1 1 0.3\n")
     ctx.tune_load(p)
     ctx.tune_save(out)
-    assert open(out).read().splitlines() == ["bbc-tune 2 gfx950", "3 4 8192 256 1 1 0.3000"]
+    assert open(out).read().splitlines() == ["bbc-tune 3 gfx950", "3 4 8192 256 1 1 0 0 0 0 0.3000"]
+    # version 3: regime and dense-block columns; an entry may hold only the latter
+    with open(p, "w") as f:
+        f.write("bbc-tune 3 gfx950\n3 4 8192 256 1 0 4 -1 512 64 0.2\n5 6 0 0 0 0 0 0 1024 128 0.1\n")
+    ctx.tune_load(p)
+    ctx.tune_save(out)
+    assert open(out).read().splitlines() == ["bbc-tune 3 gfx950", "3 4 8192 256 1 0 4 -1 512 64 0.2000",
+                                              "5 6 0 0 0 0 0 0 1024 128 0.1000"]
+
+
+def test_autotune_batched_records_the_batch_class(ctx):
+    graphs = synth.batch_graphs(60, seed=4)
+    b = bbc.Batch(graphs, "cuda:0")
+    want = [oracle.count(g) for g in graphs]
+    chosen = ctx.autotune_batched(b, reps=1)
+    assert (chosen["band_words"], chosen["wg_size"]) in bbc.WEDGE_SHAPES
+    assert chosen["queue_chunk"] in (1, 2, 4, 8) and chosen["wave_max_work"] in (0, 256, -1)
+    assert list(b.totals.cpu().numpy()[: len(graphs)]) == want
+    assert list(ctx.count_batched(b).cpu().numpy()[: len(graphs)]) == want
+    st = ctx.stats()
+    assert st["tuned"] == 1 and st["band_words"] == chosen["band_words"]
+    plan = ctx.plan(b)
+    for _ in range(2):
+        plan.launch()
+        assert list(plan.wait().cpu().numpy()[: len(graphs)]) == want
+    plan.close()
+
+
+def test_autotune_blocks_and_the_int8_tiles(ctx):
+    g = synth.hybrid_graph(12_000, 6_000, 40_000, 3, 200, 0.5, 0.1, seed=8)
+    want = oracle.count(g)
+    off, adj, sg = bbc.graph_tensors(g, "cuda:0")
+    blocks = [(torch.from_numpy(c).to("cuda:0"), torch.from_numpy(r).to("cuda:0")) for r, c in g.meta["blocks"]]
+    # both tiles on the planted blocks (200 rows: not a multiple of either tile)
+    for tile in (64, 128, 0):
+        assert ctx.count(off, adj, sg, g.n_v, opts=bbc.options(blocks=blocks, dense_tile=tile)) == want
+    with pytest.raises(bbc.BbcError) as e:
+        ctx.count(off, adj, sg, g.n_v, opts=bbc.options(blocks=blocks, dense_tile=96))
+    assert e.value.status == bbc.EINVAL
+    chosen = ctx.autotune_blocks(off, adj, sg, g.n_v, reps=1)
+    assert chosen["min_degree"] in (128, 256, 512, 1024) and chosen["dense_tile"] in (64, 128)
+    # planner calls with min_degree 0 and counts with dense_tile 0 of the class use the entry
+    found = ctx.plan_blocks(off, adj, g.n_v)
+    assert ctx.count(off, adj, sg, g.n_v, opts=bbc.options(blocks=found)) == want
+    path_blocks = ctx.plan_blocks(off, adj, g.n_v, opts=bbc.plan_options(min_degree=chosen["min_degree"]))
+    assert len(path_blocks) == len(found)
