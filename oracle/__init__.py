@@ -75,6 +75,8 @@ def _load():
         lib.oracle_brute.argtypes = head + [PU, PU, PU]
         lib.oracle_count_classes.argtypes = head + [ctypes.c_int, PU]
         lib.oracle_brute_classes.argtypes = head + [ctypes.c_int, PU]
+        lib.oracle_per_vertex_classes.argtypes = head + [ctypes.c_int, PU]
+        lib.oracle_brute_per_vertex_classes.argtypes = head + [ctypes.c_int, PU]
         lib.oracle_count_bicliques.argtypes = head + [ctypes.c_int, ctypes.c_int, PU]
         lib.oracle_brute_bicliques.argtypes = head + [ctypes.c_int, ctypes.c_int, PU]
         lib.oracle_count_anchors.argtypes = head + [ctypes.c_int, i32, i32, PU, PU]
@@ -222,6 +224,25 @@ def brute_classes(g, side: int = SIDE_AUTO) -> list:
     out = (ctypes.c_uint64 * 6)()
     _check(_load().oracle_brute_classes(*a, side, out))
     return [int(x) for x in out]
+
+
+def per_vertex_classes(g, side: int = SIDE_AUTO) -> np.ndarray:
+    """uint64 [n_u + n_v, 6]: class-k butterflies containing each vertex
+    (U first), classes in the order of count_classes."""
+    keep, a = _args(g)
+    out = np.zeros((int(g.n_u) + int(g.n_v), 6), np.uint64)
+    _check(_load().oracle_per_vertex_classes(*a, side, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    del keep
+    return out
+
+
+def brute_per_vertex_classes(g, side: int = SIDE_AUTO) -> np.ndarray:
+    """The same by brute force over every 2 x 2 vertex choice (tiny graphs)."""
+    keep, a = _args(g)
+    out = np.zeros((int(g.n_u) + int(g.n_v), 6), np.uint64)
+    _check(_load().oracle_brute_per_vertex_classes(*a, side, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    del keep
+    return out
 
 
 def count_bicliques(g, k: int, side: int = SIDE_AUTO) -> int:

@@ -310,6 +310,131 @@ int oracle_count_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off
     return 0;
 }
 
+/* Per-vertex class counts (the case study's classes, Table 8, for every
+ * vertex): cnt[6 x + k] is the number of class-k butterflies (order of
+ * oracle_count_classes) that contain vertex x, U first, then V.  An anchor
+ * pair {u, w} with p / n / b shared centres of pattern ++ / -- / +- closes
+ * C(p,2), p n, C(n,2), C(b,2), p b and n b butterflies of the six classes,
+ * each containing u and w.  A centre c of a wedge u-c-w lies in the
+ * butterflies pairing that wedge with another shared centre c' of {u, w},
+ * and the class is the pair of patterns (c, c'):
+ *   c is ++: (p - 1) of class 0, n of class 1, b of class 4;
+ *   c is --: p of class 1, (n - 1) of class 2, b of class 5;
+ *   c is +-: (b - 1) of class 3, p of class 4, n of class 5.
+ * Pairs by plain id order as in oracle_count_classes. */
+int oracle_per_vertex_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                              const int8_t* sg, int side, uint64_t* cnt) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    const int s_is_u = pick_side(n_u, n_v, side) == 1;
+    sides_t g;
+    build_sides(n_u, n_v, m, off, adj, sg, side, &g);
+    uint64_t* cs = cnt + 6 * (size_t)(s_is_u ? 0 : n_u); /* anchor-side block */
+    uint64_t* cc = cnt + 6 * (size_t)(s_is_u ? n_u : 0); /* centre-side block */
+    memset(cnt, 0, sizeof(uint64_t) * 6 * ((size_t)n_u + (size_t)n_v));
+    uint32_t* P = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* N = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    uint32_t* B = (uint32_t*)calloc((size_t)g.n_s + 1, sizeof(uint32_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)g.n_s + 1));
+    for (int32_t u = 0; u < g.n_s; ++u) {
+        int32_t nt = 0;
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            const int32_t c = g.s_nbr[i];
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                const int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                if (P[w] == 0 && N[w] == 0 && B[w] == 0) touched[nt++] = w;
+                if (g.c_sgn[j] != g.s_sgn[i]) B[w]++;
+                else if (g.s_sgn[i] > 0) P[w]++;
+                else N[w]++;
+            }
+        }
+        /* second walk with the pair counts complete: the centres */
+        for (int64_t i = g.s_off[u]; i < g.s_off[u + 1]; ++i) {
+            const int32_t c = g.s_nbr[i];
+            uint64_t* x = cc + 6 * (size_t)c;
+            for (int64_t j = g.c_off[c]; j < g.c_off[c + 1]; ++j) {
+                const int32_t w = g.c_nbr[j];
+                if (w <= u) continue;
+                const uint64_t p = P[w], n = N[w], b = B[w];
+                if (g.c_sgn[j] != g.s_sgn[i]) { /* +- */
+                    x[3] += b - 1;
+                    x[4] += p;
+                    x[5] += n;
+                } else if (g.s_sgn[i] > 0) { /* ++ */
+                    x[0] += p - 1;
+                    x[1] += n;
+                    x[4] += b;
+                } else { /* -- */
+                    x[1] += p;
+                    x[2] += n - 1;
+                    x[5] += b;
+                }
+            }
+        }
+        for (int32_t k = 0; k < nt; ++k) {
+            const int32_t w = touched[k];
+            const uint64_t p = P[w], n = N[w], b = B[w];
+            const uint64_t t[6] = {choose2(p), p * n, choose2(n), choose2(b), p * b, n * b};
+            for (int q = 0; q < 6; ++q) {
+                cs[6 * (size_t)u + q] += t[q];
+                cs[6 * (size_t)w + q] += t[q];
+            }
+            P[w] = N[w] = B[w] = 0;
+        }
+    }
+    free(P);
+    free(N);
+    free(B);
+    free(touched);
+    sides_free(&g);
+    return 0;
+}
+
+/* The same per-vertex classes by brute force over every 2 x 2 vertex
+ * choice (tiny graphs): each butterfly adds one to its class at its four
+ * vertices. */
+int oracle_brute_per_vertex_classes(int32_t n_u, int32_t n_v, int64_t m, const int32_t* off, const int32_t* adj,
+                                    const int8_t* sg, int side, uint64_t* cnt) {
+    if (check_csr(n_u, n_v, m, off, adj, sg)) return 1;
+    if ((int64_t)n_u * n_v > (1LL << 24)) return 1;
+    const int su = pick_side(n_u, n_v, side) == 1;
+    const int32_t n_s = su ? n_u : n_v, n_c = su ? n_v : n_u;
+    int8_t* M = (int8_t*)calloc((size_t)n_s * (size_t)n_c + 1, 1); /* M[anchor][centre] */
+    for (int32_t u = 0; u < n_u; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            const int32_t a = su ? u : adj[e], c = su ? adj[e] : u;
+            M[(size_t)a * n_c + c] = sg[e];
+        }
+    memset(cnt, 0, sizeof(uint64_t) * 6 * ((size_t)n_u + (size_t)n_v));
+    const size_t abase = su ? 0 : (size_t)n_u, cbase = su ? (size_t)n_u : 0;
+    for (int32_t a1 = 0; a1 < n_s; ++a1)
+        for (int32_t a2 = a1 + 1; a2 < n_s; ++a2)
+            for (int32_t c1 = 0; c1 < n_c; ++c1) {
+                const int8_t x1 = M[(size_t)a1 * n_c + c1], y1 = M[(size_t)a2 * n_c + c1];
+                if (!x1 || !y1) continue;
+                for (int32_t c2 = c1 + 1; c2 < n_c; ++c2) {
+                    const int8_t x2 = M[(size_t)a1 * n_c + c2], y2 = M[(size_t)a2 * n_c + c2];
+                    if (!x2 || !y2) continue;
+                    const int t1 = x1 != y1 ? 2 : (x1 > 0 ? 0 : 1);
+                    const int t2 = x2 != y2 ? 2 : (x2 > 0 ? 0 : 1);
+                    const int lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
+                    int k;
+                    if (lo == 0 && hi == 0) k = 0;
+                    else if (lo == 0 && hi == 1) k = 1;
+                    else if (lo == 1 && hi == 1) k = 2;
+                    else if (lo == 2) k = 3;
+                    else if (lo == 0) k = 4;
+                    else k = 5;
+                    cnt[6 * (abase + (size_t)a1) + k]++;
+                    cnt[6 * (abase + (size_t)a2) + k]++;
+                    cnt[6 * (cbase + (size_t)c1) + k]++;
+                    cnt[6 * (cbase + (size_t)c2) + k]++;
+                }
+            }
+    free(M);
+    return 0;
+}
+
 /* Balanced (2,k)-bicliques (Definition 5; the extension named in Sec.
  * "Future Directions"): two vertices of the chosen side and k common
  * neighbours on the other, all 2k edges present, with no unbalanced

@@ -754,3 +754,122 @@ def test_update_batch_equals_sequence():
         assert oracle.count(oracle.apply_updates(g, uu, vv, ss)) == py_brute(oracle.apply_updates(g, uu, vv, ss))[0]
     with pytest.raises(ValueError):
         oracle.apply_updates(synth.complete_graph(2, 2), [0, 0], [1, 1], [1, -1])
+
+
+# ------------------------------------------- per-vertex sign-pattern classes
+
+def py_per_vertex_classes(g, side):
+    """Definition-level per-vertex classes (pure Python, tiny graphs): every
+    butterfly, classified by the patterns at its two centres, adds one to
+    its class at each of its four vertices (U first, then V)."""
+    import itertools
+
+    su = oracle.SIDE_U == side or (side == oracle.SIDE_AUTO and g.n_u < g.n_v)
+    sign = {}
+    for u in range(g.n_u):
+        for e in range(g.offsets[u], g.offsets[u + 1]):
+            sign[(u, int(g.adj[e]))] = int(g.signs[e])
+    n_s, n_c = (g.n_u, g.n_v) if su else (g.n_v, g.n_u)
+    key = (lambda a, c: (a, c)) if su else (lambda a, c: (c, a))
+    gid_a = (lambda a: a) if su else (lambda a: g.n_u + a)
+    gid_c = (lambda c: g.n_u + c) if su else (lambda c: c)
+    order = {("pp", "pp"): 0, ("mm", "pp"): 1, ("mm", "mm"): 2, ("pm", "pm"): 3, ("pm", "pp"): 4, ("mm", "pm"): 5}
+    out = np.zeros((g.n_u + g.n_v, 6), np.uint64)
+    for a1, a2 in itertools.combinations(range(n_s), 2):
+        for c1, c2 in itertools.combinations(range(n_c), 2):
+            s = [sign.get(key(a, c)) for a in (a1, a2) for c in (c1, c2)]
+            if None in s:
+                continue
+            x1, x2, y1, y2 = s
+            pat = sorted("pm" if x != y else ("pp" if x > 0 else "mm") for x, y in ((x1, y1), (x2, y2)))
+            k = order[tuple(pat)]
+            for x in (gid_a(a1), gid_a(a2), gid_c(c1), gid_c(c2)):
+                out[x, k] += 1
+    return out
+
+
+def test_per_vertex_classes_match_definitions():
+    """The walk equals the brute force and a pure-Python enumeration."""
+    rng = np.random.default_rng(41)
+    for i in range(60):
+        g = synth.small_random_graph(rng, max_n=8)
+        for side in (oracle.SIDE_AUTO, oracle.SIDE_U, oracle.SIDE_V):
+            got = oracle.per_vertex_classes(g, side)
+            np.testing.assert_array_equal(got, oracle.brute_per_vertex_classes(g, side))
+            if i < 25:
+                np.testing.assert_array_equal(got, py_per_vertex_classes(g, side))
+
+
+def test_per_vertex_classes_sums():
+    """Each butterfly holds two vertices of each side: per class the U
+    column and the V column sum to twice the class total; the four balanced
+    classes add up to the balanced per-vertex count."""
+    for g in _mid_graphs():
+        for side in (oracle.SIDE_U, oracle.SIDE_V):
+            pv = oracle.per_vertex_classes(g, side).astype(np.int64)
+            tot = oracle.count_classes(g, side)
+            assert list(pv[: g.n_u].sum(axis=0)) == [2 * t for t in tot]
+            assert list(pv[g.n_u:].sum(axis=0)) == [2 * t for t in tot]
+            np.testing.assert_array_equal(pv[:, :4].sum(axis=1), oracle.per_vertex(g, side).astype(np.int64))
+
+
+@pytest.mark.parametrize("s,c", [(2, 3), (4, 5)])
+def test_per_vertex_classes_closed_forms(s, c):
+    """K_{s,c} all positive: every butterfly is ++/++; a U vertex lies in
+    (s - 1) C(c,2) of them, a V vertex in (c - 1) C(s,2).  All negative with
+    the pair on U: the same counts as --/--."""
+    u, v = np.divmod(np.arange(s * c), c)
+    for sg, k in ((np.ones(s * c, np.int8), 0), (-np.ones(s * c, np.int8), 2)):
+        g = synth.from_edges(s, c, u, v, sg)
+        pv = oracle.per_vertex_classes(g, oracle.SIDE_U)
+        want = np.zeros((s + c, 6), np.uint64)
+        want[:s, k] = (s - 1) * comb(c, 2)
+        want[s:, k] = (c - 1) * comb(s, 2)
+        np.testing.assert_array_equal(pv, want)
+
+
+PV_CLASS_MUTANTS = {
+    "++ centre counts itself": ("                    x[0] += p - 1;", "                    x[0] += p;"),
+    "+- centre loses the ++ partners": ("                    x[3] += b - 1;\n                    x[4] += p;",
+                                        "                    x[3] += b - 1;\n                    x[4] += n;"),
+    "anchor w gets nothing": ("                cs[6 * (size_t)w + q] += t[q];\n", ""),
+    "-- centre: mixed class swapped": ("                    x[2] += n - 1;\n                    x[5] += b;",
+                                       "                    x[2] += n - 1;\n                    x[4] += b;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PV_CLASS_MUTANTS))
+def test_per_vertex_class_pins_catch_planted_mistakes(name, tmp_path):
+    """Each plausible slip in the per-vertex class walk makes a pin fail."""
+    import ctypes
+
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "bbc_oracle.c")).read()
+    old, new = PV_CLASS_MUTANTS[name]
+    i = src.index("int oracle_per_vertex_classes(")
+    j = src.index("int oracle_brute_per_vertex_classes(")
+    body = src[i:j]
+    assert old in body
+    mut = tmp_path / "mut.c"
+    mut.write_text(src[:i] + body.replace(old, new) + src[j:])
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(so), str(mut)])
+    lib = ctypes.CDLL(str(so))
+    P32, P8 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)
+    lib.oracle_per_vertex_classes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P32, P32, P8,
+                                              ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+
+    def mpv(g, side):
+        off = np.ascontiguousarray(g.offsets, np.int32)
+        adj = np.ascontiguousarray(g.adj, np.int32)
+        sg = np.ascontiguousarray(g.signs, np.int8)
+        out = np.zeros((g.n_u + g.n_v, 6), np.uint64)
+        lib.oracle_per_vertex_classes(g.n_u, g.n_v, adj.size, off.ctypes.data_as(P32), adj.ctypes.data_as(P32),
+                                      sg.ctypes.data_as(P8), side, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+        return out
+
+    rng = np.random.default_rng(43)
+    failures = 0
+    for _ in range(40):
+        g = synth.small_random_graph(rng, max_n=7)
+        failures += not np.array_equal(mpv(g, oracle.SIDE_U), py_per_vertex_classes(g, oracle.SIDE_U))
+    assert failures > 0, f"mutant '{name}' passed every pin"
