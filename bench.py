@@ -221,9 +221,10 @@ def bench_skewed(ctx, steps: int, warmup: int, seed: int) -> dict:
 
 def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
     """Graphs/s of the 10,000-graph batch: one captured batch plan replayed
-    (inputs resident in HBM), against a loop of plain per-graph bbc_count
-    calls on views of the same device arrays.  Both must give identical
-    per-graph totals."""
+    (inputs resident in HBM), tuned once for this batch by the autotuner
+    (untimed; the untuned plan is timed too), against a loop of plain
+    per-graph bbc_count calls on views of the same device arrays.  All must
+    give identical per-graph totals."""
     import torch
 
     from paper_2601_17707_amd import bbc, synth
@@ -235,21 +236,31 @@ def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
     n = len(graphs)
     edges = sum(g.m for g in graphs)
     print(f"# batch-10k: {n} graphs, {edges} edges (generated in {gen_s:.1f} s)", file=sys.stderr, flush=True)
-    plan = ctx.plan(batch)
-    for _ in range(max(1, warmup)):
-        plan.launch()
-        plan.wait()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    def time_plan(opts):
+        plan = ctx.plan(batch, opts=opts)
+        for _ in range(max(1, warmup)):
+            plan.launch()
+            plan.wait()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(steps):
+            plan.launch()
+        ev1.record()
+        tot = plan.wait().cpu().numpy()[:n].copy()
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / steps
+        plan.close()
+        return tot, ms, ev0.elapsed_time(ev1) / steps
+
+    # untuned plan, then the autotuner on this batch (untimed), then the
+    # tuned plan, which is the batch figure
+    totals_untuned, ms_untuned, _ = time_plan(bbc.options(no_tuning=True))
     t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(steps):
-        plan.launch()
-    ev1.record()
-    totals = plan.wait().cpu().numpy()[:n].copy()
-    torch.cuda.synchronize()
-    ms_batch = 1000.0 * (time.perf_counter() - t0) / steps
-    ms_batch_ev = ev0.elapsed_time(ev1) / steps
+    tuned = ctx.autotune_batched(batch, reps=1)
+    tune_s = time.perf_counter() - t0
+    totals, ms_batch, ms_batch_ev = time_plan(bbc.options())
 
     # aggregate rate of the batch: every graph's wedges, and the wedge
     # kernel's algorithmic bytes over its HIP-event time (one eager pass)
@@ -270,8 +281,9 @@ def bench_batched(ctx, steps: int, warmup: int, seed: int) -> dict:
         loop[i] = ctx.count(off, adj, sg, d.n_v)
     torch.cuda.synchronize()
     loop_s = time.perf_counter() - t0
-    plan.close()
     return dict(workload="batch-10k", graphs=n, edges=edges, ms_per_batch=ms_batch, ms_per_batch_events=ms_batch_ev,
+                tuned=tuned, tune_s=tune_s, ms_per_batch_untuned=ms_untuned,
+                totals_match_untuned=bool(list(totals) == list(totals_untuned)),
                 graphs_per_s=n / (ms_batch / 1e3), per_graph_loop_s=loop_s, per_graph_loop_graphs_per_s=n / loop_s,
                 speedup_vs_loop=(n / (ms_batch / 1e3)) / (n / loop_s),
                 totals_match_loop=bool(list(totals) == loop), balanced_butterflies=int(totals.sum()),

@@ -16,11 +16,14 @@
  * kernels on the caller's stream; counts are exact integers.
  *
  * Entry points: bbc_count (total, optional per-vertex counts and dense
- * blocks), bbc_count_batched and the captured batch plans, bbc_plan_blocks
- * (dense-block planner), bbc_autotune with bbc_tune_save / _load, and the
- * extensions bbc_count_classes (the six sign-pattern classes of the case
- * study), bbc_count_bicliques (balanced (2,k)-bicliques) and
- * bbc_update_delta (the change of the count under edge updates).
+ * blocks), bbc_count_noalloc (the same without any allocation),
+ * bbc_count_batched and the captured batch plans, bbc_plan_blocks
+ * (dense-block planner), bbc_autotune (and its batched and dense-block
+ * forms) with bbc_tune_save / _load, and the extensions bbc_count_classes
+ * and bbc_count_classes_per_vertex (the six sign-pattern classes of the
+ * case study, in total and per vertex), bbc_count_bicliques (balanced
+ * (2,k)-bicliques) and bbc_update_delta (the change of the count under edge
+ * updates).
  *
  * Conventions for every entry point
  *   - Graphs are a CSR over U: offsets[n_u + 1] (int32, offsets[0] = 0,
@@ -341,6 +344,22 @@ bbc_status bbc_tune_load(bbc_ctx* ctx, const char* path);
 bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                              const int32_t* adj, const int8_t* signs, uint64_t* classes, const bbc_options* opts,
                              void* stream);
+
+/* The six classes for every vertex (the case study's classes, Table 8,
+ * per vertex): per_vertex (device, (n_u + n_v) x 6 uint64, vertex-major,
+ * U ids first, then V ids) receives, for each vertex x and class k in the
+ * order of bbc_count_classes, the number of class-k butterflies that contain
+ * x; classes (host, 6 uint64) receives the totals.  Each class's U entries
+ * and its V entries both sum to twice its total.  Walks every anchor's whole
+ * list (ranks above and below it, as bbc_count's per-vertex output does)
+ * and a second time per band for the centres (one kernel shape: 256
+ * threads, 8,192-word bands).  per_vertex is overwritten, not accumulated;
+ * NULL is BBC_EINVAL unless the graph has no vertices.  Other arguments, errors and synchronisation as
+ * bbc_count_classes. */
+bbc_status bbc_count_classes_per_vertex(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
+                                        const int32_t* offsets, const int32_t* adj, const int8_t* signs,
+                                        uint64_t* classes, uint64_t* per_vertex, const bbc_options* opts,
+                                        void* stream);
 
 /* Balanced (2,k)-bicliques (Definition 5; the generalisation named in Sec.
  * "Future Directions"): two vertices of the pair side and k common

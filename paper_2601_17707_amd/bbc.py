@@ -174,6 +174,9 @@ def load_library(path: str = LIB_PATH):
     lib.bbc_count_classes.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64),
                                       ctypes.POINTER(Options), vp]
     lib.bbc_count_classes.restype = ctypes.c_int
+    lib.bbc_count_classes_per_vertex.argtypes = [vp, i32, i32, i64, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64),
+                                                 vp, ctypes.POINTER(Options), vp]
+    lib.bbc_count_classes_per_vertex.restype = ctypes.c_int
     lib.bbc_count_bicliques.argtypes = [vp, i32, i32, i64, vp, vp, vp, i32, ctypes.POINTER(ctypes.c_uint64),
                                         ctypes.POINTER(Options), vp]
     lib.bbc_count_bicliques.restype = ctypes.c_int
@@ -363,6 +366,28 @@ class Context:
         o = opts if opts is not None else options()
         st = self._lib.bbc_count_classes(self._h, offsets.numel() - 1, int(n_v), adj.numel(), _ptr(offsets),
                                          _ptr(adj), _ptr(signs), out, ctypes.byref(o), _stream_ptr(stream, offsets))
+        if st != OK:
+            raise BbcError(st, self.last_error())
+        return [int(x) for x in out]
+
+    def count_classes_per_vertex(self, offsets, adj, signs, n_v: int, per_vertex, opts: Options | None = None,
+                                 stream=None) -> list:
+        """The six classes in total (returned) and per vertex: per_vertex is a
+        device int64 tensor of shape (n_u + n_v, 6), U first, overwritten."""
+        import torch
+
+        _check_tensor("offsets", offsets, torch.int32, torch)
+        _check_tensor("adj", adj, torch.int32, torch)
+        _check_tensor("signs", signs, torch.int8, torch)
+        _check_tensor("per_vertex", per_vertex, torch.int64, torch)
+        n_u = offsets.numel() - 1
+        if per_vertex.numel() != (n_u + int(n_v)) * 6:
+            raise ValueError("per_vertex must hold (n_u + n_v) x 6 entries")
+        out = (ctypes.c_uint64 * 6)()
+        o = opts if opts is not None else options()
+        st = self._lib.bbc_count_classes_per_vertex(self._h, n_u, int(n_v), adj.numel(), _ptr(offsets), _ptr(adj),
+                                                    _ptr(signs), out, _ptr(per_vertex), ctypes.byref(o),
+                                                    _stream_ptr(stream, offsets))
         if st != OK:
             raise BbcError(st, self.last_error())
         return [int(x) for x in out]

@@ -20,7 +20,8 @@ void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* 
                           uint8_t* en, hipStream_t s);
 void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
                            const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
-                           uint32_t* ea, uint32_t* ec, uint8_t* en, hipStream_t s);
+                           uint32_t* ea, uint32_t* ec, uint8_t* en, uint32_t* deg_s, int64_t n_s, uint32_t* deg_c,
+                           int64_t n_c, hipStream_t s);
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,
                  int64_t scratch_words, const DevStatus* st, hipStream_t s);
 void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s);
@@ -83,6 +84,7 @@ bool wedge_shape_ok(int band_words, int wg);
 int wedge_block(int band_words, int wg, bool full);
 int wedge_blocks_per_cu(int band_words, int wg, bool full);
 int wedge_class_blocks_per_cu();
+int wedge_class_pv_blocks_per_cu();
 int wedge_class_band();
 int wedge_band(int band_words, int wg, bool full);
 int wedge_shape_count();
@@ -365,7 +367,8 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     uint8_t* en = (uint8_t*)P.back;
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, st);
     if (J.batched)
-        launch_decode_batched(J.off, J.adj, J.sg, P.graphs, P.vstart, J.n_graphs, m, check_sign, st, ea, ec, en, s);
+        launch_decode_batched(J.off, J.adj, J.sg, P.graphs, P.vstart, J.n_graphs, m, check_sign, st, ea, ec, en,
+                              P.deg_s, n_s, P.deg_c, n_c, s);
     else
         launch_decode_single(J.off, J.adj, J.sg, J.n_u, J.n_v, m, J.s_is_u ? 1 : 0, check_sign, st, ea, ec, en, s);
     if (hybrid) {  // block of every block vertex; ids checked in range, distinct and disjoint
@@ -379,10 +382,7 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     // degrees and ranks (Definition 6: degree, then id; ascending; a batch
     // orders by graph first)
     // (histogram replicas live in k_a, free until the edge sort)
-    if (J.batched) {
-        launch_hist(ea, m, P.deg_s, n_s, P.k_a, m, st, s);
-        launch_hist(ec, m, P.deg_c, n_c, P.k_a, m, st, s);
-    } else {  // the U side's degrees are the CSR row lengths
+    if (!J.batched) {  // (a batch's degrees come with its decode) the U side's are the CSR row lengths
         uint32_t* deg_u = J.s_is_u ? P.deg_s : P.deg_c;
         uint32_t* deg_v = J.s_is_u ? P.deg_c : P.deg_s;
         launch_row_degrees(J.off, J.n_u, deg_u, st, s);
@@ -454,7 +454,7 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
                P.hist_scan, P.partials, s, &ok, nullptr, &order);
     if (ev) (void)hipEventRecord(ev[1], s);
 
-    if (J.pv) fill_bytes(J.pv, ((int64_t)J.n_u + J.n_v) * 8, s);
+    if (J.pv) fill_bytes(J.pv, ((int64_t)J.n_u + J.n_v) * 8 * (J.classes ? 6 : 1), s);
     if (J.batched) fill_bytes(J.totals, (int64_t)J.n_graphs * 8, s);
     if (hybrid) {  // dense block products (int8 matrix cores), then the sparse walk reads their tables
         if (ev) (void)hipEventRecord(ev[4], s);
@@ -927,6 +927,50 @@ void tune_keep(bbc_ctx* ctx, int64_t n_s, int64_t m, const TuneEntry& best, bbc_
     }
 }
 
+// bbc_count_classes and bbc_count_classes_per_vertex: the class walk, with
+// per_vertex (device, (n_u + n_v) x 6) when given.
+bbc_status count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
+                         const int32_t* adj, const int8_t* signs, uint64_t* classes, uint64_t* per_vertex,
+                         const bbc_options* opts_in, void* stream) {
+    if (!ctx) return BBC_EINVAL;
+    ctx->err.clear();
+    bbc_options opts;
+    bbc_status rc = read_options(ctx, opts_in, &opts);
+    if (rc != BBC_OK) return rc;
+    if (!classes) return fail(ctx, BBC_EINVAL, "classes is NULL");
+    if (opts.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with class counts");
+    if (opts.side == BBC_SIDE_MIN_WEDGES)
+        return fail(ctx, BBC_EINVAL, "class counts depend on the paired side: choose BBC_SIDE_U, _V or _AUTO");
+    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
+    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
+        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
+    if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+
+    DeviceGuard guard(ctx->device);
+    Job J;
+    J.off = offsets;
+    J.adj = adj;
+    J.sg = signs;
+    J.n_u = n_u;
+    J.n_v = n_v;
+    J.s_is_u = side_is_u(opts.side, n_u, n_v);
+    J.m = n_edges;
+    J.n_s = J.s_is_u ? n_u : n_v;
+    J.n_c = J.s_is_u ? n_v : n_u;
+    J.checks = opts.checks;
+    J.classes = true;
+    J.pv = (unsigned long long*)per_vertex;
+    J.band_words = wedge_class_band();
+    J.schedule = opts.schedule;
+    J.wg_size = 256;
+    J.grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu
+                                             : per_vertex ? wedge_class_pv_blocks_per_cu() : wedge_class_blocks_per_cu());
+    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
+    if (rc != BBC_OK) return rc;
+    for (int k = 0; k < 6; ++k) classes[k] = (uint64_t)ctx->st_host->cls[k] / (per_vertex ? 2 : 1);
+    return BBC_OK;
+}
+
 // bbc_count and bbc_count_noalloc: the same pipeline, its buffers carved
 // from the context's arena (grown on demand) or from the device's fixed
 // scratch (no allocation; sizes beyond it are rejected).
@@ -1119,41 +1163,15 @@ bbc_status bbc_count_noalloc(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_e
 bbc_status bbc_count_classes(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,
                              const int32_t* adj, const int8_t* signs, uint64_t* classes, const bbc_options* opts_in,
                              void* stream) {
-    if (!ctx) return BBC_EINVAL;
-    ctx->err.clear();
-    bbc_options opts;
-    bbc_status rc = read_options(ctx, opts_in, &opts);
-    if (rc != BBC_OK) return rc;
-    if (!classes) return fail(ctx, BBC_EINVAL, "classes is NULL");
-    if (opts.n_blocks > 0) return fail(ctx, BBC_EINVAL, "dense blocks do not combine with class counts");
-    if (opts.side == BBC_SIDE_MIN_WEDGES)
-        return fail(ctx, BBC_EINVAL, "class counts depend on the paired side: choose BBC_SIDE_U, _V or _AUTO");
-    if (n_u < 0 || n_v < 0 || n_edges < 0) return fail(ctx, BBC_EINVAL, "negative size");
-    if (n_edges > INT32_MAX || (int64_t)n_u + (int64_t)n_v > INT32_MAX)
-        return fail(ctx, BBC_ETOOBIG, "n_edges or n_u + n_v exceeds INT32_MAX");
-    if (!offsets || (n_edges > 0 && (!adj || !signs))) return fail(ctx, BBC_EINVAL, "input pointer is NULL");
+    return count_classes(ctx, n_u, n_v, n_edges, offsets, adj, signs, classes, nullptr, opts_in, stream);
+}
 
-    DeviceGuard guard(ctx->device);
-    Job J;
-    J.off = offsets;
-    J.adj = adj;
-    J.sg = signs;
-    J.n_u = n_u;
-    J.n_v = n_v;
-    J.s_is_u = side_is_u(opts.side, n_u, n_v);
-    J.m = n_edges;
-    J.n_s = J.s_is_u ? n_u : n_v;
-    J.n_c = J.s_is_u ? n_v : n_u;
-    J.checks = opts.checks;
-    J.classes = true;
-    J.band_words = wedge_class_band();
-    J.schedule = opts.schedule;
-    J.wg_size = 256;
-    J.grid = ctx->n_cu * (opts.wg_per_cu > 0 ? opts.wg_per_cu : wedge_class_blocks_per_cu());
-    rc = run_job(ctx, J, opts, (hipStream_t)stream, nullptr, nullptr, nullptr);
-    if (rc != BBC_OK) return rc;
-    for (int k = 0; k < 6; ++k) classes[k] = (uint64_t)ctx->st_host->cls[k];
-    return BBC_OK;
+bbc_status bbc_count_classes_per_vertex(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges,
+                                        const int32_t* offsets, const int32_t* adj, const int8_t* signs,
+                                        uint64_t* classes, uint64_t* per_vertex, const bbc_options* opts_in,
+                                        void* stream) {
+    if (!per_vertex && ctx && (int64_t)n_u + n_v > 0) return fail(ctx, BBC_EINVAL, "per_vertex is NULL");
+    return count_classes(ctx, n_u, n_v, n_edges, offsets, adj, signs, classes, per_vertex, opts_in, stream);
 }
 
 bbc_status bbc_count_bicliques(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* offsets,

@@ -89,9 +89,14 @@ __global__ void k_decode_single(const int32_t* off, const int32_t* adj, const in
 // Edge j of a batch (graphs laid end to end by vstart, a prefix of the edge
 // counts) -> global (anchor id, centre id, negative).  Each graph's anchors
 // and centres are numbered from its anchor_base / centre_base.
+// The V side's degrees are counted here as well (deg_s or deg_c, whichever
+// holds the graph's V vertices, zeroed beforehand; ids out of range are
+// only flagged); the U side's come from the row lengths
+// (k_row_degrees_batched).
 __global__ void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat,
                                  const DevGraph* gr, const int64_t* vstart, int32_t n_graphs, int64_t m,
-                                 int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec, uint8_t* en) {
+                                 int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec, uint8_t* en,
+                                 uint32_t* deg_s, uint32_t* deg_c) {
     GRID_STRIDE(j, m) {
         int32_t lo = 0, hi = n_graphs - 1;  // graph holding j: last g with vstart[g] <= j
         while (lo < hi) {
@@ -106,10 +111,25 @@ __global__ void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat,
         const int32_t v = adj_cat[pe];
         const int8_t s = sg_cat[pe];
         if (v < 0 || v >= g.n_v) flag_bad(st, kBadRange, &st->bad_range, pe);
+        else if (g.s_is_u) atomicAdd(&deg_c[g.centre_base + v], 1u);
+        else atomicAdd(&deg_s[g.anchor_base + v], 1u);
         if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, pe);
         ea[j] = (uint32_t)(g.anchor_base + (g.s_is_u ? u : v));
         ec[j] = (uint32_t)(g.centre_base + (g.s_is_u ? v : u));
         en[j] = s < 0 ? 1 : 0;
+    }
+}
+
+// Degrees of the U side of every graph of a batch: its row lengths (one
+// workgroup per graph; decreasing offsets, which the checks flag, give 0).
+__global__ void k_row_degrees_batched(const int32_t* off_cat, const DevGraph* gr, uint32_t* deg_s,
+                                      uint32_t* deg_c) {
+    const DevGraph g = gr[blockIdx.x];
+    const int32_t* off = off_cat + g.off_base;
+    uint32_t* deg = g.s_is_u ? deg_s + g.anchor_base : deg_c + g.centre_base;
+    for (int32_t u = threadIdx.x; u < g.n_u; u += blockDim.x) {
+        const int32_t d = off[u + 1] - off[u];
+        deg[u] = d > 0 ? (uint32_t)d : 0u;
     }
 }
 
@@ -403,14 +423,19 @@ void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* 
                            s_is_u, check_sign, st, ea, ec, en);
 }
 
+// Decodes a batch and fills both degree arrays (deg_s: n_s, deg_c: n_c).
 void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
                            const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
-                           uint32_t* ea, uint32_t* ec, uint8_t* en, hipStream_t s) {
+                           uint32_t* ea, uint32_t* ec, uint8_t* en, uint32_t* deg_s, int64_t n_s, uint32_t* deg_c,
+                           int64_t n_c, hipStream_t s) {
     if (n_graphs <= 0) return;
+    fill_u32(deg_s, 0u, n_s, s);
+    fill_u32(deg_c, 0u, n_c, s);
     hipLaunchKernelGGL(k_check_offsets_batched, dim3(n_graphs), dim3(256), 0, s, off_cat, gr, st);
     if (m > 0)
         hipLaunchKernelGGL(k_decode_batched, dim3(grid_for(m, 256)), dim3(256), 0, s, off_cat, adj_cat, sg_cat, gr,
-                           vstart, n_graphs, m, check_sign, st, ea, ec, en);
+                           vstart, n_graphs, m, check_sign, st, ea, ec, en, deg_s, deg_c);
+    hipLaunchKernelGGL(k_row_degrees_batched, dim3(n_graphs), dim3(256), 0, s, off_cat, gr, deg_s, deg_c);
 }
 
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,

@@ -589,6 +589,53 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
 template <int MODE, int BAND_WORDS>
 __device__ __forceinline__ bool dense_band(int32_t total) { return MODE >= 6 || total >= BAND_WORDS / 16; }
 
+// The three counters (both edges positive, both negative, different) of
+// an endpoint's slot in a class layout (modes 4-7).
+template <int MODE, int BAND_WORDS>
+__device__ __forceinline__ void class_fields(const uint32_t* cnt, uint32_t rank, uint32_t& p, uint32_t& n,
+                                             uint32_t& b) {
+    uint32_t byte, shift;
+    slot_field<MODE, BAND_WORDS>(rank, 0u, byte, shift);
+    const uint32_t w = byte >> 2;
+    if constexpr (MODE == 4) {
+        const uint32_t v = cnt[w] >> shift;
+        p = v & 15u;
+        n = (v >> 4) & 15u;
+        b = (v >> 8) & 15u;
+    } else if constexpr (MODE == 5) {
+        const uint32_t v = cnt[w];
+        p = v & 255u;
+        n = (v >> 8) & 255u;
+        b = (v >> 16) & 255u;
+    } else if constexpr (MODE == 6) {
+        p = cnt[w] & 0xffffu;
+        n = cnt[w] >> 16;
+        b = cnt[w + 1] & 0xffffu;
+    } else {
+        p = cnt[w];
+        n = cnt[w + 1];
+        b = cnt[w + 2];
+    }
+}
+
+// Per-vertex class mode: an anchor walking its whole list meets itself
+// once per centre (a wedge u - c - u of pattern ++ or --); its slot is
+// cleared before the band is reduced.  Ends with a barrier.
+template <int MODE, int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void clear_self(WedgeShared<WG, BAND_WORDS, FULL>& sh, int32_t self, int64_t lo,
+                                           int64_t hi) {
+    if (threadIdx.x == 0 && (int64_t)self >= lo && (int64_t)self < hi) {
+        uint32_t byte, shift;
+        slot_field<MODE, BAND_WORDS>((uint32_t)self, 0u, byte, shift);
+        const uint32_t w = byte >> 2;
+        if constexpr (MODE == 4) sh.cnt[w] &= ~(0xfffu << shift);
+        else if constexpr (MODE == 5) sh.cnt[w] = 0u;
+        else if constexpr (MODE == 6) sh.cnt[w] = sh.cnt[w + 1] = 0u;
+        else sh.cnt[w] = sh.cnt[w + 1] = sh.cnt[w + 2] = 0u;
+    }
+    __syncthreads();
+}
+
 // One band in one call: compaction, walk, and in per-vertex mode the centre
 // walk (phases: bit 0 counts the wedges, bit 1 runs the centre walk, which
 // needs the band's counters complete over every centre of the anchor).
@@ -597,7 +644,8 @@ template <int MODE, bool FULL, int WG, int BAND_WORDS>
 __device__ __forceinline__ int32_t walk_band(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t* __restrict__ packed,
                                           const uint32_t* __restrict__ bidx, int gs, int32_t nk, int64_t lo,
                                           int64_t hi, bool seek_start, bool last, int32_t self, int phases,
-                                          int32_t& pre, bool use_pre, int64_t next_hi, const CentreMeta& cm) {
+                                          int32_t& pre, bool use_pre, int64_t next_hi, const CentreMeta& cm,
+                                          unsigned long long* __restrict__ pv = nullptr, int64_t centre_base = 0) {
     constexpr int NW = WG / kWave;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), lane = lane_id();
     SliceTable<WG>& t = sh.tab[0];
@@ -616,7 +664,66 @@ __device__ __forceinline__ int32_t walk_band(WedgeShared<WG, BAND_WORDS, FULL>& 
     }
     __syncthreads();
 
-    if constexpr (FULL) {
+    if constexpr (FULL && MODE >= 4) {
+        // per-vertex classes: the centre of every wedge u - c - w lies in
+        // the butterflies pairing it with another shared centre of {u, w};
+        // by the pattern t of this wedge (0 ++, 1 --, 2 +-) and the
+        // endpoint's counters p, n, b:
+        //   ++: p - 1 of ++/++, n of ++/--, b of ++/+-
+        //   --: p of ++/--, n - 1 of --/--, b of +-/--
+        //   +-: b - 1 of +-/+-, p of ++/+-, n of +-/--
+        // summed per lane and added to the centre's six global counters
+        // when the lane leaves the slice (halved at the end: every pair is
+        // walked from both ends)
+        if ((phases & 2) && r0 < r1) {
+            int32_t j = r0 * kWave + lane;
+            int32_t k = slice_of(t, nkc, min(j, total - 1));
+            int32_t nb = t.pre[k + 1];
+            uint32_t st = t.start[k];
+            int32_t base = (int32_t)(st & 0x7fffffffu) - t.pre[k];
+            unsigned long long run[6] = {0, 0, 0, 0, 0, 0};
+            auto flush = [&](int32_t kk) {
+                unsigned long long* dst = pv + (centre_base + sh.c_id[sh.w_k[kk]]) * 6;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    if (run[q]) atomicAdd(&dst[q], run[q]);
+                    run[q] = 0;
+                }
+            };
+            for (int32_t r = r0; r < r1; ++r, j += kWave) {
+                if (j >= total) continue;
+                while (j >= nb) {
+                    flush(k);
+                    ++k;
+                    nb = t.pre[k + 1];
+                    st = t.start[k];
+                    base = (int32_t)(st & 0x7fffffffu) - t.pre[k];
+                }
+                const uint32_t x = packed[(uint32_t)(base + j)];
+                if ((int32_t)(x >> 1) != self) {
+                    const uint32_t ng = st >> 31;
+                    const uint32_t pat = ((x & 1u) != ng) ? 2u : ng;
+                    uint32_t p, n, b;
+                    class_fields<MODE, BAND_WORDS>(sh.cnt, x >> 1, p, n, b);
+                    if (pat == 0u) {
+                        run[0] += p - 1u;
+                        run[1] += n;
+                        run[4] += b;
+                    } else if (pat == 1u) {
+                        run[1] += p;
+                        run[2] += n - 1u;
+                        run[5] += b;
+                    } else {
+                        run[3] += b - 1u;
+                        run[4] += p;
+                        run[5] += n;
+                    }
+                }
+            }
+            flush(k);
+        }
+        __syncthreads();
+    } else if constexpr (FULL) {
         // centre walk over the same rows with the band's counters complete
         if ((phases & 2) && r0 < r1) {
             constexpr uint32_t fmask = MODE == 0 ? 15u : MODE == 1 ? 255u : MODE == 2 ? 0xffffu : 0xffffffffu;
@@ -1103,13 +1210,15 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
             // the next band's end is a granule multiple unless it is the last band
             const int64_t nh = hi < n_s ? band_end(hi) : -1;
             const int32_t total = walk_band<MODE, FULL>(sh, packed, bidx, gs, deg, lo, hi, false, hi == n_s, r,
-                                                        FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm);
+                                                        FULL ? 3 : 1, pre, lo != lo0, nh < n_s ? nh : -1, cm, pv,
+                                                        centre_base);
+            if constexpr (FULL && MODE >= 4) clear_self<MODE>(sh, r, lo, hi);
             if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense_band<MODE, BAND_WORDS>(total));
             else if constexpr (BIC) reduce_bic<MODE>(sh, bv, cs, dense_band<MODE, BAND_WORDS>(total));
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense_band<MODE, BAND_WORDS>(total), total);
             ++bands;
         }
-        if constexpr (FULL) {
+        if constexpr (FULL && MODE < 4) {
             if (threadIdx.x < deg && sh.c_sum[threadIdx.x])
                 atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
         }
@@ -1139,11 +1248,14 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
                     __syncthreads();
                     int32_t pre = 0;
                     walk_band<MODE, FULL>(sh, packed, bidx, gs, nk, lo, hi, !first, hi == n_s, r, 2, pre, false, -1,
-                                          cm);
-                    if (threadIdx.x < nk && sh.c_sum[threadIdx.x])
-                        atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
+                                          cm, pv, centre_base);
+                    if constexpr (MODE < 4) {
+                        if (threadIdx.x < nk && sh.c_sum[threadIdx.x])
+                            atomicAdd(&pv[centre_base + sh.c_id[threadIdx.x]], sh.c_sum[threadIdx.x]);
+                    }
                 }
             }
+            if constexpr (FULL && MODE >= 4) clear_self<MODE>(sh, r, lo, hi);
             if constexpr (MODE >= 4) reduce_classes<MODE>(sh, cs, dense);
             else if constexpr (BIC) reduce_bic<MODE>(sh, bv, cs, dense);
             else acc += reduce_band<MODE, FULL>(sh, lo, hi, r, cr, dense, total);
@@ -1308,19 +1420,29 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
         if (deg < (BIC ? bv.k : 2) || (!FULL && r >= n_end - 1)) return;
         constexpr int M0 = CLS ? 4 : 0;  // counter mode of degree class 0; classes use modes 4-7
         unsigned long long a;
+        // per-vertex classes: the anchor's own six sums, then the totals
+        ClassSums ca;
+        ClassSums& csa = (FULL && CLS) ? ca : cs;
         if (deg <= 15)
             a = count_anchor<M0 + 0, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
-                                                  pv, centre_base, bands, hv, cs, bv);
+                                                  pv, centre_base, bands, hv, csa, bv);
         else if (deg <= 255)
             a = count_anchor<M0 + 1, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
-                                                  pv, centre_base, bands, hv, cs, bv);
+                                                  pv, centre_base, bands, hv, csa, bv);
         else if (deg <= 65535)
             a = count_anchor<M0 + 2, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
-                                                  pv, centre_base, bands, hv, cs, bv);
+                                                  pv, centre_base, bands, hv, csa, bv);
         else
             a = count_anchor<M0 + 3, FULL, BIC>(sh, acent, aneg, back, coff, packed, bidx, bmeta, a0, deg, r, n_end,
-                                                  pv, centre_base, bands, hv, cs, bv);
-        if constexpr (FULL) {
+                                                  pv, centre_base, bands, hv, csa, bv);
+        if constexpr (FULL && CLS) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const unsigned long long s = block_sum<WG>(ca.c[q], (unsigned long long*)sh.scan_tmp);
+                if (tid == 0) pv[(anchor_base + inv[r]) * 6 + q] = s;
+                cs.c[q] += ca.c[q];
+            }
+        } else if constexpr (FULL) {
             const unsigned long long s = block_sum<WG>(a, (unsigned long long*)sh.scan_tmp);
             if (tid == 0) pv[anchor_base + inv[r]] = s;
         } else if (gtotals) {
@@ -1453,6 +1575,7 @@ static const WedgeShape kShapes[] = {BBC_SHAPE(256, 8192),  BBC_SHAPE(512, 16384
                                      BBC_SHAPE(128, 4096),  BBC_SHAPE(128, 8192),   BBC_SHAPE(256, 4096)};
 #undef BBC_SHAPE
 constexpr int kFullWG = 256, kFullBW = 16384;
+constexpr int kFullClsWG = 256, kFullClsBW = 8192;  // per-vertex classes
 constexpr int kClsWG = 256, kClsBW = 8192;  // sign-pattern classes: one shape
 constexpr int kBicWG = 256, kBicBW = 8192;  // (2,k)-bicliques: one shape, the count layouts
 
@@ -1490,6 +1613,8 @@ void wedge_shape(int i, int* wg, int* band_words) {
 
 int wedge_class_blocks_per_cu() { return occupancy<kClsWG, kClsBW, false, true>(); }
 
+int wedge_class_pv_blocks_per_cu() { return occupancy<kFullClsWG, kFullClsBW, true, true>(); }
+
 int wedge_class_band() { return kClsBW; }
 
 int wedge_bic_blocks_per_cu() { return occupancy<kBicWG, kBicBW, false, false, true>(); }
@@ -1517,11 +1642,15 @@ void launch_wedge(int band_words, int wg, int grid, const uint32_t* aoff, const 
                       SchedArgs{sched == 1 ? 1 : 0, queue_chunk > 0 ? queue_chunk : 1,
                                 light_chunk > 0 ? light_chunk : 1}};
     if (pv) {
-        launch_shape<kFullWG, kFullBW, true>(a, grid, s);
+        // per-vertex output: U ids first, then V ids; six counters per
+        // vertex in class mode
+        const int64_t per = kind == kWedgeClasses ? 6 : 1;
+        if (kind == kWedgeClasses) launch_shape<kFullClsWG, kFullClsBW, true, true>(a, grid, s);
+        else launch_shape<kFullWG, kFullBW, true>(a, grid, s);
         if (n_centre > 0) {
-            int64_t g = (n_centre + 255) / 256;
-            hipLaunchKernelGGL(k_halve, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, s, pv + centre_base,
-                               n_centre);
+            int64_t g = (n_centre * per + 255) / 256;
+            hipLaunchKernelGGL(k_halve, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0, s,
+                               pv + centre_base * per, n_centre * per);
         }
         return;
     }
