@@ -17,14 +17,17 @@
 namespace bbc {
 void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v,
                           int64_t m, int s_is_u, int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec,
-                          uint8_t* en, hipStream_t s);
+                          uint8_t* en, uint32_t* pay, hipStream_t s);
 void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
                            const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
-                           uint32_t* ea, uint32_t* ec, uint8_t* en, uint32_t* deg_s, int64_t n_s, uint32_t* deg_c,
-                           int64_t n_c, hipStream_t s);
+                           uint32_t* ea, uint32_t* pay, hipStream_t s);
+void launch_run_degrees(const uint32_t* key, int64_t m, uint32_t* first, uint32_t* deg, int64_t n,
+                        const DevStatus* st, hipStream_t s);
+void launch_move_lists(const uint32_t* key, const uint32_t* pay, int64_t m, const uint32_t* first,
+                       const int32_t* rank, const uint32_t* aoff, int32_t* acent, uint8_t* aneg, uint32_t* apack,
+                       const DevStatus* st, hipStream_t s);
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,
                  int64_t scratch_words, const DevStatus* st, hipStream_t s);
-void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s);
 void launch_side_wedges(const int32_t* off, int32_t n_u, const int32_t* adj, int64_t m, int32_t n_v, uint32_t* deg,
                         unsigned long long* out, hipStream_t s);
 void dyn_check(const int32_t* uu, const int32_t* vv, const int8_t* ss, int32_t q, int32_t n_u, int32_t n_v,
@@ -47,11 +50,6 @@ void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, h
 void launch_gather(const uint32_t* idx, const uint32_t* src, int64_t n, uint32_t* out, hipStream_t s);
 void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32_t* rank, uint32_t* adeg,
                   const uint32_t* agid, int32_t* agraph, hipStream_t s);
-void launch_edge_keys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
-                      uint32_t* key, uint32_t* pay, const DevStatus* st, hipStream_t s);
-void launch_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, int32_t* acent, uint8_t* aneg,
-                         uint32_t* apack, const DevStatus* st, hipStream_t s);
-void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s);
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s);
 void launch_work(const uint32_t* apack, const int32_t* acent, const int32_t* back, const uint32_t* coff, int64_t m,
                  int64_t n_s, unsigned long long* work, uint32_t* key, const uint32_t* aoff, const int32_t* agraph,
@@ -245,6 +243,7 @@ struct Job {
     const int8_t* sg = nullptr;
     int32_t n_u = 0, n_v = 0;
     bool s_is_u = false;
+    bool all_su = false;  // batch: every graph's anchors are its U rows (edges already grouped by anchor)
     unsigned long long* pv = nullptr;  // single graph: per-vertex output or null
     int32_t n_graphs = 0;              // batch
     unsigned long long* totals = nullptr;
@@ -361,16 +360,16 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     const int64_t m = J.m, n_s = J.n_s, n_c = J.n_c;
     const bool hybrid = J.n_blocks > 0;
     const int check_sign = (J.checks & BBC_CHECK_SIGNS) ? 1 : 0;
-    // edge decode buffers alias space that is free until the centre sort
+    // decoded edges (anchor id; centre id | negative << 31) in buffers that
+    // are free until the centre sort
     uint32_t* ea = P.v1_a;
-    uint32_t* ec = P.v1_b;
-    uint8_t* en = (uint8_t*)P.back;
+    uint32_t* pay = P.v1_b;
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, st);
     if (J.batched)
-        launch_decode_batched(J.off, J.adj, J.sg, P.graphs, P.vstart, J.n_graphs, m, check_sign, st, ea, ec, en,
-                              P.deg_s, n_s, P.deg_c, n_c, s);
+        launch_decode_batched(J.off, J.adj, J.sg, P.graphs, P.vstart, J.n_graphs, m, check_sign, st, ea, pay, s);
     else
-        launch_decode_single(J.off, J.adj, J.sg, J.n_u, J.n_v, m, J.s_is_u ? 1 : 0, check_sign, st, ea, ec, en, s);
+        launch_decode_single(J.off, J.adj, J.sg, J.n_u, J.n_v, m, J.s_is_u ? 1 : 0, check_sign, st, ea, nullptr,
+                             nullptr, pay, s);
     if (hybrid) {  // block of every block vertex; ids checked in range, distinct and disjoint
         fill_u32(P.agrp, 0u, n_s, s);
         fill_u32((uint32_t*)P.cblk, 0xffffffffu, n_c, s);
@@ -379,15 +378,20 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     }
     if (ev) (void)hipEventRecord(ev[0], s);
 
-    // degrees and ranks (Definition 6: degree, then id; ascending; a batch
-    // orders by graph first)
-    // (histogram replicas live in k_a, free until the edge sort)
-    if (!J.batched) {  // (a batch's degrees come with its decode) the U side's are the CSR row lengths
-        uint32_t* deg_u = J.s_is_u ? P.deg_s : P.deg_c;
-        uint32_t* deg_v = J.s_is_u ? P.deg_c : P.deg_s;
-        launch_row_degrees(J.off, J.n_u, deg_u, st, s);
-        launch_hist(J.s_is_u ? ec : ea, m, deg_v, J.n_v, P.k_a, m, st, s);
-    }
+    // edges grouped by anchor by a stable sort on the anchor id (CSR rows
+    // are grouped already when the anchors are U): each anchor's run gives
+    // its degree and its first position (held in the work array, which is
+    // free until the schedule)
+    const uint32_t *sk = ea, *sp = pay;
+    if (!(J.batched ? J.all_su : J.s_is_u))
+        radix_sort(ea, P.k_a, P.k_b, pay, P.v0_a, P.v0_b, nullptr, nullptr, nullptr, m,
+                   bits_for(n_s > 0 ? (uint64_t)(n_s - 1) : 0), P.hist, P.hist_scan, P.partials, s, &sk, &sp,
+                   nullptr);
+    uint32_t* afirst = reinterpret_cast<uint32_t*>(P.work);
+    launch_run_degrees(sk, m, afirst, P.deg_s, n_s, st, s);
+
+    // ranks (Definition 6: degree, then id; ascending; a batch orders by
+    // graph first)
     const uint32_t *rk_k = nullptr, *inv = nullptr;
     radix_sort(P.deg_s, P.rk_ka, P.rk_kb, nullptr, nullptr, nullptr, nullptr, P.rk_va, P.rk_vb, n_s,
                bits_for((uint64_t)(m > 0 ? m : 1)), P.hist, P.hist_scan, P.partials, s, &rk_k, nullptr, &inv);
@@ -409,22 +413,19 @@ void enqueue(const Job& J, Plan& P, DevStatus* st, hipStream_t s, hipEvent_t* ev
     launch_ranks(inv, P.deg_s, n_s, P.rank, P.adeg, J.batched ? P.agid : nullptr, J.batched ? P.agraph : nullptr, s);
     scan_exclusive_u32(P.adeg, P.aoff, n_s, P.partials, s);
 
-    // anchor lists by a stable sort of the edges on their anchor's rank, then
+    // anchor lists in rank order (each anchor's run moved as a whole), then
     // centre lists by a stable sort on the centre id of the rank-ordered
-    // anchor entries (each centre list comes out rank-sorted)
-    launch_edge_keys(ea, ec, en, m, P.rank, P.k_b, P.v0_b, st, s);
-    {
-        const uint32_t *sk = nullptr, *sp = nullptr;
-        radix_sort(P.k_b, P.k_a, P.k_b, P.v0_b, P.v0_a, P.v0_b, nullptr, nullptr, nullptr, m,
-                   bits_for(n_s > 0 ? (uint64_t)(n_s - 1) : 0), P.hist, P.hist_scan, P.partials, s, &sk, &sp, nullptr);
-        launch_unpack_edges(sk, sp, m, P.acent, P.aneg, P.apack, st, s);
-    }
-    const uint32_t *ckey = nullptr, *packed = nullptr, *perm = nullptr;
+    // anchor entries (each centre list comes out rank-sorted); the sort's
+    // last pass writes back[] (where each anchor entry went)
+    launch_move_lists(sk, sp, m, afirst, P.rank, P.aoff, P.acent, P.aneg, P.apack, st, s);
+    const uint32_t *ckey = nullptr, *packed = nullptr;
     radix_sort((const uint32_t*)P.acent, P.k_a, P.k_b, P.apack, P.v0_a, P.v0_b, nullptr, P.v1_a, P.v1_b, m,
                bits_for(n_c > 0 ? (uint64_t)(n_c - 1) : 0), P.hist, P.hist_scan, P.partials, s, &ckey, &packed,
-               &perm);
+               nullptr, P.back);
+    // centre degrees from the runs of the sorted centre ids (coff holds the
+    // runs' first positions until the scan)
+    launch_run_degrees(ckey, m, P.coff, P.deg_c, n_c, st, s);
     scan_exclusive_u32(P.deg_c, P.coff, n_c, P.partials, s);
-    launch_back(perm, m, P.back, s);
     if (J.checks & BBC_CHECK_DUPLICATES) launch_check_dup(ckey, packed, m, st, s);
     if (!J.pv) {  // band ends of the count-mode wedge kernel fall on multiples of its granule
         int gs = 0;
@@ -649,6 +650,8 @@ bbc_status batch_job(bbc_ctx* ctx, int32_t n_graphs, const bbc_graph_desc* d, co
     }
     vstart[(size_t)n_graphs] = m;
     rend[(size_t)n_graphs] = ns;
+    J.all_su = true;
+    for (const DevGraph& y : dg) J.all_su = J.all_su && y.s_is_u;
     J.batched = true;
     J.off = off_cat;
     J.adj = adj_cat;
@@ -1300,7 +1303,7 @@ bbc_status bbc_update_delta(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_ed
     DevStatus* st = ctx->st_dev;
     // checks first (the builds below index with the ids), one wait
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, st);
-    launch_decode_single(offsets, adj, signs, n_u, n_v, m, 1, 1, st, D.ea, D.ec, D.en, s);
+    launch_decode_single(offsets, adj, signs, n_u, n_v, m, 1, 1, st, D.ea, D.ec, D.en, nullptr, s);
     dyn_check(upd_u, upd_v, upd_state, (int32_t)q, n_u, n_v, st, s);
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
@@ -1667,7 +1670,8 @@ bbc_status bbc_plan_blocks(bbc_ctx* ctx, int32_t n_u, int32_t n_v, int64_t n_edg
 
     // edges as (anchor, centre) with the offset and id-range checks
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, ctx->st_dev);
-    launch_decode_single(offsets, adj, nullptr, n_u, n_v, m, su ? 1 : 0, 0, ctx->st_dev, ea, ec, nullptr, s);
+    launch_decode_single(offsets, adj, nullptr, n_u, n_v, m, su ? 1 : 0, 0, ctx->st_dev, ea, ec, nullptr, nullptr,
+                         s);
     HIP_OR_FAIL(hipMemcpyAsync(ctx->st_host, ctx->st_dev, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(hipStreamSynchronize(s));
     bbc_status rc = status_result(ctx, *ctx->st_host);

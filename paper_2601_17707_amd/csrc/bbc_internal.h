@@ -166,12 +166,14 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
 // one of the two ping-pong buffers, returned through *_out.  v0_in may be
 // NULL (no payload 0); v1_in == NULL with v1 buffers set means payload 1 is
 // the input index.  `hist` needs radix_hist_size(n) uint32 and `partials`
-// scan_partials_size(radix_hist_size(n)).
+// scan_partials_size(radix_hist_size(n)).  With inv_out (n int32), payload
+// 1 is not returned: inv_out[payload 1 of an item] = its sorted position
+// (with v1_in == NULL: inv_out[i] = where input item i went).
 size_t radix_hist_size(int64_t n);
 void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32_t* v0_in, uint32_t* v0_a,
                 uint32_t* v0_b, const uint32_t* v1_in, uint32_t* v1_a, uint32_t* v1_b, int64_t n, int bits,
                 uint32_t* hist, uint32_t* hist_scan, uint32_t* partials, hipStream_t s, const uint32_t** k_out,
-                const uint32_t** v0_out, const uint32_t** v1_out);
+                const uint32_t** v0_out, const uint32_t** v1_out, int32_t* inv_out = nullptr);
 
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void fill_bytes(void* p, int64_t bytes, hipStream_t s);  // zero fill

@@ -57,10 +57,9 @@ __global__ void k_check_offsets_batched(const int32_t* off_cat, const DevGraph* 
     }
 }
 
-// Row of CSR entry e: the u with off[u] <= e < off[u + 1] (in range even
-// for malformed offsets; those are flagged separately).
-__device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n_u, int64_t e) {
-    int32_t lo = 0, hi = n_u - 1;
+// Row of CSR entry e among rows [lo, hi]: the last u with off[u] <= e (in
+// range even for malformed offsets; those are flagged separately).
+__device__ __forceinline__ int32_t row_in(const int32_t* off, int32_t lo, int32_t hi, int64_t e) {
     while (lo < hi) {
         int32_t mid = lo + (hi - lo + 1) / 2;
         if ((int64_t)off[mid] <= e) lo = mid;
@@ -69,67 +68,125 @@ __device__ __forceinline__ int32_t row_of(const int32_t* off, int32_t n_u, int64
     return lo;
 }
 
-// Edge e of a single graph -> (anchor id, centre id, negative), with the
+// Graph of batch edge j among graphs [lo, hi]: the last g with vstart[g] <= j.
+__device__ __forceinline__ int32_t graph_in(const int64_t* vstart, int32_t lo, int32_t hi, int64_t j) {
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo + 1) / 2;
+        if (vstart[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The decode kernels give each workgroup a chunk of kDecChunk consecutive
+// edges: the rows (and graphs) of the chunk lie between those of its first
+// and last edge, found once per workgroup, so each edge searches only that
+// range.
+constexpr int kDecThreads = 256;
+constexpr int kDecChunk = kDecThreads * 16;
+
+// Edge e of a single graph -> anchor id ea[e] and either pay[e] = centre id
+// | negative << 31 (the count) or ec[e] and en[e] (other users), with the
 // id-range and sign checks.
-__global__ void k_decode_single(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v,
-                                int64_t m, int s_is_u, int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec,
-                                uint8_t* en) {
-    GRID_STRIDE(e, m) {
-        const int32_t u = row_of(off, n_u, e);
+__global__ __launch_bounds__(kDecThreads) void k_decode_single(const int32_t* off, const int32_t* adj,
+                                                               const int8_t* sg, int32_t n_u, int32_t n_v, int64_t m,
+                                                               int s_is_u, int check_sign, DevStatus* st, uint32_t* ea,
+                                                               uint32_t* ec, uint8_t* en, uint32_t* pay) {
+    __shared__ int32_t rr[2];
+    const int64_t e0 = (int64_t)blockIdx.x * kDecChunk;
+    const int64_t e1 = min(m, e0 + kDecChunk);
+    if (threadIdx.x < 2) rr[threadIdx.x] = row_in(off, 0, n_u - 1, threadIdx.x ? e1 - 1 : e0);
+    __syncthreads();
+    const int32_t lo = rr[0], hi = rr[1];
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kDecThreads) {
+        const int32_t u = row_in(off, lo, hi, e);
         const int32_t v = adj[e];
         const int8_t s = sg ? sg[e] : (int8_t)1;  // no signs: the block planner
         if (v < 0 || v >= n_v) flag_bad(st, kBadRange, &st->bad_range, e);
         if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, e);
+        const uint32_t neg = s < 0 ? 1u : 0u;
         ea[e] = (uint32_t)(s_is_u ? u : v);
-        ec[e] = (uint32_t)(s_is_u ? v : u);
-        if (en) en[e] = s < 0 ? 1 : 0;
+        if (pay) {
+            pay[e] = (uint32_t)(s_is_u ? v : u) | (neg << 31);
+        } else {
+            ec[e] = (uint32_t)(s_is_u ? v : u);
+            if (en) en[e] = (uint8_t)neg;
+        }
     }
 }
 
 // Edge j of a batch (graphs laid end to end by vstart, a prefix of the edge
-// counts) -> global (anchor id, centre id, negative).  Each graph's anchors
-// and centres are numbered from its anchor_base / centre_base.
-// The V side's degrees are counted here as well (deg_s or deg_c, whichever
-// holds the graph's V vertices, zeroed beforehand; ids out of range are
-// only flagged); the U side's come from the row lengths
-// (k_row_degrees_batched).
-__global__ void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat,
-                                 const DevGraph* gr, const int64_t* vstart, int32_t n_graphs, int64_t m,
-                                 int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec, uint8_t* en,
-                                 uint32_t* deg_s, uint32_t* deg_c) {
-    GRID_STRIDE(j, m) {
-        int32_t lo = 0, hi = n_graphs - 1;  // graph holding j: last g with vstart[g] <= j
-        while (lo < hi) {
-            int32_t mid = lo + (hi - lo + 1) / 2;
-            if (vstart[mid] <= j) lo = mid;
-            else hi = mid - 1;
-        }
-        const DevGraph g = gr[lo];
-        const int64_t e = j - vstart[lo];  // edge index inside the graph
+// counts) -> global anchor id ea[j] and pay[j] = global centre id |
+// negative << 31.  Each graph's anchors and centres are numbered from its
+// anchor_base / centre_base.
+__global__ __launch_bounds__(kDecThreads) void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat,
+                                                                const int8_t* sg_cat, const DevGraph* gr,
+                                                                const int64_t* vstart, int32_t n_graphs, int64_t m,
+                                                                int check_sign, DevStatus* st, uint32_t* ea,
+                                                                uint32_t* pay) {
+    __shared__ int32_t gg[2], rr[2];
+    const int t = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * kDecChunk;
+    const int64_t e1 = min(m, e0 + kDecChunk);
+    if (t < 2) gg[t] = graph_in(vstart, 0, n_graphs - 1, t ? e1 - 1 : e0);
+    __syncthreads();
+    if (t < 2) {  // rows of the first and last edge inside their graphs
+        const DevGraph g = gr[gg[t]];
+        rr[t] = row_in(off_cat + g.off_base, 0, g.n_u - 1, (t ? e1 - 1 : e0) - vstart[gg[t]]);
+    }
+    __syncthreads();
+    const int32_t g_lo = gg[0], g_hi = gg[1];
+    for (int64_t j = e0 + t; j < e1; j += kDecThreads) {
+        const int32_t gi = graph_in(vstart, g_lo, g_hi, j);
+        const DevGraph g = gr[gi];
+        const int64_t e = j - vstart[gi];    // edge index inside the graph
         const int64_t pe = g.edge_base + e;  // position in the concatenated arrays
-        const int32_t u = row_of(off_cat + g.off_base, g.n_u, e);
+        const int32_t u = row_in(off_cat + g.off_base, gi == g_lo ? rr[0] : 0, gi == g_hi ? rr[1] : g.n_u - 1, e);
         const int32_t v = adj_cat[pe];
         const int8_t s = sg_cat[pe];
         if (v < 0 || v >= g.n_v) flag_bad(st, kBadRange, &st->bad_range, pe);
-        else if (g.s_is_u) atomicAdd(&deg_c[g.centre_base + v], 1u);
-        else atomicAdd(&deg_s[g.anchor_base + v], 1u);
         if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, pe);
         ea[j] = (uint32_t)(g.anchor_base + (g.s_is_u ? u : v));
-        ec[j] = (uint32_t)(g.centre_base + (g.s_is_u ? v : u));
-        en[j] = s < 0 ? 1 : 0;
+        pay[j] = (uint32_t)(g.centre_base + (g.s_is_u ? v : u)) | ((s < 0 ? 1u : 0u) << 31);
     }
 }
 
-// Degrees of the U side of every graph of a batch: its row lengths (one
-// workgroup per graph; decreasing offsets, which the checks flag, give 0).
-__global__ void k_row_degrees_batched(const int32_t* off_cat, const DevGraph* gr, uint32_t* deg_s,
-                                      uint32_t* deg_c) {
-    const DevGraph g = gr[blockIdx.x];
-    const int32_t* off = off_cat + g.off_base;
-    uint32_t* deg = g.s_is_u ? deg_s + g.anchor_base : deg_c + g.centre_base;
-    for (int32_t u = threadIdx.x; u < g.n_u; u += blockDim.x) {
-        const int32_t d = off[u + 1] - off[u];
-        deg[u] = d > 0 ? (uint32_t)d : 0u;
+// Degrees from a sorted id array: every id's entries form one run, so the
+// run's first position goes to first[id] and its end to deg[id] (zeroed
+// beforehand); k_run_degrees then leaves the run length in deg (0 for ids
+// that never occur).  Nothing runs after an input error (ids may be out of
+// range then).
+__global__ void k_run_bounds(const uint32_t* key, int64_t m, uint32_t* first, uint32_t* deg, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(p, m) {
+        const uint32_t k = key[p];
+        if (p == 0 || key[p - 1] != k) first[k] = (uint32_t)p;
+        if (p == m - 1 || key[p + 1] != k) deg[k] = (uint32_t)(p + 1);
+    }
+}
+
+__global__ void k_run_degrees(const uint32_t* first, int64_t n, uint32_t* deg) {
+    GRID_STRIDE(i, n) {
+        const uint32_t end = deg[i];
+        deg[i] = end ? end - first[i] : 0u;
+    }
+}
+
+// Anchor lists in rank order from the edges sorted (stably) by anchor id:
+// the run of anchor a moves, in its order, to aoff[rank[a]]; each entry
+// becomes centre id, sign, and the packed rank << 1 | neg that goes into
+// the centre lists.
+__global__ void k_move_lists(const uint32_t* key, const uint32_t* pay, int64_t m, const uint32_t* first,
+                             const int32_t* rank, const uint32_t* aoff, int32_t* acent, uint8_t* aneg,
+                             uint32_t* apack, const DevStatus* st) {
+    if (input_bad(st)) return;
+    GRID_STRIDE(p, m) {
+        const uint32_t a = key[p], c = pay[p];
+        const int32_t r = rank[a];
+        const int64_t q = (int64_t)aoff[r] + (p - (int64_t)first[a]);
+        acent[q] = (int32_t)(c & 0x7fffffffu);
+        aneg[q] = (uint8_t)(c >> 31);
+        apack[q] = ((uint32_t)r << 1) | (c >> 31);
     }
 }
 
@@ -191,12 +248,6 @@ __global__ void k_side_bins(const uint32_t* deg, int32_t n_v, unsigned long long
     if (lane_id() == 0 && acc) atomicAdd(&out[1], acc);
 }
 
-// Degrees of the CSR rows (U) straight from the offsets.
-__global__ void k_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st) {
-    const bool bad = input_bad(st);
-    GRID_STRIDE(i, n_u) deg[i] = bad ? 0u : (uint32_t)(off[i + 1] - off[i]);
-}
-
 // graph id of every anchor of a batch (one workgroup per graph)
 __global__ void k_anchor_graph(const DevGraph* gr, uint32_t* agid) {
     const DevGraph g = gr[blockIdx.x];
@@ -218,37 +269,6 @@ __global__ void k_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s,
         adeg[r] = deg_s[id];
         if (agraph) agraph[r] = (int32_t)agid[id];
     }
-}
-
-// ------------------------------------------------------------- anchor lists
-
-// Sort key (anchor rank) and payload (centre id | negative << 31) of every
-// edge; a stable sort on the key lays out the anchor lists in rank order.
-__global__ void k_edge_keys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m,
-                            const int32_t* rank, uint32_t* key, uint32_t* pay, const DevStatus* st) {
-    if (input_bad(st)) return;
-    GRID_STRIDE(e, m) {
-        key[e] = (uint32_t)rank[ea[e]];
-        pay[e] = ec[e] | ((uint32_t)en[e] << 31);
-    }
-}
-
-// Anchor lists from the rank-sorted edges: centre id, sign, and the packed
-// rank << 1 | neg that goes into the centre lists.
-__global__ void k_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, int32_t* acent, uint8_t* aneg,
-                               uint32_t* apack, const DevStatus* st) {
-    if (input_bad(st)) return;
-    GRID_STRIDE(p, m) {
-        const uint32_t c = pay[p];
-        acent[p] = (int32_t)(c & 0x7fffffffu);
-        aneg[p] = (uint8_t)(c >> 31);
-        apack[p] = (key[p] << 1) | (c >> 31);
-    }
-}
-
-// back[perm[q]] = q: where each anchor entry sits in its centre's list
-__global__ void k_back(const uint32_t* perm, int64_t m, int32_t* back) {
-    GRID_STRIDE(q, m) back[perm[q]] = (int32_t)q;
 }
 
 // A repeated (u, v) pair shows up as the same anchor rank twice in a row of
@@ -416,26 +436,39 @@ static int grid_for(int64_t n, int threads, int cap = 16384) {
 
 void launch_decode_single(const int32_t* off, const int32_t* adj, const int8_t* sg, int32_t n_u, int32_t n_v,
                           int64_t m, int s_is_u, int check_sign, DevStatus* st, uint32_t* ea, uint32_t* ec,
-                          uint8_t* en, hipStream_t s) {
+                          uint8_t* en, uint32_t* pay, hipStream_t s) {
     hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n_u + 1, 256)), dim3(256), 0, s, off, n_u, m, st);
     if (m > 0)
-        hipLaunchKernelGGL(k_decode_single, dim3(grid_for(m, 256)), dim3(256), 0, s, off, adj, sg, n_u, n_v, m,
-                           s_is_u, check_sign, st, ea, ec, en);
+        hipLaunchKernelGGL(k_decode_single, dim3((unsigned)((m + kDecChunk - 1) / kDecChunk)), dim3(kDecThreads), 0, s,
+                           off, adj, sg, n_u, n_v, m, s_is_u, check_sign, st, ea, ec, en, pay);
 }
 
-// Decodes a batch and fills both degree arrays (deg_s: n_s, deg_c: n_c).
 void launch_decode_batched(const int32_t* off_cat, const int32_t* adj_cat, const int8_t* sg_cat, const DevGraph* gr,
                            const int64_t* vstart, int32_t n_graphs, int64_t m, int check_sign, DevStatus* st,
-                           uint32_t* ea, uint32_t* ec, uint8_t* en, uint32_t* deg_s, int64_t n_s, uint32_t* deg_c,
-                           int64_t n_c, hipStream_t s) {
+                           uint32_t* ea, uint32_t* pay, hipStream_t s) {
     if (n_graphs <= 0) return;
-    fill_u32(deg_s, 0u, n_s, s);
-    fill_u32(deg_c, 0u, n_c, s);
     hipLaunchKernelGGL(k_check_offsets_batched, dim3(n_graphs), dim3(256), 0, s, off_cat, gr, st);
     if (m > 0)
-        hipLaunchKernelGGL(k_decode_batched, dim3(grid_for(m, 256)), dim3(256), 0, s, off_cat, adj_cat, sg_cat, gr,
-                           vstart, n_graphs, m, check_sign, st, ea, ec, en, deg_s, deg_c);
-    hipLaunchKernelGGL(k_row_degrees_batched, dim3(n_graphs), dim3(256), 0, s, off_cat, gr, deg_s, deg_c);
+        hipLaunchKernelGGL(k_decode_batched, dim3((unsigned)((m + kDecChunk - 1) / kDecChunk)), dim3(kDecThreads), 0,
+                           s, off_cat, adj_cat, sg_cat, gr, vstart, n_graphs, m, check_sign, st, ea, pay);
+}
+
+// deg[id] = number of entries of id in the sorted key array (n ids);
+// first[id] = position of its first entry (ids that occur)
+void launch_run_degrees(const uint32_t* key, int64_t m, uint32_t* first, uint32_t* deg, int64_t n,
+                        const DevStatus* st, hipStream_t s) {
+    if (n <= 0) return;
+    fill_u32(deg, 0u, n, s);
+    if (m > 0) hipLaunchKernelGGL(k_run_bounds, dim3(grid_for(m, 256)), dim3(256), 0, s, key, m, first, deg, st);
+    hipLaunchKernelGGL(k_run_degrees, dim3(grid_for(n, 256)), dim3(256), 0, s, first, n, deg);
+}
+
+void launch_move_lists(const uint32_t* key, const uint32_t* pay, int64_t m, const uint32_t* first,
+                       const int32_t* rank, const uint32_t* aoff, int32_t* acent, uint8_t* aneg, uint32_t* apack,
+                       const DevStatus* st, hipStream_t s) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_move_lists, dim3(grid_for(m, 256)), dim3(256), 0, s, key, pay, m, first, rank, aoff,
+                           acent, aneg, apack, st);
 }
 
 void launch_hist(const uint32_t* ids, int64_t n, uint32_t* deg, int64_t n_bins, uint32_t* scratch,
@@ -461,11 +494,6 @@ void launch_side_wedges(const int32_t* off, int32_t n_u, const int32_t* adj, int
     if (n_v > 0) hipLaunchKernelGGL(k_side_bins, dim3(grid_for(n_v, 256)), dim3(256), 0, s, deg, n_v, out);
 }
 
-void launch_row_degrees(const int32_t* off, int32_t n_u, uint32_t* deg, const DevStatus* st, hipStream_t s) {
-    if (n_u > 0)
-        hipLaunchKernelGGL(k_row_degrees, dim3(grid_for(n_u, 256)), dim3(256), 0, s, off, n_u, deg, st);
-}
-
 void launch_anchor_graph(const DevGraph* gr, int32_t n_graphs, uint32_t* agid, hipStream_t s) {
     if (n_graphs > 0) hipLaunchKernelGGL(k_anchor_graph, dim3(n_graphs), dim3(256), 0, s, gr, agid);
 }
@@ -479,23 +507,6 @@ void launch_ranks(const uint32_t* inv, const uint32_t* deg_s, int64_t n_s, int32
     if (n_s > 0)
         hipLaunchKernelGGL(k_ranks, dim3(grid_for(n_s, 256)), dim3(256), 0, s, inv, deg_s, n_s, rank, adeg, agid,
                            agraph);
-}
-
-void launch_edge_keys(const uint32_t* ea, const uint32_t* ec, const uint8_t* en, int64_t m, const int32_t* rank,
-                      uint32_t* key, uint32_t* pay, const DevStatus* st, hipStream_t s) {
-    if (m > 0)
-        hipLaunchKernelGGL(k_edge_keys, dim3(grid_for(m, 256)), dim3(256), 0, s, ea, ec, en, m, rank, key, pay, st);
-}
-
-void launch_unpack_edges(const uint32_t* key, const uint32_t* pay, int64_t m, int32_t* acent, uint8_t* aneg,
-                         uint32_t* apack, const DevStatus* st, hipStream_t s) {
-    if (m > 0)
-        hipLaunchKernelGGL(k_unpack_edges, dim3(grid_for(m, 256)), dim3(256), 0, s, key, pay, m, acent, aneg, apack,
-                           st);
-}
-
-void launch_back(const uint32_t* perm, int64_t m, int32_t* back, hipStream_t s) {
-    if (m > 0) hipLaunchKernelGGL(k_back, dim3(grid_for(m, 256)), dim3(256), 0, s, perm, m, back);
 }
 
 void launch_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_t m, DevStatus* st, hipStream_t s) {

@@ -163,12 +163,15 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* keys, in
 // every digit's places are offset by the counts of the waves before, each
 // item goes to its place in the tile sorted by digit (in LDS), and the
 // sorted tile is written out in order, every digit's run at its global
-// offset.  Items stay in registers between the phases.
+// offset.  Items stay in registers between the phases.  With inv_out the
+// second payload is not moved: inv_out[v1] receives the item's new position
+// instead (the inverse of the permutation that payload tracks).
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys, uint32_t* keys_out,
                                                            const uint32_t* v0, uint32_t* v0_out,
                                                            const uint32_t* v1, uint32_t* v1_out, int v1_iota,
-                                                           int64_t n, int shift, const uint32_t* hist,
-                                                           const uint32_t* hist_scan, int64_t nblk) {
+                                                           int32_t* inv_out, int64_t n, int shift,
+                                                           const uint32_t* hist, const uint32_t* hist_scan,
+                                                           int64_t nblk) {
     __shared__ uint32_t s_key[kRsTile];
     __shared__ uint32_t s_v0[kRsTile];
     __shared__ uint32_t s_v1[kRsTile];
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
 #pragma unroll
     for (int k = 0; k < kRsWaves; ++k) wcnt[k][t] = 0;
     __syncthreads();
-    const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr;
+    const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr || inv_out != nullptr;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * (kRsRounds * kWave);
     uint32_t key[kRsRounds], a[kRsRounds], b[kRsRounds], place[kRsRounds];
@@ -242,27 +245,31 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
         const uint32_t g = gstart[d] + (p - lstart[d]);
         keys_out[g] = k;
         if (with_v0) v0_out[g] = s_v0[p];
-        if (with_v1) v1_out[g] = s_v1[p];
+        if (inv_out) inv_out[s_v1[p]] = (int32_t)g;
+        else if (with_v1) v1_out[g] = s_v1[p];
     }
 }
 
 void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32_t* v0_in, uint32_t* v0_a,
                 uint32_t* v0_b, const uint32_t* v1_in, uint32_t* v1_a, uint32_t* v1_b, int64_t n, int bits,
                 uint32_t* hist, uint32_t* hist_scan, uint32_t* partials, hipStream_t s, const uint32_t** k_out,
-                const uint32_t** v0_out, const uint32_t** v1_out) {
+                const uint32_t** v0_out, const uint32_t** v1_out, int32_t* inv_out) {
     const uint32_t *ks = k_in, *v0s = v0_in, *v1s = v1_in;
     int v1_iota = (v1_a != nullptr && v1_in == nullptr) ? 1 : 0;
     int64_t nblk = (n + kRsTile - 1) / kRsTile;
     if (bits < 1) bits = 1;
+    const int n_pass = (bits + 7) / 8;
     int pass = 0;
     for (int shift = 0; shift < bits && n > 0; shift += 8, ++pass) {
         uint32_t* kd = (pass & 1) ? k_b : k_a;
         uint32_t* v0d = v0_in ? ((pass & 1) ? v0_b : v0_a) : nullptr;
-        uint32_t* v1d = v1_a ? ((pass & 1) ? v1_b : v1_a) : nullptr;
+        int32_t* inv = (inv_out && pass == n_pass - 1) ? inv_out : nullptr;
+        uint32_t* v1d = (v1_a && !inv) ? ((pass & 1) ? v1_b : v1_a) : nullptr;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, n, shift, hist, nblk);
         scan_exclusive_u32(hist, hist_scan, 256 * nblk, partials, s);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, kd, v0s, v0d, v1s, v1d,
-                           v1_iota, n, shift, (const uint32_t*)hist, (const uint32_t*)hist_scan, nblk);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kRsThreads), 0, s, ks, kd, v0s, v0d, v1s,
+                           v1d, v1_iota, inv, n, shift, (const uint32_t*)hist,
+                           (const uint32_t*)hist_scan, nblk);
         ks = kd;
         v0s = v0d;
         v1s = v1d;
