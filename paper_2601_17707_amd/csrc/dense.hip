@@ -29,6 +29,8 @@
 // barrier per slice); two workgroups per CU.  A 64 x 64 tile (one MFMA tile
 // per wave, four workgroups per CU) is the alternative the autotuner can
 // pick for small blocks.
+#include <type_traits>
+
 #include "bbc_internal.h"
 
 namespace bbc {
@@ -116,8 +118,9 @@ constexpr int kDRowsPerPass = 256 * 16 / kDK;  // rows one pass of the workgroup
 __device__ __forceinline__ int mfma_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
 
 // One TILE x TILE output tile of the upper triangle of a block product per
-// workgroup (TILE = 128: four waves of 64 x 64, 2 x 2 MFMA tiles each;
-// TILE = 64: four waves of 32 x 32, one MFMA tile each).
+// workgroup, operands staged through registers into two LDS buffers
+// (TILE = 64: four waves of 32 x 32, one MFMA tile each; the 64-row tile
+// option runs this kernel, the 128-row default runs k_dense_lds below).
 template <int TILE>
 __global__ __launch_bounds__(256, TILE == 128 ? 2 : 4) void k_dense(const DevBlock* __restrict__ blocks,
                                                                     const DevTile* __restrict__ tiles,
@@ -232,6 +235,175 @@ __global__ __launch_bounds__(256, TILE == 128 ? 2 : 4) void k_dense(const DevBlo
     if (lane == 0 && acc) atomicAdd(&st->total, acc);
 }
 
+// The 128 x 128 tile with operands loaded straight into LDS
+// (global_load_lds_dwordx4: a wave's load fills 1,024 consecutive LDS
+// bytes, 16 per lane) through kQStages stages of kQK bytes of K, so three
+// stages are in flight while one feeds the matrix cores and no registers
+// hold staged operands.  A stage holds 128 rows of kQK = 64 bytes per
+// matrix; the four 16-byte chunks of row r sit at chunk c ^ qswz(r), which
+// spreads the rows one wave reads at one K offset over all LDS banks (the
+// loads pick their global chunk to match).  Each wave waits for its own
+// loads of a stage, then one barrier makes every wave's loads visible and
+// frees the stage read before it, which is refilled at once.
+constexpr int kQK = 64;
+constexpr int kQStages = 4;
+constexpr int kQTile = 128;
+constexpr int kQStageBytes = kQTile * kQK;
+
+__device__ __forceinline__ int qswz(int r) { return ((r >> 1 ^ r >> 3) & 1) | ((r >> 1) & 2); }
+
+// s_waitcnt with at most n vector memory operations outstanding (expcnt and
+// lgkmcnt left at their maximum)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 16, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
+// kQWaves waves per workgroup in a 2 x kQWaves/2 grid, each owning a 64 x
+// (256 / kQWaves) piece of the tile; wave w loads rows 128 / kQWaves * w ..
+// of both matrices, 16 rows per load.  Four waves of 64 x 64 (two
+// workgroups, eight waves per CU) measured faster than eight of 64 x 32
+// (four waves per SIMD, but half the reuse of each fragment read).
+constexpr int kQWaves = 4;
+__global__ __launch_bounds__(kQWaves * kWave, 2) void k_dense_lds(const DevBlock* __restrict__ blocks,
+                                                                 const DevTile* __restrict__ tiles,
+                                                                 const int8_t* __restrict__ mats,
+                                                                 uint32_t* __restrict__ tabs, DevStatus* st) {
+    constexpr int NWAVE = kQWaves;
+    constexpr int WC = NWAVE / 2;                 // wave columns
+    constexpr int WTR = kQTile / 2, WTC = kQTile / WC;  // wave tile rows, columns
+    constexpr int NTR = WTR / 32, NTC = WTC / 32;  // MFMA tiles per wave tile edge
+    constexpr int RPW = kQTile / NWAVE;            // rows each wave loads per matrix
+    constexpr int LPM = RPW / 16;                  // loads per wave, matrix and stage
+    constexpr int kInFlight = 2 * 2 * LPM;         // loads of the two stages after the one waited for
+    typedef __attribute__((address_space(3))) void lds_t;
+    if (status_bad(st)) return;
+    // one LDS object per stage and matrix: the compiler then sees that a
+    // stage's loads do not touch the stage being read and adds no wait of
+    // its own (the waits below are the ones needed)
+    __shared__ __align__(1024) int8_t A0[kQStageBytes], A1[kQStageBytes], A2[kQStageBytes], A3[kQStageBytes];
+    __shared__ __align__(1024) int8_t B0[kQStageBytes], B1[kQStageBytes], B2[kQStageBytes], B3[kQStageBytes];
+    const DevTile T = tiles[blockIdx.x];
+    const DevBlock B = blocks[T.blk];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int wr = wave / WC, wc = wave % WC;
+    // on a diagonal tile a wave whose outputs all lie below the diagonal
+    // (u > w) loads its share of the operands but issues no matrix
+    // instruction
+    const bool idle = T.ti == T.tj && wr * WTR > wc * WTC + WTC - 1;
+    // this lane's pieces: load j of the wave covers rows RPW w + 16 j ..,
+    // lane l row RPW w + 16 j + l / 4, slot l % 4
+    const int rl = RPW * wave + (lane >> 2), slot = lane & 3;
+    const int64_t kp = B.kpad;
+    const int8_t* ga[LPM];
+    const int8_t* gb[LPM];
+#pragma unroll
+    for (int j = 0; j < LPM; ++j) {
+        const int r = rl + 16 * j;
+        ga[j] = mats + B.mat_off + ((int64_t)T.ti * kQTile + r) * kp + 16 * (slot ^ qswz(r));
+        gb[j] = mats + B.mat_off + ((int64_t)T.tj * kQTile + r) * kp + 16 * (slot ^ qswz(r));
+    }
+    const int n_st = (int)(kp / kQK);  // kpad is a multiple of 64
+
+    v16i accD[NTR][NTC], accP[NTR][NTC];
+#pragma unroll
+    for (int i = 0; i < NTR; ++i)
+#pragma unroll
+        for (int j = 0; j < NTC; ++j) {
+            accD[i][j] = v16i{};
+            accP[i][j] = v16i{};
+        }
+
+    // stage k (K bytes 64 k ..) into stage buffers S (= k % kQStages)
+    auto issue = [&](auto S, int k) {
+        constexpr int I = decltype(S)::value;
+        int8_t* as = I == 0 ? A0 : I == 1 ? A1 : I == 2 ? A2 : A3;
+        int8_t* bs = I == 0 ? B0 : I == 1 ? B1 : I == 2 ? B2 : B3;
+        const int64_t k0 = (int64_t)k * kQK;
+#pragma unroll
+        for (int j = 0; j < LPM; ++j) {
+            __builtin_amdgcn_global_load_lds(ga[j] + k0, (lds_t*)(as + (RPW * wave + 16 * j) * kQK), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(gb[j] + k0, (lds_t*)(bs + (RPW * wave + 16 * j) * kQK), 16, 0, 0);
+        }
+    };
+    // stage k from buffers S: wait for it (every step issues the same number
+    // of loads, so those of the two later stages may stay in flight), refill
+    // the buffers read before it with stage k + 3 (past the last stage the
+    // last one is loaded again, which keeps the count uniform), then feed
+    // the matrix cores
+    auto step = [&](auto S, int k) {
+        constexpr int I = decltype(S)::value;
+        wait_vm<kInFlight>();
+        __builtin_amdgcn_s_barrier();
+        issue(std::integral_constant<int, (I + kQStages - 1) % kQStages>{}, min(k + kQStages - 1, n_st - 1));
+        if (idle) return;
+        const int8_t* as = I == 0 ? A0 : I == 1 ? A1 : I == 2 ? A2 : A3;
+        const int8_t* bs = I == 0 ? B0 : I == 1 ? B1 : I == 2 ? B2 : B3;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            v4i a[NTR], b[NTC], aa[NTR], ba[NTC];
+            const int c = 2 * ks + (lane >> 5);  // logical 16-byte chunk of this lane
+#pragma unroll
+            for (int i = 0; i < NTR; ++i) {
+                const int ra = wr * WTR + i * 32 + (lane & 31);
+                a[i] = *(const v4i*)&as[ra * kQK + 16 * (c ^ qswz(ra))];
+                aa[i] = a[i] & 0x01010101;
+            }
+#pragma unroll
+            for (int j = 0; j < NTC; ++j) {
+                const int rb = wc * WTC + j * 32 + (lane & 31);
+                b[j] = *(const v4i*)&bs[rb * kQK + 16 * (c ^ qswz(rb))];
+                ba[j] = b[j] & 0x01010101;
+            }
+#pragma unroll
+            for (int i = 0; i < NTR; ++i)
+#pragma unroll
+                for (int j = 0; j < NTC; ++j) {
+                    accD[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], accD[i][j], 0, 0, 0);
+                    accP[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[i], ba[j], accP[i][j], 0, 0, 0);
+                }
+        }
+    };
+    // n_st >= 1 (a block has a centre)
+    issue(std::integral_constant<int, 0>{}, 0);
+    issue(std::integral_constant<int, 1>{}, min(1, n_st - 1));
+    issue(std::integral_constant<int, 2>{}, min(2, n_st - 1));
+    int k = 0;
+    for (; k + kQStages <= n_st; k += kQStages) {
+        step(std::integral_constant<int, 0>{}, k);
+        step(std::integral_constant<int, 1>{}, k + 1);
+        step(std::integral_constant<int, 2>{}, k + 2);
+        step(std::integral_constant<int, 3>{}, k + 3);
+    }
+    if (k < n_st) step(std::integral_constant<int, 0>{}, k);
+    if (k + 1 < n_st) step(std::integral_constant<int, 1>{}, k + 1);
+    if (k + 2 < n_st) step(std::integral_constant<int, 2>{}, k + 2);
+    wait_vm<0>();  // no load may still be writing LDS when the workgroup ends
+    if (idle) return;
+
+    unsigned long long acc = 0;
+    uint32_t* tab = tabs + B.tab_off;
+#pragma unroll
+    for (int i = 0; i < NTR; ++i)
+#pragma unroll
+        for (int j = 0; j < NTC; ++j) {
+            const int gw = T.tj * kQTile + wc * WTC + j * 32 + (lane & 31);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int gu = T.ti * kQTile + wr * WTR + i * 32 + mfma_row(e, lane);
+                if (gu < gw && gw < B.n_r) {
+                    const uint32_t P = (uint32_t)accP[i][j][e], D = (uint32_t)accD[i][j][e];
+                    const uint32_t a = (P + D) >> 1, b = (P - D) >> 1;
+                    acc += (unsigned long long)(a * (a - (a > 0u))) + b * (b - (b > 0u));  // twice the pair terms
+                    tab[(int64_t)gu * B.rpad + gw] = a | (b << 16);
+                }
+            }
+        }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc) atomicAdd(&st->total, acc);
+}
+
 // ------------------------------------------------------------ host launchers
 
 void launch_block_mark(const DevBlock* blocks, int32_t n_blocks, int64_t max_ids, int32_t n_s, int32_t n_c,
@@ -267,7 +439,8 @@ void launch_dense(const DevBlock* blocks, const DevTile* tiles, int32_t n_tiles,
     if (tile == 64)
         hipLaunchKernelGGL(k_dense<64>, dim3((unsigned)n_tiles), dim3(256), 0, s, blocks, tiles, mats, tabs, st);
     else
-        hipLaunchKernelGGL(k_dense<128>, dim3((unsigned)n_tiles), dim3(256), 0, s, blocks, tiles, mats, tabs, st);
+        hipLaunchKernelGGL(k_dense_lds, dim3((unsigned)n_tiles), dim3(kQWaves * kWave), 0, s, blocks, tiles, mats, tabs,
+                           st);
 }
 
 }  // namespace bbc

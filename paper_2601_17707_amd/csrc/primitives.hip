@@ -136,20 +136,54 @@ constexpr int kRsWaves = kRsThreads / kWave;
 
 size_t radix_hist_size(int64_t n) { return (size_t)256 * (size_t)((n + kRsTile - 1) / kRsTile) + 1; }
 
-// Digit counts of one tile; hist is digit-major: hist[d * nblk + block].
+// Tile of workgroup b.  Workgroups are dealt round robin over the eight
+// XCDs, so XCD x = b % 8 is given a contiguous range of tiles: consecutive
+// tiles write neighbouring pieces of every digit's output run (and of the
+// digit-major histogram), which then meet in the same L2.
+__device__ __forceinline__ int64_t rs_tile(int64_t b, int64_t nblk) {
+    const int64_t x = b & 7, i = b >> 3, q = nblk >> 3, r = nblk & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Lanes of the wave holding the same 8-bit digit d (eight ballots), among
+// the lanes where valid is set.
+__device__ __forceinline__ unsigned long long digit_peers(uint32_t d, bool valid) {
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        const int on = (d >> bit) & 1u;
+        const unsigned long long m = __ballot(on);
+        peers &= on ? m : ~m;
+    }
+    return peers;
+}
+
+// Digit counts of one tile; hist is digit-major: hist[d * nblk + tile].
+// When every lane of a wave holds the same digit (the high digits of
+// narrow or grouped keys) one lane adds them all, instead of 64 atomics on
+// one LDS word.
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* keys, int64_t n, int shift, uint32_t* hist,
                                                         int64_t nblk) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const int64_t tile = rs_tile(blockIdx.x, nblk);
+    const int64_t base = tile * kRsTile;
 #pragma unroll 4
     for (int r = 0; r < kRsRounds; ++r) {
-        int64_t i = base + (int64_t)r * kRsThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        const int64_t i = base + (int64_t)r * kRsThreads + threadIdx.x;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        if (__all(d == d0 || !valid)) {
+            const unsigned long long vm = __ballot(valid);
+            if (lane_id() == 0 && vm) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblk + tile] = h[threadIdx.x];
 }
 
 // Stable scatter of one tile, staged through LDS so that global writes are
@@ -180,17 +214,19 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
     __shared__ uint32_t wcnt[kRsWaves][256];
     __shared__ uint32_t scan_tmp[kRsWaves + 1];
     const int t = threadIdx.x, w = t / kWave, lane = lane_id();
-    const uint32_t cnt = hist[(int64_t)t * nblk + blockIdx.x];
+    // the inverse scatter's writes go anywhere: tiles in launch order there
+    const int64_t tile = inv_out ? (int64_t)blockIdx.x : rs_tile(blockIdx.x, nblk);
+    const uint32_t cnt = hist[(int64_t)t * nblk + tile];
     uint32_t tot;
     const uint32_t ls = block_exclusive_scan<kRsThreads>(cnt, scan_tmp, &tot);
     lstart[t] = ls;
-    gstart[t] = hist_scan[(int64_t)t * nblk + blockIdx.x];
+    gstart[t] = hist_scan[(int64_t)t * nblk + tile];
 #pragma unroll
     for (int k = 0; k < kRsWaves; ++k) wcnt[k][t] = 0;
     __syncthreads();
     const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr || inv_out != nullptr;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * (kRsRounds * kWave);
+    const int64_t base = tile * kRsTile + (int64_t)w * (kRsRounds * kWave);
     uint32_t key[kRsRounds], a[kRsRounds], b[kRsRounds], place[kRsRounds];
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
@@ -204,13 +240,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
     for (int r = 0; r < kRsRounds; ++r) {
         const bool valid = base + (int64_t)r * kWave + lane < n;
         const uint32_t d = (key[r] >> shift) & 255u;
-        unsigned long long peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const int on = (d >> bit) & 1u;
-            const unsigned long long m = __ballot(on);
-            peers &= on ? m : ~m;
-        }
+        const unsigned long long peers = digit_peers(d, valid);
         const uint32_t rk = (uint32_t)__popcll(peers & below);
         const uint32_t run = wcnt[w][d];
         place[r] = run + rk;
@@ -237,7 +267,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
         }
     }
     __syncthreads();
-    const int64_t tbase = (int64_t)blockIdx.x * kRsTile;
+    const int64_t tbase = tile * kRsTile;
     const uint32_t tile_n = (uint32_t)min((int64_t)kRsTile, n - tbase);
     for (uint32_t p = t; p < tile_n; p += kRsThreads) {
         const uint32_t k = s_key[p];
