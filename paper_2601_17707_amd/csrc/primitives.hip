@@ -194,10 +194,13 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* keys, in
 // items of that digit is the wave's running count of the digit plus the
 // number of such lanes below it (the lowest of them then advances the
 // count; a wave's LDS operations complete in order).  After one barrier
-// every digit's places are offset by the counts of the waves before, each
-// item goes to its place in the tile sorted by digit (in LDS), and the
-// sorted tile is written out in order, every digit's run at its global
-// offset.  Items stay in registers between the phases.  With inv_out the
+// every digit's places are offset by the counts of the waves before.  The
+// key, then each payload, goes to its place in the tile sorted by digit
+// (one LDS buffer, reused) and is written out in order, every digit's run
+// at its global offset (the digit of each place is kept in LDS for the
+// payloads).  Keys and places stay in registers between the phases; each
+// payload is read when its turn comes.  One buffer and few registers let
+// six tiles run per CU (26 KB of LDS each).  With inv_out the
 // second payload is not moved: inv_out[v1] receives the item's new position
 // instead (the inverse of the permutation that payload tracks).
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys, uint32_t* keys_out,
@@ -206,9 +209,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
                                                            int32_t* inv_out, int64_t n, int shift,
                                                            const uint32_t* hist, const uint32_t* hist_scan,
                                                            int64_t nblk) {
-    __shared__ uint32_t s_key[kRsTile];
-    __shared__ uint32_t s_v0[kRsTile];
-    __shared__ uint32_t s_v1[kRsTile];
+    __shared__ uint32_t s_buf[kRsTile];
+    __shared__ uint8_t s_dig[kRsTile];
     __shared__ uint32_t lstart[256];  // first place of each digit in the sorted tile
     __shared__ uint32_t gstart[256];  // global position of that place
     __shared__ uint32_t wcnt[kRsWaves][256];
@@ -226,19 +228,18 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
     __syncthreads();
     const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr || inv_out != nullptr;
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-    const int64_t base = tile * kRsTile + (int64_t)w * (kRsRounds * kWave);
-    uint32_t key[kRsRounds], a[kRsRounds], b[kRsRounds], place[kRsRounds];
+    // 32-bit positions (n < 2^31)
+    const uint32_t n32 = (uint32_t)n;
+    const uint32_t base = (uint32_t)tile * kRsTile + (uint32_t)(w * (kRsRounds * kWave));
+    uint32_t key[kRsRounds], place[kRsRounds];
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
-        const int64_t i = base + (int64_t)r * kWave + lane;
-        const bool valid = i < n;
-        key[r] = valid ? keys[i] : 0u;
-        a[r] = (valid && with_v0) ? v0[i] : 0u;
-        b[r] = (valid && with_v1) ? (v1_iota ? (uint32_t)i : v1[i]) : 0u;
+        const uint32_t i = base + (uint32_t)(r * kWave + lane);
+        key[r] = i < n32 ? keys[i] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
-        const bool valid = base + (int64_t)r * kWave + lane < n;
+        const bool valid = base + (uint32_t)(r * kWave + lane) < n32;
         const uint32_t d = (key[r] >> shift) & 255u;
         const unsigned long long peers = digit_peers(d, valid);
         const uint32_t rk = (uint32_t)__popcll(peers & below);
@@ -257,26 +258,59 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
         }
     }
     __syncthreads();
+    // places in the sorted tile (invalid items get none)
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
-        if (base + (int64_t)r * kWave + lane < n) {
-            const uint32_t pos = wcnt[w][(key[r] >> shift) & 255u] + place[r];
-            s_key[pos] = key[r];
-            if (with_v0) s_v0[pos] = a[r];
-            if (with_v1) s_v1[pos] = b[r];
+        const uint32_t d = (key[r] >> shift) & 255u;
+        place[r] = base + (uint32_t)(r * kWave + lane) < n32 ? wcnt[w][d] + place[r] : 0xffffffffu;
+    }
+    const uint32_t tbase = (uint32_t)tile * kRsTile;
+    const uint32_t tile_n = min((uint32_t)kRsTile, n32 - tbase);
+    // keys (and the digit of every place)
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        if (place[r] != 0xffffffffu) {
+            s_buf[place[r]] = key[r];
+            s_dig[place[r]] = (uint8_t)((key[r] >> shift) & 255u);
         }
     }
     __syncthreads();
-    const int64_t tbase = tile * kRsTile;
-    const uint32_t tile_n = (uint32_t)min((int64_t)kRsTile, n - tbase);
     for (uint32_t p = t; p < tile_n; p += kRsThreads) {
-        const uint32_t k = s_key[p];
-        const uint32_t d = (k >> shift) & 255u;
-        const uint32_t g = gstart[d] + (p - lstart[d]);
-        keys_out[g] = k;
-        if (with_v0) v0_out[g] = s_v0[p];
-        if (inv_out) inv_out[s_v1[p]] = (int32_t)g;
-        else if (with_v1) v1_out[g] = s_v1[p];
+        const uint32_t d = s_dig[p];
+        keys_out[gstart[d] + (p - lstart[d])] = s_buf[p];
+    }
+    if (with_v0) {
+        uint32_t a[kRsRounds];
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r) a[r] = place[r] != 0xffffffffu ? v0[base + (uint32_t)(r * kWave + lane)] : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r)
+            if (place[r] != 0xffffffffu) s_buf[place[r]] = a[r];
+        __syncthreads();
+        for (uint32_t p = t; p < tile_n; p += kRsThreads) {
+            const uint32_t d = s_dig[p];
+            v0_out[gstart[d] + (p - lstart[d])] = s_buf[p];
+        }
+    }
+    if (with_v1) {
+        uint32_t b[kRsRounds];
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r) {
+            const uint32_t i = base + (uint32_t)(r * kWave + lane);
+            b[r] = place[r] != 0xffffffffu ? (v1_iota ? i : v1[i]) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r)
+            if (place[r] != 0xffffffffu) s_buf[place[r]] = b[r];
+        __syncthreads();
+        for (uint32_t p = t; p < tile_n; p += kRsThreads) {
+            const uint32_t d = s_dig[p];
+            const uint32_t g = gstart[d] + (p - lstart[d]);
+            if (inv_out) inv_out[s_buf[p]] = (int32_t)g;
+            else v1_out[g] = s_buf[p];
+        }
     }
 }
 
