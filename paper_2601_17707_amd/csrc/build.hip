@@ -176,17 +176,43 @@ __global__ void k_run_degrees(const uint32_t* first, int64_t n, uint32_t* deg) {
 // the run of anchor a moves, in its order, to aoff[rank[a]]; each entry
 // becomes centre id, sign, and the packed rank << 1 | neg that goes into
 // the centre lists.
-__global__ void k_move_lists(const uint32_t* key, const uint32_t* pay, int64_t m, const uint32_t* first,
-                             const int32_t* rank, const uint32_t* aoff, int32_t* acent, uint8_t* aneg,
-                             uint32_t* apack, const DevStatus* st) {
+__global__ void k_move_lists(const uint32_t* __restrict__ key, const uint32_t* __restrict__ pay, int64_t m,
+                             const uint32_t* __restrict__ first, const int32_t* __restrict__ rank,
+                             const uint32_t* __restrict__ aoff, int32_t* __restrict__ acent,
+                             uint8_t* __restrict__ aneg, uint32_t* __restrict__ apack, const DevStatus* st) {
     if (input_bad(st)) return;
-    GRID_STRIDE(p, m) {
-        const uint32_t a = key[p], c = pay[p];
-        const int32_t r = rank[a];
-        const int64_t q = (int64_t)aoff[r] + (p - (int64_t)first[a]);
-        acent[q] = (int32_t)(c & 0x7fffffffu);
-        aneg[q] = (uint8_t)(c >> 31);
-        apack[q] = ((uint32_t)r << 1) | (c >> 31);
+    constexpr int U = 4;  // entries per thread whose gathers are in flight together
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * U;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x; p0 < m; p0 += stride) {
+        uint32_t a[U], c[U], f[U], o[U];
+        int32_t r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            a[u] = p < m ? key[p] : 0u;
+            c[u] = p < m ? pay[p] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            r[u] = p < m ? rank[a[u]] : 0;
+            f[u] = p < m ? first[a[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            o[u] = p < m ? aoff[r[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            if (p < m) {
+                const int64_t q = (int64_t)o[u] + (p - (int64_t)f[u]);
+                acent[q] = (int32_t)(c[u] & 0x7fffffffu);
+                aneg[q] = (uint8_t)(c[u] >> 31);
+                apack[q] = ((uint32_t)r[u] << 1) | (c[u] >> 31);
+            }
+        }
     }
 }
 
@@ -288,41 +314,61 @@ __global__ void k_check_dup(const uint32_t* ckey, const uint32_t* packed, int64_
 // a wave sums runs of equal rank with a segmented scan and adds each run
 // once.  st->wedges receives the sum over centres of C(deg, 2), st->walked
 // the wedges the walk visits.
-__global__ __launch_bounds__(256) void k_work(const uint32_t* apack, const int32_t* acent, const int32_t* back,
-                                              const uint32_t* coff, int64_t m, unsigned long long* work,
-                                              DevStatus* st, HybridView hv) {
+__global__ __launch_bounds__(256) void k_work(const uint32_t* __restrict__ apack, const int32_t* __restrict__ acent,
+                                              const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
+                                              int64_t m, unsigned long long* __restrict__ work, DevStatus* st,
+                                              HybridView hv) {
     if (input_bad(st)) return;
+    constexpr int U = 4;  // entries per thread whose loads are in flight together
     __shared__ unsigned long long red[256 / kWave];
     const int lane = lane_id();
     unsigned long long all = 0, walked = 0;
     // whole waves walk the entries, so the scan below sees every lane
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x; p0 < m; p0 += stride) {
-        const int64_t p = p0 + threadIdx.x;
-        const bool valid = p < m;
-        uint32_t r = 0xffffffffu;
-        unsigned long long wk = 0;
-        if (valid) {
-            r = apack[p] >> 1;
-            const int32_t c = acent[p];
-            const uint32_t suffix = coff[c + 1] - (uint32_t)back[p] - 1u;
-            all += suffix;
-            wk = suffix;
-            if (hv.ablk1) {
-                const int32_t blk = (int32_t)hv.ablk1[r] - 1;
-                if (blk >= 0 && hv.cblk[c] == blk) wk = coff[c + 1] - (uint32_t)hv.cpos[c];
-            }
-            walked += wk;
-        }
-        // inclusive segmented sum over lanes of equal rank
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * U;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x * U; p0 < m; p0 += stride) {
+        uint32_t r[U];
+        unsigned long long wk[U];
+        int32_t c[U];
+        uint32_t bk[U];
 #pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const unsigned long long y = __shfl_up(wk, o, kWave);
-            const uint32_t ry = __shfl_up(r, o, kWave);
-            if (lane >= o && ry == r) wk += y;
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = p0 + u * blockDim.x + threadIdx.x;
+            r[u] = 0xffffffffu;
+            c[u] = 0;
+            bk[u] = 0;
+            if (p < m) {
+                r[u] = apack[p] >> 1;
+                c[u] = acent[p];
+                bk[u] = (uint32_t)back[p];
+            }
         }
-        const uint32_t rn = __shfl_down(r, 1, kWave);
-        if (valid && (lane == kWave - 1 || rn != r) && wk) atomicAdd(&work[r], wk);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wk[u] = 0;
+            if (r[u] != 0xffffffffu) {
+                const uint32_t suffix = coff[c[u] + 1] - bk[u] - 1u;
+                all += suffix;
+                wk[u] = suffix;
+                if (hv.ablk1) {
+                    const int32_t blk = (int32_t)hv.ablk1[r[u]] - 1;
+                    if (blk >= 0 && hv.cblk[c[u]] == blk) wk[u] = coff[c[u] + 1] - (uint32_t)hv.cpos[c[u]];
+                }
+                walked += wk[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // inclusive segmented sum over lanes of equal rank
+            unsigned long long x = wk[u];
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const unsigned long long y = __shfl_up(x, o, kWave);
+                const uint32_t ry = __shfl_up(r[u], o, kWave);
+                if (lane >= o && ry == r[u]) x += y;
+            }
+            const uint32_t rn = __shfl_down(r[u], 1, kWave);
+            if (r[u] != 0xffffffffu && (lane == kWave - 1 || rn != r[u]) && x) atomicAdd(&work[r[u]], x);
+        }
     }
     all = block_sum<256>(all, red);
     walked = block_sum<256>(walked, red);
@@ -395,16 +441,21 @@ __global__ void k_bidx_count(const uint32_t* coff, const uint32_t* packed, int64
 // One thread per list entry q > list start of an indexed list: the granule
 // boundaries that fall between the previous entry's rank and its own point
 // at q.
-__global__ void k_bidx_fill(const uint32_t* ckey, const uint32_t* coff, const uint32_t* packed, int64_t m, int gs,
-                            const uint32_t* ioff, uint32_t* idx, const DevStatus* st) {
+// The neighbour entries are read first (coalesced): an entry that starts
+// its list or crosses no boundary needs no lookup of its centre.
+__global__ void k_bidx_fill(const uint32_t* __restrict__ ckey, const uint32_t* __restrict__ coff,
+                            const uint32_t* __restrict__ packed, int64_t m, int gs, const uint32_t* __restrict__ ioff,
+                            uint32_t* __restrict__ idx, const DevStatus* st) {
     if (input_bad(st)) return;
     GRID_STRIDE(q, m) {
+        if (q == 0) continue;
         const uint32_t c = ckey[q];
-        const uint32_t q0 = coff[c];
-        if ((uint32_t)q == q0 || ioff[c + 1] == ioff[c]) continue;  // list start, or list not indexed
         const uint32_t g = (packed[q] >> 1) >> gs, gp = (packed[q - 1] >> 1) >> gs;
-        const uint32_t klo = ((packed[q0] >> 1) >> gs) + 1u;
-        for (uint32_t k = gp + 1; k <= g; ++k) idx[ioff[c] + (k - klo)] = (uint32_t)q;
+        if (ckey[q - 1] != c || g == gp) continue;  // list start, or no granule boundary crossed
+        const uint32_t i0 = ioff[c];
+        if (ioff[c + 1] == i0) continue;  // list not indexed
+        const uint32_t klo = ((packed[coff[c]] >> 1) >> gs) + 1u;
+        for (uint32_t k = gp + 1; k <= g; ++k) idx[i0 + (k - klo)] = (uint32_t)q;
     }
 }
 
