@@ -79,11 +79,46 @@ __device__ __forceinline__ int32_t graph_in(const int64_t* vstart, int32_t lo, i
 }
 
 // The decode kernels give each workgroup a chunk of kDecChunk consecutive
-// edges: the rows (and graphs) of the chunk lie between those of its first
-// and last edge, found once per workgroup, so each edge searches only that
-// range.
+// edges.  The rows (and graphs) of the chunk lie between those of its first
+// and last edge, found once per workgroup by binary search; every row that
+// starts inside the chunk marks its first edge in LDS (an empty row shares
+// its start with the next row, and the larger index wins), and a running
+// maximum over the chunk then gives every edge its row.
 constexpr int kDecThreads = 256;
-constexpr int kDecChunk = kDecThreads * 16;
+constexpr int kDecItems = 16;  // marks per thread in the running maximum
+constexpr int kDecChunk = kDecThreads * kDecItems;
+
+// LDS index of chunk position i: one pad word per 16 keeps the running
+// maximum (thread t reads positions 16 t ..) free of bank conflicts
+__device__ __forceinline__ int dec_slot(int i) { return i + (i >> 4); }
+
+// In-place running maximum of the chunk's marks (kDecChunk entries, -1
+// where nothing starts), seeded with seed.  Ends with a barrier.
+__device__ __forceinline__ void dec_running_max(int32_t* marks, int32_t seed, int32_t* wmax) {
+    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    int32_t v[kDecItems];
+    int32_t run = -1;
+#pragma unroll
+    for (int k = 0; k < kDecItems; ++k) {
+        run = max(run, marks[dec_slot(t * kDecItems + k)]);
+        v[k] = run;
+    }
+    int32_t x = run;  // inclusive maximum over the wave's threads
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x = max(x, y);
+    }
+    if (lane == kWave - 1) wmax[wave] = x;
+    int32_t before = __shfl_up(x, 1, kWave);
+    if (lane == 0) before = -1;
+    __syncthreads();
+    for (int w = 0; w < wave; ++w) before = max(before, wmax[w]);
+    before = max(before, seed);
+#pragma unroll
+    for (int k = 0; k < kDecItems; ++k) marks[dec_slot(t * kDecItems + k)] = max(before, v[k]);
+    __syncthreads();
+}
 
 // Edge e of a single graph -> anchor id ea[e] and either pay[e] = centre id
 // | negative << 31 (the count) or ec[e] and en[e] (other users), with the
@@ -93,13 +128,23 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_single(const int32_t* of
                                                                int s_is_u, int check_sign, DevStatus* st, uint32_t* ea,
                                                                uint32_t* ec, uint8_t* en, uint32_t* pay) {
     __shared__ int32_t rr[2];
+    __shared__ int32_t rowof[kDecChunk + kDecChunk / 16];
+    __shared__ int32_t wmax[kDecThreads / kWave];
+    const int t = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * kDecChunk;
     const int64_t e1 = min(m, e0 + kDecChunk);
-    if (threadIdx.x < 2) rr[threadIdx.x] = row_in(off, 0, n_u - 1, threadIdx.x ? e1 - 1 : e0);
+    if (t < 2) rr[t] = row_in(off, 0, n_u - 1, t ? e1 - 1 : e0);
+    for (int i = t; i < kDecChunk + kDecChunk / 16; i += kDecThreads) rowof[i] = -1;
     __syncthreads();
     const int32_t lo = rr[0], hi = rr[1];
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kDecThreads) {
-        const int32_t u = row_in(off, lo, hi, e);
+    for (int32_t u = lo + 1 + t; u <= hi; u += kDecThreads) {
+        const int64_t s = off[u];
+        if (s > e0 && s < e1) atomicMax(&rowof[dec_slot((int)(s - e0))], u);
+    }
+    __syncthreads();
+    dec_running_max(rowof, lo, wmax);
+    for (int64_t e = e0 + t; e < e1; e += kDecThreads) {
+        const int32_t u = rowof[dec_slot((int)(e - e0))];
         const int32_t v = adj[e];
         const int8_t s = sg ? sg[e] : (int8_t)1;  // no signs: the block planner
         if (v < 0 || v >= n_v) flag_bad(st, kBadRange, &st->bad_range, e);
@@ -118,30 +163,52 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_single(const int32_t* of
 // Edge j of a batch (graphs laid end to end by vstart, a prefix of the edge
 // counts) -> global anchor id ea[j] and pay[j] = global centre id |
 // negative << 31.  Each graph's anchors and centres are numbered from its
-// anchor_base / centre_base.
+// anchor_base / centre_base.  Graph starts and row starts are marked as
+// above; row u of graph g is marked by anchor_base + centre_base + u, which
+// grows along the batch (each graph adds n_u + n_v to the base).
 __global__ __launch_bounds__(kDecThreads) void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat,
                                                                 const int8_t* sg_cat, const DevGraph* gr,
                                                                 const int64_t* vstart, int32_t n_graphs, int64_t m,
                                                                 int check_sign, DevStatus* st, uint32_t* ea,
                                                                 uint32_t* pay) {
     __shared__ int32_t gg[2], rr[2];
+    __shared__ int32_t graphof[kDecChunk + kDecChunk / 16];
+    __shared__ int32_t rowof[kDecChunk + kDecChunk / 16];
+    __shared__ int32_t wmax[kDecThreads / kWave];
     const int t = threadIdx.x;
     const int64_t e0 = (int64_t)blockIdx.x * kDecChunk;
     const int64_t e1 = min(m, e0 + kDecChunk);
     if (t < 2) gg[t] = graph_in(vstart, 0, n_graphs - 1, t ? e1 - 1 : e0);
+    for (int i = t; i < kDecChunk + kDecChunk / 16; i += kDecThreads) graphof[i] = rowof[i] = -1;
     __syncthreads();
     if (t < 2) {  // rows of the first and last edge inside their graphs
         const DevGraph g = gr[gg[t]];
         rr[t] = row_in(off_cat + g.off_base, 0, g.n_u - 1, (t ? e1 - 1 : e0) - vstart[gg[t]]);
     }
-    __syncthreads();
     const int32_t g_lo = gg[0], g_hi = gg[1];
+    for (int32_t g = g_lo + 1 + t; g <= g_hi; g += kDecThreads) {
+        const int64_t s = vstart[g];
+        if (s > e0 && s < e1) atomicMax(&graphof[dec_slot((int)(s - e0))], g);
+    }
+    __syncthreads();
+    for (int32_t g = g_lo; g <= g_hi; ++g) {
+        const DevGraph G = gr[g];
+        const int64_t vs = vstart[g];
+        const int32_t u0 = g == g_lo ? rr[0] + 1 : 0, u1 = g == g_hi ? rr[1] : G.n_u - 1;
+        for (int32_t u = u0 + t; u <= u1; u += kDecThreads) {
+            const int64_t s = vs + off_cat[G.off_base + u];
+            if (s > e0 && s < e1) atomicMax(&rowof[dec_slot((int)(s - e0))], (int32_t)(G.anchor_base + G.centre_base + u));
+        }
+    }
+    __syncthreads();
+    dec_running_max(graphof, g_lo, wmax);
+    dec_running_max(rowof, (int32_t)(gr[g_lo].anchor_base + gr[g_lo].centre_base + rr[0]), wmax);
     for (int64_t j = e0 + t; j < e1; j += kDecThreads) {
-        const int32_t gi = graph_in(vstart, g_lo, g_hi, j);
+        const int slot = dec_slot((int)(j - e0));
+        const int32_t gi = graphof[slot];
         const DevGraph g = gr[gi];
-        const int64_t e = j - vstart[gi];    // edge index inside the graph
-        const int64_t pe = g.edge_base + e;  // position in the concatenated arrays
-        const int32_t u = row_in(off_cat + g.off_base, gi == g_lo ? rr[0] : 0, gi == g_hi ? rr[1] : g.n_u - 1, e);
+        const int32_t u = rowof[slot] - (int32_t)(g.anchor_base + g.centre_base);
+        const int64_t pe = g.edge_base + (j - vstart[gi]);  // position in the concatenated arrays
         const int32_t v = adj_cat[pe];
         const int8_t s = sg_cat[pe];
         if (v < 0 || v >= g.n_v) flag_bad(st, kBadRange, &st->bad_range, pe);
