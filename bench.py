@@ -17,6 +17,11 @@ recount), the
 dense-block
 workload (hybrid int8 matrix-core path against the sparse-only path), the
 roofline of the wedge kernel and the CPU oracle's rate.
+
+The main graph's configuration (kernel shape, grid, schedule, queue chunk,
+wave-regime threshold) is chosen by the library's autotuner on that graph
+before the timed steps (untimed, like the batch plan's); the time with the
+library's defaults is reported beside it (--no-tune skips the tuning).
 """
 from __future__ import annotations
 
@@ -175,10 +180,12 @@ def bench_uniform(ctx, seed: int, calls: int = 200) -> dict:
                 balanced_butterflies=t)
 
 
-def bench_skewed(ctx, steps: int, warmup: int, seed: int) -> dict:
+def bench_skewed(ctx, steps: int, warmup: int, seed: int, no_tune: bool = False) -> dict:
     """The highly skewed workload (|U| = 5e6, |V| = 2e5, 2e8 edges, hub V
     vertices near 430,000 edges): end-to-end, build and wedge-kernel times,
-    wedges/s and the kernel's roofline fraction on algorithmic bytes."""
+    wedges/s and the kernel's roofline fraction on algorithmic bytes, with
+    the autotuner's configuration for this graph (tuning untimed) and the
+    end-to-end time of the library's defaults beside it."""
     import torch
 
     from paper_2601_17707_amd import bbc, synth
@@ -191,14 +198,22 @@ def bench_skewed(ctx, steps: int, warmup: int, seed: int) -> dict:
     off, adj, sg = bbc.graph_tensors(g, "cuda:0")
     n_v = g.n_v
     del g
-    for _ in range(max(1, warmup)):
-        total = ctx.count(off, adj, sg, n_v)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(steps):
-        total = ctx.count(off, adj, sg, n_v)
-    torch.cuda.synchronize()
-    ms = 1000.0 * (time.perf_counter() - t) / steps
+
+    def time_calls(o):
+        for _ in range(max(1, warmup)):
+            tot = ctx.count(off, adj, sg, n_v, opts=o)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            tot = ctx.count(off, adj, sg, n_v, opts=o)
+        torch.cuda.synchronize()
+        return tot, 1000.0 * (time.perf_counter() - t) / steps
+
+    # defaults, then the autotuner on this graph (untimed), then its choice
+    total_untuned, ms_untuned = time_calls(bbc.options(no_tuning=True))
+    tuned = None if no_tune else ctx.autotune(off, adj, sg, n_v, reps=1)
+    total, ms = time_calls(bbc.options())
+    assert total == total_untuned
     kern, build = [], []
     for _ in range(3):
         ctx.count(off, adj, sg, n_v, opts=bbc.options(timing=True))
@@ -212,7 +227,8 @@ def bench_skewed(ctx, steps: int, warmup: int, seed: int) -> dict:
     del off, adj, sg
     torch.cuda.empty_cache()
     return dict(workload="skewed-5m-200k-200m", seed=seed, n_edges=int(st["n_edges"]), wedges=wedges,
-                ms_per_call=ms, kernel_ms=kavg, build_ms=sum(build) / len(build),
+                ms_per_call=ms, ms_per_call_untuned=ms_untuned, tuned=tuned, kernel_ms=kavg,
+                build_ms=sum(build) / len(build),
                 wedges_per_s=wedges / (ms / 1e3) / 1e9, kernel_wedges_per_s=wedges / (kavg / 1e3) / 1e9, unit="G/s",
                 balanced_butterflies=total, bands=int(st["bands"]),
                 roofline=dict(bound="hbm", kernel="k_wedge", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
@@ -460,6 +476,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-graph batch measurement")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the library's default configuration (no autotuning of the main graph)")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the dense-block workload")
     ap.add_argument("--no-classes", action="store_true", help="skip the sign-pattern class count")
     ap.add_argument("--no-bicliques", action="store_true", help="skip the (2,k)-biclique counts")
@@ -504,15 +522,29 @@ def main():
     opts_t = bbc.options(timing=True)
     opts = bbc.options()
 
-    for _ in range(args.warmup):
-        total = ctx.count(off, adj, sg, g.n_v, opts=opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        total = ctx.count(off, adj, sg, g.n_v, opts=opts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = 1000.0 * elapsed / args.steps
+    def time_steps(o):
+        for _ in range(args.warmup):
+            t = ctx.count(off, adj, sg, g.n_v, opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t = ctx.count(off, adj, sg, g.n_v, opts=o)
+        torch.cuda.synchronize()
+        return t, 1000.0 * (time.perf_counter() - t0) / args.steps
+
+    # the library's defaults first, then the autotuner on this graph
+    # (untimed; it records the fastest configuration for the graph's size
+    # class, which later calls with default options use), then the timed
+    # steps with that configuration
+    total_untuned, ms_untuned = (None, None) if args.no_tune else time_steps(bbc.options(no_tuning=True))
+    tuned, tune_s = None, None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = ctx.autotune(off, adj, sg, g.n_v, reps=1)
+        tune_s = time.perf_counter() - t0
+        print(f"# autotuned in {tune_s:.1f} s: {tuned}", file=sys.stderr, flush=True)
+    total, ms_step = time_steps(opts)
+    assert total_untuned is None or total_untuned == total
 
     # kernel durations from HIP events recorded on the launch stream
     kern_ms, build_ms = [], []
@@ -548,6 +580,10 @@ def main():
         kernel_ms=kavg,
         build_ms=sum(build_ms) / len(build_ms),
         kernel_wedges_per_s=wedges / (kavg / 1e3) / 1e9,
+        tuned=tuned,
+        tune_s=tune_s,
+        ms_per_step_untuned=ms_untuned,
+        value_untuned=None if ms_untuned is None else wedges / (ms_untuned / 1e3) / 1e9,
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                       traffic=measured_traffic(args.workload), kernel="k_wedge", algorithmic_bytes=nbytes,
                       bands=int(st["bands"])),
@@ -571,7 +607,7 @@ def main():
     if not args.no_hybrid and args.workload == WORKLOAD:
         line["hybrid"] = bench_hybrid(ctx, max(1, min(args.steps, 5)), args.warmup, args.seed)
     if not args.no_skewed and args.workload == WORKLOAD:
-        line["skewed"] = bench_skewed(ctx, max(1, min(args.steps, 3)), args.warmup, args.seed)
+        line["skewed"] = bench_skewed(ctx, max(1, min(args.steps, 3)), args.warmup, args.seed, args.no_tune)
     if not args.no_copy:
         line["hbm_copy"] = bench_copy()
     line["host"] = host_info()

@@ -834,7 +834,7 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
 // and returns a result every configuration must reproduce.  Stage 1 times
 // every instantiated shape x grid (1, 2 and as many workgroups per CU as
 // fit) x schedule with the default regimes; stage 2 times the best of them
-// with queue_chunk in {1, 2, 4, 8} x wave_max_work in {shape's largest,
+// with queue_chunk in {1, 2, 4, 8, 16} x wave_max_work in {shape's largest,
 // 256, off}.  Each configuration runs reps + 1 times (the first warms up);
 // its score is the best HIP-event time of the wedge kernel.
 template <class Run>
@@ -885,7 +885,7 @@ bbc_status tune_wedge(bbc_ctx* ctx, int32_t reps, Run run, TuneEntry& best) {
         }
     }
     const TuneEntry shape = best;
-    for (const int32_t qc : {1, 2, 4, 8})
+    for (const int32_t qc : {1, 2, 4, 8, 16})
         for (const int32_t wm : {0, 256, -1}) {
             if (qc == 1 && wm == 0) continue;  // timed in stage 1
             bbc_options o;

@@ -27,7 +27,7 @@ def test_autotune_picks_an_instantiated_shape_and_keeps_the_count(ctx, tmp_path)
     chosen = ctx.autotune(off, adj, sg, g.n_v, reps=1)
     assert (chosen["band_words"], chosen["wg_size"]) in bbc.WEDGE_SHAPES
     assert chosen["wg_per_cu"] >= 1
-    assert chosen["queue_chunk"] in (1, 2, 4, 8) and chosen["wave_max_work"] in (0, 256, -1)
+    assert chosen["queue_chunk"] in (1, 2, 4, 8, 16) and chosen["wave_max_work"] in (0, 256, -1)
     # a default call of the same class now uses the entry
     assert ctx.count(off, adj, sg, g.n_v) == want
     st = ctx.stats()
@@ -153,7 +153,7 @@ def test_autotune_batched_records_the_batch_class(ctx):
     want = [oracle.count(g) for g in graphs]
     chosen = ctx.autotune_batched(b, reps=1)
     assert (chosen["band_words"], chosen["wg_size"]) in bbc.WEDGE_SHAPES
-    assert chosen["queue_chunk"] in (1, 2, 4, 8) and chosen["wave_max_work"] in (0, 256, -1)
+    assert chosen["queue_chunk"] in (1, 2, 4, 8, 16) and chosen["wave_max_work"] in (0, 256, -1)
     assert list(b.totals.cpu().numpy()[: len(graphs)]) == want
     assert list(ctx.count_batched(b).cpu().numpy()[: len(graphs)]) == want
     st = ctx.stats()
