@@ -478,6 +478,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 10,000-graph batch measurement")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the library's default configuration (no autotuning of the main graph)")
+    ap.add_argument("--save-tune", default="", help="write the tuning table after autotuning the main graph")
+    ap.add_argument("--tune-file", default="",
+                    help="load this tuning table instead of autotuning (profiled runs: the tuned configuration "
+                         "without the tuning launches; the default-configuration steps still run unless --no-tune)")
     ap.add_argument("--no-hybrid", action="store_true", help="skip the dense-block workload")
     ap.add_argument("--no-classes", action="store_true", help="skip the sign-pattern class count")
     ap.add_argument("--no-bicliques", action="store_true", help="skip the (2,k)-biclique counts")
@@ -538,11 +542,15 @@ def main():
     # steps with that configuration
     total_untuned, ms_untuned = (None, None) if args.no_tune else time_steps(bbc.options(no_tuning=True))
     tuned, tune_s = None, None
-    if not args.no_tune:
+    if args.tune_file:  # a table an earlier run saved: same configuration, no tuning launches
+        ctx.tune_load(args.tune_file)
+    elif not args.no_tune:
         t0 = time.perf_counter()
         tuned = ctx.autotune(off, adj, sg, g.n_v, reps=1)
         tune_s = time.perf_counter() - t0
         print(f"# autotuned in {tune_s:.1f} s: {tuned}", file=sys.stderr, flush=True)
+        if args.save_tune:
+            ctx.tune_save(args.save_tune)
     total, ms_step = time_steps(opts)
     assert total_untuned is None or total_untuned == total
 

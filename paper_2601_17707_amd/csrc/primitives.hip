@@ -80,7 +80,8 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* partial, int64
 }
 
 // Each thread owns kScanItems consecutive inputs, staged through LDS so the
-// global reads and writes stay coalesced.
+// global reads and writes stay coalesced.  partial == NULL: a single tile
+// (no partial sums to add).
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
                                                              const uint32_t* partial) {
     __shared__ uint32_t stage[kScanTile];
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const uint32_t* in,
         s += v[k];
     }
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan<kScanThreads>(s, tmp, &tot) + partial[blockIdx.x];
+    uint32_t ex = block_exclusive_scan<kScanThreads>(s, tmp, &tot) + (partial ? partial[blockIdx.x] : 0u);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         stage[threadIdx.x * kScanItems + k] = ex;
@@ -121,6 +122,10 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
         return;
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {  // one tile: one launch
+        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)nullptr);
+        return;
+    }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n,
@@ -314,6 +319,85 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* keys,
     }
 }
 
+// Every pass of a sort of at most one tile (n <= kRsTile) in one
+// workgroup: the items stay in LDS between the passes, read back in the
+// (wave, round, lane) order the ranking uses, so each pass is stable as in
+// k_rs_scatter.  Used for the small sorts (per-anchor keys of small graphs),
+// where the launches of the multi-tile passes would dominate.
+__global__ __launch_bounds__(kRsThreads) void k_rs_single(const uint32_t* keys, uint32_t* keys_out,
+                                                          const uint32_t* v0, uint32_t* v0_out, const uint32_t* v1,
+                                                          uint32_t* v1_out, int v1_iota, int32_t* inv_out, int n,
+                                                          int bits) {
+    __shared__ uint32_t s_key[kRsTile];
+    __shared__ uint32_t s_v0[kRsTile];
+    __shared__ uint32_t s_v1[kRsTile];
+    __shared__ uint32_t wcnt[kRsWaves][256];
+    __shared__ uint32_t scan_tmp[kRsWaves + 1];
+    const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+    const bool with_v0 = v0 != nullptr, with_v1 = v1_out != nullptr || inv_out != nullptr;
+    for (int i = t; i < n; i += kRsThreads) {
+        s_key[i] = keys[i];
+        if (with_v0) s_v0[i] = v0[i];
+        if (with_v1) s_v1[i] = v1_iota ? (uint32_t)i : v1[i];
+    }
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    const int base = w * (kRsRounds * kWave);
+    for (int shift = 0; shift < bits; shift += 8) {
+        __syncthreads();  // the previous pass's items are in place
+        uint32_t key[kRsRounds], a[kRsRounds], b[kRsRounds], place[kRsRounds];
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r) {
+            const int i = base + r * kWave + lane;
+            const bool valid = i < n;
+            key[r] = valid ? s_key[i] : 0u;
+            a[r] = (valid && with_v0) ? s_v0[i] : 0u;
+            b[r] = (valid && with_v1) ? s_v1[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kRsWaves; ++k) wcnt[k][t] = 0;
+        __syncthreads();  // every item read; counts cleared
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r) {
+            const bool valid = base + r * kWave + lane < n;
+            const uint32_t d = (key[r] >> shift) & 255u;
+            const unsigned long long peers = digit_peers(d, valid);
+            const uint32_t rk = (uint32_t)__popcll(peers & below);
+            const uint32_t run = wcnt[w][d];
+            place[r] = run + rk;
+            if (valid && rk == 0) wcnt[w][d] = run + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        uint32_t c_all = 0;  // digit t over all waves
+#pragma unroll
+        for (int k = 0; k < kRsWaves; ++k) c_all += wcnt[k][t];
+        uint32_t tot;
+        uint32_t off = block_exclusive_scan<kRsThreads>(c_all, scan_tmp, &tot);
+#pragma unroll
+        for (int k = 0; k < kRsWaves; ++k) {
+            const uint32_t c = wcnt[k][t];
+            wcnt[k][t] = off;
+            off += c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRsRounds; ++r) {
+            if (base + r * kWave + lane < n) {
+                const uint32_t pos = wcnt[w][(key[r] >> shift) & 255u] + place[r];
+                s_key[pos] = key[r];
+                if (with_v0) s_v0[pos] = a[r];
+                if (with_v1) s_v1[pos] = b[r];
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kRsThreads) {
+        keys_out[i] = s_key[i];
+        if (with_v0) v0_out[i] = s_v0[i];
+        if (inv_out) inv_out[s_v1[i]] = i;
+        else if (with_v1) v1_out[i] = s_v1[i];
+    }
+}
+
 void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32_t* v0_in, uint32_t* v0_a,
                 uint32_t* v0_b, const uint32_t* v1_in, uint32_t* v1_a, uint32_t* v1_b, int64_t n, int bits,
                 uint32_t* hist, uint32_t* hist_scan, uint32_t* partials, hipStream_t s, const uint32_t** k_out,
@@ -322,6 +406,16 @@ void radix_sort(const uint32_t* k_in, uint32_t* k_a, uint32_t* k_b, const uint32
     int v1_iota = (v1_a != nullptr && v1_in == nullptr) ? 1 : 0;
     int64_t nblk = (n + kRsTile - 1) / kRsTile;
     if (bits < 1) bits = 1;
+    if (n > 0 && nblk == 1) {  // one tile: every pass in one launch
+        uint32_t* v0d = v0_in ? v0_a : nullptr;
+        uint32_t* v1d = (v1_a && !inv_out) ? v1_a : nullptr;
+        hipLaunchKernelGGL(k_rs_single, dim3(1), dim3(kRsThreads), 0, s, k_in, k_a, v0_in, v0d, v1_in, v1d, v1_iota,
+                           inv_out, (int)n, bits);
+        *k_out = k_a;
+        if (v0_out) *v0_out = v0d;
+        if (v1_out) *v1_out = v1d;
+        return;
+    }
     const int n_pass = (bits + 7) / 8;
     int pass = 0;
     for (int shift = 0; shift < bits && n > 0; shift += 8, ++pass) {
