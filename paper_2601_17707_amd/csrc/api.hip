@@ -109,6 +109,7 @@ __global__ void k_status_init(DevStatus* st) {
         st->walked = 0;
         st->bands = 0;
         st->queue = 0;
+        st->queue2 = 0;
         st->n_light = 0;
     }
 }

@@ -11,7 +11,7 @@ constexpr int kWave = 64;
 // Device-side status and accumulators of one bbc_count call.
 struct DevStatus {
     int32_t flags;  // kBad* bits
-    int32_t pad0;
+    unsigned int queue2;  // second work queue head (the wave-regime launch of count mode)
     int64_t bad_offset;  // first offending index (atomicMin)
     int64_t bad_range;
     int64_t bad_sign;

@@ -1380,7 +1380,12 @@ struct SchedArgs {
 // mode only), summed into st->cls.  BIC: balanced (2,k)-bicliques, the
 // 128-bit sum as 32-bit limbs in st->cls[0..3] and the count of terms
 // beyond 128 bits in st->cls[4].
-template <int WG, int BAND_WORDS, bool FULL, bool CLS = false, bool BIC = false>
+// PH: 0 runs every anchor; count mode runs in two launches, PH = 1 for the
+// workgroup-regime anchors (queue st->queue) and PH = 2 for the wave-regime
+// anchors (queue st->queue2), so that neither path's registers weigh on the
+// other (in one kernel the wave path made the compiler spill the workgroup
+// path's per-anchor state).
+template <int WG, int BAND_WORDS, bool FULL, bool CLS = false, bool BIC = false, int PH = 0>
 __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restrict__ aoff, const int32_t* __restrict__ acent,
                                               const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back,
                                               const uint32_t* __restrict__ coff, const uint32_t* __restrict__ packed,
@@ -1400,15 +1405,21 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
     if (BIC && tid < 16) sh.ctab[tid] = (uint32_t)bv.tab[2 * tid];
     unsigned long long acc = 0, bands = 0;
     ClassSums cs;
-    constexpr bool kLight = !FULL && !CLS && !BIC;
+    constexpr bool kCount = !FULL && !CLS && !BIC;
+    constexpr bool kLight = kCount && PH != 1;  // this launch runs wave-regime anchors
+    constexpr bool kHeavy = PH != 2;            // this launch runs workgroup-regime anchors
     constexpr int NW = WG / kWave;
     constexpr int TW = BAND_WORDS / NW < 2048 ? BAND_WORDS / NW : 2048;  // light table slots per wave
-    const uint32_t n_light = kLight ? *(volatile const uint32_t*)&st->n_light : 0u;
+    const uint32_t n_light = kCount ? *(volatile const uint32_t*)&st->n_light : 0u;
     const uint32_t n_heavy = (uint32_t)n_s - n_light;
     // 32-bit task arithmetic: n_s < 2^31 and both chunks are at most 2^16
     const uint32_t qc = (uint32_t)sc.queue_chunk, lc = (uint32_t)sc.light_chunk;
     const uint32_t heavy_tasks = (n_heavy + qc - 1) / qc;
-    const uint32_t n_tasks = heavy_tasks + (n_light + lc - 1) / lc;
+    const uint32_t light_tasks = kLight ? (n_light + lc - 1) / lc : 0u;
+    // tasks of this launch are [t_first, n_tasks)
+    const uint32_t t_first = PH == 2 ? heavy_tasks : 0u;
+    const uint32_t n_tasks = heavy_tasks + light_tasks;
+    unsigned int* queue = PH == 2 ? &st->queue2 : &st->queue;
 
     // one anchor of the workgroup regime (schedule position pos)
     auto heavy = [&](uint32_t pos) {
@@ -1452,7 +1463,7 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
         acc += a;
     };
 
-    uint32_t snext = blockIdx.x;  // static deal: tasks b, b + grid, b + 2 grid, ... (< 2^32)
+    uint32_t snext = t_first + blockIdx.x;  // static deal: tasks b, b + grid, b + 2 grid, ... (< 2^32)
     for (;;) {
         __syncthreads();
         uint32_t task;
@@ -1460,16 +1471,18 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             task = snext;
             snext += gridDim.x;
         } else {  // dynamic: the next task of the shared queue
-            if (tid == 0) sh.task = (int32_t)atomicAdd(&st->queue, 1u);
+            if (tid == 0) sh.task = (int32_t)atomicAdd(queue, 1u);
             __syncthreads();
-            task = (uint32_t)sh.task;
+            task = t_first + (uint32_t)sh.task;
         }
         if (task >= n_tasks) break;
         if (task < heavy_tasks) {
-            const uint32_t p1 = min(n_heavy, (task + 1) * qc);
-            for (uint32_t pos = task * qc; pos < p1; ++pos) {
-                if (pos > task * qc) __syncthreads();
-                heavy((uint32_t)pos);
+            if constexpr (kHeavy) {
+                const uint32_t p1 = min(n_heavy, (task + 1) * qc);
+                for (uint32_t pos = task * qc; pos < p1; ++pos) {
+                    if (pos > task * qc) __syncthreads();
+                    heavy((uint32_t)pos);
+                }
             }
         } else if constexpr (kLight) {
             // a chunk of light anchors, dealt round robin to the waves
@@ -1547,17 +1560,29 @@ struct WedgeArgs {
     SchedArgs sc;
 };
 
+template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false, int PH = 0>
+static void launch_phase(const WedgeArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS, BIC, PH>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg,
+                       a.back, a.coff, a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base,
+                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv, a.sc);
+}
+
+// Count mode: the workgroup-regime anchors, then the wave-regime ones.
 template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
 static void launch_shape(const WedgeArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_wedge<WG, BW, FULL, CLS, BIC>), dim3(grid), dim3(WG), 0, s, a.aoff, a.acent, a.aneg, a.back,
-                       a.coff, a.packed, a.bidx, a.bmeta, a.order, a.n_s, a.st, a.pv, a.inv, a.anchor_base,
-                       a.centre_base, a.agraph, a.rank_end, a.gtotals, a.hv, a.bv, a.sc);
+    if constexpr (!FULL && !CLS && !BIC) {
+        launch_phase<WG, BW, false, false, false, 1>(a, grid, s);
+        launch_phase<WG, BW, false, false, false, 2>(a, grid, s);
+    } else {
+        launch_phase<WG, BW, FULL, CLS, BIC>(a, grid, s);
+    }
 }
 
 template <int WG, int BW, bool FULL, bool CLS = false, bool BIC = false>
 static int occupancy() {
+    constexpr int PH = (!FULL && !CLS && !BIC) ? 1 : 0;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL, CLS, BIC>, WG, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wedge<WG, BW, FULL, CLS, BIC, PH>, WG, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
