@@ -39,14 +39,15 @@ HYBRID_WORKLOAD = "hybrid-2m-1m-50m-16x4096"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix throughput, 5.0 POPS
 
-# HBM traffic of one k_wedge launch on the default workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
-# scaled by what the counter reads for a 1 GiB device copy (fetch x 2.000,
-# write x 1.000).  Valid only for the kernel sources it was taken on: the
-# bench reports null once their hash differs.
+# HBM traffic of one call's wedge launches (both regimes) on the default
+# workload with the tuned configuration, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# counter reads for a 1 GiB device copy (fetch x 2.000, write x 1.000).
+# Valid only for the kernel sources it was taken on: the bench reports null
+# once their hash differs.
 KERNEL_SOURCES = ["paper_2601_17707_amd/csrc/wedge.hip", "paper_2601_17707_amd/csrc/bbc_internal.h"]
-MEASURED_TRAFFIC = dict(kernel="k_wedge", workload=WORKLOAD, bytes=52679925074,
-                        sources_sha256="43571c78d5f6824eb2c2e3030394371f4a6b4afda503f0d036c8bf6e0f7ceaff",
+MEASURED_TRAFFIC = dict(kernel="k_wedge", workload=WORKLOAD, bytes=56259260896,
+                        sources_sha256="000b91f9ea8a86143cf20d418b22d4c27c549632223124fbc5434d7502156f9d",
                         summary="profiles/k_wedge_powerlaw-1m-500k-20m_pmc.md")
 
 
