@@ -1297,36 +1297,68 @@ __device__ __forceinline__ uint32_t light_insert(uint32_t* __restrict__ tab, uin
 // Rows of 64 wedges loaded together by the wave regime.
 constexpr int kLightRows = 4;
 
-// Twice the pair terms of light anchor r, summed over the wave's lanes
+// A wave-regime anchor read ahead of its walk, in steps a wave can issue
+// while it still walks the anchor before: its rank r (-1: none), then its
+// list range (a0, deg), then each lane's centre (lane < deg: back-pointer,
+// centre id, sign of the anchor edge).
+struct LightAhead {
+    int32_t r, a0, deg;
+    int32_t bk, ce;
+    uint32_t ng;
+};
+
+__device__ __forceinline__ void light_head(LightAhead& n, const uint32_t* __restrict__ aoff) {
+    n.a0 = 0;
+    n.deg = 0;
+    if (n.r >= 0) {
+        n.a0 = (int32_t)aoff[n.r];
+        n.deg = (int32_t)aoff[n.r + 1] - n.a0;
+    }
+}
+
+__device__ __forceinline__ void light_lanes(LightAhead& n, const int32_t* __restrict__ acent,
+                                            const uint8_t* __restrict__ aneg, const int32_t* __restrict__ back) {
+    const int lane = lane_id();
+    n.bk = 0;
+    n.ce = 0;
+    n.ng = 0;
+    if (n.deg >= 2 && lane < n.deg) {
+        const int32_t p = n.a0 + lane;
+        n.bk = back[p];
+        n.ce = acent[p];
+        n.ng = aneg[p];
+    }
+}
+
+// Twice the pair terms of light anchor c, summed over the wave's lanes
 // (each lane returns its share).  cpre / cst: this wave's 64-entry slices
 // of LDS for the prefix of the slice lengths and the slice starts | sign.
+// touched: the hashed table holds entries to clear (light_clear).
 template <int TW>
-__device__ __forceinline__ uint32_t light_anchor(uint32_t* __restrict__ tab, int32_t* __restrict__ cpre,
-                                                 uint32_t* __restrict__ cst, const uint32_t* __restrict__ aoff,
-                                                 const int32_t* __restrict__ acent, const uint8_t* __restrict__ aneg,
-                                                 const int32_t* __restrict__ back, const uint32_t* __restrict__ coff,
-                                                 const uint32_t* __restrict__ packed, int32_t r) {
+__device__ __forceinline__ uint32_t light_walk(uint32_t* __restrict__ tab, int32_t* __restrict__ cpre,
+                                               uint32_t* __restrict__ cst, const uint32_t* __restrict__ coff,
+                                               const uint32_t* __restrict__ packed, const LightAhead& c,
+                                               bool& touched) {
     const int lane = lane_id();
-    const int32_t a0 = (int32_t)aoff[r];
-    const int32_t deg = (int32_t)aoff[r + 1] - a0;
-    if (deg < 2) return 0u;
+    touched = false;
+    if (c.deg < 2) return 0u;
     // slice of centre `lane`: the suffix of its list above the anchor
     int32_t len = 0;
     uint32_t stv = 0;
-    if (lane < deg) {
-        const int32_t p = a0 + lane;
-        const uint32_t s0 = (uint32_t)back[p] + 1u;
-        len = (int32_t)(coff[acent[p] + 1] - s0);
-        stv = s0 | ((uint32_t)aneg[p] << 31);
+    if (lane < c.deg) {
+        const uint32_t s0 = (uint32_t)c.bk + 1u;
+        len = (int32_t)(coff[c.ce + 1] - s0);
+        stv = s0 | (c.ng << 31);
     }
     const int32_t inc = wave_inclusive_scan(len);
     const int32_t total = __shfl(inc, kWave - 1, kWave);
     if (total < 2) return 0u;
-    if (lane < deg) {
+    touched = true;
+    if (lane < c.deg) {
         cpre[lane] = inc - len;
         cst[lane] = stv;
     }
-    if (lane == 0) cpre[deg] = total;
+    if (lane == 0) cpre[c.deg] = total;
     __builtin_amdgcn_wave_barrier();
     // per-lane cursor on the slice holding its wedge
     int32_t k = 0, cb = 0, nb = cpre[1];
@@ -1354,13 +1386,17 @@ __device__ __forceinline__ uint32_t light_anchor(uint32_t* __restrict__ tab, int
 #pragma unroll
         for (int u = 0; u < kLightRows; ++u)
             if ((vm >> u) & 1u)
-                acc += light_insert<TW>(tab, (x[u] >> 1) - (uint32_t)r, (x[u] ^ (ngm >> u)) & 1u);
+                acc += light_insert<TW>(tab, (x[u] >> 1) - (uint32_t)c.r, (x[u] ^ (ngm >> u)) & 1u);
     }
     __builtin_amdgcn_wave_barrier();
-    uint4* t4 = reinterpret_cast<uint4*>(tab);
-    for (int i = lane; i < TW / 4; i += kWave) t4[i] = uint4{0u, 0u, 0u, 0u};
-    __builtin_amdgcn_wave_barrier();
     return 2u * acc;
+}
+
+template <int TW>
+__device__ __forceinline__ void light_clear(uint32_t* __restrict__ tab) {
+    uint4* t4 = reinterpret_cast<uint4*>(tab);
+    for (int i = lane_id(); i < TW / 4; i += kWave) t4[i] = uint4{0u, 0u, 0u, 0u};
+    __builtin_amdgcn_wave_barrier();
 }
 
 // How the persistent workgroups take work: positions [0, n_s - n_light) of
@@ -1494,10 +1530,22 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             const uint32_t p1 = min((uint32_t)n_s, p0 + lc);
             int32_t g_cur = -1;
             uint32_t g_acc = 0;  // this lane's share of the current graph's total (batches)
-            for (uint32_t pos = p0 + wave; pos < p1; pos += NW) {
-                const int32_t r = (int32_t)order[pos];
+            // the wave's anchors pos, pos + NW, ...: the next one's list
+            // range is read during the current walk and its centres during
+            // the current table clear; the one after that's rank one
+            // anchor earlier still
+            uint32_t pos = p0 + wave;
+            LightAhead cur, nxt;
+            cur.r = pos < p1 ? (int32_t)order[pos] : -1;
+            light_head(cur, aoff);
+            light_lanes(cur, acent, aneg, back);
+            int32_t r_n = pos + NW < p1 ? (int32_t)order[pos + NW] : -1;
+            for (; pos < p1; pos += NW) {
+                nxt.r = r_n;
+                light_head(nxt, aoff);
+                r_n = pos + 2 * NW < p1 ? (int32_t)order[pos + 2 * NW] : -1;
                 if (gtotals) {
-                    const int32_t g = agraph[r];
+                    const int32_t g = agraph[cur.r];
                     if (g != g_cur) {
                         const uint32_t t = wave_sum(g_acc);
                         if (lane_id() == 0 && t && g_cur >= 0) atomicAdd(&gtotals[g_cur], (unsigned long long)(t >> 1));
@@ -1505,9 +1553,13 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
                         g_acc = 0;
                     }
                 }
-                const uint32_t a = light_anchor<TW>(tab, cpre, cst, aoff, acent, aneg, back, coff, packed, r);
+                bool touched;
+                const uint32_t a = light_walk<TW>(tab, cpre, cst, coff, packed, cur, touched);
+                light_lanes(nxt, acent, aneg, back);
+                if (touched) light_clear<TW>(tab);
                 acc += a;
                 g_acc += a;
+                cur = nxt;
             }
             if (gtotals) {
                 const unsigned long long t = wave_sum((unsigned long long)g_acc);
