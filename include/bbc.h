@@ -290,8 +290,8 @@ bbc_status bbc_last_stats(const bbc_ctx* ctx, bbc_stats* out);
  * means 2, one warm-up run before them): first every instantiated shape
  * (threads per workgroup, LDS band), persistent grid (1, 2 and as many
  * workgroups per CU as fit) and schedule (BBC_SCHED_*), then, with the
- * fastest of those, queue_chunk in {1, 2, 4, 8, 16} x wave_max_work in {the
- * shape's largest, 256, -1}.  The winner is recorded in the context's table
+ * fastest shape and grid, both schedules x queue_chunk in {1, 2, 4, 8, 16}
+ * x wave_max_work in {the shape's largest, 256, -1}.  The winner is recorded in the context's table
  * under the graph's size class: (bit length of n_S, bit length of
  * m / n_S), n_S the anchor side of the default side rule.  Later bbc_count
  * and batched calls of the same class use it unless their options fix the

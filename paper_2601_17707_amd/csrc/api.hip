@@ -834,9 +834,9 @@ bbc_status run_job(bbc_ctx* ctx, const Job& J, const bbc_options& opts, hipStrea
 // batched tuner.  `run(options, &result)` performs one call (timing on)
 // and returns a result every configuration must reproduce.  Stage 1 times
 // every instantiated shape x grid (1, 2 and as many workgroups per CU as
-// fit) x schedule with the default regimes; stage 2 times the best of them
-// with queue_chunk in {1, 2, 4, 8, 16} x wave_max_work in {shape's largest,
-// 256, off}.  Each configuration runs reps + 1 times (the first warms up);
+// fit) x schedule with the default regimes; stage 2 times the best shape
+// and grid with both schedules x queue_chunk in {1, 2, 4, 8, 16} x
+// wave_max_work in {shape's largest, 256, off}.  Each configuration runs reps + 1 times (the first warms up);
 // its score is the best HIP-event time of the wedge kernel.
 template <class Run>
 bbc_status tune_wedge(bbc_ctx* ctx, int32_t reps, Run run, TuneEntry& best) {
@@ -886,26 +886,29 @@ bbc_status tune_wedge(bbc_ctx* ctx, int32_t reps, Run run, TuneEntry& best) {
         }
     }
     const TuneEntry shape = best;
-    for (const int32_t qc : {1, 2, 4, 8, 16})
-        for (const int32_t wm : {0, 256, -1}) {
-            if (qc == 1 && wm == 0) continue;  // timed in stage 1
-            bbc_options o;
-            bbc_options_init(&o);
-            o.band_words = shape.band_words;
-            o.wg_size = shape.wg_size;
-            o.wg_per_cu = shape.wg_per_cu;
-            o.schedule = shape.schedule;
-            o.queue_chunk = qc;
-            o.wave_max_work = wm;
-            float ms = 0.f;
-            const bbc_status rc = time_cfg(o, &ms);
-            if (rc != BBC_OK) return rc;
-            if (ms < best.ms) {
-                best.queue_chunk = qc;
-                best.wave_max_work = wm;
-                best.ms = ms;
+    // both schedules again: the best chunk can change which one wins
+    for (const int32_t sched : {BBC_SCHED_DYNAMIC, BBC_SCHED_STATIC})
+        for (const int32_t qc : {1, 2, 4, 8, 16})
+            for (const int32_t wm : {0, 256, -1}) {
+                if (qc == 1 && wm == 0) continue;  // timed in stage 1
+                bbc_options o;
+                bbc_options_init(&o);
+                o.band_words = shape.band_words;
+                o.wg_size = shape.wg_size;
+                o.wg_per_cu = shape.wg_per_cu;
+                o.schedule = sched;
+                o.queue_chunk = qc;
+                o.wave_max_work = wm;
+                float ms = 0.f;
+                const bbc_status rc = time_cfg(o, &ms);
+                if (rc != BBC_OK) return rc;
+                if (ms < best.ms) {
+                    best.schedule = sched;
+                    best.queue_chunk = qc;
+                    best.wave_max_work = wm;
+                    best.ms = ms;
+                }
             }
-        }
     return BBC_OK;
 }
 
