@@ -1298,13 +1298,13 @@ __device__ __forceinline__ uint32_t light_insert(uint32_t* __restrict__ tab, uin
 constexpr int kLightRows = 4;
 
 // A wave-regime anchor read ahead of its walk, in steps a wave can issue
-// while it still walks the anchor before: its rank r (-1: none), then its
+// while it still walks the anchors before: its rank r (-1: none), then its
 // list range (a0, deg), then each lane's centre (lane < deg: back-pointer,
-// centre id, sign of the anchor edge).
+// centre id, sign of the anchor edge), then the end of that centre's list.
 struct LightAhead {
     int32_t r, a0, deg;
     int32_t bk, ce;
-    uint32_t ng;
+    uint32_t ng, cend;
 };
 
 __device__ __forceinline__ void light_head(LightAhead& n, const uint32_t* __restrict__ aoff) {
@@ -1330,15 +1330,18 @@ __device__ __forceinline__ void light_lanes(LightAhead& n, const int32_t* __rest
     }
 }
 
+__device__ __forceinline__ void light_ends(LightAhead& n, const uint32_t* __restrict__ coff) {
+    n.cend = (n.deg >= 2 && lane_id() < n.deg) ? coff[n.ce + 1] : 0u;
+}
+
 // Twice the pair terms of light anchor c, summed over the wave's lanes
 // (each lane returns its share).  cpre / cst: this wave's 64-entry slices
 // of LDS for the prefix of the slice lengths and the slice starts | sign.
 // touched: the hashed table holds entries to clear (light_clear).
 template <int TW>
 __device__ __forceinline__ uint32_t light_walk(uint32_t* __restrict__ tab, int32_t* __restrict__ cpre,
-                                               uint32_t* __restrict__ cst, const uint32_t* __restrict__ coff,
-                                               const uint32_t* __restrict__ packed, const LightAhead& c,
-                                               bool& touched) {
+                                               uint32_t* __restrict__ cst, const uint32_t* __restrict__ packed,
+                                               const LightAhead& c, bool& touched) {
     const int lane = lane_id();
     touched = false;
     if (c.deg < 2) return 0u;
@@ -1347,7 +1350,7 @@ __device__ __forceinline__ uint32_t light_walk(uint32_t* __restrict__ tab, int32
     uint32_t stv = 0;
     if (lane < c.deg) {
         const uint32_t s0 = (uint32_t)c.bk + 1u;
-        len = (int32_t)(coff[c.ce + 1] - s0);
+        len = (int32_t)(c.cend - s0);
         stv = s0 | (c.ng << 31);
     }
     const int32_t inc = wave_inclusive_scan(len);
@@ -1530,22 +1533,25 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             const uint32_t p1 = min((uint32_t)n_s, p0 + lc);
             int32_t g_cur = -1;
             uint32_t g_acc = 0;  // this lane's share of the current graph's total (batches)
-            // the wave's anchors pos, pos + NW, ...: the next one's list
-            // range is read during the current walk and its centres during
-            // the current table clear; the one after that's rank one
-            // anchor earlier still
+            // the wave's anchors pos, pos + NW, ... in a pipeline three deep:
+            // while anchor A is walked, B's list ends and C's list range are
+            // in flight, and C's centres while A's table is cleared
             uint32_t pos = p0 + wave;
-            LightAhead cur, nxt;
-            cur.r = pos < p1 ? (int32_t)order[pos] : -1;
-            light_head(cur, aoff);
-            light_lanes(cur, acent, aneg, back);
-            int32_t r_n = pos + NW < p1 ? (int32_t)order[pos + NW] : -1;
+            LightAhead A, B, C;
+            A.r = pos < p1 ? (int32_t)order[pos] : -1;
+            light_head(A, aoff);
+            light_lanes(A, acent, aneg, back);
+            light_ends(A, coff);
+            B.r = pos + NW < p1 ? (int32_t)order[pos + NW] : -1;
+            light_head(B, aoff);
+            light_lanes(B, acent, aneg, back);
+            C.r = pos + 2 * NW < p1 ? (int32_t)order[pos + 2 * NW] : -1;
             for (; pos < p1; pos += NW) {
-                nxt.r = r_n;
-                light_head(nxt, aoff);
-                r_n = pos + 2 * NW < p1 ? (int32_t)order[pos + 2 * NW] : -1;
+                light_ends(B, coff);
+                light_head(C, aoff);
+                const int32_t r_n = pos + 3 * NW < p1 ? (int32_t)order[pos + 3 * NW] : -1;
                 if (gtotals) {
-                    const int32_t g = agraph[cur.r];
+                    const int32_t g = agraph[A.r];
                     if (g != g_cur) {
                         const uint32_t t = wave_sum(g_acc);
                         if (lane_id() == 0 && t && g_cur >= 0) atomicAdd(&gtotals[g_cur], (unsigned long long)(t >> 1));
@@ -1554,12 +1560,14 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
                     }
                 }
                 bool touched;
-                const uint32_t a = light_walk<TW>(tab, cpre, cst, coff, packed, cur, touched);
-                light_lanes(nxt, acent, aneg, back);
+                const uint32_t a = light_walk<TW>(tab, cpre, cst, packed, A, touched);
+                light_lanes(C, acent, aneg, back);
                 if (touched) light_clear<TW>(tab);
                 acc += a;
                 g_acc += a;
-                cur = nxt;
+                A = B;
+                B = C;
+                C.r = r_n;
             }
             if (gtotals) {
                 const unsigned long long t = wave_sum((unsigned long long)g_acc);
