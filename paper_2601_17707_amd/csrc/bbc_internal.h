@@ -104,6 +104,37 @@ __device__ __forceinline__ T wave_sum(T x) {
     return x;
 }
 
+// A lane's value from `CTRL` (a DPP row shift or row broadcast), or 0 where
+// the source lane is out of reach or the lane's row is masked off.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_take(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive max / sum over the lanes of a wave, in registers: shifts by 1,
+// 2, 4 and 8 lanes within each row of 16 (row_shr), then lane 15 of each row
+// into the next row (row_bcast:15, rows 1 and 3) and lane 31 into rows 2 and
+// 3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_inclusive_max_dpp(uint32_t x) {
+    x = max(x, dpp_take<0x111, 0xf>(x));
+    x = max(x, dpp_take<0x112, 0xf>(x));
+    x = max(x, dpp_take<0x114, 0xf>(x));
+    x = max(x, dpp_take<0x118, 0xf>(x));
+    x = max(x, dpp_take<0x142, 0xa>(x));
+    x = max(x, dpp_take<0x143, 0xc>(x));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_sum_dpp(uint32_t x) {
+    x += dpp_take<0x111, 0xf>(x);
+    x += dpp_take<0x112, 0xf>(x);
+    x += dpp_take<0x114, 0xf>(x);
+    x += dpp_take<0x118, 0xf>(x);
+    x += dpp_take<0x142, 0xa>(x);
+    x += dpp_take<0x143, 0xc>(x);
+    return x;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
     const int lane = lane_id();

@@ -1278,20 +1278,52 @@ __device__ __forceinline__ unsigned long long count_anchor(WedgeShared<WG, BAND_
 // the value an increment returns is its share and no reduction pass is
 // needed; the table is then cleared.
 
-// Slot of `key` for wedge type t: claims an empty slot or increments the
-// key's counter; returns the counter's value before the increment.
 template <int TW>
-__device__ __forceinline__ uint32_t light_insert(uint32_t* __restrict__ tab, uint32_t key, uint32_t t) {
-    constexpr int kBits = ilog2(TW);
+__device__ __forceinline__ uint32_t light_hash(uint32_t key) {
+    return (key * 0x9E3779B1u) >> (32 - ilog2(TW));
+}
+
+// Slot of `key` for wedge type t, probing from slot h: claims an empty slot
+// or increments the key's counter; returns the counter's value before the
+// increment.  A slot, once claimed, keeps its key until the table is
+// cleared, so every probe for a key stops at the same slot whatever the
+// order of the insertions.
+template <int TW>
+__device__ __forceinline__ uint32_t light_insert(uint32_t* __restrict__ tab, uint32_t key, uint32_t t, uint32_t h) {
     const uint32_t sh = 6u * t;
     const uint32_t inc = 1u << sh;
-    uint32_t h = (key * 0x9E3779B1u) >> (32 - kBits);
     for (;;) {
         const uint32_t old = atomicCAS(&tab[h], 0u, (key << 12) | inc);
         if (old == 0u) return 0u;
         if ((old >> 12) == key) return (atomicAdd(&tab[h], inc) >> sh) & 63u;
         h = (h + 1u) & (uint32_t)(TW - 1);
     }
+}
+
+// The inserts of N rows (row u valid where bit u of vm is set), taken in
+// lock step: the first probes of all rows go out together, then the
+// increments of the rows whose key was there already; rows that met another
+// key probe on one by one.  Returns the sum of the counters' values before
+// their increments.
+template <int TW, int N>
+__device__ __forceinline__ uint32_t light_insert_rows(uint32_t* __restrict__ tab, const uint32_t (&key)[N],
+                                                      const uint32_t (&t)[N], uint32_t vm) {
+    uint32_t h[N], old[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        h[u] = light_hash<TW>(key[u]);
+        old[u] = ((vm >> u) & 1u) ? atomicCAS(&tab[h[u]], 0u, (key[u] << 12) | (1u << (6u * t[u]))) : 0u;
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+        if (old[u] != 0u && (old[u] >> 12) == key[u])
+            acc += (atomicAdd(&tab[h[u]], 1u << (6u * t[u])) >> (6u * t[u])) & 63u;
+#pragma unroll
+    for (int u = 0; u < N; ++u)
+        if (old[u] != 0u && (old[u] >> 12) != key[u])
+            acc += light_insert<TW>(tab, key[u], t[u], (h[u] + 1u) & (uint32_t)(TW - 1));
+    return acc;
 }
 
 // Rows of 64 wedges loaded together by the wave regime.
@@ -1334,64 +1366,106 @@ __device__ __forceinline__ void light_ends(LightAhead& n, const uint32_t* __rest
     n.cend = (n.deg >= 2 && lane_id() < n.deg) ? coff[n.ce + 1] : 0u;
 }
 
-// Twice the pair terms of light anchor c, summed over the wave's lanes
-// (each lane returns its share).  cpre / cst: this wave's 64-entry slices
-// of LDS for the prefix of the slice lengths and the slice starts | sign.
-// touched: the hashed table holds entries to clear (light_clear).
-template <int TW>
-__device__ __forceinline__ uint32_t light_walk(uint32_t* __restrict__ tab, int32_t* __restrict__ cpre,
-                                               uint32_t* __restrict__ cst, const uint32_t* __restrict__ packed,
-                                               const LightAhead& c, bool& touched) {
+// A wave-regime anchor whose walk has begun.  Lane k holds centre k's
+// slice (the suffix of its list above the anchor): pp its first position in
+// the flattened walk (exclusive prefix of the lengths) | one past its last
+// << 16 (a walk has at most kLightMaxWork positions), sv its list start |
+// sign of the anchor edge << 31.  carry is one more than
+// the slice holding the last position of the rows loaded so far (0 before
+// the first).  The next kLightRows rows are loaded: row u in x[u], bit u of
+// ngm the sign of the anchor edge, bit u of vm set where the lane holds a
+// wedge.  total = 0: nothing to count and the hashed table left untouched.
+static_assert(kLightMaxWork < 65536, "walk positions must fit 16 bits");
+struct LightWalk {
+    int32_t r, total;
+    uint32_t pp, sv, carry;
+    uint32_t x[kLightRows];
+    uint32_t ngm, vm;
+};
+
+// Loads rows j0 .. j0 + kLightRows - 1 of the walk (one wedge per lane and
+// row).  The slice of position j is the last non-empty slice starting at or
+// before j: each non-empty slice marks its start in the wave's LDS marks
+// (mark u + (p & 63) for a start p in row u, value slice + 1), and a running
+// maximum over the lanes, carried from row to row, gives every lane its
+// slice; the marks are zeroed again as they are read.  A lane loads only
+// when its position lies inside the slice found, so every load stays in
+// the slice's list.
+__device__ __forceinline__ void light_rows(LightWalk& w, int32_t j0, uint32_t* __restrict__ mark,
+                                           const uint32_t* __restrict__ packed) {
     const int lane = lane_id();
-    touched = false;
-    if (c.deg < 2) return 0u;
-    // slice of centre `lane`: the suffix of its list above the anchor
+    const int32_t d = (int32_t)(w.pp & 0xffffu) - j0;
+    if ((w.pp >> 16) > (w.pp & 0xffffu) && d >= 0 && d < kLightRows * kWave) mark[d] = (uint32_t)lane + 1u;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t m[kLightRows];
+#pragma unroll
+    for (int u = 0; u < kLightRows; ++u) m[u] = mark[u * kWave + lane];
+#pragma unroll
+    for (int u = 0; u < kLightRows; ++u) mark[u * kWave + lane] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t ngm = 0, vm = 0;
+#pragma unroll
+    for (int u = 0; u < kLightRows; ++u) {
+        const uint32_t kk = max(wave_inclusive_max_dpp(m[u]), w.carry);
+        w.carry = (uint32_t)__builtin_amdgcn_readlane((int)kk, kWave - 1);
+        const int src = ((int)kk - 1) & (kWave - 1);
+        const uint32_t sp = (uint32_t)__shfl((int)w.pp, src, kWave);
+        const int32_t s0 = (int32_t)(sp & 0xffffu), s1 = (int32_t)(sp >> 16);
+        const uint32_t st = (uint32_t)__shfl((int)w.sv, src, kWave);
+        const int32_t j = j0 + u * kWave + lane;
+        w.x[u] = 0u;
+        if (kk != 0u && j < w.total && j >= s0 && j < s1) {
+            w.x[u] = packed[(st & 0x7fffffffu) + (uint32_t)(j - s0)];
+            ngm |= (st >> 31) << u;
+            vm |= 1u << u;
+        }
+    }
+    w.ngm = ngm;
+    w.vm = vm;
+}
+
+// Begins the walk of light anchor c and loads its first rows.
+__device__ __forceinline__ void light_start(LightWalk& w, uint32_t* __restrict__ mark,
+                                            const uint32_t* __restrict__ packed, const LightAhead& c) {
+    const int lane = lane_id();
+    w.r = c.r;
+    w.total = 0;
+    if (c.deg < 2) return;
     int32_t len = 0;
-    uint32_t stv = 0;
+    w.sv = 0;
     if (lane < c.deg) {
         const uint32_t s0 = (uint32_t)c.bk + 1u;
         len = (int32_t)(c.cend - s0);
-        stv = s0 | (c.ng << 31);
+        w.sv = s0 | (c.ng << 31);
     }
-    const int32_t inc = wave_inclusive_scan(len);
-    const int32_t total = __shfl(inc, kWave - 1, kWave);
-    if (total < 2) return 0u;
-    touched = true;
-    if (lane < c.deg) {
-        cpre[lane] = inc - len;
-        cst[lane] = stv;
-    }
-    if (lane == 0) cpre[c.deg] = total;
-    __builtin_amdgcn_wave_barrier();
-    // per-lane cursor on the slice holding its wedge
-    int32_t k = 0, cb = 0, nb = cpre[1];
-    uint32_t cs = cst[0];
+    const int32_t inc = (int32_t)wave_inclusive_sum_dpp((uint32_t)len);
+    const int32_t total = __builtin_amdgcn_readlane(inc, kWave - 1);
+    if (total < 2) return;
+    w.total = total;
+    w.pp = (uint32_t)(inc - len) | ((uint32_t)inc << 16);
+    w.carry = 0;
+    light_rows(w, 0, mark, packed);
+}
+
+// Twice the pair terms of the anchor whose walk w began, summed over the
+// wave's lanes (each lane returns its share): counts the loaded rows, then
+// loads and counts the rest.
+template <int TW>
+__device__ __forceinline__ uint32_t light_finish(LightWalk& w, uint32_t* __restrict__ tab, uint32_t* __restrict__ mark,
+                                                 const uint32_t* __restrict__ packed) {
     uint32_t acc = 0;  // at most kLightMaxWork increments of at most 63
-    for (int32_t j0 = 0; j0 < total; j0 += kWave * kLightRows) {
-        uint32_t x[kLightRows];
-        uint32_t ngm = 0, vm = 0;
+    for (int32_t j0 = 0;;) {
+        uint32_t key[kLightRows], t[kLightRows];
 #pragma unroll
         for (int u = 0; u < kLightRows; ++u) {
-            const int32_t j = j0 + u * kWave + lane;
-            x[u] = 0u;
-            if (j < total) {
-                while (j >= nb) {
-                    ++k;
-                    cb = nb;
-                    nb = cpre[k + 1];
-                    cs = cst[k];
-                }
-                x[u] = packed[(cs & 0x7fffffffu) + (uint32_t)(j - cb)];
-                ngm |= (cs >> 31) << u;
-                vm |= 1u << u;
-            }
+            key[u] = (w.x[u] >> 1) - (uint32_t)w.r;
+            t[u] = (w.x[u] ^ (w.ngm >> u)) & 1u;
         }
-#pragma unroll
-        for (int u = 0; u < kLightRows; ++u)
-            if ((vm >> u) & 1u)
-                acc += light_insert<TW>(tab, (x[u] >> 1) - (uint32_t)c.r, (x[u] ^ (ngm >> u)) & 1u);
+        acc += light_insert_rows<TW>(tab, key, t, w.vm);
+        j0 += kWave * kLightRows;
+        if (j0 >= w.total) break;
+        light_rows(w, j0, mark, packed);
     }
-    __builtin_amdgcn_wave_barrier();
     return 2u * acc;
 }
 
@@ -1527,29 +1601,43 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             // a chunk of light anchors, dealt round robin to the waves
             const int wave = tid / kWave;
             uint32_t* tab = sh.cnt + wave * TW;
-            int32_t* cpre = sh.tab[1].pre + wave * kWave;
-            uint32_t* cst = sh.tab[1].start + wave * kWave;
             const uint32_t p0 = n_heavy + (task - heavy_tasks) * lc;
             const uint32_t p1 = min((uint32_t)n_s, p0 + lc);
             int32_t g_cur = -1;
             uint32_t g_acc = 0;  // this lane's share of the current graph's total (batches)
-            // the wave's anchors pos, pos + NW, ... in a pipeline three deep:
-            // while anchor A is walked, B's list ends and C's list range are
-            // in flight, and C's centres while A's table is cleared
+            // the wave's anchors pos, pos + NW, ... in a pipeline four deep:
+            // while anchor A is counted, the first rows of B are in flight,
+            // C's list ends and D's list range; D's centres while A's table
+            // is cleared.  The marks of the row loads: kLightRows * 64 words
+            // per wave, in the slice tables (unused by wave-regime anchors),
+            // zero between loads.
+            static_assert(sizeof(sh.tab) >= (size_t)NW * kLightRows * kWave * 4, "light marks must fit");
+            uint32_t* const mark = reinterpret_cast<uint32_t*>(&sh.tab[0]) + wave * (kLightRows * kWave);
+#pragma unroll
+            for (int u = 0; u < kLightRows; ++u) mark[u * kWave + lane_id()] = 0u;
+            __builtin_amdgcn_wave_barrier();
             uint32_t pos = p0 + wave;
-            LightAhead A, B, C;
-            A.r = pos < p1 ? (int32_t)order[pos] : -1;
-            light_head(A, aoff);
-            light_lanes(A, acent, aneg, back);
-            light_ends(A, coff);
+            LightAhead B, C, D;
+            B.r = pos < p1 ? (int32_t)order[pos] : -1;
+            light_head(B, aoff);
+            light_lanes(B, acent, aneg, back);
+            light_ends(B, coff);
+            LightWalk A;
+            light_start(A, mark, packed, B);
             B.r = pos + NW < p1 ? (int32_t)order[pos + NW] : -1;
             light_head(B, aoff);
             light_lanes(B, acent, aneg, back);
+            light_ends(B, coff);
             C.r = pos + 2 * NW < p1 ? (int32_t)order[pos + 2 * NW] : -1;
+            light_head(C, aoff);
+            light_lanes(C, acent, aneg, back);
+            D.r = pos + 3 * NW < p1 ? (int32_t)order[pos + 3 * NW] : -1;
             for (; pos < p1; pos += NW) {
-                light_ends(B, coff);
-                light_head(C, aoff);
-                const int32_t r_n = pos + 3 * NW < p1 ? (int32_t)order[pos + 3 * NW] : -1;
+                LightWalk Bw;
+                light_start(Bw, mark, packed, B);
+                light_ends(C, coff);
+                light_head(D, aoff);
+                const int32_t r_n = pos + 4 * NW < p1 ? (int32_t)order[pos + 4 * NW] : -1;
                 if (gtotals) {
                     const int32_t g = agraph[A.r];
                     if (g != g_cur) {
@@ -1559,15 +1647,16 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
                         g_acc = 0;
                     }
                 }
-                bool touched;
-                const uint32_t a = light_walk<TW>(tab, cpre, cst, packed, A, touched);
-                light_lanes(C, acent, aneg, back);
+                const bool touched = A.total > 0;
+                const uint32_t a = touched ? light_finish<TW>(A, tab, mark, packed) : 0u;
+                light_lanes(D, acent, aneg, back);
                 if (touched) light_clear<TW>(tab);
                 acc += a;
                 g_acc += a;
-                A = B;
+                A = Bw;
                 B = C;
-                C.r = r_n;
+                C = D;
+                D.r = r_n;
             }
             if (gtotals) {
                 const unsigned long long t = wave_sum((unsigned long long)g_acc);
