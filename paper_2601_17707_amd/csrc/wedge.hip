@@ -1331,20 +1331,24 @@ constexpr int kLightRows = 4;
 
 // A wave-regime anchor read ahead of its walk, in steps a wave can issue
 // while it still walks the anchors before: its rank r (-1: none), then its
-// list range (a0, deg), then each lane's centre (lane < deg: back-pointer,
-// centre id, sign of the anchor edge), then the end of that centre's list.
+// list range (a0, deg) and, in a batch, its graph g, then each lane's centre
+// (lane < deg: back-pointer, centre id, sign of the anchor edge), then the
+// end of that centre's list.
 struct LightAhead {
-    int32_t r, a0, deg;
+    int32_t r, a0, deg, g;
     int32_t bk, ce;
     uint32_t ng, cend;
 };
 
-__device__ __forceinline__ void light_head(LightAhead& n, const uint32_t* __restrict__ aoff) {
+__device__ __forceinline__ void light_head(LightAhead& n, const uint32_t* __restrict__ aoff,
+                                           const int32_t* __restrict__ agraph) {
     n.a0 = 0;
     n.deg = 0;
+    n.g = -1;
     if (n.r >= 0) {
         n.a0 = (int32_t)aoff[n.r];
         n.deg = (int32_t)aoff[n.r + 1] - n.a0;
+        if (agraph) n.g = agraph[n.r];
     }
 }
 
@@ -1377,7 +1381,7 @@ __device__ __forceinline__ void light_ends(LightAhead& n, const uint32_t* __rest
 // wedge.  total = 0: nothing to count and the hashed table left untouched.
 static_assert(kLightMaxWork < 65536, "walk positions must fit 16 bits");
 struct LightWalk {
-    int32_t r, total;
+    int32_t r, g, total;
     uint32_t pp, sv, carry;
     uint32_t x[kLightRows];
     uint32_t ngm, vm;
@@ -1429,6 +1433,7 @@ __device__ __forceinline__ void light_start(LightWalk& w, uint32_t* __restrict__
                                             const uint32_t* __restrict__ packed, const LightAhead& c) {
     const int lane = lane_id();
     w.r = c.r;
+    w.g = c.g;
     w.total = 0;
     if (c.deg < 2) return;
     int32_t len = 0;
@@ -1619,27 +1624,27 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             uint32_t pos = p0 + wave;
             LightAhead B, C, D;
             B.r = pos < p1 ? (int32_t)order[pos] : -1;
-            light_head(B, aoff);
+            light_head(B, aoff, agraph);
             light_lanes(B, acent, aneg, back);
             light_ends(B, coff);
             LightWalk A;
             light_start(A, mark, packed, B);
             B.r = pos + NW < p1 ? (int32_t)order[pos + NW] : -1;
-            light_head(B, aoff);
+            light_head(B, aoff, agraph);
             light_lanes(B, acent, aneg, back);
             light_ends(B, coff);
             C.r = pos + 2 * NW < p1 ? (int32_t)order[pos + 2 * NW] : -1;
-            light_head(C, aoff);
+            light_head(C, aoff, agraph);
             light_lanes(C, acent, aneg, back);
             D.r = pos + 3 * NW < p1 ? (int32_t)order[pos + 3 * NW] : -1;
             for (; pos < p1; pos += NW) {
                 LightWalk Bw;
                 light_start(Bw, mark, packed, B);
                 light_ends(C, coff);
-                light_head(D, aoff);
+                light_head(D, aoff, agraph);
                 const int32_t r_n = pos + 4 * NW < p1 ? (int32_t)order[pos + 4 * NW] : -1;
                 if (gtotals) {
-                    const int32_t g = agraph[A.r];
+                    const int32_t g = A.g;
                     if (g != g_cur) {
                         const uint32_t t = wave_sum(g_acc);
                         if (lane_id() == 0 && t && g_cur >= 0) atomicAdd(&gtotals[g_cur], (unsigned long long)(t >> 1));
