@@ -87,6 +87,7 @@ __device__ __forceinline__ int32_t graph_in(const int64_t* vstart, int32_t lo, i
 constexpr int kDecThreads = 256;
 constexpr int kDecItems = 16;  // marks per thread in the running maximum
 constexpr int kDecChunk = kDecThreads * kDecItems;
+constexpr int kDecGroup = 4;  // edges per thread whose loads are issued together
 
 // LDS index of chunk position i: one pad word per 16 keeps the running
 // maximum (thread t reads positions 16 t ..) free of bank conflicts
@@ -166,11 +167,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_single(const int32_t* of
 // anchor_base / centre_base.  Graph starts and row starts are marked as
 // above; row u of graph g is marked by anchor_base + centre_base + u, which
 // grows along the batch (each graph adds n_u + n_v to the base).
-__global__ __launch_bounds__(kDecThreads) void k_decode_batched(const int32_t* off_cat, const int32_t* adj_cat,
-                                                                const int8_t* sg_cat, const DevGraph* gr,
-                                                                const int64_t* vstart, int32_t n_graphs, int64_t m,
-                                                                int check_sign, DevStatus* st, uint32_t* ea,
-                                                                uint32_t* pay) {
+__global__ __launch_bounds__(kDecThreads) void k_decode_batched(const int32_t* __restrict__ off_cat,
+                                                                const int32_t* __restrict__ adj_cat,
+                                                                const int8_t* __restrict__ sg_cat,
+                                                                const DevGraph* __restrict__ gr,
+                                                                const int64_t* __restrict__ vstart, int32_t n_graphs,
+                                                                int64_t m, int check_sign, DevStatus* st,
+                                                                uint32_t* __restrict__ ea, uint32_t* __restrict__ pay) {
     __shared__ int32_t gg[2], rr[2];
     __shared__ int32_t graphof[kDecChunk + kDecChunk / 16];
     __shared__ int32_t rowof[kDecChunk + kDecChunk / 16];
@@ -203,18 +206,46 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(const int32_t* o
     __syncthreads();
     dec_running_max(graphof, g_lo, wmax);
     dec_running_max(rowof, (int32_t)(gr[g_lo].anchor_base + gr[g_lo].centre_base + rr[0]), wmax);
-    for (int64_t j = e0 + t; j < e1; j += kDecThreads) {
-        const int slot = dec_slot((int)(j - e0));
-        const int32_t gi = graphof[slot];
-        const DevGraph g = gr[gi];
-        const int32_t u = rowof[slot] - (int32_t)(g.anchor_base + g.centre_base);
-        const int64_t pe = g.edge_base + (j - vstart[gi]);  // position in the concatenated arrays
-        const int32_t v = adj_cat[pe];
-        const int8_t s = sg_cat[pe];
-        if (v < 0 || v >= g.n_v) flag_bad(st, kBadRange, &st->bad_range, pe);
-        if (check_sign && s != 1 && s != -1) flag_bad(st, kBadSign, &st->bad_sign, pe);
-        ea[j] = (uint32_t)(g.anchor_base + (g.s_is_u ? u : v));
-        pay[j] = (uint32_t)(g.centre_base + (g.s_is_u ? v : u)) | ((s < 0 ? 1u : 0u) << 31);
+    // kDecGroup edges per thread at a time, every load of the group issued
+    // before any of its values is used (the graph of an edge decides where
+    // its adjacency entry lies)
+    for (int64_t jb = e0 + t; jb < e1; jb += kDecGroup * kDecThreads) {
+        int32_t gi[kDecGroup], uu[kDecGroup];
+#pragma unroll
+        for (int q = 0; q < kDecGroup; ++q) {
+            const int64_t j = jb + q * kDecThreads;
+            const int slot = dec_slot((int)(min(j, e1 - 1) - e0));
+            gi[q] = graphof[slot];
+            uu[q] = rowof[slot];
+        }
+        int64_t pe[kDecGroup], ab[kDecGroup], cb[kDecGroup];
+        int32_t nv[kDecGroup], su[kDecGroup];
+#pragma unroll
+        for (int q = 0; q < kDecGroup; ++q) {
+            const DevGraph& g = gr[gi[q]];
+            pe[q] = g.edge_base + (min(jb + q * kDecThreads, e1 - 1) - vstart[gi[q]]);
+            ab[q] = g.anchor_base;
+            cb[q] = g.centre_base;
+            nv[q] = g.n_v;
+            su[q] = g.s_is_u;
+        }
+        int32_t v[kDecGroup];
+        int8_t sv[kDecGroup];
+#pragma unroll
+        for (int q = 0; q < kDecGroup; ++q) {
+            v[q] = adj_cat[pe[q]];
+            sv[q] = sg_cat[pe[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < kDecGroup; ++q) {
+            const int64_t j = jb + q * kDecThreads;
+            if (j >= e1) continue;
+            const int32_t u = uu[q] - (int32_t)(ab[q] + cb[q]);
+            if (v[q] < 0 || v[q] >= nv[q]) flag_bad(st, kBadRange, &st->bad_range, pe[q]);
+            if (check_sign && sv[q] != 1 && sv[q] != -1) flag_bad(st, kBadSign, &st->bad_sign, pe[q]);
+            ea[j] = (uint32_t)(ab[q] + (su[q] ? u : v[q]));
+            pay[j] = (uint32_t)(cb[q] + (su[q] ? v[q] : u)) | ((sv[q] < 0 ? 1u : 0u) << 31);
+        }
     }
 }
 
