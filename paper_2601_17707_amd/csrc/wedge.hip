@@ -497,15 +497,15 @@ __device__ __forceinline__ Batch load_batch(const SliceTable<WG>& t, const uint3
     return bt;
 }
 
-// Counts the wedges of one batch: every loaded element lies in the current
-// band (slices are cut at the band's ends), so no range test is needed.
-// In MASKED batches rows past the wave's last row are skipped and lanes
-// holding no wedge add zero.  Dense bands increment without a return
-// value; sparse ones mark the first increment of a word in the
-// touched-word bitmap.
-template <int MODE, bool MASKED, int WG, int BAND_WORDS, bool FULL>
-__device__ __forceinline__ void count_batch(WedgeShared<WG, BAND_WORDS, FULL>& sh, const Batch& b, bool dense) {
-    uint32_t byte[kUnroll], inc[kUnroll];
+// Counts the wedges of one batch in two steps: count_prep takes each
+// loaded element to its counter field (byte offset in the band, increment),
+// count_apply adds the increments.  Every loaded element lies in the current
+// band (slices are cut at the band's ends), so no range test is needed.  In
+// MASKED batches rows past the wave's last row are skipped and lanes holding
+// no wedge add zero.  Dense bands increment without a return value; sparse
+// ones mark the first increment of a word in the touched-word bitmap.
+template <int MODE, bool MASKED, int BAND_WORDS>
+__device__ __forceinline__ void count_prep(const Batch& b, uint32_t (&byte)[kUnroll], uint32_t (&inc)[kUnroll]) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
         const uint32_t ng = (MASKED ? b.ngmask >> u : b.ngmask) & 1u;
@@ -516,18 +516,23 @@ __device__ __forceinline__ void count_batch(WedgeShared<WG, BAND_WORDS, FULL>& s
         const uint32_t one = MASKED ? (b.vmask >> u) & 1u : 1u;
         inc[u] = (MODE == 3 || MODE == 7) ? one : one << shift;
     }
+}
+
+template <int MODE, bool MASKED, int WG, int BAND_WORDS, bool FULL>
+__device__ __forceinline__ void count_apply(WedgeShared<WG, BAND_WORDS, FULL>& sh, const uint32_t (&byte)[kUnroll],
+                                            const uint32_t (&inc)[kUnroll], int32_t rows, bool dense) {
     char* base = reinterpret_cast<char*>(sh.cnt);
     if (dense) {  // no return value needed: the reduction scans the band
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            if (!MASKED || u < b.rows)
+            if (!MASKED || u < rows)
                 (void)__hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(base + byte[u]), inc[u], __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
         uint32_t old[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            old[u] = (!MASKED || u < b.rows) ? atomicAdd(reinterpret_cast<uint32_t*>(base + byte[u]), inc[u]) : 1u;
+            old[u] = (!MASKED || u < rows) ? atomicAdd(reinterpret_cast<uint32_t*>(base + byte[u]), inc[u]) : 1u;
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
             if (old[u] == 0 && inc[u] != 0) atomicOr(&sh.bmp[byte[u] >> 7], 1u << ((byte[u] >> 2) & 31u));
@@ -569,6 +574,13 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         const Batch cur = have_next ? next : load_batch(t, packed, w);
         w.j += kUnroll * kWave;
         have_next = w.r + 2 * kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb);
+        // the current batch's fields first, then the next batch's loads:
+        // a wave's loads complete in order, so a use of the current batch
+        // placed after the next batch's loads would wait for those as well
+        uint32_t byte[kUnroll], inc[kUnroll];
+        if (cur.full) count_prep<MODE, false, BAND_WORDS>(cur, byte, inc);
+        else count_prep<MODE, true, BAND_WORDS>(cur, byte, inc);
+        __builtin_amdgcn_sched_barrier(0);
         if (have_next) {
             const uint32_t* row = packed + (uint32_t)(w.base + w.j);
 #pragma unroll
@@ -578,8 +590,9 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
             next.rows = kUnroll;
             next.full = true;
         }
-        if (cur.full) count_batch<MODE, false>(sh, cur, dense);
-        else count_batch<MODE, true>(sh, cur, dense);
+        __builtin_amdgcn_sched_barrier(0);
+        if (cur.full) count_apply<MODE, false>(sh, byte, inc, kUnroll, dense);
+        else count_apply<MODE, true>(sh, byte, inc, cur.rows, dense);
     }
 }
 
