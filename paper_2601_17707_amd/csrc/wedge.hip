@@ -1465,24 +1465,35 @@ __device__ __forceinline__ void light_start(LightWalk& w, uint32_t* __restrict__
     light_rows(w, 0, mark, packed);
 }
 
-// Twice the pair terms of the anchor whose walk w began, summed over the
-// wave's lanes (each lane returns its share): counts the loaded rows, then
-// loads and counts the rest.
+// Turns the loaded rows of walk w into table keys (endpoint rank minus the
+// anchor's rank, in x) and wedge types (bit u of ngm: 0 signs agree, 1
+// differ).
+__device__ __forceinline__ void light_prep(LightWalk& w) {
+    uint32_t tm = 0;
+#pragma unroll
+    for (int u = 0; u < kLightRows; ++u) {
+        tm |= ((w.x[u] ^ (w.ngm >> u)) & 1u) << u;
+        w.x[u] = (w.x[u] >> 1) - (uint32_t)w.r;
+    }
+    w.ngm = tm;
+}
+
+// Twice the pair terms of the anchor whose walk w began, its loaded rows
+// prepared (light_prep), summed over the wave's lanes (each lane returns
+// its share): counts the loaded rows, then loads and counts the rest.
 template <int TW>
 __device__ __forceinline__ uint32_t light_finish(LightWalk& w, uint32_t* __restrict__ tab, uint32_t* __restrict__ mark,
                                                  const uint32_t* __restrict__ packed) {
     uint32_t acc = 0;  // at most kLightMaxWork increments of at most 63
     for (int32_t j0 = 0;;) {
-        uint32_t key[kLightRows], t[kLightRows];
+        uint32_t t[kLightRows];
 #pragma unroll
-        for (int u = 0; u < kLightRows; ++u) {
-            key[u] = (w.x[u] >> 1) - (uint32_t)w.r;
-            t[u] = (w.x[u] ^ (w.ngm >> u)) & 1u;
-        }
-        acc += light_insert_rows<TW>(tab, key, t, w.vm);
+        for (int u = 0; u < kLightRows; ++u) t[u] = (w.ngm >> u) & 1u;
+        acc += light_insert_rows<TW>(tab, w.x, t, w.vm);
         j0 += kWave * kLightRows;
         if (j0 >= w.total) break;
         light_rows(w, j0, mark, packed);
+        light_prep(w);
     }
     return 2u * acc;
 }
@@ -1651,6 +1662,11 @@ __global__ __launch_bounds__(WG, 1024 / WG) void k_wedge(const uint32_t* __restr
             light_lanes(C, acent, aneg, back);
             D.r = pos + 3 * NW < p1 ? (int32_t)order[pos + 3 * NW] : -1;
             for (; pos < p1; pos += NW) {
+                // A's rows are used before any load below is issued: a wave's
+                // loads complete in order, so a use placed after newer loads
+                // would wait for those too
+                if (A.total > 0) light_prep(A);
+                __builtin_amdgcn_sched_barrier(0);
                 LightWalk Bw;
                 light_start(Bw, mark, packed, B);
                 light_ends(C, coff);
