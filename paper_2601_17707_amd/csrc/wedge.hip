@@ -563,17 +563,18 @@ __device__ __forceinline__ void walk_start(const SliceTable<WG>& t, const uint32
     }
 }
 
-// Counts the wedges of this wave's rows.  The batch after the current one
-// is loaded before the current one is counted when it lies inside every
-// lane's slice.
+// Counts the wedges of this wave's rows.  walk_start has loaded the first
+// batch (next, have_next set when the wave has rows); each step loads the
+// batch after the current one (a full batch by one address, else through
+// the slice cursors) before the current one's increments are applied.
 template <int MODE, int WG, int BAND_WORDS, bool FULL>
 __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh, const SliceTable<WG>& t,
                                           const uint32_t* __restrict__ packed, bool dense, RowWalk& w, Batch& next,
                                           bool& have_next) {
-    for (; w.r < w.r1; w.r += kUnroll) {
-        const Batch cur = have_next ? next : load_batch(t, packed, w);
+    while (w.r < w.r1) {
+        const Batch cur = next;
         w.j += kUnroll * kWave;
-        have_next = w.r + 2 * kUnroll <= w.r1 && __all(w.j + (kUnroll - 1) * kWave < w.nb);
+        w.r += kUnroll;
         // the current batch's fields first, then the next batch's loads:
         // a wave's loads complete in order, so a use of the current batch
         // placed after the next batch's loads would wait for those as well
@@ -581,15 +582,8 @@ __device__ __forceinline__ void walk_rows(WedgeShared<WG, BAND_WORDS, FULL>& sh,
         if (cur.full) count_prep<MODE, false, BAND_WORDS>(cur, byte, inc);
         else count_prep<MODE, true, BAND_WORDS>(cur, byte, inc);
         __builtin_amdgcn_sched_barrier(0);
-        if (have_next) {
-            const uint32_t* row = packed + (uint32_t)(w.base + w.j);
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) next.x[u] = row[u * kWave];
-            next.ngmask = (w.st >> 31) ? 0xffffffffu : 0u;
-            next.vmask = (1u << kUnroll) - 1u;
-            next.rows = kUnroll;
-            next.full = true;
-        }
+        have_next = w.r < w.r1;
+        if (have_next) next = load_batch(t, packed, w);
         __builtin_amdgcn_sched_barrier(0);
         if (cur.full) count_apply<MODE, false>(sh, byte, inc, kUnroll, dense);
         else count_apply<MODE, true>(sh, byte, inc, cur.rows, dense);
